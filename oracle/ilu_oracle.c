@@ -1,0 +1,573 @@
+/*
+ * Sequential CPU oracle for level-of-fill ILU(k) preconditioning.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path links, loads or
+ * calls this file: only the test-suite, the package smoke check and the
+ * benchmark's CPU-baseline leg do.  It shares no code, header, table or
+ * helper with the GPU library; both sides only consume the same seeded input
+ * arrays.
+ *
+ * Every routine is the plain sequential definition written out, in the order
+ * of operations the paper fixes (Dong & Cooperman, "A Bit-Compatible Shared
+ * Memory Parallelization for ILU(k) Preconditioning ...").  Floating point is
+ * IEEE-754 binary64 with round-to-nearest-even; every product and every sum
+ * is rounded on its own (the file is compiled with -ffp-contract=off, no
+ * -ffast-math, SSE2 arithmetic as on any x86-64 target).
+ *
+ * Conventions: 0-based indices, CSR with columns strictly ascending in each
+ * row; F holds L~ strictly below the diagonal (unit diagonal implicit) and U~
+ * on and above it (Sec. 2, "filled matrix").
+ *
+ * Status codes: 0 ok, 1 invalid input, 2 out of memory, 3 zero pivot,
+ * 5 not converged.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL 1
+#define ORC_ENOMEM 2
+#define ORC_EZEROPIVOT 3
+#define ORC_ENOTCONV 5
+
+/* ------------------------------------------------------------------------ */
+/* Input validation: strictly ascending in-range columns, diagonal stored.   */
+/* Every stored entry counts as a nonzero of A (structural reading of        */
+/* Def. 2.3), so explicit zeros take part in the pattern.                    */
+/* ------------------------------------------------------------------------ */
+int orc_validate(int64_t n, const int64_t *rp, const int32_t *ci)
+{
+    if (n < 0 || rp[0] != 0) return ORC_EINVAL;
+    for (int64_t j = 0; j < n; ++j) {
+        if (rp[j + 1] < rp[j]) return ORC_EINVAL;
+        int has_diag = 0;
+        for (int64_t p = rp[j]; p < rp[j + 1]; ++p) {
+            if (ci[p] < 0 || ci[p] >= n) return ORC_EINVAL;
+            if (p > rp[j] && ci[p] <= ci[p - 1]) return ORC_EINVAL;
+            if (ci[p] == j) has_diag = 1;
+        }
+        if (!has_diag) return ORC_EINVAL;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Phase I: symbolic factorization, Algorithm 1 (Sec. 2.2).                  */
+/*                                                                           */
+/* For each row j in ascending order: admit A's entries with level 0, then   */
+/* repeatedly take the smallest not yet processed column i < j of row j      */
+/* (entries inserted while the row is being merged included), and for each   */
+/* entry t > i of the already final row i compute the weight                 */
+/* level(j,i) + level(i,t) + 1; an existing entry keeps the minimum, a new   */
+/* one is inserted when its weight does not exceed k.                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n, nnz;
+    int64_t *rowptr; /* n+1 */
+    int32_t *col;    /* nnz */
+    int32_t *lev;    /* nnz */
+} orc_pattern;
+
+void orc_pattern_free(orc_pattern *p)
+{
+    free(p->rowptr);
+    free(p->col);
+    free(p->lev);
+    p->rowptr = NULL;
+    p->col = NULL;
+    p->lev = NULL;
+}
+
+/* binary min-heap of column indices */
+static void heap_push(int32_t *h, int64_t *sz, int32_t v)
+{
+    int64_t i = (*sz)++;
+    h[i] = v;
+    while (i > 0) {
+        int64_t par = (i - 1) / 2;
+        if (h[par] <= h[i]) break;
+        int32_t t = h[par];
+        h[par] = h[i];
+        h[i] = t;
+        i = par;
+    }
+}
+
+static int32_t heap_pop(int32_t *h, int64_t *sz)
+{
+    int32_t top = h[0];
+    int64_t s = --(*sz);
+    h[0] = h[s];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < s && h[l] < h[m]) m = l;
+        if (r < s && h[r] < h[m]) m = r;
+        if (m == i) break;
+        int32_t t = h[m];
+        h[m] = h[i];
+        h[i] = t;
+        i = m;
+    }
+    return top;
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+int orc_symbolic(int64_t n, const int64_t *rp, const int32_t *ci, int32_t k, orc_pattern *out)
+{
+    memset(out, 0, sizeof(*out));
+    if (k < 0) return ORC_EINVAL;
+    int st = orc_validate(n, rp, ci);
+    if (st) return st;
+
+    int64_t cap = rp[n] > 16 ? rp[n] : 16;
+    int64_t *rowptr = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int32_t *col = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
+    int32_t *lev = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
+    int32_t *lev_of = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t)); /* -1: absent */
+    int32_t *list = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *heap = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!rowptr || !col || !lev || !lev_of || !list || !heap) {
+        free(rowptr); free(col); free(lev); free(lev_of); free(list); free(heap);
+        return ORC_ENOMEM;
+    }
+    for (int64_t t = 0; t < n; ++t) lev_of[t] = -1;
+
+    int64_t nnz = 0;
+    rowptr[0] = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t len = 0, hs = 0;
+        /* initialization: admit the entries of A with level 0 */
+        for (int64_t p = rp[j]; p < rp[j + 1]; ++p) {
+            int32_t t = ci[p];
+            lev_of[t] = 0;
+            list[len++] = t;
+            if (t < j) heap_push(heap, &hs, t);
+        }
+        /* row-merge update pass */
+        while (hs > 0) {
+            int32_t i = heap_pop(heap, &hs);
+            int64_t lji = lev_of[i];
+            for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+                int32_t t = col[q];
+                if (t <= i) continue;
+                int64_t w = lji + (int64_t)lev[q] + 1;
+                if (lev_of[t] >= 0) {
+                    if (w < lev_of[t]) lev_of[t] = (int32_t)w;
+                } else if (w <= k) {
+                    lev_of[t] = (int32_t)w;
+                    list[len++] = t;
+                    if (t < j) heap_push(heap, &hs, t);
+                }
+            }
+        }
+        qsort(list, (size_t)len, sizeof(int32_t), cmp_i32);
+        if (nnz + len > cap) {
+            while (nnz + len > cap) cap *= 2;
+            int32_t *c2 = (int32_t *)realloc(col, (size_t)cap * sizeof(int32_t));
+            if (!c2) { free(col); col = NULL; }
+            else col = c2;
+            int32_t *l2 = col ? (int32_t *)realloc(lev, (size_t)cap * sizeof(int32_t)) : NULL;
+            if (!l2) { free(lev); lev = NULL; }
+            else lev = l2;
+            if (!col || !lev) {
+                free(rowptr); free(col); free(lev); free(lev_of); free(list); free(heap);
+                return ORC_ENOMEM;
+            }
+        }
+        for (int64_t a = 0; a < len; ++a) {
+            col[nnz + a] = list[a];
+            lev[nnz + a] = lev_of[list[a]];
+            lev_of[list[a]] = -1;
+        }
+        nnz += len;
+        rowptr[j + 1] = nnz;
+    }
+    free(lev_of);
+    free(list);
+    free(heap);
+    out->n = n;
+    out->nnz = nnz;
+    out->rowptr = rowptr;
+    out->col = col;
+    out->lev = lev;
+    return ORC_OK;
+}
+
+/* diagonal slot of every row of a pattern; -1 if absent */
+static int find_diag(int64_t n, const int64_t *rpF, const int32_t *ciF, int64_t *diag)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        diag[i] = -1;
+        for (int64_t s = rpF[i]; s < rpF[i + 1]; ++s)
+            if (ciF[s] == i) { diag[i] = s; break; }
+        if (diag[i] < 0) return ORC_EINVAL;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Phase II: numeric factorization, row-wise IKJ (Eq. 2 read as running      */
+/* updates, Eqs. 5a/5b).  F starts as A scattered into the pattern, fill     */
+/* entries +0.0.  Row j in ascending order; for each pivot h < j of row j in */
+/* ascending order:  f_jh <- f_jh / f_hh, then for every t > h stored in     */
+/* both row h and row j:  f_jt <- f_jt - f_jh * f_ht.                        */
+/* A zero pivot does not stop the elimination (IEEE division yields +-inf or */
+/* NaN); *bad_row receives the smallest row whose final pivot f_jj is +-0,   */
+/* or -1.                                                                    */
+/* ------------------------------------------------------------------------ */
+int orc_numeric(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
+                const int64_t *rpF, const int32_t *ciF, double *vF, int64_t *bad_row)
+{
+    *bad_row = -1;
+    int64_t *slot_of = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *diag = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!slot_of || !diag) { free(slot_of); free(diag); return ORC_ENOMEM; }
+    int st = find_diag(n, rpF, ciF, diag);
+    if (st) { free(slot_of); free(diag); return st; }
+    for (int64_t t = 0; t < n; ++t) slot_of[t] = -1;
+
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t s = rpF[j]; s < rpF[j + 1]; ++s) {
+            slot_of[ciF[s]] = s;
+            vF[s] = 0.0;
+        }
+        for (int64_t p = rpA[j]; p < rpA[j + 1]; ++p) {
+            int64_t s = slot_of[ciA[p]];
+            if (s < 0) { st = ORC_EINVAL; break; }
+            vF[s] = vA[p];
+        }
+        if (st) break;
+        for (int64_t s = rpF[j]; s < diag[j]; ++s) {
+            int64_t h = ciF[s];
+            vF[s] = vF[s] / vF[diag[h]];
+            double l = vF[s];
+            for (int64_t q = diag[h] + 1; q < rpF[h + 1]; ++q) {
+                int64_t p = slot_of[ciF[q]];
+                if (p >= 0) vF[p] = vF[p] - l * vF[q];
+            }
+        }
+        if (vF[diag[j]] == 0.0 && *bad_row < 0) *bad_row = j;
+        for (int64_t s = rpF[j]; s < rpF[j + 1]; ++s) slot_of[ciF[s]] = -1;
+    }
+    free(slot_of);
+    free(diag);
+    if (st) return st;
+    return *bad_row >= 0 ? ORC_EZEROPIVOT : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Applying M^-1 = U~^-1 L~^-1 (Eq. 1): forward substitution (Eq. 3b) with   */
+/* a running subtraction in ascending column order, then backward            */
+/* substitution, running subtraction in ascending column order, then the     */
+/* division by the pivot.                                                    */
+/* ------------------------------------------------------------------------ */
+int orc_apply(int64_t n, const int64_t *rpF, const int32_t *ciF, const double *vF,
+              const double *p, double *x, double *y)
+{
+    int64_t *diag = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!diag) return ORC_ENOMEM;
+    int st = find_diag(n, rpF, ciF, diag);
+    if (st) { free(diag); return st; }
+    for (int64_t i = 0; i < n; ++i) {
+        double s = p[i];
+        for (int64_t q = rpF[i]; q < diag[i]; ++q) s = s - vF[q] * x[ciF[q]];
+        x[i] = s;
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double s = x[i];
+        for (int64_t q = diag[i] + 1; q < rpF[i + 1]; ++q) s = s - vF[q] * y[ciF[q]];
+        y[i] = s / vF[diag[i]];
+    }
+    free(diag);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Krylov building blocks.  The paper keeps inner products sequential so     */
+/* their result does not depend on the thread count (Sec. 3.5); here every   */
+/* reduction has one fixed shape that depends only on the vector length.    */
+/* ------------------------------------------------------------------------ */
+
+/* y = A x, each row summed from +0.0 in ascending column order */
+void orc_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+              const double *x, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s = s + v[p] * x[ci[p]];
+        y[i] = s;
+    }
+}
+
+#define ORC_DOT_LANES 16384
+
+/* Fixed-shape inner product: 16384 strided partial sums (lane l sums the    */
+/* products of elements l, l+16384, ... in ascending order from +0.0), then  */
+/* a pairwise tree: at stride w = 1, 2, 4, ..., lane l (l a multiple of 2w)  */
+/* becomes lane l + lane l+w.  The result is lane 0.                         */
+double orc_dot(int64_t n, const double *x, const double *y)
+{
+    static double s[ORC_DOT_LANES];
+    for (int64_t l = 0; l < ORC_DOT_LANES; ++l) {
+        double a = 0.0;
+        for (int64_t e = l; e < n; e += ORC_DOT_LANES) a = a + x[e] * y[e];
+        s[l] = a;
+    }
+    for (int64_t w = 1; w < ORC_DOT_LANES; w *= 2)
+        for (int64_t l = 0; l < ORC_DOT_LANES; l += 2 * w) s[l] = s[l] + s[l + w];
+    return s[0];
+}
+
+double orc_nrm2(int64_t n, const double *x) { return sqrt(orc_dot(n, x, x)); }
+
+/* ------------------------------------------------------------------------ */
+/* Restarted GMRES(m), right preconditioned: the solver works on A M^-1,     */
+/* M = L~ U~ (Sec. 2: the iterative solver implicitly solves A U~^-1 L~^-1). */
+/* Modified Gram-Schmidt Arnoldi, Givens rotations (rho computed as          */
+/* sqrt(a*a + b*b), no hypot), inner loop stopped on the implicit residual   */
+/* |g_{j+1}|, outer loop on the true residual.  maxit counts inner           */
+/* iterations over all cycles.  x holds x0 on entry.  hist (nullable, maxit  */
+/* entries) receives |g_{j+1}| after every inner iteration.                  */
+/* ------------------------------------------------------------------------ */
+int orc_gmres(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
+              const int64_t *rpF, const int32_t *ciF, const double *vF,
+              const double *b, double *x, int32_t m, int32_t maxit, double rtol,
+              int32_t *iters_out, double *relres_out, double *hist)
+{
+    *iters_out = 0;
+    *relres_out = 0.0;
+    if (m < 1 || maxit < 0) return ORC_EINVAL;
+    size_t N = (size_t)(n > 0 ? n : 1);
+    double *V = (double *)malloc((size_t)(m + 1) * N * sizeof(double));
+    double *w = (double *)malloc(N * sizeof(double));
+    double *z = (double *)malloc(N * sizeof(double));
+    double *t = (double *)malloc(N * sizeof(double));
+    double *H = (double *)malloc((size_t)(m + 1) * (size_t)m * sizeof(double));
+    double *cs = (double *)malloc((size_t)m * sizeof(double));
+    double *sn = (double *)malloc((size_t)m * sizeof(double));
+    double *g = (double *)malloc((size_t)(m + 1) * sizeof(double));
+    double *yv = (double *)malloc((size_t)m * sizeof(double));
+    if (!V || !w || !z || !t || !H || !cs || !sn || !g || !yv) {
+        free(V); free(w); free(z); free(t); free(H); free(cs); free(sn); free(g); free(yv);
+        return ORC_ENOMEM;
+    }
+#define HH(i, j) H[(size_t)(i) * (size_t)m + (size_t)(j)]
+    int st = ORC_OK;
+    int32_t iters = 0;
+    double bnorm = orc_nrm2(n, b);
+    if (bnorm == 0.0) {
+        for (int64_t e = 0; e < n; ++e) x[e] = 0.0;
+        goto done;
+    }
+    double tol = rtol * bnorm;
+    for (;;) {
+        /* true residual */
+        orc_spmv(n, rpA, ciA, vA, x, w);
+        for (int64_t e = 0; e < n; ++e) w[e] = b[e] - w[e];
+        double beta = orc_nrm2(n, w);
+        if (beta <= tol || iters >= maxit) break;
+        for (int64_t e = 0; e < n; ++e) V[e] = w[e] / beta;
+        g[0] = beta;
+        int32_t jj = 0;
+        for (int32_t j = 0; j < m; ++j) {
+            double *vj = V + (size_t)j * N;
+            orc_apply(n, rpF, ciF, vF, vj, t, z);
+            orc_spmv(n, rpA, ciA, vA, z, w);
+            for (int32_t i = 0; i <= j; ++i) {
+                double *vi = V + (size_t)i * N;
+                double hij = orc_dot(n, w, vi);
+                HH(i, j) = hij;
+                for (int64_t e = 0; e < n; ++e) w[e] = w[e] - hij * vi[e];
+            }
+            double hn = orc_nrm2(n, w);
+            HH(j + 1, j) = hn;
+            if (hn != 0.0) {
+                double *vn = V + (size_t)(j + 1) * N;
+                for (int64_t e = 0; e < n; ++e) vn[e] = w[e] / hn;
+            }
+            for (int32_t i = 0; i < j; ++i) {
+                double a = HH(i, j), c = HH(i + 1, j);
+                double tau = cs[i] * a + sn[i] * c;
+                HH(i + 1, j) = cs[i] * c - sn[i] * a;
+                HH(i, j) = tau;
+            }
+            double a = HH(j, j), c = HH(j + 1, j);
+            double rho = sqrt(a * a + c * c);
+            cs[j] = a / rho;
+            sn[j] = c / rho;
+            HH(j, j) = rho;
+            HH(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            if (hist) hist[iters] = fabs(g[j + 1]);
+            ++iters;
+            jj = j + 1;
+            if (fabs(g[j + 1]) <= tol || iters >= maxit || hn == 0.0) break;
+        }
+        /* back substitution H(0:jj,0:jj) y = g, then x += M^-1 (V y) */
+        for (int32_t i = jj - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int32_t l = i + 1; l < jj; ++l) s = s - HH(i, l) * yv[l];
+            yv[i] = s / HH(i, i);
+        }
+        for (int64_t e = 0; e < n; ++e) {
+            double s = 0.0;
+            for (int32_t i = 0; i < jj; ++i) s = s + yv[i] * V[(size_t)i * N + (size_t)e];
+            w[e] = s;
+        }
+        orc_apply(n, rpF, ciF, vF, w, t, z);
+        for (int64_t e = 0; e < n; ++e) x[e] = x[e] + z[e];
+    }
+    orc_spmv(n, rpA, ciA, vA, x, w);
+    for (int64_t e = 0; e < n; ++e) w[e] = b[e] - w[e];
+    *relres_out = orc_nrm2(n, w) / bnorm;
+    if (!(*relres_out <= rtol)) st = ORC_ENOTCONV;
+done:
+    *iters_out = iters;
+#undef HH
+    free(V); free(w); free(z); free(t); free(H); free(cs); free(sn); free(g); free(yv);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of y = U~^-1 L~^-1 b (reverse mode).  With x = L~^-1 b:           */
+/*   z = U~^-T ybar  (i ascending, z_i = (ybar_i - sum_{j<i} f_ji z_j)/f_ii, */
+/*                    running subtraction in ascending j)                    */
+/*   w = L~^-T z     (i descending, w_i = z_i - sum_{j>i} f_ji w_j,          */
+/*                    running subtraction in ascending j)                    */
+/*   bbar = w;  Fbar_ij = -(z_i y_j) on U (j >= i);  Fbar_ih = -(w_i x_h)    */
+/*   on the strict lower part.                                               */
+/* ------------------------------------------------------------------------ */
+static int transpose_pattern(int64_t n, const int64_t *rp, const int32_t *ci, int64_t **tp_out,
+                             int64_t **tslot_out)
+{
+    int64_t nnz = rp[n];
+    int64_t *tp = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t *ts = (int64_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
+    int64_t *fillp = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!tp || !ts || !fillp) { free(tp); free(ts); free(fillp); return ORC_ENOMEM; }
+    for (int64_t s = 0; s < nnz; ++s) tp[ci[s] + 1]++;
+    for (int64_t c = 0; c < n; ++c) tp[c + 1] += tp[c];
+    for (int64_t c = 0; c < n; ++c) fillp[c] = tp[c];
+    for (int64_t r = 0; r < n; ++r) /* rows ascending: each column lists rows ascending */
+        for (int64_t s = rp[r]; s < rp[r + 1]; ++s) ts[fillp[ci[s]]++] = s;
+    free(fillp);
+    *tp_out = tp;
+    *tslot_out = ts;
+    return ORC_OK;
+}
+
+/* row index of slot s, by binary search in rp */
+static int64_t row_of(int64_t n, const int64_t *rp, int64_t s)
+{
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) / 2;
+        if (rp[mid] <= s) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+int orc_apply_adjoint(int64_t n, const int64_t *rpF, const int32_t *ciF, const double *vF,
+                      const double *x, const double *y, const double *ybar, double *bbar,
+                      double *Fbar)
+{
+    int64_t *diag = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    double *z = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!diag || !z) { free(diag); free(z); return ORC_ENOMEM; }
+    int st = find_diag(n, rpF, ciF, diag);
+    int64_t *tp = NULL, *ts = NULL;
+    if (!st) st = transpose_pattern(n, rpF, ciF, &tp, &ts);
+    if (st) { free(diag); free(z); return st; }
+    /* z = U^-T ybar: column i of U above the diagonal = rows j < i */
+    for (int64_t i = 0; i < n; ++i) {
+        double s = ybar[i];
+        for (int64_t a = tp[i]; a < tp[i + 1]; ++a) {
+            int64_t q = ts[a];
+            int64_t j = row_of(n, rpF, q);
+            if (j >= i) break; /* rows ascending: the rest are on/below the diagonal */
+            s = s - vF[q] * z[j];
+        }
+        z[i] = s / vF[diag[i]];
+    }
+    /* w = L^-T z: column i of L = rows j > i */
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double s = z[i];
+        for (int64_t a = tp[i]; a < tp[i + 1]; ++a) {
+            int64_t q = ts[a];
+            int64_t j = row_of(n, rpF, q);
+            if (j <= i) continue;
+            s = s - vF[q] * bbar[j];
+        }
+        bbar[i] = s;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t q = rpF[i]; q < diag[i]; ++q) Fbar[q] = -(bbar[i] * x[ciF[q]]);
+        for (int64_t q = diag[i]; q < rpF[i + 1]; ++q) Fbar[q] = -(z[i] * y[ciF[q]]);
+    }
+    free(diag); free(z); free(tp); free(ts);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the numeric factorization (reverse sweep of Eqs. 5a/5b).       */
+/* Fbar holds dL/dF on entry (final factor values); rows are undone in       */
+/* descending order, pivots of a row in descending order.  For pivot h of    */
+/* row j with l = f_jh:                                                      */
+/*   lbar = Fbar_jh - sum_t Fbar_jt f_ht      (t ascending, t in U(h)∩P(j))  */
+/*   Fbar_ht <- Fbar_ht - Fbar_jt * l         (each such t)                  */
+/*   Fbar_jh <- lbar / f_hh                                                  */
+/*   Fbar_hh <- Fbar_hh - (lbar * l) / f_hh                                  */
+/* Afterwards Fbar_j* is the gradient with respect to row j's initial        */
+/* values; abar[p] picks A's entries (fill entries were constants).  Every   */
+/* entry of row h therefore receives its contributions in descending j.      */
+/* ------------------------------------------------------------------------ */
+int orc_numeric_adjoint(int64_t n, const int64_t *rpA, const int32_t *ciA, const int64_t *rpF,
+                        const int32_t *ciF, const double *vF, double *Fbar, double *abar)
+{
+    int64_t *slot_of = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *diag = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!slot_of || !diag) { free(slot_of); free(diag); return ORC_ENOMEM; }
+    int st = find_diag(n, rpF, ciF, diag);
+    if (st) { free(slot_of); free(diag); return st; }
+    for (int64_t t = 0; t < n; ++t) slot_of[t] = -1;
+    for (int64_t j = n - 1; j >= 0; --j) {
+        for (int64_t s = rpF[j]; s < rpF[j + 1]; ++s) slot_of[ciF[s]] = s;
+        for (int64_t s = diag[j] - 1; s >= rpF[j]; --s) {
+            int64_t h = ciF[s];
+            double l = vF[s];
+            double lbar = Fbar[s];
+            for (int64_t q = diag[h] + 1; q < rpF[h + 1]; ++q) {
+                int64_t p = slot_of[ciF[q]];
+                if (p >= 0) lbar = lbar - Fbar[p] * vF[q];
+            }
+            for (int64_t q = diag[h] + 1; q < rpF[h + 1]; ++q) {
+                int64_t p = slot_of[ciF[q]];
+                if (p >= 0) Fbar[q] = Fbar[q] - Fbar[p] * l;
+            }
+            Fbar[s] = lbar / vF[diag[h]];
+            double tmp = lbar * l;
+            tmp = tmp / vF[diag[h]];
+            Fbar[diag[h]] = Fbar[diag[h]] - tmp;
+        }
+        for (int64_t p = rpA[j]; p < rpA[j + 1]; ++p) {
+            int64_t s = slot_of[ciA[p]];
+            if (s < 0) { st = ORC_EINVAL; break; }
+            abar[p] = Fbar[s];
+        }
+        for (int64_t s = rpF[j]; s < rpF[j + 1]; ++s) slot_of[ciF[s]] = -1;
+        if (st) break;
+    }
+    free(slot_of);
+    free(diag);
+    return st;
+}

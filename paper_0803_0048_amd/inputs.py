@@ -1,0 +1,335 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only builds matrices and vectors; it holds none of the ILU(k)
+arithmetic.  Both the GPU path and the sequential oracle consume the arrays it
+returns, so that the two sides see identical inputs.
+
+All matrices are returned as CSR with 0-based indices, columns sorted
+ascending inside every row, the diagonal always stored:
+
+    rowptr  int64[n+1]
+    col     int32[nnz]
+    val     float64[nnz]            (single instance)
+    val     float64[nnz, B]         (batch of B instances sharing one pattern,
+                                     entry-major / instance-minor, the layout
+                                     the batched entry points take)
+
+Workloads (the paper's own matrices are not available; these stand in for
+them):
+
+* ``conv_diff_2d`` / ``conv_diff_3d``: -eps*Laplace(u) + b.grad(u) on the unit
+  square / cube, central differences on an m^d interior grid, h = 1/(m+1),
+  Dirichlet boundary, natural (lexicographic) row order, every coefficient
+  multiplied by h^2.  With cell Peclet number |b_c| h / (2 eps) > 1 the matrix
+  is not diagonally dominant (stand-in for the paper's driven-cavity and 3-D
+  stencil problems, Sec. 4.1-4.2).
+* ``random_banded``: general sparse non-symmetric matrix, a fixed number of
+  off-diagonal columns per row drawn uniformly inside a band plus a few drawn
+  anywhere, values U(-1, 1), diagonal 1.1 x the row's absolute sum, so the
+  matrix is strictly diagonally dominant (stand-in for the diagonally dominant
+  general sparse matrices of dimension up to 160,000 in Sec. 4.4).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "CSR",
+    "conv_diff_2d",
+    "conv_diff_3d",
+    "random_banded",
+    "random_pattern",
+    "config1",
+    "config2",
+    "config3",
+    "config4",
+    "config5",
+    "CONFIGS",
+]
+
+
+@dataclass
+class CSR:
+    n: int
+    rowptr: np.ndarray  # int64[n+1]
+    col: np.ndarray  # int32[nnz]
+    val: np.ndarray  # float64[nnz] or float64[nnz, B]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    @property
+    def batch(self) -> int:
+        return 1 if self.val.ndim == 1 else int(self.val.shape[1])
+
+    def instance(self, b: int) -> "CSR":
+        """Instance ``b`` of a batch as a single-instance CSR (values copied)."""
+        v = self.val if self.val.ndim == 1 else np.ascontiguousarray(self.val[:, b])
+        return CSR(self.n, self.rowptr, self.col, v, dict(self.meta))
+
+    def to_dense(self, b: int | None = None) -> np.ndarray:
+        v = self.val if self.val.ndim == 1 else self.val[:, 0 if b is None else b]
+        d = np.zeros((self.n, self.n), dtype=np.float64)
+        rows = np.repeat(np.arange(self.n), np.diff(self.rowptr))
+        d[rows, self.col] = v
+        return d
+
+
+def _stencil_pattern(shape):
+    """Rows/cols/offset-id arrays of a (2*dim+1)-point stencil in natural order.
+
+    Returns (rowptr, col, kind, sign) where ``kind[e]`` is the axis (0..dim-1)
+    of a neighbour entry or -1 for the diagonal, and ``sign[e]`` is +1 for the
+    forward neighbour, -1 for the backward one, 0 for the diagonal.
+    """
+    dim = len(shape)
+    n = int(np.prod(shape))
+    idx = np.arange(n)
+    coords = np.unravel_index(idx, shape[::-1])[::-1]  # coords[0] = fastest axis
+    strides = [1]
+    for a in range(1, dim):
+        strides.append(strides[-1] * shape[a - 1])
+    # offsets in increasing column order: -stride[dim-1] .. -1, 0, +1 .. +stride[dim-1]
+    offs = []
+    for a in reversed(range(dim)):
+        offs.append((a, -1))
+    offs.append((-1, 0))
+    for a in range(dim):
+        offs.append((a, +1))
+    cols = np.empty((n, len(offs)), dtype=np.int64)
+    valid = np.empty((n, len(offs)), dtype=bool)
+    kind = np.empty((n, len(offs)), dtype=np.int64)
+    sign = np.empty((n, len(offs)), dtype=np.int64)
+    for k, (a, s) in enumerate(offs):
+        if a < 0:
+            cols[:, k] = idx
+            valid[:, k] = True
+        else:
+            cols[:, k] = idx + s * strides[a]
+            c = coords[a]
+            valid[:, k] = (c > 0) if s < 0 else (c < shape[a] - 1)
+        kind[:, k] = a
+        sign[:, k] = s
+    counts = valid.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    return rowptr, cols[valid].astype(np.int32), kind[valid], sign[valid]
+
+
+def _stencil_values(kind, sign, eps, bvec, h, dim):
+    """Coefficients of -eps*Laplace + b.grad, central differences, times h^2."""
+    eps = np.asarray(eps, dtype=np.float64)
+    bvec = np.asarray(bvec, dtype=np.float64)
+    batched = eps.ndim == 1
+    if not batched:
+        eps = eps[None]
+        bvec = bvec[None, :]
+    B = eps.shape[0]
+    val = np.empty((kind.shape[0], B), dtype=np.float64)
+    diag = kind < 0
+    val[diag, :] = (2.0 * dim) * eps[None, :]
+    for a in range(dim):
+        m = kind == a
+        half = bvec[:, a] * (h / 2.0)  # [B]
+        val[m, :] = -eps[None, :] + sign[m][:, None] * half[None, :]
+    return val if batched else val[:, 0].copy()
+
+
+def conv_diff_2d(m: int, eps, bx, by) -> CSR:
+    """2-D 5-point convection-diffusion on an m x m grid (see module doc)."""
+    h = 1.0 / (m + 1)
+    rowptr, col, kind, sign = _stencil_pattern((m, m))
+    eps_a = np.asarray(eps, dtype=np.float64)
+    bvec = np.stack([np.asarray(bx, dtype=np.float64), np.asarray(by, dtype=np.float64)], axis=-1)
+    val = _stencil_values(kind, sign, eps_a, bvec, h, 2)
+    return CSR(m * m, rowptr, col, val, {"kind": "conv_diff_2d", "m": m, "h": h})
+
+
+def conv_diff_3d(m: int, eps, bvec) -> CSR:
+    """3-D 7-point convection-diffusion on an m^3 grid (see module doc)."""
+    h = 1.0 / (m + 1)
+    rowptr, col, kind, sign = _stencil_pattern((m, m, m))
+    val = _stencil_values(kind, sign, np.asarray(eps, dtype=np.float64), np.asarray(bvec, dtype=np.float64), h, 3)
+    return CSR(m**3, rowptr, col, val, {"kind": "conv_diff_3d", "m": m, "h": h})
+
+
+def _first_distinct(cand: np.ndarray, forbid: np.ndarray, need: int) -> tuple[np.ndarray, np.ndarray]:
+    """For every row take the first ``need`` candidates that are distinct from
+    each other and from the row's forbidden values.  Returns (chosen, ok)."""
+    n, K = cand.shape
+    dup = np.zeros((n, K), dtype=bool)
+    for f in range(forbid.shape[1]):
+        dup |= cand == forbid[:, f : f + 1]
+    for a in range(1, K):
+        dup[:, a] |= (cand[:, :a] == cand[:, a : a + 1]).any(axis=1)
+    good = ~dup
+    rank = np.cumsum(good, axis=1)
+    ok = rank[:, -1] >= need
+    chosen = np.zeros((n, need), dtype=np.int64)
+    for r in range(need):
+        pos = np.argmax(good & (rank == r + 1), axis=1)
+        chosen[:, r] = cand[np.arange(n), pos]
+    return chosen, ok
+
+
+def random_banded(n: int, seed: int, band: int = 2000, n_band: int = 8, n_any: int = 2,
+                  dominance: float = 1.1) -> CSR:
+    """General sparse non-symmetric, strictly diagonally dominant matrix.
+
+    Row i holds its diagonal, ``n_band`` distinct columns drawn uniformly from
+    [max(0, i-band), min(n-1, i+band)] minus {i}, and ``n_any`` further
+    distinct columns drawn uniformly from [0, n) minus the ones already taken.
+    Off-diagonal values are U(-1, 1); a_ii = dominance * sum_j |a_ij|.
+    """
+    rng = np.random.default_rng(seed)
+    i = np.arange(n, dtype=np.int64)
+    lo = np.maximum(0, i - band)
+    hi = np.minimum(n - 1, i + band)
+    K1 = n_band * 3
+    cand = rng.integers(lo[:, None], hi[:, None] + 1, size=(n, K1))
+    bcols, ok = _first_distinct(cand, i[:, None], n_band)
+    for r in np.nonzero(~ok)[0]:  # rare: not enough distinct draws; redraw that row
+        while True:
+            c = rng.integers(lo[r], hi[r] + 1, size=4 * n_band)
+            ch, okr = _first_distinct(c[None, :], np.array([[r]]), n_band)
+            if okr[0]:
+                bcols[r] = ch[0]
+                break
+    K2 = n_any * 4
+    cand2 = rng.integers(0, n, size=(n, K2))
+    acols, ok2 = _first_distinct(cand2, np.concatenate([i[:, None], bcols], axis=1), n_any)
+    for r in np.nonzero(~ok2)[0]:
+        while True:
+            c = rng.integers(0, n, size=8 * n_any)
+            ch, okr = _first_distinct(c[None, :], np.concatenate([[r], bcols[r]])[None, :], n_any)
+            if okr[0]:
+                acols[r] = ch[0]
+                break
+    off = np.concatenate([bcols, acols], axis=1)
+    offv = rng.uniform(-1.0, 1.0, size=off.shape)
+    diagv = dominance * np.abs(offv).sum(axis=1)
+    cols = np.concatenate([off, i[:, None]], axis=1)
+    vals = np.concatenate([offv, diagv[:, None]], axis=1)
+    order = np.argsort(cols, axis=1, kind="stable")
+    cols = np.take_along_axis(cols, order, axis=1)
+    vals = np.take_along_axis(vals, order, axis=1)
+    per = cols.shape[1]
+    rowptr = np.arange(n + 1, dtype=np.int64) * per
+    return CSR(n, rowptr, cols.reshape(-1).astype(np.int32), vals.reshape(-1).copy(),
+               {"kind": "random_banded", "band": band, "n_band": n_band, "n_any": n_any})
+
+
+def random_pattern(n: int, density: float, seed: int, *, diag_dominant: bool = True,
+                   batch: int | None = None, explicit_zeros: float = 0.0) -> CSR:
+    """Small random non-symmetric matrix for sweeps and edge cases.
+
+    Every diagonal entry is stored.  Off-diagonal entries are kept with
+    probability ``density``; values U(-1, 1); with ``diag_dominant`` the
+    diagonal is 1 + sum |a_ij| of its row, else U(-1, 1) shifted away from 0.
+    ``explicit_zeros`` is the probability that a stored off-diagonal value is
+    set to exactly 0.0 (the entry stays in the pattern).
+    """
+    rng = np.random.default_rng(seed)
+    mask = rng.random((n, n)) < density
+    np.fill_diagonal(mask, True)
+    rows, cols = np.nonzero(mask)
+    nnz = rows.size
+    B = 1 if batch is None else batch
+    vals = rng.uniform(-1.0, 1.0, size=(nnz, B))
+    if explicit_zeros > 0:
+        z = rng.random(nnz) < explicit_zeros
+        z &= rows != cols
+        vals[z, :] = 0.0
+    isdiag = rows == cols
+    if diag_dominant:
+        absum = np.zeros((n, B))
+        np.add.at(absum, rows[~isdiag], np.abs(vals[~isdiag]))
+        vals[isdiag, :] = 1.0 + absum[rows[isdiag]]
+    else:
+        d = vals[isdiag, :]
+        vals[isdiag, :] = np.where(d >= 0, d + 0.5, d - 0.5)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    v = vals[:, 0].copy() if batch is None else np.ascontiguousarray(vals)
+    return CSR(n, rowptr, cols.astype(np.int32), v, {"kind": "random_pattern", "density": density})
+
+
+# ----------------------------------------------------------------------------
+# The five named workloads.  Seeds 1001-1005; batched instance i draws from
+# SeedSequence(seed).spawn(B)[i].
+# ----------------------------------------------------------------------------
+
+def config1(seed: int = 1001):
+    """2-D 5-point, 64 x 64, eps = 1, (bx, by) ~ U[-20, 20]^2; ILU(1)."""
+    rng = np.random.default_rng(seed)
+    bx, by = rng.uniform(-20.0, 20.0, size=2)
+    A = conv_diff_2d(64, 1.0, bx, by)
+    b = rng.standard_normal(A.n)
+    return {"name": "conv_diff_2d_64x64_ilu1", "A": A, "b": b, "k": 1, "restart": 30, "rtol": 1e-8}
+
+
+def config2(seed: int = 1002, n: int = 160_000):
+    """Random banded n = 160,000, 8 band + 2 anywhere columns; ILU(2), GMRES(30)."""
+    A = random_banded(n, seed)
+    rng = np.random.default_rng(seed + 7919)
+    b = rng.standard_normal(n)
+    return {"name": f"random_banded_n{n}_ilu2", "A": A, "b": b, "k": 2, "restart": 30, "rtol": 1e-8}
+
+
+def config3(seed: int = 1003, m: int = 64, k: int = 2):
+    """3-D 7-point, 64^3, eps = 1, b ~ U[-200, 200]^3 with max |b_c| > 2/h
+    (cell Peclet > 1, not diagonally dominant); ILU(k) for k = 0..3, GMRES(50)."""
+    h = 1.0 / (m + 1)
+    s = seed
+    while True:
+        rng = np.random.default_rng(s)
+        bvec = rng.uniform(-200.0, 200.0, size=3)
+        if np.max(np.abs(bvec)) > 2.0 / h:
+            break
+        s += 1
+    A = conv_diff_3d(m, 1.0, bvec)
+    b = rng.standard_normal(A.n)
+    return {"name": f"conv_diff_3d_{m}cubed_ilu{k}", "A": A, "b": b, "k": k, "restart": 50, "rtol": 1e-8}
+
+
+def config4(seed: int = 1004, B: int = 256, m: int = 128):
+    """B instances of a 2-D 5-point 128 x 128 stencil sharing one pattern,
+    eps ~ U[0.5, 2], (bx, by) ~ U[-50, 50]^2 per instance; ILU(2)."""
+    kids = np.random.SeedSequence(seed).spawn(B)
+    eps = np.empty(B)
+    bxy = np.empty((B, 2))
+    rhs = np.empty((m * m, B))
+    for i, ss in enumerate(kids):
+        rng = np.random.default_rng(ss)
+        eps[i] = rng.uniform(0.5, 2.0)
+        bxy[i] = rng.uniform(-50.0, 50.0, size=2)
+        rhs[:, i] = rng.standard_normal(m * m)
+    A = conv_diff_2d(m, eps, bxy[:, 0], bxy[:, 1])
+    return {"name": f"batched_conv_diff_2d_{m}x{m}_x{B}_ilu2", "A": A, "b": rhs, "k": 2}
+
+
+def config5(seed: int = 1005, B: int = 16, m: int = 32):
+    """B instances of a 3-D 7-point 32^3 stencil, eps ~ U[0.5, 2],
+    b ~ U[-50, 50]^3 per instance, rhs and target t ~ N(0, 1); ILU(1)."""
+    kids = np.random.SeedSequence(seed).spawn(B)
+    n = m**3
+    eps = np.empty(B)
+    bv = np.empty((B, 3))
+    rhs = np.empty((n, B))
+    tgt = np.empty((n, B))
+    for i, ss in enumerate(kids):
+        rng = np.random.default_rng(ss)
+        eps[i] = rng.uniform(0.5, 2.0)
+        bv[i] = rng.uniform(-50.0, 50.0, size=3)
+        rhs[:, i] = rng.standard_normal(n)
+        tgt[:, i] = rng.standard_normal(n)
+    A = conv_diff_3d(m, eps, bv)
+    return {"name": f"diff_conv_diff_3d_{m}cubed_x{B}_ilu1", "A": A, "b": rhs, "t": tgt, "k": 1}
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

@@ -1,0 +1,575 @@
+"""Pins of the sequential oracle against what the paper and the mathematics fix.
+
+Every test here runs on the CPU.  A plausible mistake anywhere in the oracle
+(a dropped term, a wrong sign, a wrong index, a transposed operand, a changed
+order of operations) fails at least one of them.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import oracle as O
+from paper_0803_0048_amd import inputs as I
+from tests import pins as P
+
+
+def _tiny_cases(count, seed=7):
+    rng = np.random.default_rng(seed)
+    for c in range(count):
+        n = int(rng.integers(1, 13))
+        dens = float(rng.choice([0.1, 0.2, 0.3, 0.5]))
+        M = rng.random((n, n)) < dens
+        np.fill_diagonal(M, True)
+        yield c, n, M
+
+
+# --------------------------------------------------------------------------
+# Symbolic factorization (Def. 2.3, Algorithm 1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("chunk", range(4))
+def test_symbolic_matches_definition_and_fill_paths(chunk):
+    """Algorithm 1 keeps exactly the entries whose Def. 2.3 level is <= k,
+    with that level; checked against the literal recurrence and, separately,
+    against the fill-path characterisation."""
+    for c, n, M in _tiny_cases(400, seed=100 + chunk):
+        lev_dp = P.levels_dp(M)
+        if c % 4 == 0:
+            lev_bfs = P.levels_paths(M)
+            assert np.array_equal(np.minimum(lev_dp, P.INF), np.minimum(lev_bfs, P.INF)), (n, M)
+        rp, ci, _ = P.csr_from_dense_mask(M)
+        for k in sorted({0, 1, 2, 3, max(n - 1, 0)}):
+            rpF, ciF, lvF = O.symbolic(n, rp, ci, k)
+            got = P.dense_pattern(n, rpF, ciF)
+            want = lev_dp <= k
+            assert np.array_equal(got, want), (c, n, k)
+            rows = np.repeat(np.arange(n), np.diff(rpF))
+            assert np.array_equal(lvF, lev_dp[rows, ciF]), (c, n, k)
+
+
+def test_symbolic_k0_is_pattern_of_A():
+    A = I.random_pattern(60, 0.08, seed=3)
+    rpF, ciF, lvF = O.symbolic(A.n, A.rowptr, A.col, 0)
+    assert np.array_equal(rpF, A.rowptr) and np.array_equal(ciF, A.col)
+    assert not lvF.any()
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_symbolic_k1_boolean_product(seed):
+    """k = 1 (Sec. 3.3): an entry has level 1 exactly when some h < min(i,j)
+    has a_ih and a_hj stored, i.e. the structure of tril(A,-1) * triu(A,1)."""
+    A = I.random_pattern(300, 0.01, seed=seed)
+    S = sp.csr_matrix((np.ones(A.nnz), A.col, A.rowptr), shape=(A.n, A.n))
+    prod = (sp.tril(S, -1) @ sp.triu(S, 1)).tocsr()
+    want = ((S + prod) != 0).astype(np.int8).tocsr()
+    want.sort_indices()
+    rpF, ciF, lvF = O.symbolic(A.n, A.rowptr, A.col, 1)
+    assert np.array_equal(rpF, want.indptr) and np.array_equal(ciF, want.indices)
+    P1 = sp.csr_matrix((lvF.astype(np.int64) + 1, ciF, rpF), shape=(A.n, A.n))
+    assert np.array_equal((P1 == 2).toarray(), (prod != 0).toarray() & ~(S != 0).toarray())
+
+
+def test_symbolic_k_infinity_is_full_fill():
+    """k = infinity gives the pattern of the complete LU factors (Sec. 2)."""
+    for seed in range(20):
+        A = I.random_pattern(40, 0.06, seed=200 + seed)
+        M = P.dense_pattern(A.n, A.rowptr, A.col)
+        want = P.full_fill(M)
+        rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, 2**31 - 1)
+        assert np.array_equal(P.dense_pattern(A.n, rpF, ciF), want)
+        rpF2, ciF2, _ = O.symbolic(A.n, A.rowptr, A.col, A.n - 1)
+        assert np.array_equal(rpF2, rpF) and np.array_equal(ciF2, ciF)
+
+
+@pytest.mark.parametrize("m", [8, 17, 32])
+def test_symbolic_closed_forms_2d(m):
+    """Natural-order 5-point stencil: ILU(0) keeps 5m^2-4m entries, ILU(1)
+    adds the 2(m-1)^2 entries next to the far neighbours, ILU(2) adds a
+    further 2(m-1)(m-2)."""
+    A = I.conv_diff_2d(m, 1.0, 3.0, -2.0)
+    assert A.nnz == 5 * m * m - 4 * m
+    n1 = O.symbolic(A.n, A.rowptr, A.col, 1)[0][-1]
+    n2 = O.symbolic(A.n, A.rowptr, A.col, 2)[0][-1]
+    assert n1 == 5 * m * m - 4 * m + 2 * (m - 1) ** 2
+    assert n2 == n1 + 2 * (m - 1) * (m - 2)
+
+
+@pytest.mark.parametrize("m", [5, 9, 16])
+def test_symbolic_closed_forms_3d(m):
+    A = I.conv_diff_3d(m, 1.0, [1.0, 2.0, 3.0])
+    assert A.nnz == 7 * m**3 - 6 * m**2
+    n1 = O.symbolic(A.n, A.rowptr, A.col, 1)[0][-1]
+    assert n1 == 7 * m**3 - 6 * m**2 + 6 * m * (m - 1) ** 2
+
+
+def test_symbolic_tridiagonal_has_no_fill():
+    n = 50
+    rows = np.arange(n)
+    M = np.zeros((n, n), bool)
+    M[rows, rows] = True
+    M[rows[1:], rows[:-1]] = True
+    M[rows[:-1], rows[1:]] = True
+    rp, ci, _ = P.csr_from_dense_mask(M)
+    for k in (1, 2, 5, n - 1):
+        rpF, ciF, _ = O.symbolic(n, rp, ci, k)
+        assert np.array_equal(rpF, rp) and np.array_equal(ciF, ci)
+
+
+def test_symbolic_rejects_invalid_input():
+    rp = np.array([0, 1, 2], np.int64)
+    assert O.validate(2, rp, np.array([0, 0], np.int32)) == O.EINVAL  # row 1 lacks its diagonal
+    assert O.validate(2, np.array([0, 2, 3], np.int64), np.array([1, 0, 1], np.int32)) == O.EINVAL  # unsorted
+    assert O.validate(2, np.array([0, 2, 3], np.int64), np.array([0, 0, 1], np.int32)) == O.EINVAL  # duplicate
+    assert O.validate(2, np.array([0, 1, 2], np.int64), np.array([0, 2], np.int32)) == O.EINVAL  # out of range
+    assert O.validate(2, np.array([0, 1, 2], np.int64), np.array([0, 1], np.int32)) == O.OK
+    with pytest.raises(O.OracleError):
+        O.symbolic(2, rp, np.array([0, 0], np.int32), 1)
+
+
+def test_symbolic_explicit_zero_is_structural():
+    """A stored zero is an entry of level 0 (structural reading of a_ij != 0):
+    the pattern does not depend on the values."""
+    A = I.random_pattern(80, 0.05, seed=5, explicit_zeros=0.5)
+    assert (A.val == 0).any()
+    rpF, ciF, lvF = O.symbolic(A.n, A.rowptr, A.col, 2)
+    M = P.dense_pattern(A.n, A.rowptr, A.col)
+    want = P.levels_dp(M) <= 2
+    assert np.array_equal(P.dense_pattern(A.n, rpF, ciF), want)
+
+
+# --------------------------------------------------------------------------
+# Numeric factorization (Eq. 2 / Eqs. 5a-5b)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_numeric_bitwise_equals_dense_masked_elimination(seed):
+    rng = np.random.default_rng(900 + seed)
+    for _ in range(25):
+        n = int(rng.integers(1, 40))
+        A = I.random_pattern(n, float(rng.choice([0.05, 0.1, 0.2])), seed=int(rng.integers(1 << 30)),
+                             diag_dominant=bool(rng.integers(2)))
+        k = int(rng.choice([0, 1, 2, 3, n]))
+        M = P.dense_pattern(n, A.rowptr, A.col)
+        mask = P.levels_dp(M) <= k
+        rpF, ciF, _ = P.csr_from_dense_mask(mask)
+        vF, bad = O.numeric(n, A.rowptr, A.col, A.val, rpF, ciF)
+        D = P.dense_masked_lu(A.to_dense(), mask)
+        rows = np.repeat(np.arange(n), np.diff(rpF))
+        assert np.array_equal(P.bits(vF), P.bits(D[rows, ciF])), (n, k)
+        assert bad == -1 or vF[rpF[bad]:rpF[bad + 1]][ciF[rpF[bad]:rpF[bad + 1]] == bad][0] == 0.0
+
+
+def test_numeric_full_fill_is_exact_lu():
+    """k = infinity: L~ U~ is the LU factorization of A (no pivoting), so the
+    two triangular solves solve A y = b to rounding."""
+    for seed in range(5):
+        A = I.random_pattern(60, 0.08, seed=40 + seed)
+        rpF, ciF, _, vF, bad = O.ilu(A, 2**31 - 1)
+        assert bad == -1
+        b = np.random.default_rng(seed).standard_normal(A.n)
+        _, y = O.apply(A.n, rpF, ciF, vF, b)
+        ref = np.linalg.solve(A.to_dense(), b)
+        assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_numeric_ilu_defining_property():
+    """(L~ U~)_ij = a_ij on every position kept in the pattern."""
+    c = I.config1()
+    A = c["A"]
+    for k in (0, 1, 2):
+        rpF, ciF, _, vF, bad = O.ilu(A, k)
+        F = sp.csr_matrix((vF, ciF, rpF), shape=(A.n, A.n)).toarray()
+        L = np.tril(F, -1) + np.eye(A.n)
+        U = np.triu(F)
+        LU = L @ U
+        rows = np.repeat(np.arange(A.n), np.diff(rpF))
+        Ad = P.to_dense_vals(A.n, A.rowptr, A.col, A.val)
+        err = np.abs(LU[rows, ciF] - Ad[rows, ciF]).max()
+        assert err <= 1e-13 * np.abs(A.val).max(), (k, err)
+
+
+def test_numeric_tridiagonal_is_thomas():
+    """Tridiagonal A: l_i = a_{i,i-1}/u_{i-1}, u_i = d_i - l_i c_{i-1} bit for bit."""
+    rng = np.random.default_rng(3)
+    n = 200
+    d = rng.uniform(2.0, 3.0, n)
+    lo = rng.uniform(-1, 1, n - 1)
+    up = rng.uniform(-1, 1, n - 1)
+    Ad = np.diag(d) + np.diag(lo, -1) + np.diag(up, 1)
+    rp, ci, v = P.csr_from_dense_mask(Ad != 0, Ad)
+    rpF, ciF, _, vF, _ = O.ilu(I.CSR(n, rp, ci, v), 3)
+    u = np.empty(n)
+    l = np.empty(n - 1)
+    u[0] = d[0]
+    for i in range(1, n):
+        l[i - 1] = lo[i - 1] / u[i - 1]
+        u[i] = d[i] - l[i - 1] * up[i - 1]
+    F = P.to_dense_vals(n, rpF, ciF, vF)
+    assert np.array_equal(P.bits(np.diag(F)), P.bits(u))
+    assert np.array_equal(P.bits(np.diag(F, -1)), P.bits(l))
+    assert np.array_equal(P.bits(np.diag(F, 1)), P.bits(up))
+
+
+def test_numeric_diagonal_matrix_unchanged():
+    n = 30
+    d = np.random.default_rng(1).uniform(-2, 2, n)
+    rp = np.arange(n + 1, dtype=np.int64)
+    ci = np.arange(n, dtype=np.int32)
+    vF, bad = O.numeric(n, rp, ci, d, rp, ci)
+    assert np.array_equal(P.bits(vF), P.bits(d)) and bad == -1
+
+
+def test_numeric_exact_rational():
+    """Small integer matrix: every ILU(k) value against exact rational
+    elimination on the same mask (catches a dropped or mis-signed term)."""
+    rng = np.random.default_rng(77)
+    for _ in range(20):
+        n = int(rng.integers(2, 9))
+        M = rng.random((n, n)) < 0.5
+        np.fill_diagonal(M, True)
+        Ai = rng.integers(-4, 5, size=(n, n))
+        Ai[np.arange(n), np.arange(n)] = 20 + rng.integers(0, 5, n)
+        k = int(rng.integers(0, 3))
+        mask = P.levels_dp(M) <= k
+        Fq = [[Fraction(int(Ai[i, j])) if M[i, j] else Fraction(0) for j in range(n)] for i in range(n)]
+        for i in range(n):
+            for h in range(i):
+                if not mask[i, h]:
+                    continue
+                Fq[i][h] = Fq[i][h] / Fq[h][h]
+                for j in range(h + 1, n):
+                    if mask[h, j] and mask[i, j]:
+                        Fq[i][j] -= Fq[i][h] * Fq[h][j]
+        rp, ci, v = P.csr_from_dense_mask(M, Ai.astype(np.float64))
+        rpF, ciF, _ = P.csr_from_dense_mask(mask)
+        vF, _ = O.numeric(n, rp, ci, v, rpF, ciF)
+        rows = np.repeat(np.arange(n), np.diff(rpF))
+        for s in range(vF.size):
+            ex = Fq[rows[s]][ciF[s]]
+            assert abs(vF[s] - float(ex)) <= 1e-14 * max(1.0, abs(float(ex))), (s, vF[s], ex)
+
+
+def test_numeric_zero_pivot_reports_smallest_row():
+    rp = np.array([0, 2, 4], np.int64)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    vF, bad = O.numeric(2, rp, ci, np.array([1.0, 1.0, 1.0, 1.0]), rp, ci)
+    assert bad == 1 and vF[3] == 0.0
+    vF, bad = O.numeric(2, rp, ci, np.array([0.0, 1.0, 1.0, 1.0]), rp, ci)
+    assert bad == 0
+
+
+# --------------------------------------------------------------------------
+# Triangular solves (Eq. 1, Eq. 3b)
+# --------------------------------------------------------------------------
+
+def test_apply_against_triangular_solves():
+    c = I.config1()
+    A = c["A"]
+    rpF, ciF, _, vF, _ = O.ilu(A, 2)
+    F = sp.csr_matrix((vF, ciF, rpF), shape=(A.n, A.n)).toarray()
+    x, y = O.apply(A.n, rpF, ciF, vF, c["b"])
+    xr = sla.solve_triangular(F, c["b"], lower=True, unit_diagonal=True)
+    yr = sla.solve_triangular(F, xr, lower=False)
+    assert np.linalg.norm(x - xr) <= 1e-12 * np.linalg.norm(xr)
+    assert np.linalg.norm(y - yr) <= 1e-12 * np.linalg.norm(yr)
+    L = np.tril(F, -1) + np.eye(A.n)
+    U = np.triu(F)
+    assert np.linalg.norm(L @ (U @ y) - c["b"]) <= 1e-13 * np.linalg.norm(c["b"]) * 10
+
+
+def test_apply_order_of_subtractions():
+    """The running subtraction goes in ascending column order: a row whose
+    terms cancel differently in another order exposes the order."""
+    # row 3 of L: x3 = p3 - f30 x0 - f31 x1 - f32 x2 with x = (2^53, 1, 1)
+    n = 4
+    M = np.eye(n, dtype=bool)
+    M[3, :3] = True
+    vals = np.eye(n)
+    vals[3, :3] = -1.0  # subtracting -1*x adds x
+    rp, ci, v = P.csr_from_dense_mask(M, vals)
+    p = np.array([2.0**53, 1.0, 1.0, 0.0])
+    x, y = O.apply(n, rp, ci, v, p)
+    # ((0 + 2^53) + 1) + 1 in that order rounds each +1 away: 2^53
+    assert x[3] == 2.0**53
+    # backward row 0 of U: y0 = (x0 - f01 y1 - f02 y2 - f03 y3)/1, ascending
+    M2 = np.eye(n, dtype=bool)
+    M2[0, 1:] = True
+    vals2 = np.eye(n)
+    vals2[0, 1:] = -1.0
+    rp2, ci2, v2 = P.csr_from_dense_mask(M2, vals2)
+    x2, y2 = O.apply(n, rp2, ci2, v2, np.array([1.0, 1.0, 1.0, 2.0**53]))
+    # ((1 + 1) + 1) + 2^53 = 2^53 + 3 -> rounds to 2^53 + 4
+    assert y2[0] == 2.0**53 + 4.0
+
+
+def test_apply_exact_rational():
+    rng = np.random.default_rng(5)
+    n = 7
+    M = rng.random((n, n)) < 0.6
+    np.fill_diagonal(M, True)
+    Fi = rng.integers(-3, 4, size=(n, n)).astype(np.float64)
+    Fi[np.arange(n), np.arange(n)] = 1.0  # unit U diagonal keeps everything integral
+    rp, ci, v = P.csr_from_dense_mask(M, Fi)
+    p = rng.integers(-5, 6, size=n).astype(np.float64)
+    x, y = O.apply(n, rp, ci, v, p)
+    Fd = np.where(M, Fi, 0)
+    xq = [Fraction(0)] * n
+    for i in range(n):
+        xq[i] = Fraction(int(p[i])) - sum(Fraction(int(Fd[i, h])) * xq[h] for h in range(i))
+    yq = [Fraction(0)] * n
+    for i in reversed(range(n)):
+        yq[i] = (xq[i] - sum(Fraction(int(Fd[i, j])) * yq[j] for j in range(i + 1, n))) / int(Fd[i, i])
+    assert [float(a) for a in xq] == list(x) and [float(a) for a in yq] == list(y)
+
+
+# --------------------------------------------------------------------------
+# Fixed-shape reductions and SpMV
+# --------------------------------------------------------------------------
+
+def test_dot_error_bound_against_exact_sum():
+    rng = np.random.default_rng(1)
+    u = 2.0**-53
+    for n in (1, 100, 16384, 16385, 100_000, 300_001):
+        x = rng.standard_normal(n) * np.exp(rng.uniform(-20, 20, n))
+        y = rng.standard_normal(n)
+        d = O.dot(x, y)
+        exact = math.fsum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(x[:2000], y[:2000])) if n <= 2000 else None
+        prods = x * y
+        ref = math.fsum(prods)
+        m = math.ceil(n / 16384) + 14 + 1
+        gam = m * u / (1 - m * u)
+        bound = gam * np.abs(prods).sum() + np.abs(prods).sum() * u
+        assert abs(d - ref) <= bound, (n, d, ref)
+        if exact is not None:
+            assert abs(d - float(exact)) <= bound
+
+
+def test_dot_shape_is_fixed():
+    """Lane l sums elements l, l+16384, ... first; lanes are then combined
+    pairwise (0+1, 2+3, ...), then (0+2, ...), and so on."""
+    n = 16384 * 3
+    x = np.zeros(n)
+    one = np.ones(n)
+    x[0], x[1], x[2], x[3] = 2.0**53, 1.0, 1.0, 1.0
+    # lane 0 + lane 1 = 2^53+1 -> 2^53 (tie to even); lane2+lane3 = 2; then 2^53+2
+    assert O.dot(x, one) == 2.0**53 + 2.0
+    x[:] = 0
+    x[0], x[16384], x[32768] = 2.0**53, 1.0, 1.0
+    # inside lane 0 the ones are added one at a time: 2^53
+    assert O.dot(x, one) == 2.0**53
+    # integer data: exact
+    xi = np.random.default_rng(2).integers(-1000, 1000, n).astype(np.float64)
+    assert O.dot(xi, one) == float(xi.astype(np.int64).sum())
+
+
+def test_spmv_matches_scipy_and_order():
+    c = I.config1()
+    A = c["A"]
+    x = np.random.default_rng(0).standard_normal(A.n)
+    y = O.spmv(A.n, A.rowptr, A.col, A.val, x)
+    S = sp.csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n))
+    assert np.allclose(y, S @ x, rtol=1e-14, atol=1e-14)
+    # ascending order within a row
+    rp = np.array([0, 4], np.int64)
+    ci = np.array([0, 1, 2, 3], np.int32)
+    v = np.ones(4)
+    assert O.spmv(1, rp, ci, v, np.array([2.0**53, 1.0, 1.0, 1.0]))[0] == 2.0**53
+
+
+# --------------------------------------------------------------------------
+# GMRES (right preconditioned)
+# --------------------------------------------------------------------------
+
+def test_gmres_exact_lu_converges_in_one_iteration():
+    A = I.random_pattern(80, 0.05, seed=8)
+    rpF, ciF, _, vF, _ = O.ilu(A, 2**31 - 1)
+    b = np.random.default_rng(8).standard_normal(A.n)
+    r = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, b, restart=10, rtol=1e-10)
+    assert r["status"] == O.OK and r["iters"] == 1 and r["relres"] <= 1e-10
+
+
+def test_gmres_converges_and_residuals_monotone():
+    c = I.config1()
+    A = c["A"]
+    rpF, ciF, _, vF, _ = O.ilu(A, 1)
+    r = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, c["b"], restart=10, rtol=1e-8)
+    assert r["status"] == O.OK and r["relres"] <= 1e-8
+    h = r["hist"].reshape(-1)
+    for cyc in range(0, h.size, 10):
+        seg = h[cyc:cyc + 10]
+        assert np.all(np.diff(seg) <= 1e-12 * seg[0])
+    S = sp.csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n))
+    assert np.linalg.norm(c["b"] - S @ r["x"]) <= 1e-8 * np.linalg.norm(c["b"]) * (1 + 1e-6)
+
+
+def test_gmres_first_cycle_is_krylov_minimum():
+    """Within the first cycle the implicit residual after j steps is the
+    minimum of ||b - A M^-1 v|| over the j-dimensional Krylov space of
+    A M^-1 started at b (x0 = 0) -- computed here by a dense least-squares."""
+    c = I.config1()
+    A = c["A"]
+    rpF, ciF, _, vF, _ = O.ilu(A, 0)
+    b = c["b"]
+    m = 12
+    r = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, b, restart=m, maxit=m, rtol=1e-30)
+    S = sp.csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n))
+    F = sp.csr_matrix((vF, ciF, rpF), shape=(A.n, A.n)).toarray()
+    Lm = np.tril(F, -1) + np.eye(A.n)
+    Um = np.triu(F)
+
+    def op(v):
+        return S @ sla.solve_triangular(Um, sla.solve_triangular(Lm, v, lower=True, unit_diagonal=True))
+
+    K = [b / np.linalg.norm(b)]
+    for j in range(m):
+        w = op(K[-1])
+        for q in K:
+            w = w - (w @ q) * q
+        w = w - sum((w @ q) * q for q in K)
+        K.append(w / np.linalg.norm(w))
+        Q = np.stack(K[: j + 1], axis=1)
+        AQ = np.stack([op(q) for q in K[: j + 1]], axis=1)
+        coef, *_ = np.linalg.lstsq(AQ, b, rcond=None)
+        res = np.linalg.norm(b - AQ @ coef)
+        assert abs(res - r["hist"][j]) <= 1e-8 * np.linalg.norm(b), (j, res, r["hist"][j])
+    del Q
+
+
+def test_gmres_zero_rhs_and_maxit():
+    c = I.config1()
+    A = c["A"]
+    rpF, ciF, _, vF, _ = O.ilu(A, 0)
+    r = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, np.zeros(A.n), restart=5)
+    assert r["iters"] == 0 and not r["x"].any() and r["status"] == O.OK
+    r = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, c["b"], restart=5, maxit=3, rtol=1e-14)
+    assert r["iters"] == 3 and r["status"] == O.ENOTCONV and r["relres"] > 1e-14
+
+
+def test_gmres_iterations_near_scipy():
+    sl = pytest.importorskip("scipy.sparse.linalg")
+    c = I.config1()
+    A = c["A"]
+    rpF, ciF, _, vF, _ = O.ilu(A, 1)
+    r = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, c["b"], restart=30, rtol=1e-8)
+    S = sp.csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n))
+    F = sp.csr_matrix((vF, ciF, rpF), shape=(A.n, A.n))
+    Lm = (sp.tril(F, -1) + sp.eye(A.n)).tocsr()
+    Um = sp.triu(F).tocsr()
+    # solve A M^-1 u = b, x = M^-1 u (right preconditioning) with plain GMRES
+    Minv = lambda v: sl.spsolve_triangular(Um, sl.spsolve_triangular(Lm, v, lower=True, unit_diagonal=True), lower=False)
+    op = sl.LinearOperator(S.shape, matvec=lambda v: S @ Minv(v))
+    count = [0]
+    u, info = sl.gmres(op, c["b"], rtol=1e-8, restart=30, maxiter=50,
+                       callback=lambda _: count.__setitem__(0, count[0] + 1), callback_type="pr_norm")
+    assert info == 0
+    assert abs(count[0] - r["iters"]) <= 3, (count[0], r["iters"])
+
+
+# --------------------------------------------------------------------------
+# Adjoints
+# --------------------------------------------------------------------------
+
+def _small_problem(seed, n=25, dens=0.15, k=1):
+    A = I.random_pattern(n, dens, seed=seed)
+    rpF, ciF, _, vF, bad = O.ilu(A, k)
+    assert bad == -1
+    rng = np.random.default_rng(seed + 1)
+    return A, rpF, ciF, vF, rng.standard_normal(n), rng.standard_normal(n)
+
+
+def test_apply_adjoint_dot_product_identity():
+    for seed in range(5):
+        A, rpF, ciF, vF, b, c = _small_problem(300 + seed)
+        x, y = O.apply(A.n, rpF, ciF, vF, b)
+        bbar, _ = O.apply_adjoint(A.n, rpF, ciF, vF, x, y, c)
+        assert abs(y @ c - b @ bbar) <= 1e-13 * (abs(y) @ abs(c) + abs(b) @ abs(bbar))
+
+
+def _loss(A, k, vals, b, t):
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
+    vF, _ = O.numeric(A.n, A.rowptr, A.col, vals, rpF, ciF)
+    _, y = O.apply(A.n, rpF, ciF, vF, b)
+    return float(np.sum((y - t) ** 2))
+
+
+def _grads(A, k, b, t):
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
+    vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
+    x, y = O.apply(A.n, rpF, ciF, vF, b)
+    ybar = 2.0 * (y - t)
+    bbar, Fbar = O.apply_adjoint(A.n, rpF, ciF, vF, x, y, ybar)
+    abar, _ = O.numeric_adjoint(A.n, A.rowptr, A.col, rpF, ciF, vF, Fbar)
+    return abar, bbar
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_adjoint_finite_differences(k):
+    A, _, _, _, b, t = _small_problem(17, n=30, dens=0.12, k=k)
+    abar, bbar = _grads(A, k, b, t)
+    eps = 1e-6
+    rng = np.random.default_rng(4)
+    for p in rng.choice(A.nnz, size=20, replace=False):
+        vp, vm = A.val.copy(), A.val.copy()
+        vp[p] += eps
+        vm[p] -= eps
+        fd = (_loss(A, k, vp, b, t) - _loss(A, k, vm, b, t)) / (2 * eps)
+        assert abs(fd - abar[p]) <= 1e-5 * max(abs(fd), 1e-9 * np.abs(abar).max()) + 1e-8, (p, fd, abar[p])
+    for e in rng.choice(A.n, size=8, replace=False):
+        bp, bm = b.copy(), b.copy()
+        bp[e] += eps
+        bm[e] -= eps
+        fd = (_loss(A, k, A.val, bp, t) - _loss(A, k, A.val, bm, t)) / (2 * eps)
+        assert abs(fd - bbar[e]) <= 1e-5 * max(abs(fd), 1e-9) + 1e-8
+
+
+def test_adjoint_against_dense_autograd():
+    torch = pytest.importorskip("torch")
+    for seed in range(4):
+        n = 20
+        k = seed % 3
+        A = I.random_pattern(n, 0.2, seed=60 + seed)
+        rng = np.random.default_rng(seed)
+        b = rng.standard_normal(n)
+        t = rng.standard_normal(n)
+        abar, bbar = _grads(A, k, b, t)
+        M = P.dense_pattern(n, A.rowptr, A.col)
+        mask = torch.tensor(P.levels_dp(M) <= k)
+        rows = np.repeat(np.arange(n), np.diff(A.rowptr))
+        av = torch.tensor(A.val, dtype=torch.float64, requires_grad=True)
+        bt = torch.tensor(b, dtype=torch.float64, requires_grad=True)
+        Fd = torch.zeros((n, n), dtype=torch.float64).index_put((torch.tensor(rows), torch.tensor(A.col.astype(np.int64))), av)
+        F = [[Fd[i, j] for j in range(n)] for i in range(n)]
+        for i in range(n):
+            for h in range(i):
+                if not mask[i, h]:
+                    continue
+                F[i][h] = F[i][h] / F[h][h]
+                for j in range(h + 1, n):
+                    if mask[h, j] and mask[i, j]:
+                        F[i][j] = F[i][j] - F[i][h] * F[h][j]
+        x = [None] * n
+        for i in range(n):
+            s = bt[i]
+            for h in range(i):
+                if mask[i, h]:
+                    s = s - F[i][h] * x[h]
+            x[i] = s
+        y = [None] * n
+        for i in reversed(range(n)):
+            s = x[i]
+            for j in range(i + 1, n):
+                if mask[i, j]:
+                    s = s - F[i][j] * y[j]
+            y[i] = s / F[i][i]
+        loss = sum((y[i] - float(t[i])) ** 2 for i in range(n))
+        loss.backward()
+        ga = av.grad.numpy()
+        gb = bt.grad.numpy()
+        assert np.abs(ga - abar).max() <= 1e-12 * max(1.0, np.abs(ga).max())
+        assert np.abs(gb - bbar).max() <= 1e-12 * max(1.0, np.abs(gb).max())
