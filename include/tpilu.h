@@ -1,0 +1,259 @@
+/*
+ * tpilu.h -- C ABI of the gfx950 level-of-fill ILU(k) library.
+ *
+ * What it computes (Dong & Cooperman, "A Bit-Compatible Shared Memory
+ * Parallelization for ILU(k) Preconditioning and a Bit-Compatible
+ * Generalization to Distributed Memory"):
+ *
+ *   tpilu_symbolic   Phase I, Sec. 2.2, Algorithm 1 with the levels of Def. 2.3:
+ *                    the pattern of the filled matrix F = L~ + U~ - I, every
+ *                    entry of level <= k.
+ *   tpilu_numeric    Phase II, Eq. 2 and Eqs. 5a/5b: row-wise IKJ elimination
+ *                    of A restricted to that pattern.
+ *   tpilu_apply      y = U~^-1 L~^-1 b, the triangular solves of Eq. 1
+ *                    (forward substitution Eq. 3b, then backward substitution).
+ *   tpilu_gmres      restarted GMRES(m) preconditioned on the right by
+ *                    M = L~ U~ (Sec. 2: the solver works on A U~^-1 L~^-1).
+ *   tpilu_apply_adjoint / tpilu_numeric_adjoint
+ *                    reverse-mode derivative of b -> U~^-1 L~^-1 b and of the
+ *                    elimination, giving d/d(values of A) and d/db.
+ *   tpilu_batched_graph_*
+ *                    many matrices sharing one pattern: all numeric
+ *                    factorizations plus all solves captured in one HIP graph.
+ *
+ * Results are bit-identical to the plain sequential algorithm: every entry of
+ * F receives its updates in ascending pivot order, every product and every
+ * difference is rounded on its own (no FMA contraction), divisions and
+ * square roots are correctly rounded IEEE-754 binary64, and every reduction
+ * has one fixed shape that does not depend on the launch configuration.
+ *
+ * Conventions for every entry point
+ *   - 0-based indices.  A CSR row lists its columns strictly ascending and
+ *     must store its diagonal (its value may be 0).  Every stored entry is an
+ *     entry of level 0, explicit zeros included.
+ *   - All double/int arrays passed as arguments are DEVICE pointers (memory
+ *     of the ctx's device) unless the parameter comment says "host".  The
+ *     caller owns them; the library never frees or keeps them beyond the
+ *     call, except where a graph handle records them (see below).
+ *   - Batches: `batch` instances share one pattern; their values are stored
+ *     entry-major, instance-minor: value of entry p of instance b is at
+ *     val[p * batch + b].  Vectors likewise: v[i * batch + b].
+ *   - Every call enqueues its work on the ctx stream and returns without
+ *     waiting, except where a host output (bad_row, iters, relres, info) is
+ *     requested: then it waits for the stream and reports.
+ *   - Errors: every entry point returns a tpilu_status; nothing aborts and no
+ *     C++ exception crosses the ABI.  tpilu_last_error(ctx) gives a message.
+ *   - The bit pattern 0x7FF4A5A5A5A5A5A5 (one signalling-NaN payload) is
+ *     reserved: the kernels use it to mark values not yet produced.  An input
+ *     value with exactly that pattern is replaced by the default quiet NaN
+ *     and the call reports TPILU_E_INVAL.
+ *   - Calls that use the same pattern handle must not run concurrently (they
+ *     share the handle's scratch memory and control block).
+ */
+#ifndef TPILU_H
+#define TPILU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPILU_API __attribute__((visibility("default")))
+
+typedef enum {
+    TPILU_OK = 0,
+    TPILU_E_INVAL = 1,     /* malformed CSR, bad size or argument, reserved NaN in input */
+    TPILU_E_NOMEM = 2,     /* device allocation failed */
+    TPILU_E_ZEROPIVOT = 3, /* a final pivot f_jj is +-0; the smallest such j is reported */
+    TPILU_E_DEVICE = 4,    /* a HIP runtime call failed */
+    TPILU_E_NOTCONV = 5,   /* GMRES reached maxit without meeting rtol */
+    TPILU_E_TIMEOUT = 6    /* a kernel's bounded wait for a dependency ran out (watchdog) */
+} tpilu_status;
+
+typedef struct tpilu_ctx_s *tpilu_ctx;
+typedef struct tpilu_pattern_s *tpilu_pattern;
+typedef struct tpilu_graph_s *tpilu_graph;
+
+/* Optional device allocator: alloc returns device memory of the ctx's device
+ * (NULL on failure); free releases it.  With both NULL the library uses
+ * hipMalloc/hipFree.  Only handle creation and workspace growth allocate. */
+typedef void *(*tpilu_alloc_fn)(size_t bytes, void *user);
+typedef void (*tpilu_free_fn)(void *ptr, void *user);
+
+/* Library context bound to one device and one HIP stream (a hipStream_t
+ * passed as void*; NULL = the device's null stream). */
+TPILU_API tpilu_status tpilu_ctx_create(int device, void *hip_stream, tpilu_alloc_fn alloc,
+                                        tpilu_free_fn free_fn, void *user, tpilu_ctx *out);
+TPILU_API tpilu_status tpilu_ctx_set_stream(tpilu_ctx ctx, void *hip_stream);
+TPILU_API void tpilu_ctx_destroy(tpilu_ctx ctx);
+TPILU_API const char *tpilu_status_string(tpilu_status st);
+TPILU_API const char *tpilu_last_error(tpilu_ctx ctx);
+
+/* Watchdog for the dependency waits inside the persistent kernels: a wait
+ * gives up after `timeout_us` microseconds of wall-clock time (0 = library
+ * default, 10 s), every other wait of the call then gives up at once, and the
+ * call reports TPILU_E_TIMEOUT.  `skip_publish_row` >= 0 makes the numeric
+ * kernel never publish that row (a host-forced failure for testing the
+ * watchdog); -1 turns that off. */
+TPILU_API tpilu_status tpilu_ctx_set_watchdog(tpilu_ctx ctx, uint32_t timeout_us,
+                                              int64_t skip_publish_row);
+
+/* Number of wavefronts launched for the persistent kernels (numeric, solves,
+ * adjoints); 0 = library default (the resident maximum).  Any value >= 1
+ * gives the same bits; it only changes speed.  Used to test that claim. */
+TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t waves);
+
+/* ---------------------------------------------------------------------------
+ * Phase I -- symbolic factorization (Sec. 2.2, Algorithm 1; Def. 2.3).
+ *
+ * Input: the structure of A, n x n, nnz entries: rowptr[n+1] (int64, device),
+ * col[nnz] (int32, device).  k >= 0 is the level limit; any k >= n-1 gives the
+ * complete LU pattern.  The library copies the structure; the arrays may be
+ * freed after the call.  On success *out receives a pattern handle that
+ * holds, on the device: the pattern of F (rows sorted), the level of every
+ * entry, the diagonal slot of every row, the map from A's entries to F's
+ * slots, and the per-row update schedule the numeric phase replays.  The
+ * pattern is immutable and is reused by any number of numeric calls.
+ * Errors: TPILU_E_INVAL for a malformed CSR (unsorted or duplicate column,
+ * out-of-range index, missing diagonal, rowptr not monotone), n or nnz out of
+ * range (n < 2^31, nnz(F) < 2^31); TPILU_E_NOMEM; TPILU_E_DEVICE.
+ * Waits for the stream (the pattern size is needed on the host).
+ * ------------------------------------------------------------------------- */
+TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64_t nnz, const int64_t *rowptr,
+                                      const int32_t *col, int32_t k, tpilu_pattern *out);
+
+typedef struct {
+    int64_t n, nnz_a, nnz_f;
+    int64_t nnz_l;       /* strictly lower entries of F (L~ without its unit diagonal) */
+    int64_t nnz_u;       /* entries on and above the diagonal */
+    int64_t n_updates;   /* number of f_jt <- f_jt - f_jh f_ht operations of Phase II */
+    int32_t k;
+    int32_t max_row;     /* longest row of F */
+    int32_t max_lrow;    /* most pivots in one row */
+    int32_t depth_l;     /* rows on the longest dependency chain of L~ (forward order) */
+    int32_t depth_u;     /* rows on the longest dependency chain of U~ (backward order) */
+    int32_t overflow_rows; /* rows the symbolic pass had to redo in global memory */
+} tpilu_pattern_info_t;
+
+TPILU_API tpilu_status tpilu_pattern_info(tpilu_pattern pat, tpilu_pattern_info_t *info /* host */);
+
+/* Copy the pattern out (device pointers, each nullable): rowptr[n+1] int64,
+ * col[nnz_f] int32, diag[n] int32 (slot of f_ii), level[nnz_f] uint8 (level of
+ * each entry, saturated at 255), a2f[nnz_a] int32 (F slot of A's entry p). */
+TPILU_API tpilu_status tpilu_pattern_export(tpilu_ctx ctx, tpilu_pattern pat, int64_t *rowptr,
+                                            int32_t *col, int32_t *diag, uint8_t *level,
+                                            int32_t *a2f);
+TPILU_API void tpilu_pattern_destroy(tpilu_pattern pat);
+
+/* ---------------------------------------------------------------------------
+ * Phase II -- numeric factorization (Eq. 2, Eqs. 5a/5b).
+ *
+ * a_val[nnz_a * batch]: values of A in the pattern's A order.  f_val[nnz_f *
+ * batch] receives F: strictly lower slots hold L~ (unit diagonal implicit),
+ * the others hold U~.  F starts as A with fill entries +0.0; for each row j
+ * ascending and each pivot h < j of row j ascending: f_jh <- f_jh / f_hh, then
+ * f_jt <- f_jt - f_jh * f_ht for every t > h stored in rows h and j.
+ * A zero pivot does not stop the elimination (IEEE division gives inf/NaN);
+ * the call returns TPILU_E_ZEROPIVOT and *bad_row (host, nullable) receives
+ * the smallest row whose final pivot is +-0, or -1 (for batches: smallest
+ * over all instances).  With bad_row == NULL the call does not wait and the
+ * status of the device work is read later with tpilu_pattern_check.
+ * ------------------------------------------------------------------------- */
+TPILU_API tpilu_status tpilu_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double *a_val,
+                                     int32_t batch, double *f_val, int64_t *bad_row);
+
+/* Wait for the stream and report the sticky device status of the last calls
+ * on this pattern (zero pivot, watchdog, reserved NaN), then clear it.
+ * bad_row (host, nullable) as for tpilu_numeric. */
+TPILU_API tpilu_status tpilu_pattern_check(tpilu_ctx ctx, tpilu_pattern pat, int64_t *bad_row);
+
+/* ---------------------------------------------------------------------------
+ * Apply the preconditioner (Eq. 1): y = U~^-1 (L~^-1 b).
+ *   forward  (Eq. 3b): x_i = b_i - sum_{h<i} f_ih x_h, subtractions in
+ *                      ascending h;
+ *   backward:          y_i = (x_i - sum_{j>i} f_ij y_j) / f_ii, subtractions
+ *                      in ascending j, then the division.
+ * f_val, b, y: [n * batch] / [nnz_f * batch] device arrays; x_out (nullable,
+ * n * batch) receives the intermediate x.  b and y may not alias.
+ * ------------------------------------------------------------------------- */
+TPILU_API tpilu_status tpilu_apply(tpilu_ctx ctx, tpilu_pattern pat, const double *f_val,
+                                   int32_t batch, const double *b, double *y, double *x_out);
+
+/* ---------------------------------------------------------------------------
+ * Restarted GMRES(m), right preconditioned by M = L~ U~ (single instance).
+ * Modified Gram-Schmidt, Givens rotations with rho = sqrt(a*a + b*b), inner
+ * loop stopped when the implicit residual |g_{j+1}| <= rtol ||b||, outer
+ * loop stopped on the true residual; maxit counts inner iterations over all
+ * cycles.  Inner products use one fixed shape: 16384 strided partial sums
+ * (lane l adds elements l, l+16384, ... in ascending order from +0.0) then
+ * a pairwise tree (strides 1, 2, 4, ...).  SpMV row sums run from +0.0 in
+ * ascending column order.
+ * a_val: values of A (the pattern's A structure); f_val: the factor; b, x:
+ * n-vectors, x holds x0 on entry and the result on return.  iters, relres
+ * (host) receive the inner iteration count and ||b - A x|| / ||b||; hist
+ * (host, nullable, maxit entries) receives |g_{j+1}| per inner iteration.
+ * Returns TPILU_E_NOTCONV (with the last x) when maxit is reached.
+ * ------------------------------------------------------------------------- */
+TPILU_API tpilu_status tpilu_gmres(tpilu_ctx ctx, tpilu_pattern pat, const double *a_val,
+                                   const double *f_val, const double *b, double *x,
+                                   int32_t restart, int32_t maxit, double rtol, int32_t *iters,
+                                   double *relres, double *hist);
+
+/* Building blocks exposed for testing and reuse (single instance). */
+/* y = A x with the pattern's A structure. */
+TPILU_API tpilu_status tpilu_spmv(tpilu_ctx ctx, tpilu_pattern pat, const double *a_val,
+                                  const double *x, double *y);
+/* *result (host) = fixed-shape inner product of x and y, both of length n. */
+TPILU_API tpilu_status tpilu_dot(tpilu_ctx ctx, int64_t n, const double *x, const double *y,
+                                 double *result);
+
+/* ---------------------------------------------------------------------------
+ * Reverse mode of y = U~^-1 L~^-1 b (given x = L~^-1 b and y from the forward
+ * pass, and ybar = dLoss/dy):
+ *   z = U~^-T ybar: z_i = (ybar_i - sum_{j<i} f_ji z_j) / f_ii, ascending i,
+ *                   subtractions in ascending j;
+ *   w = L~^-T z:    w_i = z_i - sum_{j>i} f_ji w_j, descending i,
+ *                   subtractions in ascending j;
+ *   bbar = w;  fbar_ij = -(z_i * y_j) on U~ (j >= i);  fbar_ih = -(w_i * x_h)
+ *   on the strictly lower part.
+ * All arrays device, [n * batch] or [nnz_f * batch].
+ * ------------------------------------------------------------------------- */
+TPILU_API tpilu_status tpilu_apply_adjoint(tpilu_ctx ctx, tpilu_pattern pat, const double *f_val,
+                                           int32_t batch, const double *x, const double *y,
+                                           const double *ybar, double *bbar, double *fbar);
+
+/* Reverse sweep of the elimination (adjoint of Eqs. 5a/5b).  fbar[nnz_f *
+ * batch] holds dLoss/dF on entry and is overwritten; abar[nnz_a * batch]
+ * receives dLoss/d(values of A).  Rows are undone in descending order; for
+ * pivot h of row j with l = f_jh:
+ *   lbar = fbar_jh - sum_t fbar_jt f_ht  (t ascending, t stored in rows h, j)
+ *   fbar_ht <- fbar_ht - fbar_jt * l     (contributions to row h arrive in
+ *                                         descending j)
+ *   fbar_jh <- lbar / f_hh;  fbar_hh <- fbar_hh - (lbar * l) / f_hh.
+ * ------------------------------------------------------------------------- */
+TPILU_API tpilu_status tpilu_numeric_adjoint(tpilu_ctx ctx, tpilu_pattern pat, const double *f_val,
+                                             int32_t batch, double *fbar, double *abar);
+
+/* ---------------------------------------------------------------------------
+ * Batched factor + solve under one captured HIP graph.  Records, on the ctx
+ * stream, tpilu_numeric(a_val -> f_val) followed by tpilu_apply(f_val, b ->
+ * y) for all `batch` instances, and instantiates the graph.  The device
+ * arrays passed here are baked into the graph: each launch recomputes f_val
+ * and y from the CURRENT contents of a_val and b.  Launch with
+ * tpilu_batched_graph_launch on any stream of the ctx's device; status
+ * (zero pivot, watchdog) is read with tpilu_pattern_check.
+ * ------------------------------------------------------------------------- */
+TPILU_API tpilu_status tpilu_batched_graph_create(tpilu_ctx ctx, tpilu_pattern pat,
+                                                  const double *a_val, int32_t batch,
+                                                  double *f_val, const double *b, double *y,
+                                                  tpilu_graph *out);
+TPILU_API tpilu_status tpilu_batched_graph_launch(tpilu_graph g, void *hip_stream);
+TPILU_API void tpilu_batched_graph_destroy(tpilu_graph g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPILU_H */

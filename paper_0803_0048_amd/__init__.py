@@ -1,0 +1,28 @@
+"""MI355X (gfx950) level-of-fill ILU(k) preconditioning, bit-compatible with
+the sequential algorithm (Dong & Cooperman, TPILU(k)).
+
+Entry points (GPU only; they raise if the HIP library is missing):
+
+    pat = symbolic(rowptr, col, k)          # Phase I, Algorithm 1
+    f   = numeric(pat, a_val)               # Phase II, Eqs. 5a/5b
+    y   = apply(pat, f, b)                  # y = U~^-1 L~^-1 b, Eq. 1
+    x, info = gmres(pat, a_val, f, b)       # right-preconditioned GMRES(m)
+    ILUApply.apply(a_val, b, pat)           # autograd: d/d a_val, d/d b
+    BatchedGraph(pat, a_vals, bs).launch()  # batch in one HIP graph
+
+``inputs`` builds the seeded synthetic workloads.
+"""
+
+_BINDING_NAMES = {
+    "symbolic", "numeric", "apply", "gmres", "spmv", "dot", "apply_adjoint", "numeric_adjoint",
+    "check", "BatchedGraph", "ILUApply", "Pattern", "TpiluError", "ZeroPivotError", "context",
+    "load_library", "LIB_PATH",
+}
+
+
+def __getattr__(name):
+    if name in _BINDING_NAMES:
+        from . import binding
+
+        return getattr(binding, name)
+    raise AttributeError(name)

@@ -1,0 +1,398 @@
+"""Python binding of the gfx950 ILU(k) library (``libtpilu.so``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/tpilu.h``.  PyTorch provides
+device memory and the current HIP stream.  There is no CPU fallback: if the
+library is not built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtpilu.so")
+
+OK, E_INVAL, E_NOMEM, E_ZEROPIVOT, E_DEVICE, E_NOTCONV, E_TIMEOUT = range(7)
+
+EXPORTED = [
+    "tpilu_ctx_create", "tpilu_ctx_set_stream", "tpilu_ctx_destroy", "tpilu_status_string",
+    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_symbolic", "tpilu_pattern_info",
+    "tpilu_pattern_export", "tpilu_pattern_destroy", "tpilu_numeric", "tpilu_pattern_check",
+    "tpilu_apply", "tpilu_gmres", "tpilu_spmv", "tpilu_dot", "tpilu_apply_adjoint",
+    "tpilu_numeric_adjoint", "tpilu_batched_graph_create", "tpilu_batched_graph_launch",
+    "tpilu_batched_graph_destroy",
+]
+
+
+class TpiluError(RuntimeError):
+    def __init__(self, status: int, message: str, bad_row: int = -1):
+        super().__init__(f"[status {status}] {message}")
+        self.status = status
+        self.bad_row = bad_row
+
+
+class ZeroPivotError(TpiluError):
+    pass
+
+
+class PatternInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz_a", C.c_int64), ("nnz_f", C.c_int64), ("nnz_l", C.c_int64),
+                ("nnz_u", C.c_int64), ("n_updates", C.c_int64), ("k", C.c_int32),
+                ("max_row", C.c_int32), ("max_lrow", C.c_int32), ("depth_l", C.c_int32),
+                ("depth_u", C.c_int32), ("overflow_rows", C.c_int32)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load_library():
+    """Load libtpilu.so (after torch, so that it binds to torch's HIP runtime)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_0803_0048_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
+        st = C.c_int
+        sig = {
+            "tpilu_ctx_create": ([C.c_int, P, P, P, P, C.POINTER(P)], st),
+            "tpilu_ctx_set_stream": ([P, P], st),
+            "tpilu_ctx_destroy": ([P], None),
+            "tpilu_status_string": ([st], C.c_char_p),
+            "tpilu_last_error": ([P], C.c_char_p),
+            "tpilu_ctx_set_watchdog": ([P, u32, i64], st),
+            "tpilu_ctx_set_grid": ([P, i32], st),
+            "tpilu_symbolic": ([P, i64, i64, P, P, i32, C.POINTER(P)], st),
+            "tpilu_pattern_info": ([P, C.POINTER(PatternInfo)], st),
+            "tpilu_pattern_export": ([P, P, P, P, P, P, P], st),
+            "tpilu_pattern_destroy": ([P], None),
+            "tpilu_numeric": ([P, P, P, i32, P, C.POINTER(i64)], st),
+            "tpilu_pattern_check": ([P, P, C.POINTER(i64)], st),
+            "tpilu_apply": ([P, P, P, i32, P, P, P], st),
+            "tpilu_gmres": ([P, P, P, P, P, P, i32, i32, dbl, C.POINTER(i32), C.POINTER(dbl), P], st),
+            "tpilu_spmv": ([P, P, P, P, P], st),
+            "tpilu_dot": ([P, i64, P, P, C.POINTER(dbl)], st),
+            "tpilu_apply_adjoint": ([P, P, P, i32, P, P, P, P, P], st),
+            "tpilu_numeric_adjoint": ([P, P, P, i32, P, P], st),
+            "tpilu_batched_graph_create": ([P, P, P, i32, P, P, P, C.POINTER(P)], st),
+            "tpilu_batched_graph_launch": ([P, P], st),
+            "tpilu_batched_graph_destroy": ([P], None),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+        return L
+
+
+# ----------------------------------------------------------------------------------
+# context per device
+# ----------------------------------------------------------------------------------
+_ctxs: dict[int, "Context"] = {}
+
+
+class Context:
+    def __init__(self, device: int):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the ILU(k) library runs on the GPU only")
+        self.device = device
+        h = C.c_void_p()
+        st = lib.tpilu_ctx_create(device, None, None, None, None, C.byref(h))
+        if st != OK:
+            raise TpiluError(st, "tpilu_ctx_create failed")
+        self.h = h
+
+    def bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        load_library().tpilu_ctx_set_stream(self.h, C.c_void_p(s))
+
+    def check(self, st: int, what: str, bad_row: int = -1):
+        if st == OK:
+            return
+        msg = load_library().tpilu_last_error(self.h).decode(errors="replace")
+        if st == E_ZEROPIVOT:
+            raise ZeroPivotError(st, f"{what}: {msg}", bad_row)
+        raise TpiluError(st, f"{what}: {msg}", bad_row)
+
+    def set_grid(self, waves: int = 0):
+        self.check(load_library().tpilu_ctx_set_grid(self.h, waves), "set_grid")
+
+    def set_watchdog(self, timeout_us: int = 0, skip_publish_row: int = -1):
+        self.check(load_library().tpilu_ctx_set_watchdog(self.h, timeout_us, skip_publish_row),
+                   "set_watchdog")
+
+
+def context(device=None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    if isinstance(device, torch.device):
+        device = device.index if device.index is not None else torch.cuda.current_device()
+    c = _ctxs.get(device)
+    if c is None:
+        c = Context(device)
+        _ctxs[device] = c
+    c.bind_stream()
+    return c
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, dtype, name, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t
+
+
+# ----------------------------------------------------------------------------------
+# pattern (Phase I)
+# ----------------------------------------------------------------------------------
+class Pattern:
+    """Level-of-fill pattern of F for one CSR structure and level k."""
+
+    def __init__(self, handle, ctx: Context, device: torch.device):
+        self.h = handle
+        self.ctx = ctx
+        self.device = device
+        info = PatternInfo()
+        load_library().tpilu_pattern_info(self.h, C.byref(info))
+        self.info = {f: getattr(info, f) for f, _ in PatternInfo._fields_}
+        self.n = info.n
+        self.nnz_a = info.nnz_a
+        self.nnz_f = info.nnz_f
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            try:
+                torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            _lib.tpilu_pattern_destroy(h)
+            self.h = None
+
+    def export(self):
+        """Pattern arrays as device tensors: rowptr, col, diag, level, a2f."""
+        ctx = context(self.device)
+        d = self.device
+        rp = torch.empty(self.n + 1, dtype=torch.int64, device=d)
+        ci = torch.empty(max(self.nnz_f, 1), dtype=torch.int32, device=d)
+        dg = torch.empty(max(self.n, 1), dtype=torch.int32, device=d)
+        lv = torch.empty(max(self.nnz_f, 1), dtype=torch.uint8, device=d)
+        a2f = torch.empty(max(self.nnz_a, 1), dtype=torch.int32, device=d)
+        st = load_library().tpilu_pattern_export(ctx.h, self.h, _ptr(rp), _ptr(ci), _ptr(dg), _ptr(lv), _ptr(a2f))
+        ctx.check(st, "pattern_export")
+        return {"rowptr": rp, "col": ci[: self.nnz_f], "diag": dg[: self.n], "level": lv[: self.nnz_f],
+                "a2f": a2f[: self.nnz_a]}
+
+
+def symbolic(rowptr: torch.Tensor, col: torch.Tensor, k: int, n: int | None = None) -> Pattern:
+    """Phase I (Algorithm 1): pattern of every entry of level <= k."""
+    d = rowptr.device
+    _need(rowptr, torch.int64, "rowptr", None)
+    _need(col, torch.int32, "col", d)
+    n = rowptr.numel() - 1 if n is None else n
+    ctx = context(d)
+    h = C.c_void_p()
+    st = load_library().tpilu_symbolic(ctx.h, n, col.numel(), _ptr(rowptr), _ptr(col), int(min(k, 2**31 - 1)),
+                                       C.byref(h))
+    ctx.check(st, "symbolic")
+    return Pattern(h, ctx, d)
+
+
+def _batch_of(t: torch.Tensor, lead: int, name: str) -> int:
+    if t.dim() == 1:
+        if t.shape[0] != lead:
+            raise ValueError(f"{name} has {t.shape[0]} entries, expected {lead}")
+        return 1
+    if t.dim() == 2 and t.shape[0] == lead:
+        return t.shape[1]
+    raise ValueError(f"{name} must have shape [{lead}] or [{lead}, batch]")
+
+
+def numeric(pat: Pattern, a_val: torch.Tensor, out: torch.Tensor | None = None, check: bool = True):
+    """Phase II (Eqs. 5a/5b): F values, shape [nnz_f] or [nnz_f, batch]."""
+    _need(a_val, torch.float64, "a_val", pat.device)
+    B = _batch_of(a_val, pat.nnz_a, "a_val")
+    shape = (pat.nnz_f,) if a_val.dim() == 1 else (pat.nnz_f, B)
+    f = torch.empty(shape, dtype=torch.float64, device=pat.device) if out is None else _need(out, torch.float64, "out", pat.device)
+    ctx = context(pat.device)
+    bad = C.c_int64(-1)
+    st = load_library().tpilu_numeric(ctx.h, pat.h, _ptr(a_val), B, _ptr(f), C.byref(bad) if check else None)
+    ctx.check(st, "numeric", bad.value)
+    return f
+
+
+def check(pat: Pattern) -> int:
+    """Wait and report the sticky device status of the last calls; returns bad_row or -1."""
+    ctx = context(pat.device)
+    bad = C.c_int64(-1)
+    st = load_library().tpilu_pattern_check(ctx.h, pat.h, C.byref(bad))
+    ctx.check(st, "check", bad.value)
+    return bad.value
+
+
+def apply(pat: Pattern, f_val: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None,
+          return_x: bool = False):
+    """y = U~^-1 L~^-1 b (Eq. 1)."""
+    _need(f_val, torch.float64, "f_val", pat.device)
+    _need(b, torch.float64, "b", pat.device)
+    B = _batch_of(b, pat.n, "b")
+    if _batch_of(f_val, pat.nnz_f, "f_val") != B:
+        raise ValueError("f_val and b batch sizes differ")
+    y = torch.empty_like(b) if out is None else _need(out, torch.float64, "out", pat.device)
+    x = torch.empty_like(b) if return_x else None
+    ctx = context(pat.device)
+    st = load_library().tpilu_apply(ctx.h, pat.h, _ptr(f_val), B, _ptr(b), _ptr(y), _ptr(x))
+    ctx.check(st, "apply")
+    return (y, x) if return_x else y
+
+
+def spmv(pat: Pattern, a_val: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    _need(a_val, torch.float64, "a_val", pat.device)
+    _need(x, torch.float64, "x", pat.device)
+    y = torch.empty(pat.n, dtype=torch.float64, device=pat.device)
+    ctx = context(pat.device)
+    ctx.check(load_library().tpilu_spmv(ctx.h, pat.h, _ptr(a_val), _ptr(x), _ptr(y)), "spmv")
+    return y
+
+
+def dot(x: torch.Tensor, y: torch.Tensor) -> float:
+    """Fixed-shape inner product (16384 strided partial sums, then a pairwise tree)."""
+    _need(x, torch.float64, "x", None)
+    _need(y, torch.float64, "y", x.device)
+    ctx = context(x.device)
+    r = C.c_double(0.0)
+    ctx.check(load_library().tpilu_dot(ctx.h, x.numel(), _ptr(x), _ptr(y), C.byref(r)), "dot")
+    return r.value
+
+
+def gmres(pat: Pattern, a_val: torch.Tensor, f_val: torch.Tensor, b: torch.Tensor, x0: torch.Tensor | None = None,
+          restart: int = 30, maxit: int | None = None, rtol: float = 1e-8, raise_notconv: bool = False):
+    """Right-preconditioned restarted GMRES.  Returns (x, info)."""
+    _need(a_val, torch.float64, "a_val", pat.device)
+    _need(f_val, torch.float64, "f_val", pat.device)
+    _need(b, torch.float64, "b", pat.device)
+    x = torch.zeros_like(b) if x0 is None else _need(x0, torch.float64, "x0", pat.device).clone()
+    if maxit is None:
+        maxit = min(10 * pat.n, 100000)
+    hist = (C.c_double * max(maxit, 1))()
+    it = C.c_int32(0)
+    rr = C.c_double(0.0)
+    ctx = context(pat.device)
+    st = load_library().tpilu_gmres(ctx.h, pat.h, _ptr(a_val), _ptr(f_val), _ptr(b), _ptr(x), restart, maxit,
+                                    rtol, C.byref(it), C.byref(rr), hist)
+    if st != E_NOTCONV or raise_notconv:
+        ctx.check(st, "gmres")
+    info = {"iters": it.value, "relres": rr.value, "status": st, "hist": list(hist[: it.value])}
+    return x, info
+
+
+def apply_adjoint(pat: Pattern, f_val, x, y, ybar):
+    """Reverse mode of y = U~^-1 L~^-1 b.  Returns (bbar, fbar)."""
+    for t, nm in ((f_val, "f_val"), (x, "x"), (y, "y"), (ybar, "ybar")):
+        _need(t, torch.float64, nm, pat.device)
+    B = _batch_of(ybar, pat.n, "ybar")
+    bbar = torch.empty_like(ybar)
+    fbar = torch.empty_like(f_val)
+    ctx = context(pat.device)
+    st = load_library().tpilu_apply_adjoint(ctx.h, pat.h, _ptr(f_val), B, _ptr(x), _ptr(y), _ptr(ybar),
+                                            _ptr(bbar), _ptr(fbar))
+    ctx.check(st, "apply_adjoint")
+    return bbar, fbar
+
+
+def numeric_adjoint(pat: Pattern, f_val, fbar):
+    """Reverse sweep of the elimination.  Returns (abar, fbar after the sweep)."""
+    _need(f_val, torch.float64, "f_val", pat.device)
+    B = _batch_of(f_val, pat.nnz_f, "f_val")
+    fb = _need(fbar, torch.float64, "fbar", pat.device).clone()
+    shape = (pat.nnz_a,) if f_val.dim() == 1 else (pat.nnz_a, B)
+    abar = torch.empty(shape, dtype=torch.float64, device=pat.device)
+    ctx = context(pat.device)
+    st = load_library().tpilu_numeric_adjoint(ctx.h, pat.h, _ptr(f_val), B, _ptr(fb), _ptr(abar))
+    ctx.check(st, "numeric_adjoint")
+    return abar, fb
+
+
+class BatchedGraph:
+    """All numeric factorizations plus all solves of a batch in one HIP graph.
+
+    The tensors given here are baked into the graph; every launch() recomputes
+    f_val and y from the current contents of a_val and b.
+    """
+
+    def __init__(self, pat: Pattern, a_val, b, f_val=None, y=None):
+        _need(a_val, torch.float64, "a_val", pat.device)
+        _need(b, torch.float64, "b", pat.device)
+        B = _batch_of(a_val, pat.nnz_a, "a_val")
+        if _batch_of(b, pat.n, "b") != B:
+            raise ValueError("a_val and b batch sizes differ")
+        self.pat, self.a_val, self.b = pat, a_val, b
+        self.f_val = torch.empty((pat.nnz_f, B) if a_val.dim() == 2 else (pat.nnz_f,), dtype=torch.float64,
+                                 device=pat.device) if f_val is None else f_val
+        self.y = torch.empty_like(b) if y is None else y
+        ctx = context(pat.device)
+        h = C.c_void_p()
+        st = load_library().tpilu_batched_graph_create(ctx.h, pat.h, _ptr(a_val), B, _ptr(self.f_val), _ptr(b),
+                                                       _ptr(self.y), C.byref(h))
+        ctx.check(st, "batched_graph_create")
+        self.h = h
+
+    def launch(self):
+        s = torch.cuda.current_stream(self.pat.device).cuda_stream
+        st = load_library().tpilu_batched_graph_launch(self.h, C.c_void_p(s))
+        if st != OK:
+            raise TpiluError(st, "batched_graph_launch failed")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            try:
+                torch.cuda.synchronize(self.pat.device)
+            except Exception:
+                pass
+            _lib.tpilu_batched_graph_destroy(h)
+            self.h = None
+
+
+class ILUApply(torch.autograd.Function):
+    """y = M^-1 b with M = L~ U~ = ILU(k) of A (values a_val on pattern pat).
+
+    Forward: numeric factorization + triangular solves.  Backward: transposed
+    solves and the reverse sweep of the elimination, giving d/d a_val and
+    d/d b.  Shapes [nnz_a] / [n] or batched [nnz_a, B] / [n, B].
+    """
+
+    @staticmethod
+    def forward(ctx, a_val, b, pat):
+        f = numeric(pat, a_val.detach().contiguous())
+        y, x = apply(pat, f, b.detach().contiguous(), return_x=True)
+        ctx.pat = pat
+        ctx.save_for_backward(f, x, y)
+        return y
+
+    @staticmethod
+    def backward(ctx, ybar):
+        f, x, y = ctx.saved_tensors
+        bbar, fbar = apply_adjoint(ctx.pat, f, x, y, ybar.contiguous())
+        abar, _ = numeric_adjoint(ctx.pat, f, fbar)
+        return abar, bbar, None

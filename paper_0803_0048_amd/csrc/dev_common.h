@@ -1,0 +1,145 @@
+// Device-side building blocks shared by the gfx950 kernels.
+//
+// Cross-wavefront hand-off without flags.  Every value a persistent kernel
+// hands from one row to another (entries of F, entries of x and y in the
+// triangular solves, adjoints in the reverse sweep) lives in an output array
+// that is first filled with a reserved signalling-NaN bit pattern, kPending.
+// The producing wavefront overwrites each slot exactly once with its final
+// value; a consumer polls the slot itself until it no longer reads kPending.
+// No arithmetic result is ever a signalling NaN, so a value that is not
+// kPending is the final one: no separate completion flag, no release/acquire
+// fence and no second round trip are needed, and every slot is its own
+// message.
+//
+// Coherence across the eight XCDs (each has a private L2): the producer
+// writes with agent-scope atomic stores (write-through to the memory-side
+// coherence point); a consumer first tries a plain load (it may hit a cache;
+// a non-kPending answer is final because the slot holds only kPending or the
+// final value during the kernel, and caches are invalidated at kernel
+// start), and only if that still shows kPending polls with agent-scope
+// atomic loads, which bypass the non-coherent caches.
+//
+// Every wait is bounded: after a wall-clock budget it sets the control
+// block's abort word and the TIMEOUT bit and returns a quiet NaN; every other
+// wait notices the abort word within a few polls and gives up too, so all
+// waves always drain.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tpilu {
+
+constexpr uint64_t kPending = 0x7FF4A5A5A5A5A5A5ull;  // reserved sNaN payload: "not written yet"
+constexpr uint64_t kQNaN = 0x7FF8000000000000ull;     // default quiet NaN
+constexpr int kWave = 64;
+
+// status bits (sticky until read by the host)
+constexpr uint32_t kStTimeout = 1u;
+constexpr uint32_t kStReservedNaN = 2u;
+
+struct Ctl {
+    uint32_t ticket;        // next task of the running persistent kernel
+    uint32_t abort;         // set once any wait ran out
+    uint32_t status;        // kSt* bits
+    uint32_t pad;
+    unsigned long long bad_row;  // smallest row with a zero final pivot, or ~0
+};
+
+__device__ __forceinline__ uint64_t as_u64(double d) { return __builtin_bit_cast(uint64_t, d); }
+__device__ __forceinline__ double as_f64(uint64_t u) { return __builtin_bit_cast(double, u); }
+
+__device__ __forceinline__ uint64_t ld_coherent(const double* p) {
+    return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_cached(const double* p) {
+    return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void st_publish(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), as_u64(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t ld_u32_coherent(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Poll slot p until it holds a final value.  `first` is a value already read
+// from p (for instance by a prefetch); it is returned at once if final.
+// `limit` is the wait budget in wall-clock ticks (s_memrealtime).
+__device__ __noinline__ double wait_final_slow(const double* p, Ctl* ctl, uint64_t limit) {
+    uint32_t n = 0;
+    uint64_t t0 = 0;
+    for (;;) {
+        uint64_t v = ld_coherent(p);
+        if (v != kPending) return as_f64(v);
+        if ((n & 31u) == 0u) {
+            if (ld_u32_coherent(&ctl->abort) != 0u) return as_f64(kQNaN);
+            const uint64_t now = wall_clock64();
+            if (n == 0) {
+                t0 = now;
+            } else if (now - t0 > limit) {
+                atomicOr(&ctl->status, kStTimeout);
+                __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return as_f64(kQNaN);
+            }
+        }
+        ++n;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__device__ __forceinline__ double wait_final(const double* p, uint64_t first, Ctl* ctl,
+                                             uint64_t limit) {
+    if (first != kPending) return as_f64(first);
+    return wait_final_slow(p, ctl, limit);
+}
+
+__device__ __forceinline__ double wait_final(const double* p, Ctl* ctl, uint64_t limit) {
+    return wait_final(p, ld_cached(p), ctl, limit);
+}
+
+// A caller-supplied value that happens to carry the reserved pattern is
+// replaced by the quiet NaN (and reported), so it can never be mistaken for
+// "not written yet".
+__device__ __forceinline__ double sanitize_input(double v, Ctl* ctl) {
+    if (as_u64(v) == kPending) {
+        atomicOr(&ctl->status, kStReservedNaN);
+        return as_f64(kQNaN);
+    }
+    return v;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// One wavefront per workgroup everywhere a kernel uses wave_sync: the
+// barrier then only orders the wave's own LDS traffic.
+__device__ __forceinline__ void wave_sync() { __syncthreads(); }
+
+// Value that is the same in every lane, made visibly uniform (SGPR) for the
+// compiler.  Only call with all lanes active.
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Grab the next task index for the whole wave.  Lane 0 does the atomic and
+// broadcasts it through LDS between two barriers: the barriers force every
+// lane to be converged here, so the compiler cannot let lane 0 run ahead into
+// the next task (a lane-0-only store at the end of a task followed by this
+// lane-0-only atomic would otherwise be merged across the loop back-edge).
+__device__ __forceinline__ uint32_t wave_ticket(Ctl* ctl) {
+    __shared__ uint32_t s_ticket;
+    __syncthreads();
+    if (lane_id() == 0) s_ticket = atomicAdd(&ctl->ticket, 1u);
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(s_ticket);
+}
+
+__device__ __forceinline__ double bcast_lane(double v, int src) {
+    uint64_t u = as_u64(v);
+    uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(u), src);
+    uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(u >> 32), src);
+    return as_f64((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+}  // namespace tpilu

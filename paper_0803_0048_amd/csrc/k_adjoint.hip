@@ -1,0 +1,271 @@
+// Reverse mode on gfx950: adjoint of b -> y = U~^-1 L~^-1 b and of the
+// elimination that produced F (reverse sweep of Eqs. 5a/5b).
+//
+// The sequential reverse sweep undoes rows in descending order; the pivot h
+// of row j then scatters fbar_ht -= fbar_jt * l into row h.  A scatter from
+// many rows at once would need floating-point atomics and lose the order, so
+// the GPU turns it into a gather: row h, once every row j > h that pivots on
+// it is done, pulls those contributions itself in descending j -- the same
+// order as the sequential sweep, hence the same bits.  "Rows that pivot on
+// h" is column h of the strict lower part (a CSC built once per pattern),
+// and the (t) positions come from the Phase II update schedule.  Values
+// handed between rows (lbar of every pivot, final adjoints of every row)
+// travel through kPending-initialised arrays as in the forward kernels.
+//
+// Batches use one task per (row, instance), instances strided in memory.
+#include "kernels.h"
+
+namespace tpilu {
+
+// ----------------------------------------------------------------------------------
+// CSC of the strict lower and strict upper parts of F
+// ----------------------------------------------------------------------------------
+__global__ void k_tcount(int32_t n, const int64_t* __restrict__ rpF, const int32_t* __restrict__ ciF,
+                         const int32_t* __restrict__ diagF, int32_t* cntL, int32_t* cntU) {
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t d = diagF[r];
+    for (int64_t s = rpF[r]; s < rpF[r + 1]; ++s) {
+        if (s < d) atomicAdd(&cntL[ciF[s]], 1);
+        else if (s > d) atomicAdd(&cntU[ciF[s]], 1);
+    }
+}
+
+hipError_t launch_transpose_count(int32_t n, const int64_t* rpF, const int32_t* ciF,
+                                  const int32_t* diagF, int32_t* cntL, int32_t* cntU,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(k_tcount, dim3((n + 255) / 256), dim3(256), 0, s, n, rpF, ciF, diagF, cntL, cntU);
+    return hipGetLastError();
+}
+
+__global__ void k_tfill(int32_t n, const int64_t* __restrict__ rpF, const int32_t* __restrict__ ciF,
+                        const int32_t* __restrict__ diagF, const int64_t* __restrict__ tpL,
+                        int32_t* tsL, int32_t* trL, const int64_t* __restrict__ tpU, int32_t* tsU,
+                        int32_t* trU, int32_t* curL, int32_t* curU) {
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t d = diagF[r];
+    for (int64_t s = rpF[r]; s < rpF[r + 1]; ++s) {
+        const int32_t c = ciF[s];
+        if (s < d) {
+            const int64_t pos = tpL[c] + atomicAdd(&curL[c], 1);
+            tsL[pos] = (int32_t)s;
+            trL[pos] = r;
+        } else if (s > d) {
+            const int64_t pos = tpU[c] + atomicAdd(&curU[c], 1);
+            tsU[pos] = (int32_t)s;
+            trU[pos] = r;
+        }
+    }
+}
+
+hipError_t launch_transpose_fill(int32_t n, const int64_t* rpF, const int32_t* ciF,
+                                 const int32_t* diagF, const int64_t* tpL, int32_t* tsL,
+                                 int32_t* trL, const int64_t* tpU, int32_t* tsU, int32_t* trU,
+                                 int32_t* curL, int32_t* curU, hipStream_t s) {
+    hipLaunchKernelGGL(k_tfill, dim3((n + 255) / 256), dim3(256), 0, s, n, rpF, ciF, diagF, tpL, tsL,
+                       trL, tpU, tsU, trU, curL, curU);
+    return hipGetLastError();
+}
+
+// sort each column's entries by row (insertion sort; columns are short)
+__global__ void k_tsort(int32_t n, const int64_t* __restrict__ tp, int32_t* ts, int32_t* tr) {
+    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int64_t a = tp[c], b = tp[c + 1];
+    for (int64_t i = a + 1; i < b; ++i) {
+        const int32_t kr = tr[i], ks = ts[i];
+        int64_t j = i - 1;
+        while (j >= a && tr[j] > kr) {
+            tr[j + 1] = tr[j];
+            ts[j + 1] = ts[j];
+            --j;
+        }
+        tr[j + 1] = kr;
+        ts[j + 1] = ks;
+    }
+}
+
+hipError_t launch_sort_columns(int32_t n, const int64_t* tp, int32_t* ts, int32_t* tr,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_tsort, dim3((n + 255) / 256), dim3(256), 0, s, n, tp, ts, tr);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------------
+// transposed solves
+// ----------------------------------------------------------------------------------
+// z = U~^-T ybar: i ascending, z_i = (ybar_i - sum_{j<i} f_ji z_j) / f_ii
+__global__ __launch_bounds__(64) void k_adj_solve_u(PatDev P, AdjPat T, const double* __restrict__ F,
+                                                    int32_t B, const double* __restrict__ ybar,
+                                                    double* z, Ctl* ctl, uint64_t spin_limit) {
+    const int lane = lane_id();
+    const uint32_t ntask = (uint32_t)P.n * (uint32_t)B;
+    for (;;) {
+        const uint32_t t = wave_ticket(ctl);
+        if (t >= ntask) break;
+        const int32_t i = (int32_t)(t / (uint32_t)B);
+        const int32_t b = (int32_t)(t % (uint32_t)B);
+        const int64_t a0 = T.tpU[i], a1 = T.tpU[i + 1];
+        double s = sanitize_input(ybar[(int64_t)i * B + b], ctl);
+        for (int64_t c = a0; c < a1; c += kWave) {
+            const int64_t a = c + lane;
+            double prod = 0.0;
+            if (a < a1) {
+                const int32_t j = T.trU[a];
+                const double f = F[(int64_t)T.tsU[a] * B + b];
+                prod = f * wait_final(z + (int64_t)j * B + b, ctl, spin_limit);
+            }
+            const int32_t cnt = (int32_t)min<int64_t>(kWave, a1 - c);
+            for (int32_t k = 0; k < cnt; ++k) s = s - bcast_lane(prod, k);
+        }
+        const double r = s / F[(int64_t)P.diagF[i] * B + b];
+        if (lane == 0) st_publish(z + (int64_t)i * B + b, r);
+    }
+}
+
+// w = L~^-T z: i descending, w_i = z_i - sum_{j>i} f_ji w_j
+__global__ __launch_bounds__(64) void k_adj_solve_l(PatDev P, AdjPat T, const double* __restrict__ F,
+                                                    int32_t B, const double* __restrict__ z,
+                                                    double* w, Ctl* ctl, uint64_t spin_limit) {
+    const int lane = lane_id();
+    const uint32_t ntask = (uint32_t)P.n * (uint32_t)B;
+    for (;;) {
+        const uint32_t t = wave_ticket(ctl);
+        if (t >= ntask) break;
+        const int32_t i = P.n - 1 - (int32_t)(t / (uint32_t)B);
+        const int32_t b = (int32_t)(t % (uint32_t)B);
+        const int64_t a0 = T.tpL[i], a1 = T.tpL[i + 1];
+        double s = z[(int64_t)i * B + b];
+        for (int64_t c = a0; c < a1; c += kWave) {
+            const int64_t a = c + lane;
+            double prod = 0.0;
+            if (a < a1) {
+                const int32_t j = T.trL[a];
+                const double f = F[(int64_t)T.tsL[a] * B + b];
+                prod = f * wait_final(w + (int64_t)j * B + b, ctl, spin_limit);
+            }
+            const int32_t cnt = (int32_t)min<int64_t>(kWave, a1 - c);
+            for (int32_t k = 0; k < cnt; ++k) s = s - bcast_lane(prod, k);
+        }
+        if (lane == 0) st_publish(w + (int64_t)i * B + b, s);
+    }
+}
+
+hipError_t launch_adj_solve_u(const PatDev& P, const AdjPat& T, const double* f_val,
+                              int32_t batch, const double* ybar, double* z, Ctl* ctl,
+                              uint64_t spin_limit, int32_t grid, hipStream_t s) {
+    if (P.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_solve_u, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, ybar, z, ctl,
+                       spin_limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_solve_l(const PatDev& P, const AdjPat& T, const double* f_val,
+                              int32_t batch, const double* z, double* w, Ctl* ctl,
+                              uint64_t spin_limit, int32_t grid, hipStream_t s) {
+    if (P.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_solve_l, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, z, w, ctl,
+                       spin_limit);
+    return hipGetLastError();
+}
+
+// fbar_ij = -(z_i y_j) on U~ (j >= i); fbar_ih = -(w_i x_h) below the diagonal
+__global__ void k_adj_fbar(PatDev P, int32_t B, const double* __restrict__ x,
+                           const double* __restrict__ y, const double* __restrict__ z,
+                           const double* __restrict__ w, double* __restrict__ fbar) {
+    const int64_t task = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (task >= (int64_t)P.n * B) return;
+    const int32_t i = (int32_t)(task / B);
+    const int32_t b = (int32_t)(task % B);
+    const int64_t rs = P.rpF[i], re = P.rpF[i + 1], d = P.diagF[i];
+    const double wi = w[(int64_t)i * B + b], zi = z[(int64_t)i * B + b];
+    for (int64_t q = rs; q < d; ++q) fbar[q * B + b] = -(wi * x[(int64_t)P.ciF[q] * B + b]);
+    for (int64_t q = d; q < re; ++q) fbar[q * B + b] = -(zi * y[(int64_t)P.ciF[q] * B + b]);
+}
+
+hipError_t launch_adj_fbar(const PatDev& P, int32_t batch, const double* x, const double* y,
+                           const double* z, const double* w, double* fbar, hipStream_t s) {
+    const int64_t tasks = (int64_t)P.n * batch;
+    if (tasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_fbar, dim3((unsigned)((tasks + 255) / 256)), dim3(256), 0, s, P, batch,
+                       x, y, z, w, fbar);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------------
+// reverse sweep of the elimination
+// ----------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_adj_numeric(PatDev P, AdjPat T, const double* __restrict__ F,
+                                                    int32_t B, const double* __restrict__ fin,
+                                                    double* G, double* lbar_out,
+                                                    double* __restrict__ abar, Ctl* ctl,
+                                                    uint64_t spin_limit) {
+    extern __shared__ double W[];
+    const int lane = lane_id();
+    const uint32_t ntask = (uint32_t)P.n * (uint32_t)B;
+    for (;;) {
+        const uint32_t t = wave_ticket(ctl);
+        if (t >= ntask) break;
+        const int32_t j = P.n - 1 - (int32_t)(t / (uint32_t)B);
+        const int32_t b = (int32_t)(t % (uint32_t)B);
+        const int64_t rs = P.rpF[j], re = P.rpF[j + 1], dj = P.diagF[j];
+        const int32_t len = (int32_t)(re - rs);
+        for (int32_t e = lane; e < len; e += kWave) W[e] = sanitize_input(fin[(rs + e) * B + b], ctl);
+        wave_sync();
+        const double ujj = F[dj * B + b];
+        // contributions of the rows i > j that pivot on j, in descending i
+        for (int64_t a = T.tpL[j + 1] - 1; a >= T.tpL[j]; --a) {
+            const int64_t s = T.tsL[a];  // slot of f_ij in row i
+            const double l = F[s * B + b];
+            const int64_t e0 = P.sptr[s], e1 = P.sptr[s + 1];
+            for (int64_t e = e0 + lane; e < e1; e += kWave) {
+                const int32_t q = P.sq[e];  // slot in row j
+                const int32_t p = P.sp[e];  // slot in row i
+                const double gv = wait_final(G + (int64_t)p * B + b, ctl, spin_limit);
+                W[q - rs] = W[q - rs] - gv * l;
+            }
+            if (lane == 0) {
+                const double lb = wait_final(lbar_out + s * B + b, ctl, spin_limit);
+                double tmp = lb * l;
+                tmp = tmp / ujj;
+                W[dj - rs] = W[dj - rs] - tmp;
+            }
+            wave_sync();
+        }
+        // own pivots, descending
+        for (int64_t s = dj - 1; s >= rs; --s) {
+            double lb = W[s - rs];
+            const int64_t e0 = P.sptr[s], e1 = P.sptr[s + 1];
+            for (int64_t c = e0; c < e1; c += kWave) {
+                const int64_t e = c + lane;
+                double prod = 0.0;
+                if (e < e1) prod = W[P.sp[e] - rs] * F[(int64_t)P.sq[e] * B + b];
+                const int32_t cnt = (int32_t)min<int64_t>(kWave, e1 - c);
+                for (int32_t k = 0; k < cnt; ++k) lb = lb - bcast_lane(prod, k);
+            }
+            if (lane == 0) {
+                st_publish(lbar_out + s * B + b, lb);
+                W[s - rs] = lb / F[(int64_t)P.lsd[s] * B + b];
+            }
+            wave_sync();
+        }
+        for (int64_t p = P.rpA[j] + lane; p < P.rpA[j + 1]; p += kWave)
+            abar[p * B + b] = W[P.a2f[p] - rs];
+        for (int32_t e = lane; e < len; e += kWave) st_publish(G + (rs + e) * B + b, W[e]);
+        wave_sync();
+    }
+}
+
+hipError_t launch_adj_numeric(const PatDev& P, const AdjPat& T, const double* f_val,
+                              int32_t batch, const double* fbar_in, double* G, double* lbar,
+                              double* abar, Ctl* ctl, uint64_t spin_limit, int32_t grid,
+                              int32_t max_row, hipStream_t s) {
+    if (P.n <= 0) return hipSuccess;
+    size_t lds = (size_t)std::max(max_row, 1) * sizeof(double);
+    hipLaunchKernelGGL(k_adj_numeric, dim3(grid), dim3(64), lds, s, P, T, f_val, batch, fbar_in, G,
+                       lbar, abar, ctl, spin_limit);
+    return hipGetLastError();
+}
+
+}  // namespace tpilu

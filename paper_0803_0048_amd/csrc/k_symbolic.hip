@@ -1,0 +1,602 @@
+// Phase I on gfx950: the level-of-fill pattern (Def. 2.3, Algorithm 1), the
+// map from A's entries to F's slots, and the per-row update schedule that
+// Phase II replays.
+//
+// Algorithm 1 merges rows in ascending order, so row j can only be built
+// after every row it pivots on.  On the GPU every row is built on its own,
+// from the graph of A, using the fill-path form of the same levels: level(i,j)
+// equals the least number of interior vertices of a path i -> j in the graph
+// of A (edge u -> v for every stored a_uv) whose interior vertices are all
+// smaller than min(i, j).  (Each term level(i,h) + level(h,j) + 1 of Def. 2.3
+// joins a path to h and a path from h through vertex h itself, which is
+// smaller than both ends.)  Algorithm 1 only minimises over entries that are
+// themselves kept, but a path through an entry of level > k is already too
+// long, so the two agree on every entry of level <= k.  Rows are therefore
+// independent (the observation Sec. 3.3 makes for k = 1 holds for every k in
+// this form) and one wavefront builds one row:
+//
+//   frontier_1 = { (v, v) : a_iv stored, v < i }      (vertex, largest interior)
+//   depth d = 1..k:  every (v, M) in frontier_d and stored a_vj with j > M
+//                    gives entry (i, j) a level candidate d;
+//                    frontier_{d+1} = { (w, max(M, w)) : a_vw stored, w < i },
+//                    keeping per w the smallest M, and dropping w when a
+//                    shorter walk already reached it with an interior maximum
+//                    no larger (that state can only lead to higher levels).
+//   level 0 for every stored a_ij.
+//
+// Per-row sets live in LDS hash maps; a row that does not fit is redone by
+// the same code with the maps in global memory sized for any row.
+#include "kernels.h"
+
+namespace tpilu {
+
+// ------------------------------------------------------------------------------------
+// validation
+// ------------------------------------------------------------------------------------
+__global__ void k_validate(int32_t n, int64_t nnz, const int64_t* __restrict__ rp,
+                           const int32_t* __restrict__ ci, uint32_t* status) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i > n) return;
+    uint32_t bad = 0;
+    if (i == 0 && rp[0] != 0) bad |= kValBadRowptr;
+    if (i == n) {
+        if (rp[n] != nnz) bad |= kValBadRowptr;
+    } else {
+        int64_t a = rp[i], b = rp[i + 1];
+        if (a > b || a < 0 || b > nnz) {
+            bad |= kValBadRowptr;
+        } else {
+            bool diag = false;
+            int32_t prev = -1;
+            for (int64_t p = a; p < b; ++p) {
+                int32_t c = ci[p];
+                if (c < 0 || c >= n) { bad |= kValBadCol; break; }
+                if (c <= prev) bad |= kValUnsorted;
+                if (c == i) diag = true;
+                prev = c;
+            }
+            if (!diag) bad |= kValNoDiag;
+        }
+    }
+    if (bad) atomicOr(status, bad);
+}
+
+hipError_t launch_validate(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* ci,
+                           uint32_t* status, hipStream_t s) {
+    int64_t threads = (int64_t)n + 1;
+    int blocks = (int)((threads + 255) / 256);
+    hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(256), 0, s, n, nnz, rp, ci, status);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// hash maps (open addressing, linear probing) keyed by a vertex, value = min
+// ------------------------------------------------------------------------------------
+constexpr int32_t kEmpty = -1;
+constexpr int32_t kBig = 0x7fffffff;
+
+__device__ __forceinline__ uint32_t hslot(int32_t key, uint32_t mask) {
+    uint32_t h = static_cast<uint32_t>(key) * 0x9E3779B1u;
+    h ^= h >> 15;
+    return h & mask;
+}
+
+// insert key (if absent) and lower its value to min(value, val); false if full
+__device__ __forceinline__ bool map_min(int32_t* keys, int32_t* vals, uint32_t mask, int32_t key,
+                                        int32_t val) {
+    uint32_t h = hslot(key, mask);
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        int32_t old = atomicCAS(&keys[h], kEmpty, key);
+        if (old == kEmpty || old == key) {
+            atomicMin(&vals[h], val);
+            return true;
+        }
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
+__device__ __forceinline__ int32_t map_get(const int32_t* keys, const int32_t* vals, uint32_t mask,
+                                           int32_t key) {
+    uint32_t h = hslot(key, mask);
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        int32_t k = keys[h];
+        if (k == key) return vals[h];
+        if (k == kEmpty) return kBig;
+        h = (h + 1) & mask;
+    }
+    return kBig;
+}
+
+struct SymWs {
+    int32_t *ek, *ev;  // endpoint map: column -> level
+    int32_t *bk, *bv;  // best interior maximum per vertex over all depths so far
+    int32_t *ck, *cv;  // candidates of the next frontier
+    int32_t *fv[2], *fm[2];  // frontier lists (vertex, interior maximum)
+    int32_t *ok, *ol;  // compacted row (column, level)
+    int32_t* ctr;      // [0],[1] frontier sizes, [2] overflow, [3] output size
+    uint32_t emask, fmask, fcap;
+};
+
+__device__ __forceinline__ void sym_row(int32_t i, const int64_t* __restrict__ rpA,
+                                        const int32_t* __restrict__ ciA, int32_t k, int mode,
+                                        int32_t* __restrict__ cnt, const int64_t* __restrict__ rpF,
+                                        int32_t* __restrict__ ciF, uint8_t* __restrict__ lvF,
+                                        int32_t* __restrict__ diagF, const SymWs& W) {
+    const int lane = lane_id();
+    for (uint32_t s = lane; s <= W.emask; s += kWave) { W.ek[s] = kEmpty; W.ev[s] = kBig; }
+    for (uint32_t s = lane; s <= W.fmask; s += kWave) {
+        W.bk[s] = kEmpty; W.bv[s] = kBig; W.ck[s] = kEmpty; W.cv[s] = kBig;
+    }
+    if (lane < 4) W.ctr[lane] = 0;
+    wave_sync();
+    const int64_t a0 = rpA[i], a1 = rpA[i + 1];
+    for (int64_t p = a0 + lane; p < a1; p += kWave) {
+        int32_t c = ciA[p];
+        bool ok = map_min(W.ek, W.ev, W.emask, c, 0);
+        if (c < i) {
+            int32_t slot = atomicAdd(&W.ctr[0], 1);
+            if (slot < (int32_t)W.fcap) { W.fv[0][slot] = c; W.fm[0][slot] = c; }
+            else ok = false;
+            ok = map_min(W.bk, W.bv, W.fmask, c, c) && ok;
+        }
+        if (!ok) W.ctr[2] = 1;
+    }
+    wave_sync();
+    int cur = 0;
+    for (int32_t d = 1; d <= k; ++d) {
+        const int32_t nf = uniform(min(W.ctr[cur], (int32_t)W.fcap));
+        if (nf == 0 || uniform(W.ctr[2])) break;
+        // endpoints reachable from this frontier in one more edge
+        for (int32_t f = lane; f < nf; f += kWave) {
+            int32_t v = W.fv[cur][f], M = W.fm[cur][f];
+            for (int64_t p = rpA[v]; p < rpA[v + 1]; ++p) {
+                int32_t j = ciA[p];
+                if (j > M && !map_min(W.ek, W.ev, W.emask, j, d)) W.ctr[2] = 1;
+            }
+        }
+        if (d == k) break;
+        // next frontier
+        for (int32_t f = lane; f < nf; f += kWave) {
+            int32_t v = W.fv[cur][f], M = W.fm[cur][f];
+            for (int64_t p = rpA[v]; p < rpA[v + 1]; ++p) {
+                int32_t w = ciA[p];
+                if (w < i && !map_min(W.ck, W.cv, W.fmask, w, max(M, w))) W.ctr[2] = 1;
+            }
+        }
+        const int nxt = cur ^ 1;
+        if (lane == 0) W.ctr[nxt] = 0;
+        wave_sync();
+        for (uint32_t s = lane; s <= W.fmask; s += kWave) {
+            int32_t w = W.ck[s];
+            if (w == kEmpty) continue;
+            int32_t c = W.cv[s];
+            W.ck[s] = kEmpty;
+            W.cv[s] = kBig;
+            if (c < map_get(W.bk, W.bv, W.fmask, w)) {
+                bool ok = map_min(W.bk, W.bv, W.fmask, w, c);
+                int32_t slot = atomicAdd(&W.ctr[nxt], 1);
+                if (slot < (int32_t)W.fcap) { W.fv[nxt][slot] = w; W.fm[nxt][slot] = c; }
+                else ok = false;
+                if (!ok) W.ctr[2] = 1;
+            }
+        }
+        wave_sync();
+        cur = nxt;
+    }
+    wave_sync();
+    if (uniform(W.ctr[2])) {
+        if (mode == 0 && lane == 0) cnt[i] = -1;
+        return;
+    }
+    // compact the row
+    for (uint32_t s = lane; s <= W.emask; s += kWave) {
+        int32_t c = W.ek[s];
+        if (c != kEmpty) {
+            int32_t idx = atomicAdd(&W.ctr[3], 1);
+            W.ok[idx] = c;
+            W.ol[idx] = W.ev[s];
+        }
+    }
+    wave_sync();
+    const int32_t len = uniform(W.ctr[3]);
+    if (mode == 0) {
+        if (lane == 0) cnt[i] = len;
+        return;
+    }
+    const int64_t base = rpF[i];
+    for (int32_t e = lane; e < len; e += kWave) {
+        int32_t key = W.ok[e];
+        int32_t rank = 0;
+        for (int32_t f = 0; f < len; ++f) rank += (W.ok[f] < key) ? 1 : 0;
+        ciF[base + rank] = key;
+        lvF[base + rank] = static_cast<uint8_t>(min(W.ol[e], 255));
+        if (key == i) diagF[i] = static_cast<int32_t>(base + rank);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_sym_rows_lds(int32_t n, const int64_t* __restrict__ rpA,
+                                                     const int32_t* __restrict__ ciA, int32_t k,
+                                                     const int32_t* __restrict__ row_list,
+                                                     int32_t n_rows, int mode,
+                                                     int32_t* __restrict__ cnt,
+                                                     const int64_t* __restrict__ rpF,
+                                                     int32_t* __restrict__ ciF,
+                                                     uint8_t* __restrict__ lvF,
+                                                     int32_t* __restrict__ diagF) {
+    __shared__ int32_t ek[kSymEndCap], ev[kSymEndCap];
+    __shared__ int32_t bk[kSymFrontCap], bv[kSymFrontCap], ck[kSymFrontCap], cv[kSymFrontCap];
+    __shared__ int32_t f0v[kSymFrontCap], f0m[kSymFrontCap], f1v[kSymFrontCap], f1m[kSymFrontCap];
+    __shared__ int32_t ok[kSymEndCap], ol[kSymEndCap];
+    __shared__ int32_t ctr[4];
+    SymWs W;
+    W.ek = ek; W.ev = ev; W.bk = bk; W.bv = bv; W.ck = ck; W.cv = cv;
+    W.fv[0] = f0v; W.fm[0] = f0m; W.fv[1] = f1v; W.fm[1] = f1m;
+    W.ok = ok; W.ol = ol; W.ctr = ctr;
+    W.emask = kSymEndCap - 1; W.fmask = kSymFrontCap - 1; W.fcap = kSymFrontCap;
+    for (int32_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
+        int32_t i = row_list ? row_list[r] : r;
+        if (mode == 1 && cnt[i] < 0) continue;  // built by the global path
+        sym_row(i, rpA, ciA, k, mode, cnt, rpF, ciF, lvF, diagF, W);
+        wave_sync();
+    }
+    (void)n;
+}
+
+__host__ __device__ size_t sym_global_scratch_ints(int32_t n, uint32_t gcap) {
+    // ek ev (gcap) bk bv ck cv (gcap) f0v f0m f1v f1m (n) ok ol (gcap) ctr (4, padded)
+    return (size_t)gcap * 8 + (size_t)n * 4 + 64;
+}
+
+__global__ __launch_bounds__(64) void k_sym_rows_global(int32_t n, const int64_t* __restrict__ rpA,
+                                                        const int32_t* __restrict__ ciA, int32_t k,
+                                                        const int32_t* __restrict__ row_list,
+                                                        int32_t n_rows, int mode,
+                                                        int32_t* __restrict__ cnt,
+                                                        const int64_t* __restrict__ rpF,
+                                                        int32_t* __restrict__ ciF,
+                                                        uint8_t* __restrict__ lvF,
+                                                        int32_t* __restrict__ diagF,
+                                                        int32_t* gscratch, uint32_t gcap) {
+    int32_t* base = gscratch + (size_t)blockIdx.x * sym_global_scratch_ints(n, gcap);
+    SymWs W;
+    W.ek = base; W.ev = base + gcap;
+    W.bk = base + 2 * (size_t)gcap; W.bv = base + 3 * (size_t)gcap;
+    W.ck = base + 4 * (size_t)gcap; W.cv = base + 5 * (size_t)gcap;
+    W.ok = base + 6 * (size_t)gcap; W.ol = base + 7 * (size_t)gcap;
+    int32_t* fl = base + 8 * (size_t)gcap;
+    W.fv[0] = fl; W.fm[0] = fl + n; W.fv[1] = fl + 2 * (size_t)n; W.fm[1] = fl + 3 * (size_t)n;
+    W.ctr = fl + 4 * (size_t)n;
+    W.emask = gcap - 1; W.fmask = gcap - 1; W.fcap = (uint32_t)n;
+    for (int32_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
+        int32_t i = row_list ? row_list[r] : r;
+        sym_row(i, rpA, ciA, k, mode, cnt, rpF, ciF, lvF, diagF, W);
+        wave_sync();
+    }
+}
+
+hipError_t launch_sym_rows(bool global, int32_t n, const int64_t* rpA, const int32_t* ciA,
+                           int32_t k, const int32_t* row_list, int32_t n_rows, int mode,
+                           int32_t* cnt, const int64_t* rpF, int32_t* ciF, uint8_t* lvF,
+                           int32_t* diagF, int32_t* gscratch, uint32_t gcap, int32_t grid,
+                           hipStream_t s) {
+    if (n_rows <= 0) return hipSuccess;
+    if (global) {
+        hipLaunchKernelGGL(k_sym_rows_global, dim3(grid), dim3(64), 0, s, n, rpA, ciA, k,
+                           row_list, n_rows, mode, cnt, rpF, ciF, lvF, diagF, gscratch, gcap);
+    } else {
+        hipLaunchKernelGGL(k_sym_rows_lds, dim3(grid), dim3(64), 0, s, n, rpA, ciA, k, row_list,
+                           n_rows, mode, cnt, rpF, ciF, lvF, diagF);
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_collect_overflow(int32_t n, const int32_t* __restrict__ cnt, int32_t* row_list,
+                                   int32_t* n_over) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && cnt[i] < 0) row_list[atomicAdd(n_over, 1)] = i;
+}
+
+hipError_t launch_collect_overflow(int32_t n, const int32_t* cnt, int32_t* row_list,
+                                   int32_t* n_over, hipStream_t s) {
+    hipLaunchKernelGGL(k_collect_overflow, dim3((n + 255) / 256), dim3(256), 0, s, n, cnt,
+                       row_list, n_over);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// exclusive scan int32 -> int64 (three passes, 1024 elements per block)
+// ------------------------------------------------------------------------------------
+constexpr int kScanTile = 1024;
+
+size_t scan_tmp_elems(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const int32_t* __restrict__ in, int64_t n,
+                                                     int64_t* __restrict__ bsum) {
+    __shared__ int64_t sh[256];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t acc = 0;
+    for (int e = threadIdx.x; e < kScanTile; e += 256) {
+        int64_t idx = base + e;
+        if (idx < n) acc += in[idx];
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(int64_t* bsum, int64_t nb) {
+    // exclusive scan of nb block sums in place; bsum[nb] = total
+    __shared__ int64_t sh[1024];
+    int64_t per = (nb + 1023) / 1024;
+    int64_t lo = threadIdx.x * per, hi = min(nb, lo + per);
+    int64_t acc = 0;
+    for (int64_t e = lo; e < hi; ++e) acc += bsum[e];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 1; w < 1024; w <<= 1) {
+        int64_t v = (int)threadIdx.x >= w ? sh[threadIdx.x - w] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = threadIdx.x ? sh[threadIdx.x - 1] : 0;
+    for (int64_t e = lo; e < hi; ++e) {
+        int64_t v = bsum[e];
+        bsum[e] = run;
+        run += v;
+    }
+    if (threadIdx.x == 1023) bsum[nb] = sh[1023];
+}
+
+__global__ __launch_bounds__(256) void k_scan_final(const int32_t* __restrict__ in, int64_t n,
+                                                    const int64_t* __restrict__ boff,
+                                                    int64_t* __restrict__ out, int64_t nb) {
+    __shared__ int64_t sh[256];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int32_t v[4];
+    int64_t loc = 0;
+    for (int e = 0; e < 4; ++e) {
+        int64_t idx = base + threadIdx.x * 4 + e;
+        v[e] = idx < n ? in[idx] : 0;
+        loc += v[e];
+    }
+    sh[threadIdx.x] = loc;
+    __syncthreads();
+    for (int w = 1; w < 256; w <<= 1) {
+        int64_t t = (int)threadIdx.x >= w ? sh[threadIdx.x - w] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int64_t run = boff[blockIdx.x] + (threadIdx.x ? sh[threadIdx.x - 1] : 0);
+    for (int e = 0; e < 4; ++e) {
+        int64_t idx = base + threadIdx.x * 4 + e;
+        if (idx < n) out[idx] = run;
+        run += v[e];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = boff[nb];
+}
+
+hipError_t launch_scan(const int32_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s) {
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, tmp, (int64_t)0);
+        hipLaunchKernelGGL(k_scan_final, dim3(1), dim3(256), 0, s, in, n, tmp, out, (int64_t)0);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, tmp, nb);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(256), 0, s, in, n, tmp, out, nb);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// A -> F slot map: merge of two sorted rows, one thread per row
+// ------------------------------------------------------------------------------------
+__global__ void k_a2f(int32_t n, const int64_t* __restrict__ rpA, const int32_t* __restrict__ ciA,
+                      const int64_t* __restrict__ rpF, const int32_t* __restrict__ ciF,
+                      int32_t* __restrict__ a2f, uint32_t* status) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t q = rpF[i], qe = rpF[i + 1];
+    for (int64_t p = rpA[i]; p < rpA[i + 1]; ++p) {
+        int32_t c = ciA[p];
+        while (q < qe && ciF[q] < c) ++q;
+        if (q < qe && ciF[q] == c) {
+            a2f[p] = static_cast<int32_t>(q);
+        } else {
+            a2f[p] = -1;
+            atomicOr(status, kValBadCol);
+        }
+    }
+}
+
+hipError_t launch_a2f(int32_t n, const int64_t* rpA, const int32_t* ciA, const int64_t* rpF,
+                      const int32_t* ciF, int32_t* a2f, uint32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_a2f, dim3((n + 255) / 256), dim3(256), 0, s, n, rpA, ciA, rpF, ciF, a2f,
+                       status);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// Update schedule.  For every pivot slot s = (j, h) of F (h < j), the pairs
+// (q, p) with q the slot of f_ht in row h and p the slot of f_jt in row j,
+// for every t > h stored in both rows, in ascending t.  Phase II replays them
+// (f_jt <- f_jt - f_jh * f_ht); their number is the number of updates.
+// One wavefront per row j; row j's columns are staged in LDS and every
+// candidate t of the pivot row is binary-searched there.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restrict__ rpF,
+                                              const int32_t* __restrict__ ciF,
+                                              const int32_t* __restrict__ diagF, int mode,
+                                              int32_t* __restrict__ scount, int32_t* __restrict__ lsd,
+                                              const int64_t* __restrict__ sptr,
+                                              int32_t* __restrict__ sq, int32_t* __restrict__ sp) {
+    extern __shared__ int32_t colsj[];
+    const int lane = lane_id();
+    for (int32_t j = blockIdx.x; j < n; j += gridDim.x) {
+        const int64_t rs = rpF[j], re = rpF[j + 1];
+        const int32_t len = static_cast<int32_t>(re - rs);
+        const int64_t dj = diagF[j];
+        for (int32_t e = lane; e < len; e += kWave) colsj[e] = ciF[rs + e];
+        if (mode == 0)
+            for (int64_t s = dj + lane; s < re; s += kWave) scount[s] = 0;
+        wave_sync();
+        for (int64_t s = rs; s < dj; ++s) {
+            const int32_t h = ciF[s];
+            const int64_t dh = diagF[h];
+            const int64_t he = rpF[h + 1];
+            if (mode == 0 && lane == 0) lsd[s] = static_cast<int32_t>(dh);
+            int32_t found = 0;
+            int64_t out = mode == 1 ? sptr[s] : 0;
+            for (int64_t q0 = dh + 1; q0 < he; q0 += kWave) {
+                const int64_t q = q0 + lane;
+                int32_t pos = -1;
+                if (q < he) {
+                    const int32_t t = ciF[q];
+                    int32_t lo = static_cast<int32_t>(s - rs) + 1, hi = len - 1;
+                    while (lo <= hi) {
+                        int32_t mid = (lo + hi) >> 1;
+                        int32_t c = colsj[mid];
+                        if (c == t) { pos = mid; break; }
+                        if (c < t) lo = mid + 1;
+                        else hi = mid - 1;
+                    }
+                }
+                const uint64_t m = __ballot(pos >= 0);
+                if (mode == 1 && pos >= 0) {
+                    const int32_t rank = __popcll(m & ((1ull << lane) - 1ull));
+                    sq[out + found + rank] = static_cast<int32_t>(q);
+                    sp[out + found + rank] = static_cast<int32_t>(rs + pos);
+                }
+                found += __popcll(m);
+            }
+            if (mode == 0 && lane == 0) scount[s] = found;
+        }
+        wave_sync();
+    }
+}
+
+hipError_t launch_sched(int32_t n, const int64_t* rpF, const int32_t* ciF, const int32_t* diagF,
+                        int mode, int32_t* scount, int32_t* lsd, const int64_t* sptr,
+                        int32_t* sq, int32_t* sp, int32_t max_row, hipStream_t s) {
+    size_t lds = (size_t)max(max_row, 1) * sizeof(int32_t);
+    int grid = min(n, 65536);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sched, dim3(grid), dim3(64), lds, s, n, rpF, ciF, diagF, mode, scount,
+                       lsd, sptr, sq, sp);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// pattern statistics
+// ------------------------------------------------------------------------------------
+__global__ void k_stats(int32_t n, const int64_t* __restrict__ rpF,
+                        const int32_t* __restrict__ diagF, PatStats* st) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t rs = rpF[i], re = rpF[i + 1], d = diagF[i];
+    atomicMax(&st->max_row, static_cast<int32_t>(re - rs));
+    atomicMax(&st->max_lrow, static_cast<int32_t>(d - rs));
+    atomicMax(&st->max_upart, static_cast<int32_t>(re - d - 1));
+    atomicAdd(&st->nnz_l, static_cast<unsigned long long>(d - rs));
+}
+
+hipError_t launch_stats(int32_t n, const int64_t* rpF, const int32_t* diagF, PatStats* st,
+                        hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stats, dim3((n + 255) / 256), dim3(256), 0, s, n, rpF, diagF, st);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// dependency depth (informational): depth_i = 1 + max depth_h over the rows h
+// row i needs (L part ascending, or U part descending); -1 = not yet known
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int32_t wait_depth(const int32_t* p, Ctl* ctl, uint64_t spin_limit) {
+    int32_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    uint32_t n = 0;
+    uint64_t t0 = 0;
+    while (v < 0) {
+        v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v >= 0) break;
+        if ((n & 31u) == 0u) {
+            if (ld_u32_coherent(&ctl->abort) != 0u) return 0;
+            const uint64_t now = wall_clock64();
+            if (n == 0) {
+                t0 = now;
+            } else if (now - t0 > spin_limit) {
+                atomicOr(&ctl->status, kStTimeout);
+                __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return 0;
+            }
+        }
+        ++n;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(64) void k_depth(int upper, int32_t n, const int64_t* __restrict__ rpF,
+                                              const int32_t* __restrict__ ciF,
+                                              const int32_t* __restrict__ diagF, int32_t* depth,
+                                              Ctl* ctl, uint64_t spin_limit) {
+    const int lane = lane_id();
+    for (;;) {
+        const uint32_t t = wave_ticket(ctl);
+        if (t >= (uint32_t)n) break;
+        const int32_t i = upper ? n - 1 - (int32_t)t : (int32_t)t;
+        int64_t a, b;
+        if (upper) { a = diagF[i] + 1; b = rpF[i + 1]; }
+        else { a = rpF[i]; b = diagF[i]; }
+        int32_t best = 0;
+        for (int64_t q = a + lane; q < b; q += kWave) best = max(best, wait_depth(depth + ciF[q], ctl, spin_limit));
+        for (int off = 32; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off));
+        if (lane == 0)
+            __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+hipError_t launch_depth(bool upper, int32_t n, const int64_t* rpF, const int32_t* ciF,
+                        const int32_t* diagF, int32_t* depth, Ctl* ctl, uint64_t spin_limit,
+                        int32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_depth, dim3(grid), dim3(64), 0, s, upper ? 1 : 0, n, rpF, ciF, diagF, depth,
+                       ctl, spin_limit);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+__global__ void k_max_i32(const int32_t* __restrict__ p, int64_t n, int32_t* out) {
+    int32_t m = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, p[i]);
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    if (lane_id() == 0) atomicMax(out, m);
+}
+
+hipError_t launch_max_i32(const int32_t* p, int64_t n, int32_t* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_max_i32, dim3(blocks), dim3(256), 0, s, p, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace tpilu

@@ -1,0 +1,161 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dev_common.h"
+
+namespace tpilu {
+
+// ---- symbolic phase --------------------------------------------------------
+// status bits written by k_validate
+constexpr uint32_t kValBadRowptr = 1u, kValBadCol = 2u, kValUnsorted = 4u, kValNoDiag = 8u;
+
+hipError_t launch_validate(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* ci,
+                           uint32_t* status, hipStream_t s);
+
+// LDS capacities of the fast symbolic path
+constexpr int kSymEndCap = 1024;   // endpoint map (row of F being built)
+constexpr int kSymFrontCap = 512;  // frontier maps and lists
+
+// Count (mode 0) or fill (mode 1) the level-<=k pattern of rows [0, n) (or of
+// the rows in row_list when non-null).  Fast path: maps in LDS; a row that
+// does not fit gets cnt = -1.  Global path: maps in `gscratch`.
+hipError_t launch_sym_rows(bool global, int32_t n, const int64_t* rpA, const int32_t* ciA,
+                           int32_t k, const int32_t* row_list, int32_t n_rows, int mode,
+                           int32_t* cnt, const int64_t* rpF, int32_t* ciF, uint8_t* lvF,
+                           int32_t* diagF, int32_t* gscratch, uint32_t gcap, int32_t grid,
+                           hipStream_t s);
+__host__ __device__ size_t sym_global_scratch_ints(int32_t n, uint32_t gcap);  // per block
+
+// rows with cnt < 0 -> row_list, *n_over
+hipError_t launch_collect_overflow(int32_t n, const int32_t* cnt, int32_t* row_list,
+                                   int32_t* n_over, hipStream_t s);
+
+// exclusive scan of int32 counts into int64 offsets out[0..n], out[n] = total
+hipError_t launch_scan(const int32_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
+size_t scan_tmp_elems(int64_t n);
+
+hipError_t launch_a2f(int32_t n, const int64_t* rpA, const int32_t* ciA, const int64_t* rpF,
+                      const int32_t* ciF, int32_t* a2f, uint32_t* status, hipStream_t s);
+
+// update schedule: mode 0 counts matches per L slot (and writes lsd = diag
+// slot of the pivot), mode 1 writes the (q, p) pairs
+hipError_t launch_sched(int32_t n, const int64_t* rpF, const int32_t* ciF, const int32_t* diagF,
+                        int mode, int32_t* scount, int32_t* lsd, const int64_t* sptr,
+                        int32_t* sq, int32_t* sp, int32_t max_row, hipStream_t s);
+
+struct PatStats {
+    unsigned long long nnz_l;
+    int32_t max_row;
+    int32_t max_lrow;
+    int32_t max_upart;
+    int32_t pad;
+};
+hipError_t launch_stats(int32_t n, const int64_t* rpF, const int32_t* diagF, PatStats* st,
+                        hipStream_t s);
+
+// dependency depth of every row (forward over L, backward over U); depth
+// arrays must be pre-filled with -1 by launch_fill_i32
+hipError_t launch_depth(bool upper, int32_t n, const int64_t* rpF, const int32_t* ciF,
+                        const int32_t* diagF, int32_t* depth, Ctl* ctl, uint64_t spin_limit,
+                        int32_t grid, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_max_i32(const int32_t* p, int64_t n, int32_t* out, hipStream_t s);
+
+// ---- numeric phase -------------------------------------------------------------
+struct PatDev {
+    int32_t n;
+    int32_t nnz_a;
+    int32_t nnz_f;
+    const int64_t* rpA;
+    const int32_t* ciA;
+    const int64_t* rpF;
+    const int32_t* ciF;
+    const int32_t* diagF;
+    const int32_t* a2f;
+    const int32_t* lsd;   // per F slot (L part): diag slot of the pivot
+    const int64_t* sptr;  // per F slot: start of its update pairs; [nnz_f + 1]
+    const int32_t* sq;    // pair: slot of f_ht in row h
+    const int32_t* sp;    // pair: slot of f_jt in row j
+};
+
+// fill `n` doubles with kPending; thread 0 also resets ctl->ticket (and, if
+// reset_status, the sticky status words)
+hipError_t launch_fill_pending(double* p, int64_t n, Ctl* ctl, bool reset_status, hipStream_t s);
+
+hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, double* f_val,
+                          Ctl* ctl, uint64_t spin_limit, int64_t skip_row, int32_t grid,
+                          int32_t max_row, hipStream_t s);
+int numeric_grid(int32_t batch, int32_t max_row, int num_cu);
+
+// ---- triangular solves -------------------------------------------------------------
+hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, const double* b,
+                          double* x, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s);
+hipError_t launch_backward(const PatDev& P, const double* f_val, int32_t batch, const double* x,
+                           double* y, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s);
+int solve_grid(int32_t batch, int num_cu);
+
+// ---- Krylov building blocks ---------------------------------------------------
+constexpr int kDotLanes = 16384;  // fixed shape of every inner product
+constexpr int kDotBlocks = 64;
+constexpr int kDotThreads = 256;
+
+hipError_t launch_spmv(int32_t n, const int64_t* rp, const int32_t* ci, const double* v,
+                       const double* x, const double* b_minus, double* y, hipStream_t s);
+hipError_t launch_dot_partial(int64_t n, const double* x, const double* y, double* partial,
+                              hipStream_t s);
+hipError_t launch_dot_final(const double* partial, double* out, int sqrt_it, hipStream_t s);
+
+struct GmresDev;  // defined in the Krylov unit
+hipError_t launch_gm_axpy_h(int64_t n, const double* partial, double* hslot, double* w,
+                            const double* v, hipStream_t s);
+hipError_t launch_gm_norm_scale(int64_t n, const double* partial, double* hslot, const double* w,
+                                double* vnext, hipStream_t s);
+hipError_t launch_gm_start(int64_t n, const double* partial, double* beta_slot, double* g0,
+                           const double* r, double* v0, hipStream_t s);
+hipError_t launch_gm_givens(double* H, double* cs, double* sn, double* g, int32_t m, int32_t j,
+                            double tol, int32_t* iters, int32_t maxit, double* hist,
+                            int32_t* stop, hipStream_t s);
+hipError_t launch_gm_backsub(const double* H, const double* g, double* yv, int32_t m, int32_t jj,
+                             hipStream_t s);
+hipError_t launch_gm_combine(int64_t n, const double* V, const double* yv, int32_t jj, double* u,
+                             hipStream_t s);
+hipError_t launch_axpy1(int64_t n, double* x, const double* z, hipStream_t s);
+hipError_t launch_sub(int64_t n, const double* b, const double* ax, double* r, hipStream_t s);
+
+// ---- adjoint -------------------------------------------------------------------
+struct AdjPat {
+    const int64_t* tpL;   // CSC of the strict lower part: column c -> entries
+    const int32_t* tsL;   //   F slots of column c's entries, rows ascending
+    const int32_t* trL;   //   and their rows
+    const int64_t* tpU;   // CSC of the strict upper part
+    const int32_t* tsU;
+    const int32_t* trU;
+};
+hipError_t launch_transpose_count(int32_t n, const int64_t* rpF, const int32_t* ciF,
+                                  const int32_t* diagF, int32_t* cntL, int32_t* cntU,
+                                  hipStream_t s);
+hipError_t launch_transpose_fill(int32_t n, const int64_t* rpF, const int32_t* ciF,
+                                 const int32_t* diagF, const int64_t* tpL, int32_t* tsL,
+                                 int32_t* trL, const int64_t* tpU, int32_t* tsU, int32_t* trU,
+                                 int32_t* curL, int32_t* curU, hipStream_t s);
+hipError_t launch_sort_columns(int32_t n, const int64_t* tp, int32_t* ts, int32_t* tr,
+                               hipStream_t s);
+
+hipError_t launch_adj_solve_u(const PatDev& P, const AdjPat& T, const double* f_val,
+                              int32_t batch, const double* ybar, double* z, Ctl* ctl,
+                              uint64_t spin_limit, int32_t grid, hipStream_t s);
+hipError_t launch_adj_solve_l(const PatDev& P, const AdjPat& T, const double* f_val,
+                              int32_t batch, const double* z, double* w, Ctl* ctl,
+                              uint64_t spin_limit, int32_t grid, hipStream_t s);
+hipError_t launch_adj_fbar(const PatDev& P, int32_t batch, const double* x, const double* y,
+                           const double* z, const double* w, double* fbar, hipStream_t s);
+hipError_t launch_adj_numeric(const PatDev& P, const AdjPat& T, const double* f_val,
+                              int32_t batch, const double* fbar_in, double* G, double* lbar,
+                              double* abar, Ctl* ctl, uint64_t spin_limit, int32_t grid,
+                              int32_t max_row, hipStream_t s);
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+
+}  // namespace tpilu

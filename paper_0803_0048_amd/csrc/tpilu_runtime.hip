@@ -1,0 +1,875 @@
+// Host runtime of the gfx950 ILU(k) library: contexts, pattern handles, the
+// orchestration of the kernels behind every C entry point, the GMRES driver
+// and batched graph capture.  Everything here is host code; every step of
+// the numeric path runs in the kernels of the k_*.hip units.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tpilu.h"
+#include "kernels.h"
+
+using namespace tpilu;
+
+struct tpilu_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    tpilu_alloc_fn alloc = nullptr;
+    tpilu_free_fn free_fn = nullptr;
+    void* user = nullptr;
+    int num_cu = 256;
+    uint64_t spin_limit = 1000000000ull;  // wait budget in wall-clock ticks (set from the clock rate)
+    uint64_t ticks_per_us = 100;
+    int64_t skip_row = -1;
+    int32_t grid_override = 0;
+    std::string err;
+};
+
+namespace {
+
+constexpr uint64_t kDefaultWaitUs = 10000000ull;  // 10 s per dependency wait
+
+// TPILU_TRACE=1 in the environment prints every host-side step to stderr.
+bool trace_on() {
+    static const bool on = [] {
+        const char* v = std::getenv("TPILU_TRACE");
+        return v && *v && *v != '0';
+    }();
+    return on;
+}
+void trace(const char* what, int64_t a = -1, int64_t b = -1) {
+    if (!trace_on()) return;
+    std::fprintf(stderr, "[tpilu] %s %lld %lld\n", what, (long long)a, (long long)b);
+    std::fflush(stderr);
+}
+
+struct Alloc {
+    tpilu_alloc_fn alloc = nullptr;
+    tpilu_free_fn free_fn = nullptr;
+    void* user = nullptr;
+    void* get(size_t bytes) const {
+        if (bytes == 0) bytes = 8;
+        if (alloc) return alloc(bytes, user);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        return p;
+    }
+    void put(void* p) const {
+        if (!p) return;
+        if (free_fn) free_fn(p, user);
+        else (void)hipFree(p);
+    }
+};
+
+// device buffer owned by a handle
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct tpilu_pattern_s {
+    Alloc al;
+    int device = 0;
+    int64_t n = 0, nnz_a = 0, nnz_f = 0, n_updates = 0;
+    int32_t k = 0;
+    PatStats st{};
+    int32_t depth_l = 0, depth_u = 0, overflow_rows = 0;
+    std::vector<DBuf> owned;
+    // device arrays
+    int64_t* rpA = nullptr;
+    int32_t* ciA = nullptr;
+    int64_t* rpF = nullptr;
+    int32_t* ciF = nullptr;
+    uint8_t* lvF = nullptr;
+    int32_t* diagF = nullptr;
+    int32_t* a2f = nullptr;
+    int32_t* lsd = nullptr;
+    int64_t* sptr = nullptr;
+    int32_t* sq = nullptr;
+    int32_t* sp = nullptr;
+    Ctl* ctl = nullptr;
+    // adjoint transposes (built on first use)
+    bool have_t = false;
+    int64_t *tpL = nullptr, *tpU = nullptr;
+    int32_t *tsL = nullptr, *trL = nullptr, *tsU = nullptr, *trU = nullptr;
+    // growable workspaces
+    DBuf ws_x, ws_z, ws_fin, ws_lbar, ws_gm;
+
+    void* take(size_t bytes) {
+        void* p = al.get(bytes);
+        if (p) owned.push_back(DBuf{p, bytes});
+        return p;
+    }
+    double* grow(DBuf& b, size_t bytes) {
+        if (b.bytes >= bytes && b.p) return static_cast<double*>(b.p);
+        al.put(b.p);
+        b.p = al.get(bytes);
+        b.bytes = b.p ? bytes : 0;
+        return static_cast<double*>(b.p);
+    }
+    PatDev dev() const {
+        PatDev d;
+        d.n = (int32_t)n;
+        d.nnz_a = (int32_t)nnz_a;
+        d.nnz_f = (int32_t)nnz_f;
+        d.rpA = rpA; d.ciA = ciA; d.rpF = rpF; d.ciF = ciF; d.diagF = diagF; d.a2f = a2f;
+        d.lsd = lsd; d.sptr = sptr; d.sq = sq; d.sp = sp;
+        return d;
+    }
+    ~tpilu_pattern_s() {
+        for (auto& b : owned) al.put(b.p);
+        al.put(ws_x.p); al.put(ws_z.p); al.put(ws_fin.p); al.put(ws_lbar.p); al.put(ws_gm.p);
+    }
+};
+
+struct tpilu_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+namespace {
+
+tpilu_status fail(tpilu_ctx ctx, tpilu_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+#define HIPCHK(ctx, call)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail((ctx), TPILU_E_DEVICE,                                                \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                   \
+    } while (0)
+
+Alloc ctx_alloc(tpilu_ctx c) {
+    Alloc a;
+    a.alloc = c->alloc;
+    a.free_fn = c->free_fn;
+    a.user = c->user;
+    return a;
+}
+
+uint32_t next_pow2(uint64_t v) {
+    uint64_t p = 1;
+    while (p < v) p <<= 1;
+    return (uint32_t)std::min<uint64_t>(p, 1ull << 31);
+}
+
+// read the control block after the stream drained and turn it into a status
+tpilu_status read_ctl(tpilu_ctx ctx, tpilu_pattern pat, int64_t* bad_row, bool clear) {
+    Ctl h{};
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(&h, pat->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    if (clear) {
+        Ctl z{};
+        z.bad_row = ~0ull;
+        HIPCHK(ctx, hipMemcpy(pat->ctl, &z, sizeof(Ctl), hipMemcpyHostToDevice));
+    }
+    const int64_t bad = h.bad_row == ~0ull ? -1 : (int64_t)h.bad_row;
+    if (bad_row) *bad_row = bad;
+    if (h.status & kStTimeout)
+        return fail(ctx, TPILU_E_TIMEOUT, "a dependency wait ran out (watchdog)");
+    if (h.status & kStReservedNaN)
+        return fail(ctx, TPILU_E_INVAL, "input holds the reserved NaN bit pattern 0x7FF4A5A5A5A5A5A5");
+    if (bad >= 0) return fail(ctx, TPILU_E_ZEROPIVOT, "zero pivot in row " + std::to_string(bad));
+    return TPILU_OK;
+}
+
+tpilu_status check_common(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (!pat) return fail(ctx, TPILU_E_INVAL, "null pattern");
+    if (batch < 1) return fail(ctx, TPILU_E_INVAL, "batch must be >= 1");
+    if ((int64_t)pat->n * batch >= (1ll << 31) || pat->nnz_f * (int64_t)batch >= (1ll << 40))
+        return fail(ctx, TPILU_E_INVAL, "batch too large");
+    return TPILU_OK;
+}
+
+constexpr size_t kBatchLdsLimit = 64 * 1024;
+size_t batch_numeric_lds(int32_t max_row) {
+    return (size_t)std::max(max_row, 1) * 8 * 64 + 24 * 1024;
+}
+
+tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val, int32_t batch,
+                             double* f_val) {
+    if (batch > 1 && batch_numeric_lds(pat->st.max_row) > kBatchLdsLimit)
+        return fail(ctx, TPILU_E_INVAL,
+                    "batched factorization supports rows of at most 80 entries");
+    if (batch == 1 && (size_t)pat->st.max_row * 8 + 12 * 1024 > kBatchLdsLimit)
+        return fail(ctx, TPILU_E_INVAL, "numeric factorization supports rows of at most 6600 entries");
+    HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, pat->ctl, true, ctx->stream));
+    const int grid = ctx->grid_override ? ctx->grid_override : numeric_grid(batch, pat->st.max_row, ctx->num_cu);
+    HIPCHK(ctx, launch_numeric(pat->dev(), a_val, batch, f_val, pat->ctl, ctx->spin_limit,
+                               ctx->skip_row, grid, pat->st.max_row, ctx->stream));
+    return TPILU_OK;
+}
+
+tpilu_status enqueue_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val, int32_t batch,
+                           const double* b, double* y, double* x, bool reset) {
+    const int grid = ctx->grid_override ? ctx->grid_override : solve_grid(batch, ctx->num_cu);
+    HIPCHK(ctx, launch_fill_pending(x, pat->n * batch, pat->ctl, reset, ctx->stream));
+    HIPCHK(ctx, launch_forward(pat->dev(), f_val, batch, b, x, pat->ctl, ctx->spin_limit, grid,
+                               ctx->stream));
+    HIPCHK(ctx, launch_fill_pending(y, pat->n * batch, pat->ctl, false, ctx->stream));
+    HIPCHK(ctx, launch_backward(pat->dev(), f_val, batch, x, y, pat->ctl, ctx->spin_limit, grid,
+                                ctx->stream));
+    return TPILU_OK;
+}
+
+tpilu_status build_transposes(tpilu_ctx ctx, tpilu_pattern pat) {
+    if (pat->have_t) return TPILU_OK;
+    const int32_t n = (int32_t)pat->n;
+    hipStream_t s = ctx->stream;
+    int32_t* cnt = (int32_t*)pat->take(sizeof(int32_t) * (size_t)(4 * n + 4));
+    int64_t* tmp = (int64_t*)pat->take(sizeof(int64_t) * scan_tmp_elems(n));
+    pat->tpL = (int64_t*)pat->take(sizeof(int64_t) * (size_t)(n + 1));
+    pat->tpU = (int64_t*)pat->take(sizeof(int64_t) * (size_t)(n + 1));
+    if (!cnt || !tmp || !pat->tpL || !pat->tpU) return fail(ctx, TPILU_E_NOMEM, "transpose");
+    int32_t *cntL = cnt, *cntU = cnt + n, *curL = cnt + 2 * n, *curU = cnt + 3 * n;
+    HIPCHK(ctx, launch_fill_i32(cnt, 4 * (int64_t)n, 0, s));
+    HIPCHK(ctx, launch_transpose_count(n, pat->rpF, pat->ciF, pat->diagF, cntL, cntU, s));
+    HIPCHK(ctx, launch_scan(cntL, n, pat->tpL, tmp, s));
+    HIPCHK(ctx, launch_scan(cntU, n, pat->tpU, tmp, s));
+    const int64_t nl = (int64_t)pat->st.nnz_l;
+    const int64_t nu = pat->nnz_f - nl - pat->n;
+    pat->tsL = (int32_t*)pat->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nl, 1));
+    pat->trL = (int32_t*)pat->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nl, 1));
+    pat->tsU = (int32_t*)pat->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nu, 1));
+    pat->trU = (int32_t*)pat->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nu, 1));
+    if (!pat->tsL || !pat->trL || !pat->tsU || !pat->trU) return fail(ctx, TPILU_E_NOMEM, "transpose");
+    HIPCHK(ctx, launch_transpose_fill(n, pat->rpF, pat->ciF, pat->diagF, pat->tpL, pat->tsL, pat->trL,
+                                      pat->tpU, pat->tsU, pat->trU, curL, curU, s));
+    HIPCHK(ctx, launch_sort_columns(n, pat->tpL, pat->tsL, pat->trL, s));
+    HIPCHK(ctx, launch_sort_columns(n, pat->tpU, pat->tsU, pat->trU, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    pat->have_t = true;
+    return TPILU_OK;
+}
+
+}  // namespace
+
+// =====================================================================================
+// context
+// =====================================================================================
+extern "C" TPILU_API tpilu_status tpilu_ctx_create(int device, void* hip_stream, tpilu_alloc_fn alloc,
+                                                   tpilu_free_fn free_fn, void* user, tpilu_ctx* out) {
+    if (!out) return TPILU_E_INVAL;
+    *out = nullptr;
+    if ((alloc == nullptr) != (free_fn == nullptr)) return TPILU_E_INVAL;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return TPILU_E_DEVICE;
+    tpilu_ctx c = new (std::nothrow) tpilu_ctx_s;
+    if (!c) return TPILU_E_NOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->alloc = alloc;
+    c->free_fn = free_fn;
+    c->user = user;
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+        c->num_cu = cu;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+        c->ticks_per_us = std::max<uint64_t>(1, (uint64_t)khz / 1000);
+    c->spin_limit = kDefaultWaitUs * c->ticks_per_us;
+    *out = c;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_stream(tpilu_ctx ctx, void* hip_stream) {
+    if (!ctx) return TPILU_E_INVAL;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API void tpilu_ctx_destroy(tpilu_ctx ctx) { delete ctx; }
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_watchdog(tpilu_ctx ctx, uint32_t timeout_us,
+                                                         int64_t skip_publish_row) {
+    if (!ctx) return TPILU_E_INVAL;
+    ctx->spin_limit = (timeout_us ? (uint64_t)timeout_us : kDefaultWaitUs) * ctx->ticks_per_us;
+    ctx->skip_row = skip_publish_row;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t waves) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (waves < 0) return fail(ctx, TPILU_E_INVAL, "waves must be >= 0");
+    ctx->grid_override = waves;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API const char* tpilu_status_string(tpilu_status st) {
+    switch (st) {
+        case TPILU_OK: return "ok";
+        case TPILU_E_INVAL: return "invalid argument";
+        case TPILU_E_NOMEM: return "out of device memory";
+        case TPILU_E_ZEROPIVOT: return "zero pivot";
+        case TPILU_E_DEVICE: return "HIP runtime error";
+        case TPILU_E_NOTCONV: return "not converged";
+        case TPILU_E_TIMEOUT: return "dependency wait timed out";
+    }
+    return "unknown status";
+}
+
+extern "C" TPILU_API const char* tpilu_last_error(tpilu_ctx ctx) {
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+// =====================================================================================
+// Phase I
+// =====================================================================================
+extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64_t nnz,
+                                                 const int64_t* rowptr, const int32_t* col, int32_t k,
+                                                 tpilu_pattern* out) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (!out) return fail(ctx, TPILU_E_INVAL, "null output");
+    *out = nullptr;
+    if (n < 0 || n >= (1ll << 31) - 1 || nnz < 0 || nnz >= (1ll << 31) || k < 0)
+        return fail(ctx, TPILU_E_INVAL, "n, nnz or k out of range");
+    if (n > 0 && (!rowptr || (nnz > 0 && !col))) return fail(ctx, TPILU_E_INVAL, "null array");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = ctx->stream;
+    tpilu_pattern P = new (std::nothrow) tpilu_pattern_s;
+    if (!P) return fail(ctx, TPILU_E_NOMEM, "pattern");
+    P->al = ctx_alloc(ctx);
+    P->device = ctx->device;
+    P->n = n;
+    P->nnz_a = nnz;
+    P->k = k;
+    auto bail = [&](tpilu_status st) {
+        delete P;
+        return st;
+    };
+    P->ctl = (Ctl*)P->take(sizeof(Ctl));
+    uint32_t* vstat = (uint32_t*)P->take(64);
+    P->rpA = (int64_t*)P->take(sizeof(int64_t) * (size_t)(n + 1));
+    P->ciA = (int32_t*)P->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
+    if (!P->ctl || !vstat || !P->rpA || !P->ciA) return bail(fail(ctx, TPILU_E_NOMEM, "pattern arrays"));
+    {
+        Ctl z{};
+        z.bad_row = ~0ull;
+        HIPCHK(ctx, hipMemcpyAsync(P->ctl, &z, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    }
+    if (n == 0) {
+        int64_t zero = 0;
+        HIPCHK(ctx, hipMemcpyAsync(P->rpA, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
+        P->rpF = P->rpA;
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        *out = P;
+        return TPILU_OK;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(P->rpA, rowptr, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz > 0)
+        HIPCHK(ctx, hipMemcpyAsync(P->ciA, col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+    // ---- a1: validation
+    trace("symbolic: validate", n, nnz);
+    HIPCHK(ctx, launch_fill_i32((int32_t*)vstat, 16, 0, s));
+    HIPCHK(ctx, launch_validate((int32_t)n, nnz, P->rpA, P->ciA, vstat, s));
+    uint32_t vs = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&vs, vstat, sizeof(vs), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (vs) {
+        std::string m = "invalid CSR:";
+        if (vs & kValBadRowptr) m += " rowptr not monotone or not [0, nnz];";
+        if (vs & kValBadCol) m += " column index out of range;";
+        if (vs & kValUnsorted) m += " columns not strictly ascending;";
+        if (vs & kValNoDiag) m += " diagonal entry missing;";
+        return bail(fail(ctx, TPILU_E_INVAL, m));
+    }
+    const int32_t ni = (int32_t)n;
+    // ---- a2: level-of-fill pattern, count pass
+    Alloc tmpal = P->al;
+    struct Tmp {
+        Alloc al;
+        std::vector<void*> v;
+        void* get(size_t b) {
+            void* p = al.get(b);
+            if (p) v.push_back(p);
+            return p;
+        }
+        ~Tmp() { for (void* p : v) al.put(p); }
+    } T{tmpal, {}};
+    int32_t* cnt = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);
+    int32_t* over_list = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);
+    int32_t* over_n = (int32_t*)T.get(64);
+    int64_t* scan_tmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(n));
+    if (!cnt || !over_list || !over_n || !scan_tmp) return bail(fail(ctx, TPILU_E_NOMEM, "symbolic scratch"));
+    const int sym_grid = std::min<int64_t>(n, (int64_t)ctx->num_cu * 4);
+    trace("symbolic: count pass", n, k);
+    HIPCHK(ctx, launch_sym_rows(false, ni, P->rpA, P->ciA, k, nullptr, ni, 0, cnt, nullptr, nullptr,
+                                nullptr, nullptr, nullptr, 0, sym_grid, s));
+    HIPCHK(ctx, launch_fill_i32(over_n, 1, 0, s));
+    HIPCHK(ctx, launch_collect_overflow(ni, cnt, over_list, over_n, s));
+    int32_t n_over = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&n_over, over_n, sizeof(n_over), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    P->overflow_rows = n_over;
+    trace("symbolic: overflow rows", n_over);
+    int32_t* gscr = nullptr;
+    uint32_t gcap = 0;
+    int ggrid = 0;
+    if (n_over > 0) {
+        gcap = next_pow2(2 * (uint64_t)n + 2);
+        ggrid = std::min(n_over, 32);
+        gscr = (int32_t*)T.get(sizeof(int32_t) * sym_global_scratch_ints(ni, gcap) * (size_t)ggrid);
+        if (!gscr) return bail(fail(ctx, TPILU_E_NOMEM, "symbolic global scratch"));
+        HIPCHK(ctx, launch_sym_rows(true, ni, P->rpA, P->ciA, k, over_list, n_over, 0, cnt, nullptr,
+                                    nullptr, nullptr, nullptr, gscr, gcap, ggrid, s));
+    }
+    P->rpF = (int64_t*)P->take(sizeof(int64_t) * (size_t)(n + 1));
+    if (!P->rpF) return bail(fail(ctx, TPILU_E_NOMEM, "rowptr"));
+    HIPCHK(ctx, launch_scan(cnt, n, P->rpF, scan_tmp, s));
+    int64_t nnzf = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&nnzf, P->rpF + n, sizeof(nnzf), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (nnzf >= (1ll << 31) - 1) return bail(fail(ctx, TPILU_E_INVAL, "nnz(F) exceeds 2^31"));
+    P->nnz_f = nnzf;
+    trace("symbolic: fill pass, nnz(F)", nnzf);
+    P->ciF = (int32_t*)P->take(sizeof(int32_t) * (size_t)nnzf);
+    P->lvF = (uint8_t*)P->take((size_t)nnzf);
+    P->diagF = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
+    P->a2f = (int32_t*)P->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
+    P->lsd = (int32_t*)P->take(sizeof(int32_t) * (size_t)nnzf);
+    P->sptr = (int64_t*)P->take(sizeof(int64_t) * (size_t)(nnzf + 1));
+    if (!P->ciF || !P->lvF || !P->diagF || !P->a2f || !P->lsd || !P->sptr)
+        return bail(fail(ctx, TPILU_E_NOMEM, "pattern arrays"));
+    // fill pass
+    HIPCHK(ctx, launch_sym_rows(false, ni, P->rpA, P->ciA, k, nullptr, ni, 1, cnt, P->rpF, P->ciF, P->lvF,
+                                P->diagF, nullptr, 0, sym_grid, s));
+    if (n_over > 0)
+        HIPCHK(ctx, launch_sym_rows(true, ni, P->rpA, P->ciA, k, over_list, n_over, 1, cnt, P->rpF, P->ciF,
+                                    P->lvF, P->diagF, gscr, gcap, ggrid, s));
+    // A -> F map
+    HIPCHK(ctx, launch_fill_i32((int32_t*)vstat, 16, 0, s));
+    HIPCHK(ctx, launch_a2f(ni, P->rpA, P->ciA, P->rpF, P->ciF, P->a2f, vstat, s));
+    // statistics
+    PatStats* dst = (PatStats*)T.get(sizeof(PatStats));
+    if (!dst) return bail(fail(ctx, TPILU_E_NOMEM, "stats"));
+    {
+        PatStats z{};
+        HIPCHK(ctx, hipMemcpyAsync(dst, &z, sizeof(z), hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(ctx, launch_stats(ni, P->rpF, P->diagF, dst, s));
+    HIPCHK(ctx, hipMemcpyAsync(&P->st, dst, sizeof(PatStats), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(&vs, vstat, sizeof(vs), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (vs) return bail(fail(ctx, TPILU_E_INVAL, "internal: an entry of A is missing from F"));
+    // ---- update schedule for Phase II
+    trace("symbolic: schedule count", P->st.max_row, P->st.max_lrow);
+    int32_t* scount = (int32_t*)T.get(sizeof(int32_t) * (size_t)nnzf);
+    int64_t* scan2 = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(nnzf));
+    if (!scount || !scan2) return bail(fail(ctx, TPILU_E_NOMEM, "schedule scratch"));
+    HIPCHK(ctx, launch_sched(ni, P->rpF, P->ciF, P->diagF, 0, scount, P->lsd, nullptr, nullptr, nullptr,
+                             P->st.max_row, s));
+    HIPCHK(ctx, launch_scan(scount, nnzf, P->sptr, scan2, s));
+    int64_t nupd = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&nupd, P->sptr + nnzf, sizeof(nupd), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    P->n_updates = nupd;
+    trace("symbolic: schedule fill, updates", nupd);
+    P->sq = (int32_t*)P->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nupd, 1));
+    P->sp = (int32_t*)P->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nupd, 1));
+    if (!P->sq || !P->sp) return bail(fail(ctx, TPILU_E_NOMEM, "schedule"));
+    HIPCHK(ctx, launch_sched(ni, P->rpF, P->ciF, P->diagF, 1, nullptr, nullptr, P->sptr, P->sq, P->sp,
+                             P->st.max_row, s));
+    // ---- dependency depths (reported by tpilu_pattern_info)
+    int32_t* depth = (int32_t*)T.get(sizeof(int32_t) * (size_t)n + 64);
+    if (!depth) return bail(fail(ctx, TPILU_E_NOMEM, "depth"));
+    int32_t* dmax = depth + n;
+    for (int up = 0; up < 2; ++up) {
+        trace("symbolic: depth pass (0 lower, 1 upper)", up);
+        HIPCHK(ctx, launch_fill_i32(depth, n, -1, s));
+        HIPCHK(ctx, launch_fill_i32(dmax, 1, 0, s));
+        HIPCHK(ctx, launch_fill_pending(nullptr, 0, P->ctl, true, s));
+        HIPCHK(ctx, launch_depth(up == 1, ni, P->rpF, P->ciF, P->diagF, depth, P->ctl, ctx->spin_limit,
+                                 solve_grid(1, ctx->num_cu), s));
+        HIPCHK(ctx, launch_max_i32(depth, n, dmax, s));
+        int32_t dm = 0;
+        HIPCHK(ctx, hipMemcpyAsync(&dm, dmax, sizeof(dm), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        (up ? P->depth_u : P->depth_l) = dm;
+    }
+    tpilu_status st = read_ctl(ctx, P, nullptr, true);
+    if (st != TPILU_OK) return bail(st);
+    *out = P;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_pattern_info(tpilu_pattern pat, tpilu_pattern_info_t* info) {
+    if (!pat || !info) return TPILU_E_INVAL;
+    info->n = pat->n;
+    info->nnz_a = pat->nnz_a;
+    info->nnz_f = pat->nnz_f;
+    info->nnz_l = (int64_t)pat->st.nnz_l;
+    info->nnz_u = pat->nnz_f - (int64_t)pat->st.nnz_l;
+    info->n_updates = pat->n_updates;
+    info->k = pat->k;
+    info->max_row = pat->st.max_row;
+    info->max_lrow = pat->st.max_lrow;
+    info->depth_l = pat->depth_l;
+    info->depth_u = pat->depth_u;
+    info->overflow_rows = pat->overflow_rows;
+    return TPILU_OK;
+}
+
+__global__ void k_u8_copy(uint8_t* dst, const uint8_t* src, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+extern "C" TPILU_API tpilu_status tpilu_pattern_export(tpilu_ctx ctx, tpilu_pattern pat, int64_t* rowptr,
+                                                       int32_t* col, int32_t* diag, uint8_t* level,
+                                                       int32_t* a2f) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (!pat) return fail(ctx, TPILU_E_INVAL, "null pattern");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = ctx->stream;
+    const size_t n = (size_t)pat->n, nf = (size_t)pat->nnz_f, na = (size_t)pat->nnz_a;
+    if (rowptr) HIPCHK(ctx, hipMemcpyAsync(rowptr, pat->rpF, 8 * (n + 1), hipMemcpyDeviceToDevice, s));
+    if (n == 0) {
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        return TPILU_OK;
+    }
+    if (col && nf) HIPCHK(ctx, hipMemcpyAsync(col, pat->ciF, 4 * nf, hipMemcpyDeviceToDevice, s));
+    if (diag) HIPCHK(ctx, hipMemcpyAsync(diag, pat->diagF, 4 * n, hipMemcpyDeviceToDevice, s));
+    if (level && nf) {
+        hipLaunchKernelGGL(k_u8_copy, dim3(1024), dim3(256), 0, s, level, pat->lvF, (int64_t)nf);
+        HIPCHK(ctx, hipGetLastError());
+    }
+    if (a2f && na) HIPCHK(ctx, hipMemcpyAsync(a2f, pat->a2f, 4 * na, hipMemcpyDeviceToDevice, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API void tpilu_pattern_destroy(tpilu_pattern pat) {
+    if (!pat) return;
+    DeviceGuard dg(pat->device);
+    delete pat;
+}
+
+// =====================================================================================
+// Phase II and the solves
+// =====================================================================================
+extern "C" TPILU_API tpilu_status tpilu_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val,
+                                                int32_t batch, double* f_val, int64_t* bad_row) {
+    tpilu_status st = check_common(ctx, pat, batch);
+    if (st) return st;
+    if (pat->n == 0) {
+        if (bad_row) *bad_row = -1;
+        return TPILU_OK;
+    }
+    if (!a_val || !f_val) return fail(ctx, TPILU_E_INVAL, "null array");
+    DeviceGuard dg(ctx->device);
+    trace("numeric", pat->n, batch);
+    st = enqueue_numeric(ctx, pat, a_val, batch, f_val);
+    if (st) return st;
+    if (bad_row) return read_ctl(ctx, pat, bad_row, false);
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_pattern_check(tpilu_ctx ctx, tpilu_pattern pat, int64_t* bad_row) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (!pat) return fail(ctx, TPILU_E_INVAL, "null pattern");
+    DeviceGuard dg(ctx->device);
+    return read_ctl(ctx, pat, bad_row, true);
+}
+
+extern "C" TPILU_API tpilu_status tpilu_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val,
+                                              int32_t batch, const double* b, double* y, double* x_out) {
+    tpilu_status st = check_common(ctx, pat, batch);
+    if (st) return st;
+    if (pat->n == 0) return TPILU_OK;
+    if (!f_val || !b || !y) return fail(ctx, TPILU_E_INVAL, "null array");
+    if (b == y) return fail(ctx, TPILU_E_INVAL, "b and y alias");
+    DeviceGuard dg(ctx->device);
+    double* x = x_out;
+    if (!x) {
+        x = pat->grow(pat->ws_x, sizeof(double) * (size_t)pat->n * batch);
+        if (!x) return fail(ctx, TPILU_E_NOMEM, "apply workspace");
+    }
+    trace("apply", pat->n, batch);
+    return enqueue_apply(ctx, pat, f_val, batch, b, y, x, true);
+}
+
+extern "C" TPILU_API tpilu_status tpilu_spmv(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val,
+                                             const double* x, double* y) {
+    tpilu_status st = check_common(ctx, pat, 1);
+    if (st) return st;
+    DeviceGuard dg(ctx->device);
+    HIPCHK(ctx, launch_spmv((int32_t)pat->n, pat->rpA, pat->ciA, a_val, x, nullptr, y, ctx->stream));
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_dot(tpilu_ctx ctx, int64_t n, const double* x, const double* y,
+                                            double* result) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (n < 0 || !result || (n > 0 && (!x || !y))) return fail(ctx, TPILU_E_INVAL, "bad argument");
+    DeviceGuard dg(ctx->device);
+    Alloc al = ctx_alloc(ctx);
+    double* buf = (double*)al.get(sizeof(double) * (kDotBlocks + 1));
+    if (!buf) return fail(ctx, TPILU_E_NOMEM, "dot");
+    hipError_t e = launch_dot_partial(n, x, y, buf, ctx->stream);
+    if (e == hipSuccess) e = launch_dot_final(buf, buf + kDotBlocks, 0, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(result, buf + kDotBlocks, sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    al.put(buf);
+    if (e != hipSuccess) return fail(ctx, TPILU_E_DEVICE, hipGetErrorString(e));
+    return TPILU_OK;
+}
+
+// =====================================================================================
+// GMRES
+// =====================================================================================
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_gmres(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val,
+                                              const double* f_val, const double* b, double* x,
+                                              int32_t restart, int32_t maxit, double rtol, int32_t* iters,
+                                              double* relres, double* hist) {
+    tpilu_status st = check_common(ctx, pat, 1);
+    if (st) return st;
+    if (!iters || !relres) return fail(ctx, TPILU_E_INVAL, "null host output");
+    *iters = 0;
+    *relres = 0.0;
+    if (restart < 1 || maxit < 0) return fail(ctx, TPILU_E_INVAL, "restart >= 1 and maxit >= 0 required");
+    const int64_t n = pat->n;
+    if (n == 0) return TPILU_OK;
+    if (!a_val || !f_val || !b || !x) return fail(ctx, TPILU_E_INVAL, "null array");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = ctx->stream;
+    const int32_t m = restart;
+    // workspace: V (m+1)n, w, z, t, u (n each), small scalars
+    const size_t nn = (size_t)n;
+    const size_t small = 64 + (size_t)(m + 1) * m + 3 * (size_t)m + 2 + (size_t)std::max(maxit, 1) + 16;
+    const size_t doubles = (size_t)(m + 1) * nn + 4 * nn + small;
+    double* wsd = pat->grow(pat->ws_gm, sizeof(double) * doubles);
+    if (!wsd) return fail(ctx, TPILU_E_NOMEM, "gmres workspace");
+    double* V = wsd;
+    double* w = V + (size_t)(m + 1) * nn;
+    double* z = w + nn;
+    double* t = z + nn;
+    double* u = t + nn;
+    double* partial = u + nn;        // 64
+    double* H = partial + 64;        // (m+1) m
+    double* cs = H + (size_t)(m + 1) * m;
+    double* sn = cs + m;
+    double* g = sn + m;              // m+1
+    double* yv = g + m + 1;          // m
+    double* scal = yv + m;           // [0] bnorm [1] beta [2] relres
+    double* dhist = scal + 8;        // maxit
+    int32_t* iflags = (int32_t*)(dhist + std::max(maxit, 1));  // [0] iters [1] stop
+    const int32_t ni = (int32_t)n;
+
+    HIPCHK(ctx, launch_dot_partial(n, b, b, partial, s));
+    HIPCHK(ctx, launch_dot_final(partial, scal + 0, 1, s));
+    HIPCHK(ctx, launch_fill_i32(iflags, 2, 0, s));
+    double bnorm = 0.0;
+    HIPCHK(ctx, hipMemcpyAsync(&bnorm, scal + 0, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (bnorm == 0.0) {
+        hipLaunchKernelGGL(k_fill_f64, dim3(256), dim3(256), 0, s, x, n, 0.0);
+        HIPCHK(ctx, hipGetLastError());
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        return TPILU_OK;
+    }
+    const double tol = rtol * bnorm;
+    int32_t it_host = 0;
+    bool reset = true;
+    for (;;) {
+        HIPCHK(ctx, launch_spmv(ni, pat->rpA, pat->ciA, a_val, x, b, w, s));
+        HIPCHK(ctx, launch_dot_partial(n, w, w, partial, s));
+        HIPCHK(ctx, launch_dot_final(partial, scal + 1, 1, s));
+        double beta = 0.0;
+        HIPCHK(ctx, hipMemcpyAsync(&beta, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        if (beta <= tol || it_host >= maxit) break;
+        HIPCHK(ctx, launch_gm_start(n, partial, scal + 1, g, w, V, s));
+        int32_t jj = 0;
+        for (int32_t j = 0; j < m; ++j) {
+            double* vj = V + (size_t)j * nn;
+            st = enqueue_apply(ctx, pat, f_val, 1, vj, z, t, reset);
+            reset = false;
+            if (st) return st;
+            HIPCHK(ctx, launch_spmv(ni, pat->rpA, pat->ciA, a_val, z, nullptr, w, s));
+            for (int32_t i = 0; i <= j; ++i) {
+                HIPCHK(ctx, launch_dot_partial(n, w, V + (size_t)i * nn, partial, s));
+                HIPCHK(ctx, launch_gm_axpy_h(n, partial, H + (size_t)i * m + j, w, V + (size_t)i * nn, s));
+            }
+            HIPCHK(ctx, launch_dot_partial(n, w, w, partial, s));
+            HIPCHK(ctx, launch_gm_norm_scale(n, partial, H + (size_t)(j + 1) * m + j, w,
+                                             V + (size_t)(j + 1) * nn, s));
+            HIPCHK(ctx, launch_gm_givens(H, cs, sn, g, m, j, tol, iflags, maxit, dhist, iflags + 1, s));
+            int32_t hf[2] = {0, 0};
+            HIPCHK(ctx, hipMemcpyAsync(hf, iflags, sizeof(hf), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipStreamSynchronize(s));
+            it_host = hf[0];
+            jj = j + 1;
+            if (hf[1]) break;
+        }
+        HIPCHK(ctx, launch_gm_backsub(H, g, yv, m, jj, s));
+        HIPCHK(ctx, launch_gm_combine(n, V, yv, jj, u, s));
+        st = enqueue_apply(ctx, pat, f_val, 1, u, z, t, false);
+        if (st) return st;
+        HIPCHK(ctx, launch_axpy1(n, x, z, s));
+    }
+    HIPCHK(ctx, launch_spmv(ni, pat->rpA, pat->ciA, a_val, x, b, w, s));
+    HIPCHK(ctx, launch_dot_partial(n, w, w, partial, s));
+    HIPCHK(ctx, launch_dot_final(partial, scal + 2, 1, s));
+    double rn = 0.0;
+    HIPCHK(ctx, hipMemcpyAsync(&rn, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (hist && it_host > 0)
+        HIPCHK(ctx, hipMemcpyAsync(hist, dhist, sizeof(double) * (size_t)it_host, hipMemcpyDeviceToHost, s));
+    st = read_ctl(ctx, pat, nullptr, false);
+    *iters = it_host;
+    *relres = rn / bnorm;
+    if (st) return st;
+    if (!(*relres <= rtol)) return fail(ctx, TPILU_E_NOTCONV, "GMRES reached maxit");
+    return TPILU_OK;
+}
+
+// =====================================================================================
+// adjoints
+// =====================================================================================
+extern "C" TPILU_API tpilu_status tpilu_apply_adjoint(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val,
+                                                      int32_t batch, const double* x, const double* y,
+                                                      const double* ybar, double* bbar, double* fbar) {
+    tpilu_status st = check_common(ctx, pat, batch);
+    if (st) return st;
+    if (pat->n == 0) return TPILU_OK;
+    if (!f_val || !x || !y || !ybar || !bbar || !fbar) return fail(ctx, TPILU_E_INVAL, "null array");
+    DeviceGuard dg(ctx->device);
+    st = build_transposes(ctx, pat);
+    if (st) return st;
+    hipStream_t s = ctx->stream;
+    double* z = pat->grow(pat->ws_z, sizeof(double) * (size_t)pat->n * batch);
+    if (!z) return fail(ctx, TPILU_E_NOMEM, "adjoint workspace");
+    AdjPat T{pat->tpL, pat->tsL, pat->trL, pat->tpU, pat->tsU, pat->trU};
+    const int grid = ctx->grid_override ? ctx->grid_override : solve_grid(batch, ctx->num_cu);
+    HIPCHK(ctx, launch_fill_pending(z, pat->n * batch, pat->ctl, true, s));
+    HIPCHK(ctx, launch_adj_solve_u(pat->dev(), T, f_val, batch, ybar, z, pat->ctl, ctx->spin_limit, grid, s));
+    HIPCHK(ctx, launch_fill_pending(bbar, pat->n * batch, pat->ctl, false, s));
+    HIPCHK(ctx, launch_adj_solve_l(pat->dev(), T, f_val, batch, z, bbar, pat->ctl, ctx->spin_limit, grid, s));
+    HIPCHK(ctx, launch_adj_fbar(pat->dev(), batch, x, y, z, bbar, fbar, s));
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_numeric_adjoint(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val,
+                                                        int32_t batch, double* fbar, double* abar) {
+    tpilu_status st = check_common(ctx, pat, batch);
+    if (st) return st;
+    if (pat->n == 0) return TPILU_OK;
+    if (!f_val || !fbar || !abar) return fail(ctx, TPILU_E_INVAL, "null array");
+    DeviceGuard dg(ctx->device);
+    st = build_transposes(ctx, pat);
+    if (st) return st;
+    hipStream_t s = ctx->stream;
+    const int64_t nfb = pat->nnz_f * batch;
+    double* fin = pat->grow(pat->ws_fin, sizeof(double) * (size_t)nfb);
+    double* lbar = pat->grow(pat->ws_lbar, sizeof(double) * (size_t)nfb);
+    if (!fin || !lbar) return fail(ctx, TPILU_E_NOMEM, "adjoint workspace");
+    if ((size_t)pat->st.max_row * 8 > kBatchLdsLimit)
+        return fail(ctx, TPILU_E_INVAL, "adjoint supports rows of at most 8192 entries");
+    AdjPat T{pat->tpL, pat->tsL, pat->trL, pat->tpU, pat->tsU, pat->trU};
+    HIPCHK(ctx, launch_copy(fin, fbar, nfb, s));
+    HIPCHK(ctx, launch_fill_pending(fbar, nfb, pat->ctl, true, s));
+    HIPCHK(ctx, launch_fill_pending(lbar, nfb, pat->ctl, false, s));
+    const int grid = ctx->grid_override ? ctx->grid_override : solve_grid(batch, ctx->num_cu);
+    HIPCHK(ctx, launch_adj_numeric(pat->dev(), T, f_val, batch, fin, fbar, lbar, abar, pat->ctl,
+                                   ctx->spin_limit, grid, pat->st.max_row, s));
+    return TPILU_OK;
+}
+
+// =====================================================================================
+// batched graph
+// =====================================================================================
+extern "C" TPILU_API tpilu_status tpilu_batched_graph_create(tpilu_ctx ctx, tpilu_pattern pat,
+                                                             const double* a_val, int32_t batch,
+                                                             double* f_val, const double* b, double* y,
+                                                             tpilu_graph* out) {
+    tpilu_status st = check_common(ctx, pat, batch);
+    if (st) return st;
+    if (!out) return fail(ctx, TPILU_E_INVAL, "null output");
+    *out = nullptr;
+    if (!a_val || !f_val || !b || !y) return fail(ctx, TPILU_E_INVAL, "null array");
+    if (pat->n == 0) return fail(ctx, TPILU_E_INVAL, "empty pattern");
+    DeviceGuard dg(ctx->device);
+    double* x = pat->grow(pat->ws_x, sizeof(double) * (size_t)pat->n * batch);
+    if (!x) return fail(ctx, TPILU_E_NOMEM, "graph workspace");
+    hipStream_t cap = nullptr;
+    HIPCHK(ctx, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t saved = ctx->stream;
+    ctx->stream = cap;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = enqueue_numeric(ctx, pat, a_val, batch, f_val);
+        if (st == TPILU_OK) st = enqueue_apply(ctx, pat, f_val, batch, b, y, x, false);
+        e = hipStreamEndCapture(cap, &graph);
+    }
+    ctx->stream = saved;
+    (void)hipStreamDestroy(cap);
+    if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(ctx, TPILU_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(ctx, TPILU_E_DEVICE, std::string("instantiate: ") + hipGetErrorString(e));
+    }
+    tpilu_graph g = new (std::nothrow) tpilu_graph_s;
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(ctx, TPILU_E_NOMEM, "graph handle");
+    }
+    g->graph = graph;
+    g->exec = exec;
+    g->device = ctx->device;
+    *out = g;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_batched_graph_launch(tpilu_graph g, void* hip_stream) {
+    if (!g) return TPILU_E_INVAL;
+    DeviceGuard dg(g->device);
+    if (hipGraphLaunch(g->exec, static_cast<hipStream_t>(hip_stream)) != hipSuccess) return TPILU_E_DEVICE;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API void tpilu_batched_graph_destroy(tpilu_graph g) {
+    if (!g) return;
+    DeviceGuard dg(g->device);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}

@@ -1,0 +1,397 @@
+"""GPU parity: the HIP path (through the C ABI) against the sequential oracle,
+bit for bit, on the same seeded inputs.
+
+Small cases span many rows and wavefronts; the named workloads run at their
+full sizes with the launch configuration the benchmark uses.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_0803_0048_amd import binding as T
+from paper_0803_0048_amd import inputs as I
+from tests.gpu_util import assert_bits_equal, bits, check_pattern, g, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu_guard(request):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    log(f"[gpu] {request.node.nodeid}")
+    ctx = T.context(0)
+    ctx.set_grid(0)
+    ctx.set_watchdog(0, -1)
+    yield
+    torch.cuda.synchronize()
+
+
+def _full(A, k, b=None, check_gmres=None):
+    """symbolic + numeric + apply on GPU and oracle, compared bit for bit"""
+    rpF, ciF, lvF = O.symbolic(A.n, A.rowptr, A.col, k)
+    pat = T.symbolic(g(A.rowptr), g(A.col), k)
+    check_pattern(pat, rpF, ciF, lvF, A)
+    vF, bad = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
+    f = T.numeric(pat, g(A.val), check=False)
+    bad_g = T.check(pat) if bad < 0 else None
+    assert_bits_equal(f, vF, "F")
+    if b is not None:
+        x_ref, y_ref = O.apply(A.n, rpF, ciF, vF, b)
+        y, x = T.apply(pat, f, g(b), return_x=True)
+        assert_bits_equal(x, x_ref, "x = L^-1 b")
+        assert_bits_equal(y, y_ref, "y = U^-1 x")
+    del bad_g
+    return pat, f, (rpF, ciF, vF)
+
+
+# ----------------------------------------------------------------------------------
+# arithmetic probes through the product path
+# ----------------------------------------------------------------------------------
+def test_division_and_update_rounding_bits():
+    """2 x 2 instances [[a, b], [c, d]]: f_10 = c / a and f_11 = d - f_10 * b
+    for a million random (and special) operands, against IEEE host arithmetic."""
+    rng = np.random.default_rng(0)
+    B = 1 << 20
+    a = rng.standard_normal(B) * np.exp2(rng.integers(-1060, 1000, B).astype(np.float64) / 1.0)
+    c = rng.standard_normal(B) * np.exp2(rng.integers(-1060, 1000, B).astype(np.float64))
+    bb = rng.standard_normal(B) * np.exp2(rng.integers(-500, 500, B).astype(np.float64))
+    d = rng.standard_normal(B) * np.exp2(rng.integers(-500, 500, B).astype(np.float64))
+    sp = np.array([5e-324, -5e-324, 2.2250738585072014e-308, 1.7976931348623157e308, 1.0, -0.0, 3.0])
+    a[: sp.size] = sp
+    c[sp.size: 2 * sp.size] = sp
+    a[a == 0] = 1.0
+    rp = np.array([0, 2, 4], np.int64)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    vals = np.stack([a, bb, c, d], axis=0)  # [nnz=4, B]
+    pat = T.symbolic(g(rp), g(ci), 1)
+    f = T.numeric(pat, g(vals), check=False)
+    fh = f.cpu().numpy()
+    with np.errstate(all="ignore"):
+        l10 = c / a
+        u11 = d - l10 * bb
+    assert_bits_equal(fh[2], l10, "c / a")
+    fin = np.isfinite(u11)
+    assert_bits_equal(fh[3][fin], u11[fin], "d - l b")
+
+
+def test_dot_bits_and_fixed_shape():
+    rng = np.random.default_rng(2)
+    for n in (0, 1, 63, 16384, 16385, 100_003, 1_000_000):
+        x = rng.standard_normal(n)
+        y = rng.standard_normal(n) * np.exp(rng.uniform(-30, 30, n))
+        got = T.dot(g(x), g(y))
+        want = O.dot(x, y) if n else 0.0
+        assert bits(np.array([got]))[0] == bits(np.array([want]))[0], (n, got, want)
+    x = np.zeros(16384 * 3)
+    x[[0, 1, 2, 3]] = [2.0**53, 1, 1, 1]
+    assert T.dot(g(x), g(np.ones_like(x))) == 2.0**53 + 2.0
+
+
+def test_spmv_bits():
+    A = I.config1()["A"]
+    x = np.random.default_rng(1).standard_normal(A.n)
+    pat = T.symbolic(g(A.rowptr), g(A.col), 0)
+    assert_bits_equal(T.spmv(pat, g(A.val), g(x)), O.spmv(A.n, A.rowptr, A.col, A.val, x), "A x")
+
+
+# ----------------------------------------------------------------------------------
+# small random matrices: many shapes, all k, explicit zeros and signed zeros
+# ----------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(4))
+def test_small_random_sweep(seed):
+    rng = np.random.default_rng(4000 + seed)
+    for case in range(30):
+        n = int(rng.integers(1, 400))
+        dens = float(rng.choice([0.002, 0.01, 0.03, 0.08]))
+        A = I.random_pattern(n, dens, seed=int(rng.integers(1 << 30)), diag_dominant=bool(rng.integers(2)),
+                             explicit_zeros=float(rng.choice([0.0, 0.2])))
+        if case % 5 == 0 and A.nnz > 3:
+            A.val[1] = -0.0
+            A.val[2] = 5e-324
+        k = int(rng.choice([0, 1, 2, 3, 5, n]))
+        b = rng.standard_normal(n)
+        _full(A, k, b)
+
+
+def test_overflow_rows_take_global_path():
+    """An arrow matrix (dense last row and column) makes rows longer than the
+    LDS maps of the fast symbolic path; they are rebuilt in global memory."""
+    n = 3000
+    M = np.zeros((n, n), bool)
+    M[np.arange(n), np.arange(n)] = True
+    M[-1, :] = True
+    M[:, -1] = True
+    rng = np.random.default_rng(9)
+    vals = np.where(M, rng.uniform(-1, 1, (n, n)), 0.0)
+    vals[np.arange(n), np.arange(n)] = 2.0 * n
+    rows, cols = np.nonzero(M)
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, rows + 1, 1)
+    A = I.CSR(n, np.cumsum(rp), cols.astype(np.int32), vals[rows, cols])
+    pat, _, _ = _full(A, 2, rng.standard_normal(n))
+    assert pat.info["overflow_rows"] >= 1
+
+
+def test_long_range_fill_k_infinity():
+    A = I.random_pattern(300, 0.01, seed=77)
+    _full(A, 2**31 - 1, np.random.default_rng(3).standard_normal(A.n))
+
+
+def test_empty_and_single():
+    A0 = I.CSR(0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    pat = T.symbolic(g(A0.rowptr), torch.zeros(0, dtype=torch.int32, device="cuda:0"), 1)
+    assert pat.nnz_f == 0
+    A1 = I.CSR(1, np.array([0, 1], np.int64), np.array([0], np.int32), np.array([3.0]))
+    _full(A1, 1, np.array([2.0]))
+
+
+# ----------------------------------------------------------------------------------
+# the named workloads at full size
+# ----------------------------------------------------------------------------------
+def _gmres_parity(pat, f, A, b, restart, maxit, rtol):
+    rpF, ciF, vF = f[1]
+    ref = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, b, restart=restart, maxit=maxit, rtol=rtol)
+    x, info = T.gmres(pat, g(A.val), f[0], g(b), restart=restart, maxit=maxit, rtol=rtol)
+    assert info["iters"] == ref["iters"], (info["iters"], ref["iters"])
+    assert_bits_equal(np.array(info["hist"]), ref["hist"], "GMRES |g| history")
+    assert_bits_equal(x, ref["x"], "GMRES x")
+    assert bits(np.array([info["relres"]]))[0] == bits(np.array([ref["relres"]]))[0]
+    return info
+
+
+def test_config1_conv_diff_2d_ilu1():
+    c = I.config1()
+    pat, f, ref = _full(c["A"], c["k"], c["b"])
+    info = _gmres_parity(pat, (f, ref), c["A"], c["b"], 30, 1000, 1e-8)
+    assert info["relres"] <= 1e-8
+
+
+def test_config2_random_banded_ilu2():
+    c = I.config2()
+    log("  oracle + gpu on n=160000, ILU(2)")
+    pat, f, ref = _full(c["A"], c["k"], c["b"])
+    log(f"  pattern info {pat.info}")
+    info = _gmres_parity(pat, (f, ref), c["A"], c["b"], 30, 300, 1e-8)
+    assert info["relres"] <= 1e-8
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_config3_conv_diff_3d(k):
+    c = I.config3(k=k)
+    _full(c["A"], k, c["b"])
+
+
+def test_config3_gmres_ilu1():
+    c = I.config3(k=1)
+    pat, f, ref = _full(c["A"], 1, c["b"])
+    _gmres_parity(pat, (f, ref), c["A"], c["b"], 50, 150, 1e-8)
+
+
+def test_repeatable_across_launch_shapes():
+    """Same bits for any number of wavefronts (race check by repetition)."""
+    c = I.config1()
+    A = c["A"]
+    pat = T.symbolic(g(A.rowptr), g(A.col), 2)
+    av, bv = g(A.val), g(c["b"])
+    ctx = T.context(0)
+    ref_f = T.numeric(pat, av)
+    ref_y = T.apply(pat, ref_f, bv)
+    for waves in (1, 2, 7, 64, 1000, 0, 40000):
+        ctx.set_grid(waves)
+        for _ in range(3):
+            f = T.numeric(pat, av)
+            y = T.apply(pat, f, bv)
+            assert torch.equal(f.view(torch.int64), ref_f.view(torch.int64)), waves
+            assert torch.equal(y.view(torch.int64), ref_y.view(torch.int64)), waves
+    ctx.set_grid(0)
+
+
+def test_repeatable_config2():
+    c = I.config2()
+    A = c["A"]
+    pat = T.symbolic(g(A.rowptr), g(A.col), 2)
+    av = g(A.val)
+    ref = T.numeric(pat, av)
+    for _ in range(5):
+        assert torch.equal(T.numeric(pat, av).view(torch.int64), ref.view(torch.int64))
+
+
+# ----------------------------------------------------------------------------------
+# failure handling (forced from the host)
+# ----------------------------------------------------------------------------------
+def test_zero_pivot_reported():
+    rp = np.array([0, 2, 4], np.int64)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    pat = T.symbolic(g(rp), g(ci), 1)
+    with pytest.raises(T.ZeroPivotError) as e:
+        T.numeric(pat, g(np.array([1.0, 1.0, 1.0, 1.0])))
+    assert e.value.bad_row == 1
+    vals = np.ones((4, 70))
+    vals[0, 5] = 0.0  # instance 5: zero first pivot
+    with pytest.raises(T.ZeroPivotError) as e:
+        T.numeric(pat, g(vals))
+    assert e.value.bad_row == 0
+    f = T.numeric(pat, g(np.array([2.0, 1.0, 1.0, 1.0])))
+    assert f.cpu().numpy()[3] == 0.5
+
+
+def test_watchdog_times_out_and_recovers():
+    c = I.config1()
+    A = c["A"]
+    pat = T.symbolic(g(A.rowptr), g(A.col), 1)
+    ctx = T.context(0)
+    ctx.set_watchdog(timeout_us=20000, skip_publish_row=100)
+    with pytest.raises(T.TpiluError) as e:
+        T.numeric(pat, g(A.val))
+    assert e.value.status == T.E_TIMEOUT
+    ctx.set_watchdog(0, -1)
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, 1)
+    vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
+    assert_bits_equal(T.numeric(pat, g(A.val)), vF, "F after recovery")
+
+
+def test_invalid_csr_rejected():
+    with pytest.raises(T.TpiluError) as e:
+        T.symbolic(g(np.array([0, 1, 2], np.int64)), g(np.array([0, 0], np.int32)), 1)  # no diag in row 1
+    assert e.value.status == T.E_INVAL
+    with pytest.raises(T.TpiluError):
+        T.symbolic(g(np.array([0, 2, 3], np.int64)), g(np.array([1, 0, 1], np.int32)), 1)  # unsorted
+    with pytest.raises(T.TpiluError):
+        T.symbolic(g(np.array([0, 1, 2], np.int64)), g(np.array([0, 5], np.int32)), 1)  # out of range
+
+
+def test_reserved_nan_input_rejected():
+    A = I.random_pattern(50, 0.05, seed=1)
+    pat = T.symbolic(g(A.rowptr), g(A.col), 1)
+    v = A.val.copy()
+    v.view(np.uint64)[3] = 0x7FF4A5A5A5A5A5A5
+    with pytest.raises(T.TpiluError) as e:
+        T.numeric(pat, g(v))
+    assert e.value.status == T.E_INVAL
+    # and the next call is clean again
+    T.numeric(pat, g(A.val))
+
+
+# ----------------------------------------------------------------------------------
+# batched factorization under one graph
+# ----------------------------------------------------------------------------------
+def test_config4_batched_graph():
+    c = I.config4()
+    A, rhs = c["A"], c["b"]
+    B = A.batch
+    pat = T.symbolic(g(A.rowptr), g(A.col), 2)
+    rpF, ciF, lvF = O.symbolic(A.n, A.rowptr, A.col, 2)
+    check_pattern(pat, rpF, ciF, lvF, A)
+    av, bv = g(A.val), g(rhs)
+    f_eager = T.numeric(pat, av)
+    y_eager = T.apply(pat, f_eager, bv)
+    fh, yh = f_eager.cpu().numpy(), y_eager.cpu().numpy()
+    for inst in range(B):
+        Ai = A.instance(inst)
+        vF, bad = O.numeric(A.n, A.rowptr, A.col, Ai.val, rpF, ciF)
+        _, yr = O.apply(A.n, rpF, ciF, vF, rhs[:, inst])
+        assert_bits_equal(fh[:, inst], vF, f"F instance {inst}")
+        assert_bits_equal(yh[:, inst], yr, f"y instance {inst}")
+    # single-instance GPU runs of a few instances agree too
+    for inst in (0, 63, 64, 255):
+        fs = T.numeric(pat, g(A.val[:, inst].copy()))
+        assert_bits_equal(fs, fh[:, inst], f"single vs batched {inst}")
+    graph = T.BatchedGraph(pat, av, bv)
+    for rep in range(3):
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(graph.f_val.view(torch.int64), f_eager.view(torch.int64)), rep
+        assert torch.equal(graph.y.view(torch.int64), y_eager.view(torch.int64)), rep
+        _ = T.numeric(pat, av)  # eager work between replays
+    av.mul_(1.5)
+    graph.launch()
+    torch.cuda.synchronize()
+    f2 = T.numeric(pat, av)
+    assert torch.equal(graph.f_val.view(torch.int64), f2.view(torch.int64))
+    assert not torch.equal(f2.view(torch.int64), f_eager.view(torch.int64))
+    assert T.check(pat) == -1
+
+
+def test_batched_partial_group():
+    """A batch that is not a multiple of 64 instances."""
+    c = I.config4(B=70, m=24)
+    A, rhs = c["A"], c["b"]
+    pat = T.symbolic(g(A.rowptr), g(A.col), 2)
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, 2)
+    f = T.numeric(pat, g(A.val)).cpu().numpy()
+    y = T.apply(pat, g(f), g(rhs)).cpu().numpy()
+    for inst in (0, 63, 64, 69):
+        vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val[:, inst].copy(), rpF, ciF)
+        assert_bits_equal(f[:, inst], vF, f"F {inst}")
+        assert_bits_equal(y[:, inst], O.apply(A.n, rpF, ciF, vF, rhs[:, inst])[1], f"y {inst}")
+
+
+# ----------------------------------------------------------------------------------
+# reverse mode
+# ----------------------------------------------------------------------------------
+def _oracle_grads(A, rpF, ciF, vals, b, t):
+    vF, _ = O.numeric(A.n, A.rowptr, A.col, vals, rpF, ciF)
+    x, y = O.apply(A.n, rpF, ciF, vF, b)
+    bbar, Fbar = O.apply_adjoint(A.n, rpF, ciF, vF, x, y, 2.0 * (y - t))
+    abar, _ = O.numeric_adjoint(A.n, A.rowptr, A.col, rpF, ciF, vF, Fbar)
+    return abar, bbar, Fbar
+
+
+def test_adjoint_small_bits():
+    rng = np.random.default_rng(11)
+    for case in range(12):
+        n = int(rng.integers(2, 300))
+        A = I.random_pattern(n, float(rng.choice([0.01, 0.04])), seed=int(rng.integers(1 << 30)))
+        k = int(rng.choice([0, 1, 2]))
+        b, t = rng.standard_normal(n), rng.standard_normal(n)
+        rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
+        abar_r, bbar_r, Fbar_r = _oracle_grads(A, rpF, ciF, A.val, b, t)
+        pat = T.symbolic(g(A.rowptr), g(A.col), k)
+        f = T.numeric(pat, g(A.val))
+        y, x = T.apply(pat, f, g(b), return_x=True)
+        bbar, fbar = T.apply_adjoint(pat, f, x, y, 2.0 * (y - g(t)))
+        assert_bits_equal(bbar, bbar_r, "bbar")
+        assert_bits_equal(fbar, Fbar_r, "Fbar")
+        abar, _ = T.numeric_adjoint(pat, f, fbar)
+        assert_bits_equal(abar, abar_r, "abar")
+
+
+def test_config5_autograd_against_oracle_and_fd():
+    c = I.config5()
+    A, rhs, tgt = c["A"], c["b"], c["t"]
+    B = A.batch
+    pat = T.symbolic(g(A.rowptr), g(A.col), 1)
+    av = g(A.val).requires_grad_(True)
+    bv = g(rhs).requires_grad_(True)
+    y = T.ILUApply.apply(av, bv, pat)
+    loss = ((y - g(tgt)) ** 2).sum()
+    loss.backward()
+    ga, gb = av.grad.cpu().numpy(), bv.grad.cpu().numpy()
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, 1)
+    for inst in (0, 7, 15):
+        abar_r, bbar_r, _ = _oracle_grads(A, rpF, ciF, A.val[:, inst].copy(), rhs[:, inst], tgt[:, inst])
+        assert_bits_equal(ga[:, inst], abar_r, f"d/dA instance {inst}")
+        assert_bits_equal(gb[:, inst], bbar_r, f"d/db instance {inst}")
+    # central finite differences on 64 sampled (instance, entry) pairs
+    rng = np.random.default_rng(5)
+    eps = 1e-6
+
+    def loss_of(vals, inst):
+        vF, _ = O.numeric(A.n, A.rowptr, A.col, vals, rpF, ciF)
+        _, yy = O.apply(A.n, rpF, ciF, vF, rhs[:, inst])
+        return float(np.sum((yy - tgt[:, inst]) ** 2))
+
+    scale = np.abs(ga).max()
+    for _ in range(64):
+        inst = int(rng.integers(B))
+        p = int(rng.integers(A.nnz))
+        vp = A.val[:, inst].copy()
+        vm = vp.copy()
+        vp[p] += eps
+        vm[p] -= eps
+        fd = (loss_of(vp, inst) - loss_of(vm, inst)) / (2 * eps)
+        assert abs(fd - ga[p, inst]) <= 1e-5 * max(abs(fd), 1e-9 * scale) + 1e-7, (inst, p, fd, ga[p, inst])
