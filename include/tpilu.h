@@ -105,6 +105,17 @@ TPILU_API tpilu_status tpilu_ctx_set_watchdog(tpilu_ctx ctx, uint32_t timeout_us
  * gives the same bits; it only changes speed.  Used to test that claim. */
 TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t waves);
 
+/* Kernel timing.  With timing on, the library brackets the main kernel of
+ * every numeric factorization, forward solve and backward solve it launches
+ * with a pair of hipEvents recorded on the ctx stream (outside graph
+ * capture).  tpilu_ctx_read_timing waits for those events, returns the summed
+ * duration in milliseconds and the number of launches of one kernel kind
+ * (TPILU_KERNEL_*) since the last read, and resets that kind. */
+enum { TPILU_KERNEL_NUMERIC = 0, TPILU_KERNEL_FORWARD = 1, TPILU_KERNEL_BACKWARD = 2 };
+TPILU_API tpilu_status tpilu_ctx_set_timing(tpilu_ctx ctx, int on);
+TPILU_API tpilu_status tpilu_ctx_read_timing(tpilu_ctx ctx, int kernel, double *total_ms /* host */,
+                                             int64_t *launches /* host */);
+
 /* ---------------------------------------------------------------------------
  * Phase I -- symbolic factorization (Sec. 2.2, Algorithm 1; Def. 2.3).
  *

@@ -20,7 +20,7 @@ OK, E_INVAL, E_NOMEM, E_ZEROPIVOT, E_DEVICE, E_NOTCONV, E_TIMEOUT = range(7)
 
 EXPORTED = [
     "tpilu_ctx_create", "tpilu_ctx_set_stream", "tpilu_ctx_destroy", "tpilu_status_string",
-    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_symbolic", "tpilu_pattern_info",
+    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
     "tpilu_pattern_export", "tpilu_pattern_destroy", "tpilu_numeric", "tpilu_pattern_check",
     "tpilu_apply", "tpilu_gmres", "tpilu_spmv", "tpilu_dot", "tpilu_apply_adjoint",
     "tpilu_numeric_adjoint", "tpilu_batched_graph_create", "tpilu_batched_graph_launch",
@@ -69,6 +69,8 @@ def load_library():
             "tpilu_last_error": ([P], C.c_char_p),
             "tpilu_ctx_set_watchdog": ([P, u32, i64], st),
             "tpilu_ctx_set_grid": ([P, i32], st),
+            "tpilu_ctx_set_timing": ([P, C.c_int], st),
+            "tpilu_ctx_read_timing": ([P, C.c_int, C.POINTER(dbl), C.POINTER(i64)], st),
             "tpilu_symbolic": ([P, i64, i64, P, P, i32, C.POINTER(P)], st),
             "tpilu_pattern_info": ([P, C.POINTER(PatternInfo)], st),
             "tpilu_pattern_export": ([P, P, P, P, P, P, P], st),
@@ -122,6 +124,18 @@ class Context:
         if st == E_ZEROPIVOT:
             raise ZeroPivotError(st, f"{what}: {msg}", bad_row)
         raise TpiluError(st, f"{what}: {msg}", bad_row)
+
+    KERNEL_NUMERIC, KERNEL_FORWARD, KERNEL_BACKWARD = 0, 1, 2
+
+    def set_timing(self, on: bool):
+        self.check(load_library().tpilu_ctx_set_timing(self.h, 1 if on else 0), "set_timing")
+
+    def read_timing(self, kernel: int):
+        """(total ms, launches) of one kernel kind since the last read."""
+        ms = C.c_double(0.0)
+        cnt = C.c_int64(0)
+        self.check(load_library().tpilu_ctx_read_timing(self.h, kernel, C.byref(ms), C.byref(cnt)), "read_timing")
+        return ms.value, cnt.value
 
     def set_grid(self, waves: int = 0):
         self.check(load_library().tpilu_ctx_set_grid(self.h, waves), "set_grid")

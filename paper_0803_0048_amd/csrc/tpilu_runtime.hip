@@ -27,7 +27,16 @@ struct tpilu_ctx_s {
     uint64_t ticks_per_us = 100;
     int64_t skip_row = -1;
     int32_t grid_override = 0;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
     std::string err;
+    ~tpilu_ctx_s() {
+        for (auto& v : ev)
+            for (auto& p : v) {
+                (void)hipEventDestroy(p.first);
+                (void)hipEventDestroy(p.second);
+            }
+    }
 };
 
 namespace {
@@ -75,6 +84,7 @@ struct DBuf {
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev) {
+        (void)hipGetLastError();  // a failure of an earlier call must not be reported by this one
         if (hipGetDevice(&prev) != hipSuccess) prev = -1;
         if (prev != dev) (void)hipSetDevice(dev);
     }
@@ -196,6 +206,27 @@ tpilu_status read_ctl(tpilu_ctx ctx, tpilu_pattern pat, int64_t* bad_row, bool c
     return TPILU_OK;
 }
 
+// Brackets one kernel launch with events when timing is on (and the stream is
+// not being captured).
+struct TimedLaunch {
+    tpilu_ctx ctx;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(tpilu_ctx c, int k) : ctx(c), kind(k) {
+        if (!ctx->timing) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+        if (hipEventCreate(&a) != hipSuccess) { a = nullptr; return; }
+        if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); a = nullptr; return; }
+        (void)hipEventRecord(a, ctx->stream);
+    }
+    ~TimedLaunch() {
+        if (!a) return;
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->ev[kind].push_back({a, b});
+    }
+};
+
 tpilu_status check_common(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch) {
     if (!ctx) return TPILU_E_INVAL;
     if (!pat) return fail(ctx, TPILU_E_INVAL, "null pattern");
@@ -219,8 +250,11 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
         return fail(ctx, TPILU_E_INVAL, "numeric factorization supports rows of at most 6600 entries");
     HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, pat->ctl, true, ctx->stream));
     const int grid = ctx->grid_override ? ctx->grid_override : numeric_grid(batch, pat->st.max_row, ctx->num_cu);
-    HIPCHK(ctx, launch_numeric(pat->dev(), a_val, batch, f_val, pat->ctl, ctx->spin_limit,
-                               ctx->skip_row, grid, pat->st.max_row, ctx->stream));
+    {
+        TimedLaunch tl(ctx, TPILU_KERNEL_NUMERIC);
+        HIPCHK(ctx, launch_numeric(pat->dev(), a_val, batch, f_val, pat->ctl, ctx->spin_limit,
+                                   ctx->skip_row, grid, pat->st.max_row, ctx->stream));
+    }
     return TPILU_OK;
 }
 
@@ -228,11 +262,17 @@ tpilu_status enqueue_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val
                            const double* b, double* y, double* x, bool reset) {
     const int grid = ctx->grid_override ? ctx->grid_override : solve_grid(batch, ctx->num_cu);
     HIPCHK(ctx, launch_fill_pending(x, pat->n * batch, pat->ctl, reset, ctx->stream));
-    HIPCHK(ctx, launch_forward(pat->dev(), f_val, batch, b, x, pat->ctl, ctx->spin_limit, grid,
-                               ctx->stream));
+    {
+        TimedLaunch tl(ctx, TPILU_KERNEL_FORWARD);
+        HIPCHK(ctx, launch_forward(pat->dev(), f_val, batch, b, x, pat->ctl, ctx->spin_limit, grid,
+                                   ctx->stream));
+    }
     HIPCHK(ctx, launch_fill_pending(y, pat->n * batch, pat->ctl, false, ctx->stream));
-    HIPCHK(ctx, launch_backward(pat->dev(), f_val, batch, x, y, pat->ctl, ctx->spin_limit, grid,
-                                ctx->stream));
+    {
+        TimedLaunch tl(ctx, TPILU_KERNEL_BACKWARD);
+        HIPCHK(ctx, launch_backward(pat->dev(), f_val, batch, x, y, pat->ctl, ctx->spin_limit, grid,
+                                    ctx->stream));
+    }
     return TPILU_OK;
 }
 
@@ -317,6 +357,35 @@ extern "C" TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t wave
     if (waves < 0) return fail(ctx, TPILU_E_INVAL, "waves must be >= 0");
     ctx->grid_override = waves;
     return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_timing(tpilu_ctx ctx, int on) {
+    if (!ctx) return TPILU_E_INVAL;
+    ctx->timing = on != 0;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_read_timing(tpilu_ctx ctx, int kernel, double* total_ms,
+                                                       int64_t* launches) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (kernel < 0 || kernel > 2 || !total_ms || !launches) return fail(ctx, TPILU_E_INVAL, "bad argument");
+    DeviceGuard dg(ctx->device);
+    double sum = 0.0;
+    int64_t cnt = 0;
+    tpilu_status st = TPILU_OK;
+    for (auto& p : ctx->ev[kernel]) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.second) != hipSuccess || hipEventElapsedTime(&ms, p.first, p.second) != hipSuccess)
+            st = fail(ctx, TPILU_E_DEVICE, "event timing failed");
+        sum += ms;
+        ++cnt;
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    ctx->ev[kernel].clear();
+    *total_ms = sum;
+    *launches = cnt;
+    return st;
 }
 
 extern "C" TPILU_API const char* tpilu_status_string(tpilu_status st) {
@@ -665,26 +734,37 @@ extern "C" TPILU_API tpilu_status tpilu_gmres(tpilu_ctx ctx, tpilu_pattern pat, 
     DeviceGuard dg(ctx->device);
     hipStream_t s = ctx->stream;
     const int32_t m = restart;
-    // workspace: V (m+1)n, w, z, t, u (n each), small scalars
+    // workspace (doubles): V (m+1)n | w, z, t, u (n each) | partial 64 | H (m+1)m |
+    // cs m | sn m | g m+1 | yv m | scal 8 | hist max(maxit,1) | flags (2 int32)
     const size_t nn = (size_t)n;
-    const size_t small = 64 + (size_t)(m + 1) * m + 3 * (size_t)m + 2 + (size_t)std::max(maxit, 1) + 16;
-    const size_t doubles = (size_t)(m + 1) * nn + 4 * nn + small;
+    const size_t mh = (size_t)std::max(maxit, 1);
+    const size_t o_w = (size_t)(m + 1) * nn;
+    const size_t o_partial = o_w + 4 * nn;
+    const size_t o_H = o_partial + kDotBlocks;
+    const size_t o_cs = o_H + (size_t)(m + 1) * m;
+    const size_t o_sn = o_cs + m;
+    const size_t o_g = o_sn + m;
+    const size_t o_yv = o_g + m + 1;
+    const size_t o_scal = o_yv + m;
+    const size_t o_hist = o_scal + 8;
+    const size_t o_flags = o_hist + mh;
+    const size_t doubles = o_flags + 1;
     double* wsd = pat->grow(pat->ws_gm, sizeof(double) * doubles);
     if (!wsd) return fail(ctx, TPILU_E_NOMEM, "gmres workspace");
     double* V = wsd;
-    double* w = V + (size_t)(m + 1) * nn;
+    double* w = wsd + o_w;
     double* z = w + nn;
     double* t = z + nn;
     double* u = t + nn;
-    double* partial = u + nn;        // 64
-    double* H = partial + 64;        // (m+1) m
-    double* cs = H + (size_t)(m + 1) * m;
-    double* sn = cs + m;
-    double* g = sn + m;              // m+1
-    double* yv = g + m + 1;          // m
-    double* scal = yv + m;           // [0] bnorm [1] beta [2] relres
-    double* dhist = scal + 8;        // maxit
-    int32_t* iflags = (int32_t*)(dhist + std::max(maxit, 1));  // [0] iters [1] stop
+    double* partial = wsd + o_partial;
+    double* H = wsd + o_H;
+    double* cs = wsd + o_cs;
+    double* sn = wsd + o_sn;
+    double* g = wsd + o_g;
+    double* yv = wsd + o_yv;
+    double* scal = wsd + o_scal;  // [0] bnorm [1] beta [2] final residual norm
+    double* dhist = wsd + o_hist;
+    int32_t* iflags = reinterpret_cast<int32_t*>(wsd + o_flags);  // [0] iters [1] stop
     const int32_t ni = (int32_t)n;
 
     HIPCHK(ctx, launch_dot_partial(n, b, b, partial, s));
