@@ -265,9 +265,10 @@ int orc_numeric(int64_t n, const int64_t *rpA, const int32_t *ciA, const double 
 
 /* ------------------------------------------------------------------------ */
 /* Applying M^-1 = U~^-1 L~^-1 (Eq. 1): forward substitution (Eq. 3b) with   */
-/* a running subtraction in ascending column order, then backward            */
-/* substitution, running subtraction in ascending column order, then the     */
-/* division by the pivot.                                                    */
+/* a running subtraction in ascending column order; then the U~ stage from   */
+/* the last row to the first and from right to left within a row (the order */
+/* Sec. 3.5 gives for the U~ stage): running subtraction in descending      */
+/* column order, then the division by the pivot.                            */
 /* ------------------------------------------------------------------------ */
 int orc_apply(int64_t n, const int64_t *rpF, const int32_t *ciF, const double *vF,
               const double *p, double *x, double *y)
@@ -283,7 +284,7 @@ int orc_apply(int64_t n, const int64_t *rpF, const int32_t *ciF, const double *v
     }
     for (int64_t i = n - 1; i >= 0; --i) {
         double s = x[i];
-        for (int64_t q = diag[i] + 1; q < rpF[i + 1]; ++q) s = s - vF[q] * y[ciF[q]];
+        for (int64_t q = rpF[i + 1] - 1; q > diag[i]; --q) s = s - vF[q] * y[ciF[q]];
         y[i] = s / vF[diag[i]];
     }
     free(diag);
@@ -442,7 +443,7 @@ done:
 /*   z = U~^-T ybar  (i ascending, z_i = (ybar_i - sum_{j<i} f_ji z_j)/f_ii, */
 /*                    running subtraction in ascending j)                    */
 /*   w = L~^-T z     (i descending, w_i = z_i - sum_{j>i} f_ji w_j,          */
-/*                    running subtraction in ascending j)                    */
+/*                    running subtraction in descending j)                   */
 /*   bbar = w;  Fbar_ij = -(z_i y_j) on U (j >= i);  Fbar_ih = -(w_i x_h)    */
 /*   on the strict lower part.                                               */
 /* ------------------------------------------------------------------------ */
@@ -499,13 +500,13 @@ int orc_apply_adjoint(int64_t n, const int64_t *rpF, const int32_t *ciF, const d
         }
         z[i] = s / vF[diag[i]];
     }
-    /* w = L^-T z: column i of L = rows j > i */
+    /* w = L^-T z: column i of L = rows j > i, taken in descending j */
     for (int64_t i = n - 1; i >= 0; --i) {
         double s = z[i];
-        for (int64_t a = tp[i]; a < tp[i + 1]; ++a) {
+        for (int64_t a = tp[i + 1] - 1; a >= tp[i]; --a) {
             int64_t q = ts[a];
             int64_t j = row_of(n, rpF, q);
-            if (j <= i) continue;
+            if (j <= i) break; /* rows descending: the rest are on/above the diagonal */
             s = s - vF[q] * bbar[j];
         }
         bbar[i] = s;

@@ -284,8 +284,10 @@ def test_apply_against_triangular_solves():
 
 
 def test_apply_order_of_subtractions():
-    """The running subtraction goes in ascending column order: a row whose
-    terms cancel differently in another order exposes the order."""
+    """Forward: running subtraction in ascending column order (Eq. 3b).
+    Backward: from right to left within a row (Sec. 3.5's order for the U~
+    stage).  A row whose terms round differently in another order exposes
+    the order."""
     # row 3 of L: x3 = p3 - f30 x0 - f31 x1 - f32 x2 with x = (2^53, 1, 1)
     n = 4
     M = np.eye(n, dtype=bool)
@@ -304,8 +306,9 @@ def test_apply_order_of_subtractions():
     vals2[0, 1:] = -1.0
     rp2, ci2, v2 = P.csr_from_dense_mask(M2, vals2)
     x2, y2 = O.apply(n, rp2, ci2, v2, np.array([1.0, 1.0, 1.0, 2.0**53]))
-    # ((1 + 1) + 1) + 2^53 = 2^53 + 3 -> rounds to 2^53 + 4
-    assert y2[0] == 2.0**53 + 4.0
+    # right to left: ((1 + 2^53) + 1) + 1, each +1 rounds away (ties to even): 2^53
+    # (left to right would give ((1 + 1) + 1) + 2^53 -> 2^53 + 4)
+    assert y2[0] == 2.0**53
 
 
 def test_apply_exact_rational():
