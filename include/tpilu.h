@@ -105,6 +105,13 @@ TPILU_API tpilu_status tpilu_ctx_set_watchdog(tpilu_ctx ctx, uint32_t timeout_us
  * gives the same bits; it only changes speed.  Used to test that claim. */
 TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t waves);
 
+/* Launch shape of the single-instance triangular solves: 0 = automatic
+ * (currently always the whole device, the faster shape on every measured
+ * workload), 1 = whole device, 2 = one workgroup (16 wavefronts on one CU).
+ * Same bits in every mode. */
+enum { TPILU_SOLVER_AUTO = 0, TPILU_SOLVER_DEVICE = 1, TPILU_SOLVER_WORKGROUP = 2 };
+TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode);
+
 /* Kernel timing.  With timing on, the library brackets the main kernel of
  * every numeric factorization, forward solve and backward solve it launches
  * with a pair of hipEvents recorded on the ctx stream (outside graph
@@ -112,6 +119,15 @@ TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t waves);
  * duration in milliseconds and the number of launches of one kernel kind
  * (TPILU_KERNEL_*) since the last read, and resets that kind. */
 enum { TPILU_KERNEL_NUMERIC = 0, TPILU_KERNEL_FORWARD = 1, TPILU_KERNEL_BACKWARD = 2 };
+
+/* Per-row timeline for analysing the dependency critical path: with a
+ * device buffer of 4n uint64 set (NULL turns it off), the single-instance
+ * numeric factorization and forward solve record, for every row i, the
+ * wall-clock tick (s_memrealtime, the device's wall clock rate) at which a
+ * wavefront started it in buf[i] and published it in buf[n + i]; the
+ * backward solve uses buf[2n + i] and buf[3n + i].  The buffer must hold 4n
+ * entries of every pattern used while it is set. */
+TPILU_API tpilu_status tpilu_ctx_set_trace(tpilu_ctx ctx, uint64_t *rows2n);
 TPILU_API tpilu_status tpilu_ctx_set_timing(tpilu_ctx ctx, int on);
 TPILU_API tpilu_status tpilu_ctx_read_timing(tpilu_ctx ctx, int kernel, double *total_ms /* host */,
                                              int64_t *launches /* host */);
@@ -185,7 +201,8 @@ TPILU_API tpilu_status tpilu_pattern_check(tpilu_ctx ctx, tpilu_pattern pat, int
  *   forward  (Eq. 3b): x_i = b_i - sum_{h<i} f_ih x_h, subtractions in
  *                      ascending h;
  *   backward:          y_i = (x_i - sum_{j>i} f_ij y_j) / f_ii, subtractions
- *                      in ascending j, then the division.
+ *                      from right to left (j descending, the order Sec. 3.5
+ *                      gives for the U~ stage), then the division.
  * f_val, b, y: [n * batch] / [nnz_f * batch] device arrays; x_out (nullable,
  * n * batch) receives the intermediate x.  b and y may not alias.
  * ------------------------------------------------------------------------- */
@@ -226,7 +243,7 @@ TPILU_API tpilu_status tpilu_dot(tpilu_ctx ctx, int64_t n, const double *x, cons
  *   z = U~^-T ybar: z_i = (ybar_i - sum_{j<i} f_ji z_j) / f_ii, ascending i,
  *                   subtractions in ascending j;
  *   w = L~^-T z:    w_i = z_i - sum_{j>i} f_ji w_j, descending i,
- *                   subtractions in ascending j;
+ *                   subtractions in descending j;
  *   bbar = w;  fbar_ij = -(z_i * y_j) on U~ (j >= i);  fbar_ih = -(w_i * x_h)
  *   on the strictly lower part.
  * All arrays device, [n * batch] or [nnz_f * batch].

@@ -20,7 +20,7 @@ OK, E_INVAL, E_NOMEM, E_ZEROPIVOT, E_DEVICE, E_NOTCONV, E_TIMEOUT = range(7)
 
 EXPORTED = [
     "tpilu_ctx_create", "tpilu_ctx_set_stream", "tpilu_ctx_destroy", "tpilu_status_string",
-    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
+    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
     "tpilu_pattern_export", "tpilu_pattern_destroy", "tpilu_numeric", "tpilu_pattern_check",
     "tpilu_apply", "tpilu_gmres", "tpilu_spmv", "tpilu_dot", "tpilu_apply_adjoint",
     "tpilu_numeric_adjoint", "tpilu_batched_graph_create", "tpilu_batched_graph_launch",
@@ -69,6 +69,8 @@ def load_library():
             "tpilu_last_error": ([P], C.c_char_p),
             "tpilu_ctx_set_watchdog": ([P, u32, i64], st),
             "tpilu_ctx_set_grid": ([P, i32], st),
+            "tpilu_ctx_set_solver": ([P, C.c_int], st),
+            "tpilu_ctx_set_trace": ([P, P], st),
             "tpilu_ctx_set_timing": ([P, C.c_int], st),
             "tpilu_ctx_read_timing": ([P, C.c_int, C.POINTER(dbl), C.POINTER(i64)], st),
             "tpilu_symbolic": ([P, i64, i64, P, P, i32, C.POINTER(P)], st),
@@ -136,6 +138,15 @@ class Context:
         cnt = C.c_int64(0)
         self.check(load_library().tpilu_ctx_read_timing(self.h, kernel, C.byref(ms), C.byref(cnt)), "read_timing")
         return ms.value, cnt.value
+
+    SOLVER_AUTO, SOLVER_DEVICE, SOLVER_WORKGROUP = 0, 1, 2
+
+    def set_solver(self, mode: int = 0):
+        self.check(load_library().tpilu_ctx_set_solver(self.h, mode), "set_solver")
+
+    def set_trace(self, buf=None):
+        """Per-row timeline: a uint64/int64 device tensor of 4n entries, or None."""
+        self.check(load_library().tpilu_ctx_set_trace(self.h, _ptr(buf)), "set_trace")
 
     def set_grid(self, waves: int = 0):
         self.check(load_library().tpilu_ctx_set_grid(self.h, waves), "set_grid")

@@ -76,7 +76,7 @@ __device__ __noinline__ double wait_final_slow(const double* p, Ctl* ctl, uint64
         uint64_t v = ld_coherent(p);
         if (v != kPending) return as_f64(v);
         if ((n & 31u) == 0u) {
-            if (ld_u32_coherent(&ctl->abort) != 0u) return as_f64(kQNaN);
+            if ((n & 255u) == 0u && ld_u32_coherent(&ctl->abort) != 0u) return as_f64(kQNaN);
             const uint64_t now = wall_clock64();
             if (n == 0) {
                 t0 = now;
@@ -118,6 +118,12 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 // barrier then only orders the wave's own LDS traffic.
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
+// Optional per-row timeline (wall-clock ticks): the slot for "started" and
+// the slot for "published" are chosen by each kernel.
+__device__ __forceinline__ void trace_mark(unsigned long long* trace, int64_t slot) {
+    if (trace && lane_id() == 0) trace[slot] = wall_clock64();
+}
+
 // Value that is the same in every lane, made visibly uniform (SGPR) for the
 // compiler.  Only call with all lanes active.
 __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -140,6 +146,81 @@ __device__ __forceinline__ double bcast_lane(double v, int src) {
     uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(u), src);
     uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(u >> 32), src);
     return as_f64((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Communication scope of the hand-off protocol: across the whole device
+// (agent-scope loads, bypassing the per-XCD L2s) or inside one workgroup
+// (all waves on one CU, whose caches are coherent for them).
+enum class Scope { Device, Workgroup };
+
+template <Scope S>
+__device__ __forceinline__ uint64_t ld_poll(const double* p) {
+    if constexpr (S == Scope::Device) return ld_coherent(p);
+    return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <Scope S>
+__device__ __forceinline__ void st_final(double* p, double v) {
+    if constexpr (S == Scope::Device) {
+        st_publish(p, v);
+    } else {
+        __hip_atomic_store(reinterpret_cast<uint64_t*>(p), as_u64(v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+// Running subtraction s <- s - f_k * v_k for k = 0 .. cnt-1 in that order,
+// where lane k holds f_k and the address of v_k (cnt <= 64).  The values are
+// produced by other rows; the chain advances over every prefix of entries
+// whose value is already final, so once the last value arrives only the rest
+// of the chain is left to do.  While blocked it polls only the entry it is
+// blocked on (all pending entries again right after it made progress, and
+// every 8th round): thousands of waiting wavefronts polling every pending
+// value would load the memory side enough to slow every hand-off down.
+// The bits are those of the plain sequential loop.  On a watchdog timeout or
+// abort the result is a quiet NaN (the call then reports the timeout).
+template <Scope S>
+__device__ __forceinline__ double chain_sub(double s, int32_t cnt, double f, const double* src, Ctl* ctl,
+                                            uint64_t limit) {
+    const int lane = lane_id();
+    const bool has = lane < cnt;
+    uint64_t v = has ? ld_cached(src) : 0ull;
+    bool ready = !has || v != kPending;
+    double prod = (has && ready) ? f * as_f64(v) : 0.0;
+    int32_t k = 0;
+    uint32_t polls = 0;
+    uint64_t t0 = 0;
+    for (;;) {
+        const uint64_t pend = ~__ballot(ready) & (k >= kWave ? 0ull : (~0ull << k));
+        const int32_t stop = pend ? min((int32_t)__builtin_ctzll(pend), cnt) : cnt;
+        const bool progressed = stop > k;
+        for (; k < stop; ++k) s = s - bcast_lane(prod, k);
+        if (k >= cnt) break;
+        if (!ready && (lane == k || progressed || (polls & 7u) == 0u)) {
+            v = ld_poll<S>(src);
+            if (v != kPending) {
+                ready = true;
+                prod = f * as_f64(v);
+            }
+        }
+        if ((polls & 31u) == 0u) {
+            if ((polls & 255u) == 0u && ld_u32_coherent(&ctl->abort) != 0u) return as_f64(kQNaN);
+            const uint64_t now = wall_clock64();
+            if (polls == 0) {
+                t0 = now;
+            } else if (now - t0 > limit) {
+                if (lane_id() == 0) {
+                    atomicOr(&ctl->status, kStTimeout);
+                    __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                return as_f64(kQNaN);
+            }
+        }
+        ++polls;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return s;
 }
 
 }  // namespace tpilu

@@ -106,25 +106,25 @@ __global__ __launch_bounds__(64) void k_adj_solve_u(PatDev P, AdjPat T, const do
         if (t >= ntask) break;
         const int32_t i = (int32_t)(t / (uint32_t)B);
         const int32_t b = (int32_t)(t % (uint32_t)B);
+        // rows j < i of column i, taken in ascending j
         const int64_t a0 = T.tpU[i], a1 = T.tpU[i + 1];
         double s = sanitize_input(ybar[(int64_t)i * B + b], ctl);
         for (int64_t c = a0; c < a1; c += kWave) {
-            const int64_t a = c + lane;
-            double prod = 0.0;
-            if (a < a1) {
-                const int32_t j = T.trU[a];
-                const double f = F[(int64_t)T.tsU[a] * B + b];
-                prod = f * wait_final(z + (int64_t)j * B + b, ctl, spin_limit);
-            }
             const int32_t cnt = (int32_t)min<int64_t>(kWave, a1 - c);
-            for (int32_t k = 0; k < cnt; ++k) s = s - bcast_lane(prod, k);
+            double f = 0.0;
+            const double* src = z;
+            if (lane < cnt) {
+                f = F[(int64_t)T.tsU[c + lane] * B + b];
+                src = z + (int64_t)T.trU[c + lane] * B + b;
+            }
+            s = chain_sub<Scope::Device>(s, cnt, f, src, ctl, spin_limit);
         }
         const double r = s / F[(int64_t)P.diagF[i] * B + b];
         if (lane == 0) st_publish(z + (int64_t)i * B + b, r);
     }
 }
 
-// w = L~^-T z: i descending, w_i = z_i - sum_{j>i} f_ji w_j
+// w = L~^-T z: i descending, w_i = z_i - sum_{j>i} f_ji w_j, j descending
 __global__ __launch_bounds__(64) void k_adj_solve_l(PatDev P, AdjPat T, const double* __restrict__ F,
                                                     int32_t B, const double* __restrict__ z,
                                                     double* w, Ctl* ctl, uint64_t spin_limit) {
@@ -135,18 +135,19 @@ __global__ __launch_bounds__(64) void k_adj_solve_l(PatDev P, AdjPat T, const do
         if (t >= ntask) break;
         const int32_t i = P.n - 1 - (int32_t)(t / (uint32_t)B);
         const int32_t b = (int32_t)(t % (uint32_t)B);
+        // rows j > i of column i, taken in descending j
         const int64_t a0 = T.tpL[i], a1 = T.tpL[i + 1];
         double s = z[(int64_t)i * B + b];
-        for (int64_t c = a0; c < a1; c += kWave) {
-            const int64_t a = c + lane;
-            double prod = 0.0;
-            if (a < a1) {
-                const int32_t j = T.trL[a];
-                const double f = F[(int64_t)T.tsL[a] * B + b];
-                prod = f * wait_final(w + (int64_t)j * B + b, ctl, spin_limit);
+        for (int64_t c = 0; c < a1 - a0; c += kWave) {
+            const int32_t cnt = (int32_t)min<int64_t>(kWave, a1 - a0 - c);
+            double f = 0.0;
+            const double* src = w;
+            if (lane < cnt) {
+                const int64_t a = a1 - 1 - (c + lane);
+                f = F[(int64_t)T.tsL[a] * B + b];
+                src = w + (int64_t)T.trL[a] * B + b;
             }
-            const int32_t cnt = (int32_t)min<int64_t>(kWave, a1 - c);
-            for (int32_t k = 0; k < cnt; ++k) s = s - bcast_lane(prod, k);
+            s = chain_sub<Scope::Device>(s, cnt, f, src, ctl, spin_limit);
         }
         if (lane == 0) st_publish(w + (int64_t)i * B + b, s);
     }

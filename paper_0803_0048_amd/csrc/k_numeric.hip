@@ -42,6 +42,50 @@ hipError_t launch_fill_pending(double* p, int64_t n, Ctl* ctl, bool reset_status
     return hipGetLastError();
 }
 
+// Wait until pivot row h's diagonal (slot dh) and every value f_ht that the
+// pivot contributes (pairs [ea, eb) of the staged group) are final.  All of
+// them are polled in the same round, so a row that is waiting on h pays one
+// round trip after h is published, not one for the diagonal and another for
+// the rest.  Final values are written back into the staged copies.  Returns
+// the diagonal's bits (a quiet NaN after a watchdog timeout or abort).
+__device__ __forceinline__ uint64_t wait_pivot(const double* F, int32_t dh, uint64_t ub, int32_t ea,
+                                               int32_t eb, const int32_t* pr_q, uint64_t* pr_v,
+                                               Ctl* ctl, uint64_t limit) {
+    const int lane = lane_id();
+    uint32_t polls = 0;
+    uint64_t t0 = 0;
+    for (;;) {
+        bool pend = false;
+        if (ub == kPending) {
+            ub = ld_coherent(F + dh);
+            pend = ub == kPending;
+        }
+        for (int32_t e = ea + lane; e < eb; e += kWave) {
+            if (pr_v[e] == kPending) {
+                const uint64_t v = ld_coherent(F + pr_q[e]);
+                if (v != kPending) pr_v[e] = v;
+                else pend = true;
+            }
+        }
+        if (!__any(pend)) return ub;
+        if ((polls & 31u) == 0u) {
+            if ((polls & 255u) == 0u && ld_u32_coherent(&ctl->abort) != 0u) return kQNaN;
+            const uint64_t now = wall_clock64();
+            if (polls == 0) {
+                t0 = now;
+            } else if (now - t0 > limit) {
+                if (lane == 0) {
+                    atomicOr(&ctl->status, kStTimeout);
+                    __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                return kQNaN;
+            }
+        }
+        ++polls;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // ----------------------------------------------------------------------------------
 // single instance: one wavefront per row, lanes over the updates of a pivot
 // ----------------------------------------------------------------------------------
@@ -63,7 +107,8 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
         if (t >= (uint32_t)n) break;
-        const int32_t j = (int32_t)t;
+        const int32_t j = P.permL ? P.permL[t] : (int32_t)t;
+        trace_mark(P.trace, j);
         const int64_t rs = P.rpF[j], re = P.rpF[j + 1];
         const int32_t len = (int32_t)(re - rs);
         const int64_t dj = P.diagF[j];
@@ -104,13 +149,22 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
             wave_sync();
             for (int32_t i = 0; i < np; ++i) {
                 const int64_t s = s0 + i;
-                const double u = wait_final(F + piv_dh[i], piv_u[i], ctl, spin_limit);
-                const double l = W[s - rs] / u;
+                uint64_t ub = piv_u[i];
+                const int32_t ea = piv_e[i], eb = piv_e[i + 1];
+                if (!big) {
+                    // the pivot and every value it contributes, polled together
+                    bool ok = ub != kPending;
+                    for (int32_t e = ea + lane; e < eb; e += kWave) ok = ok && pr_v[e] != kPending;
+                    if (!__all(ok)) ub = wait_pivot(F, piv_dh[i], ub, ea, eb, pr_q, pr_v, ctl, spin_limit);
+                } else {
+                    ub = as_u64(wait_final(F + piv_dh[i], ub, ctl, spin_limit));
+                }
+                const double l = W[s - rs] / as_f64(ub);
                 if (lane == 0) W[s - rs] = l;
                 if (!big) {
-                    const int32_t ea = piv_e[i], eb = piv_e[i + 1];
                     for (int32_t e = ea + lane; e < eb; e += kWave) {
-                        const double v = wait_final(F + pr_q[e], pr_v[e], ctl, spin_limit);
+                        const uint64_t vb = pr_v[e];
+                        const double v = as_f64(vb == kPending ? kQNaN : vb);  // pending only after a timeout
                         const int32_t p = pr_p[e];
                         W[p] = W[p] - l * v;
                     }
@@ -133,6 +187,7 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
             for (int32_t e = dl + lane; e < len; e += kWave) st_publish(F + rs + e, W[e]);
             for (int32_t e = lane; e < dl; e += kWave) F[rs + e] = W[e];
         }
+        trace_mark(P.trace, (int64_t)n + j);
         wave_sync();
     }
 }
@@ -162,7 +217,8 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
         if (t >= ntask) break;
-        const int32_t j = (int32_t)(t / (uint32_t)G);
+        const int32_t jr = (int32_t)(t / (uint32_t)G);
+        const int32_t j = P.permL ? P.permL[jr] : jr;
         const int32_t g = (int32_t)(t % (uint32_t)G);
         const int32_t col = g * kWave + lane;
         const bool act = col < B;

@@ -1,75 +1,118 @@
 // Applying M^-1 = U~^-1 L~^-1 (Eq. 1) on gfx950.
 //
 // forward  (Eq. 3b): x_i = b_i - f_ih1 x_h1 - f_ih2 x_h2 - ...   h ascending
-// backward:          y_i = (x_i - f_ij1 y_j1 - f_ij2 y_j2 - ...) / f_ii, j ascending
+// backward:          y_i = (x_i - f_ijm y_jm - ... - f_ij1 y_j1) / f_ii,
+//                    j descending (right to left, the order Sec. 3.5 gives
+//                    for the U~ stage)
 //
-// Both are dependency-driven persistent kernels (rows handed out through an
-// atomic ticket: ascending for the forward sweep, descending for the
-// backward sweep).  For one instance a wavefront owns a row: its lanes form
-// the products f_ih * x_h in parallel (each rounded on its own) as the x_h
-// arrive, and the running subtraction is then carried through the products
-// strictly in ascending column order, which keeps every bit of the
-// sequential result.  For batches the lanes are instances and each lane runs
-// its own chain.  x and y start as kPending and each slot is written once.
+// Both are dependency-driven: rows go in ascending order for the forward
+// sweep and descending for the backward one.  For one instance a wavefront
+// owns a row: its lanes form the products (each rounded on its own) and the
+// running subtraction is carried through them strictly in the order above,
+// advancing as the needed values arrive, which keeps every bit of the
+// sequential result.  With these orders the value that arrives last (the
+// nearest row) is the last term of the chain.  Two launch shapes give the
+// same bits: a persistent grid over the whole device (rows handed out by an
+// atomic ticket) and a single workgroup whose 16 wavefronts share one CU.
+// For batches the lanes are instances and each lane runs its own chain.
+// x and y start as kPending and each slot is written once.
 #include "kernels.h"
 
 namespace tpilu {
 
+// one row of the forward sweep, one wavefront: x_i = b_i - sum_h f_ih x_h,
+// h ascending
+template <Scope S>
+__device__ __forceinline__ void forward_row(const PatDev& P, const double* __restrict__ F,
+                                            const double* __restrict__ b, double* x, Ctl* ctl,
+                                            uint64_t limit, int32_t i) {
+    const int lane = lane_id();
+    trace_mark(P.trace, i);
+    const int64_t rs = P.rpF[i], dj = P.diagF[i];
+    double s = sanitize_input(b[i], ctl);
+    for (int64_t c = rs; c < dj; c += kWave) {
+        const int32_t cnt = (int32_t)min<int64_t>(kWave, dj - c);
+        double f = 0.0;
+        const double* src = x;
+        if (lane < cnt) {
+            f = F[c + lane];
+            src = x + P.ciF[c + lane];
+        }
+        s = chain_sub<S>(s, cnt, f, src, ctl, limit);
+    }
+    if (lane == 0) st_final<S>(x + i, s);
+    trace_mark(P.trace, (int64_t)P.n + i);
+}
+
+// one row of the backward sweep: y_i = (x_i - sum_j f_ij y_j) / f_ii with the
+// subtractions from right to left (j descending)
+template <Scope S>
+__device__ __forceinline__ void backward_row(const PatDev& P, const double* __restrict__ F,
+                                             const double* __restrict__ x, double* y, Ctl* ctl,
+                                             uint64_t limit, int32_t i) {
+    const int lane = lane_id();
+    trace_mark(P.trace, 2 * (int64_t)P.n + i);
+    const int64_t dj = P.diagF[i], re = P.rpF[i + 1];
+    const int64_t nu = re - dj - 1;
+    double s = x[i];
+    for (int64_t c = 0; c < nu; c += kWave) {
+        const int32_t cnt = (int32_t)min<int64_t>(kWave, nu - c);
+        double f = 0.0;
+        const double* src = y;
+        if (lane < cnt) {
+            const int64_t q = re - 1 - (c + lane);
+            f = F[q];
+            src = y + P.ciF[q];
+        }
+        s = chain_sub<S>(s, cnt, f, src, ctl, limit);
+    }
+    const double r = s / F[dj];
+    if (lane == 0) st_final<S>(y + i, r);
+    trace_mark(P.trace, 3 * (int64_t)P.n + i);
+}
+
+// whole device: persistent grid, rows handed out by an atomic ticket
 __global__ __launch_bounds__(64) void k_forward_row(PatDev P, const double* __restrict__ F,
                                                     const double* __restrict__ b, double* x,
                                                     Ctl* ctl, uint64_t spin_limit) {
-    const int lane = lane_id();
-    const int32_t n = P.n;
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
-        if (t >= (uint32_t)n) break;
-        const int32_t i = (int32_t)t;
-        const int64_t rs = P.rpF[i], dj = P.diagF[i];
-        const int32_t nl = (int32_t)(dj - rs);
-        double s = sanitize_input(b[i], ctl);
-        for (int32_t c = 0; c < nl; c += kWave) {
-            const int32_t e = c + lane;
-            double prod = 0.0;
-            if (e < nl) {
-                const int32_t h = P.ciF[rs + e];
-                const double f = F[rs + e];
-                const double xv = wait_final(x + h, ctl, spin_limit);
-                prod = f * xv;
-            }
-            const int32_t cnt = min(kWave, nl - c);
-            for (int32_t k = 0; k < cnt; ++k) s = s - bcast_lane(prod, k);
-        }
-        if (lane == 0) st_publish(x + i, s);
+        if (t >= (uint32_t)P.n) break;
+        forward_row<Scope::Device>(P, F, b, x, ctl, spin_limit, P.permL ? P.permL[t] : (int32_t)t);
     }
 }
 
 __global__ __launch_bounds__(64) void k_backward_row(PatDev P, const double* __restrict__ F,
                                                      const double* __restrict__ x, double* y,
                                                      Ctl* ctl, uint64_t spin_limit) {
-    const int lane = lane_id();
-    const int32_t n = P.n;
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
-        if (t >= (uint32_t)n) break;
-        const int32_t i = n - 1 - (int32_t)t;
-        const int64_t dj = P.diagF[i], re = P.rpF[i + 1];
-        const int32_t nu = (int32_t)(re - dj - 1);
-        double s = x[i];
-        for (int32_t c = 0; c < nu; c += kWave) {
-            const int32_t e = c + lane;
-            double prod = 0.0;
-            if (e < nu) {
-                const int32_t jc = P.ciF[dj + 1 + e];
-                const double f = F[dj + 1 + e];
-                const double yv = wait_final(y + jc, ctl, spin_limit);
-                prod = f * yv;
-            }
-            const int32_t cnt = min(kWave, nu - c);
-            for (int32_t k = 0; k < cnt; ++k) s = s - bcast_lane(prod, k);
-        }
-        const double r = s / F[dj];
-        if (lane == 0) st_publish(y + i, r);
+        if (t >= (uint32_t)P.n) break;
+        backward_row<Scope::Device>(P, F, x, y, ctl, spin_limit, P.permU ? P.permU[t] : P.n - 1 - (int32_t)t);
     }
+}
+
+// one workgroup (one CU, 16 wavefronts): for dependency graphs that are deep
+// and narrow, the hand-off through the CU's own caches is several times
+// cheaper than a round trip across XCDs.  Rows are dealt round-robin; all
+// wavefronts are resident, so the smallest unfinished row is always being
+// worked on and the sweep cannot deadlock.
+__global__ __launch_bounds__(1024) void k_forward_wg(PatDev P, const double* __restrict__ F,
+                                                     const double* __restrict__ b, double* x,
+                                                     Ctl* ctl, uint64_t spin_limit) {
+    const int32_t wave = uniform((int32_t)(threadIdx.x >> 6));
+    const int32_t nw = (int32_t)(blockDim.x >> 6);
+    for (int32_t r = wave; r < P.n; r += nw)
+        forward_row<Scope::Workgroup>(P, F, b, x, ctl, spin_limit, P.permL ? P.permL[r] : r);
+}
+
+__global__ __launch_bounds__(1024) void k_backward_wg(PatDev P, const double* __restrict__ F,
+                                                      const double* __restrict__ x, double* y,
+                                                      Ctl* ctl, uint64_t spin_limit) {
+    const int32_t wave = uniform((int32_t)(threadIdx.x >> 6));
+    const int32_t nw = (int32_t)(blockDim.x >> 6);
+    for (int32_t r = wave; r < P.n; r += nw)
+        backward_row<Scope::Workgroup>(P, F, x, y, ctl, spin_limit, P.permU ? P.permU[r] : P.n - 1 - r);
 }
 
 // batches: lanes are instances; each lane runs the sequential chain of its
@@ -87,7 +130,8 @@ __global__ __launch_bounds__(64) void k_forward_batch(PatDev P, const double* __
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
         if (t >= ntask) break;
-        const int32_t i = (int32_t)(t / (uint32_t)G);
+        const int32_t ir = (int32_t)(t / (uint32_t)G);
+        const int32_t i = P.permL ? P.permL[ir] : ir;
         const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
         if (col < B) {
             const int64_t rs = P.rpF[i], dj = P.diagF[i];
@@ -127,26 +171,28 @@ __global__ __launch_bounds__(64) void k_backward_batch(PatDev P, const double* _
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
         if (t >= ntask) break;
-        const int32_t i = n - 1 - (int32_t)(t / (uint32_t)G);
+        const int32_t ir = (int32_t)(t / (uint32_t)G);
+        const int32_t i = P.permU ? P.permU[ir] : n - 1 - ir;
         const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
         if (col < B) {
             const int64_t dj = P.diagF[i], re = P.rpF[i + 1];
             double s = x[(int64_t)i * B + col];
-            for (int64_t c = dj + 1; c < re; c += kSolveChunk) {
+            // right to left: slots re-1, re-2, ..., dj+1
+            for (int64_t c = re - 1; c > dj; c -= kSolveChunk) {
                 double fv[kSolveChunk];
                 uint64_t yv[kSolveChunk];
                 int32_t jj[kSolveChunk];
 #pragma unroll
                 for (int u = 0; u < kSolveChunk; ++u) {
-                    if (c + u < re) {
-                        jj[u] = P.ciF[c + u];
-                        fv[u] = F[(c + u) * B + col];
+                    if (c - u > dj) {
+                        jj[u] = P.ciF[c - u];
+                        fv[u] = F[(c - u) * B + col];
                         yv[u] = ld_cached(y + (int64_t)jj[u] * B + col);
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < kSolveChunk; ++u) {
-                    if (c + u < re) {
+                    if (c - u > dj) {
                         const double yy = wait_final(y + (int64_t)jj[u] * B + col, yv[u], ctl, spin_limit);
                         s = s - fv[u] * yy;
                     }
@@ -162,10 +208,13 @@ int solve_grid(int32_t batch, int num_cu) {
     return 16 * num_cu;
 }
 
+// grid <= 0 selects the one-workgroup variant (single instance only)
 hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, const double* b,
                           double* x, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    if (batch == 1)
+    if (batch == 1 && grid <= 0)
+        hipLaunchKernelGGL(k_forward_wg, dim3(1), dim3(1024), 0, s, P, f_val, b, x, ctl, spin_limit);
+    else if (batch == 1)
         hipLaunchKernelGGL(k_forward_row, dim3(grid), dim3(64), 0, s, P, f_val, b, x, ctl, spin_limit);
     else
         hipLaunchKernelGGL(k_forward_batch, dim3(grid), dim3(64), 0, s, P, f_val, batch, b, x, ctl,
@@ -176,7 +225,9 @@ hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, c
 hipError_t launch_backward(const PatDev& P, const double* f_val, int32_t batch, const double* x,
                            double* y, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    if (batch == 1)
+    if (batch == 1 && grid <= 0)
+        hipLaunchKernelGGL(k_backward_wg, dim3(1), dim3(1024), 0, s, P, f_val, x, y, ctl, spin_limit);
+    else if (batch == 1)
         hipLaunchKernelGGL(k_backward_row, dim3(grid), dim3(64), 0, s, P, f_val, x, y, ctl, spin_limit);
     else
         hipLaunchKernelGGL(k_backward_batch, dim3(grid), dim3(64), 0, s, P, f_val, batch, x, y, ctl,

@@ -518,15 +518,19 @@ hipError_t launch_stats(int32_t n, const int64_t* rpF, const int32_t* diagF, Pat
 // dependency depth (informational): depth_i = 1 + max depth_h over the rows h
 // row i needs (L part ascending, or U part descending); -1 = not yet known
 // ------------------------------------------------------------------------------------
+template <Scope S>
 __device__ __forceinline__ int32_t wait_depth(const int32_t* p, Ctl* ctl, uint64_t spin_limit) {
     int32_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     uint32_t n = 0;
     uint64_t t0 = 0;
     while (v < 0) {
-        v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if constexpr (S == Scope::Device)
+            v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (v >= 0) break;
         if ((n & 31u) == 0u) {
-            if (ld_u32_coherent(&ctl->abort) != 0u) return 0;
+            if ((n & 255u) == 0u && ld_u32_coherent(&ctl->abort) != 0u) return 0;
             const uint64_t now = wall_clock64();
             if (n == 0) {
                 t0 = now;
@@ -542,31 +546,156 @@ __device__ __forceinline__ int32_t wait_depth(const int32_t* p, Ctl* ctl, uint64
     return v;
 }
 
+template <Scope S>
+__device__ __forceinline__ void depth_row(int upper, const int64_t* __restrict__ rpF,
+                                          const int32_t* __restrict__ ciF,
+                                          const int32_t* __restrict__ diagF, int32_t* depth, Ctl* ctl,
+                                          uint64_t spin_limit, int32_t i) {
+    const int lane = lane_id();
+    int64_t a, b;
+    if (upper) { a = diagF[i] + 1; b = rpF[i + 1]; }
+    else { a = rpF[i]; b = diagF[i]; }
+    int32_t best = 0;
+    for (int64_t q = a + lane; q < b; q += kWave)
+        best = max(best, wait_depth<S>(depth + ciF[q], ctl, spin_limit));
+    for (int off = 32; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off));
+    if (lane == 0) {
+        if constexpr (S == Scope::Device)
+            __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
 __global__ __launch_bounds__(64) void k_depth(int upper, int32_t n, const int64_t* __restrict__ rpF,
                                               const int32_t* __restrict__ ciF,
                                               const int32_t* __restrict__ diagF, int32_t* depth,
                                               Ctl* ctl, uint64_t spin_limit) {
-    const int lane = lane_id();
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
         if (t >= (uint32_t)n) break;
         const int32_t i = upper ? n - 1 - (int32_t)t : (int32_t)t;
-        int64_t a, b;
-        if (upper) { a = diagF[i] + 1; b = rpF[i + 1]; }
-        else { a = rpF[i]; b = diagF[i]; }
-        int32_t best = 0;
-        for (int64_t q = a + lane; q < b; q += kWave) best = max(best, wait_depth(depth + ciF[q], ctl, spin_limit));
-        for (int off = 32; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off));
-        if (lane == 0)
-            __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        depth_row<Scope::Device>(upper, rpF, ciF, diagF, depth, ctl, spin_limit, i);
     }
 }
 
+// one workgroup, rows dealt round-robin to its 16 wavefronts
+__global__ __launch_bounds__(1024) void k_depth_wg(int upper, int32_t n, const int64_t* __restrict__ rpF,
+                                                   const int32_t* __restrict__ ciF,
+                                                   const int32_t* __restrict__ diagF, int32_t* depth,
+                                                   Ctl* ctl, uint64_t spin_limit) {
+    const int32_t wave = uniform((int32_t)(threadIdx.x >> 6));
+    const int32_t nw = (int32_t)(blockDim.x >> 6);
+    for (int32_t r = wave; r < n; r += nw)
+        depth_row<Scope::Workgroup>(upper, rpF, ciF, diagF, depth, ctl, spin_limit,
+                                    upper ? n - 1 - r : r);
+}
+
+// Lane per row: a ticket hands a wavefront 64 consecutive rows (in the
+// sweep's order), so the whole matrix can be in flight at once and wide
+// dependency graphs are not throttled by the ticket window.  A lane scans its
+// row's dependencies, at most 8 per round, and stops at the first one not
+// known yet; the wavefront keeps looping until every lane published, so lanes
+// that depend on other lanes of the same wavefront cannot deadlock.
+__global__ __launch_bounds__(64) void k_depth_lanes(int upper, int32_t n, const int64_t* __restrict__ rpF,
+                                                    const int32_t* __restrict__ ciF,
+                                                    const int32_t* __restrict__ diagF, int32_t* depth,
+                                                    Ctl* ctl, uint64_t spin_limit) {
+    const int lane = lane_id();
+    for (;;) {
+        const uint32_t t = wave_ticket(ctl);
+        const int64_t r = (int64_t)t * kWave + lane;
+        if ((int64_t)t * kWave >= n) break;
+        const bool valid = r < n;
+        const int32_t i = valid ? (upper ? n - 1 - (int32_t)r : (int32_t)r) : 0;
+        int64_t q = 0, b = 0;
+        if (valid) {
+            if (upper) { q = diagF[i] + 1; b = rpF[i + 1]; }
+            else { q = rpF[i]; b = diagF[i]; }
+        }
+        int32_t best = 0;
+        bool done = !valid;
+        uint32_t polls = 0;
+        uint64_t t0 = 0;
+        for (;;) {
+            if (!done) {
+                for (int step = 0; step < 8 && q < b; ++step) {
+                    const int32_t* src = depth + ciF[q];
+                    int32_t d = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    if (d < 0) d = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (d < 0) break;
+                    best = max(best, d);
+                    ++q;
+                }
+                if (q >= b) {
+                    __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    done = true;
+                }
+            }
+            if (__all(done)) break;
+            if ((polls & 31u) == 0u) {
+                if ((polls & 255u) == 0u && ld_u32_coherent(&ctl->abort) != 0u) break;
+                const uint64_t now = wall_clock64();
+                if (polls == 0) {
+                    t0 = now;
+                } else if (now - t0 > spin_limit) {
+                    if (lane == 0) {
+                        atomicOr(&ctl->status, kStTimeout);
+                        __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    break;
+                }
+            }
+            ++polls;
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+}
+
+// Rows sorted by level (counting sort): hist, scan (shared scan kernel),
+// scatter.  The order inside a level is whatever the atomics give; any
+// order that lists every level before the next is a valid schedule, and the
+// results never depend on it.
+__global__ void k_level_hist(int32_t n, const int32_t* __restrict__ depth, int32_t* hist) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&hist[depth[i] - 1], 1);
+}
+
+__global__ void k_level_scatter(int32_t n, int upper, const int32_t* __restrict__ depth,
+                                const int64_t* __restrict__ off, int32_t* cursor, int32_t* perm) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t d = depth[i] - 1;
+    perm[off[d] + atomicAdd(&cursor[d], 1)] = i;
+    (void)upper;
+}
+
+hipError_t launch_level_order(int32_t n, int upper, const int32_t* depth, int32_t max_depth, int32_t* hist,
+                              int64_t* off, int64_t* scan_tmp, int32_t* perm, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipError_t e = launch_fill_i32(hist, 2 * (int64_t)max_depth, 0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_level_hist, dim3((n + 255) / 256), dim3(256), 0, s, n, depth, hist);
+    e = launch_scan(hist, max_depth, off, scan_tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_level_scatter, dim3((n + 255) / 256), dim3(256), 0, s, n, upper, depth, off,
+                       hist + max_depth, perm);
+    return hipGetLastError();
+}
+
+// grid <= 0 selects the one-workgroup variant
 hipError_t launch_depth(bool upper, int32_t n, const int64_t* rpF, const int32_t* ciF,
                         const int32_t* diagF, int32_t* depth, Ctl* ctl, uint64_t spin_limit,
                         int32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_depth, dim3(grid), dim3(64), 0, s, upper ? 1 : 0, n, rpF, ciF, diagF, depth,
-                       ctl, spin_limit);
+    if (grid == 0)
+        hipLaunchKernelGGL(k_depth_wg, dim3(1), dim3(1024), 0, s, upper ? 1 : 0, n, rpF, ciF, diagF,
+                           depth, ctl, spin_limit);
+    else if (grid < 0)
+        hipLaunchKernelGGL(k_depth_lanes, dim3(-grid), dim3(64), 0, s, upper ? 1 : 0, n, rpF, ciF, diagF,
+                           depth, ctl, spin_limit);
+    else
+        hipLaunchKernelGGL(k_depth, dim3(grid), dim3(64), 0, s, upper ? 1 : 0, n, rpF, ciF, diagF, depth,
+                           ctl, spin_limit);
     return hipGetLastError();
 }
 

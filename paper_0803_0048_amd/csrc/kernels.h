@@ -61,6 +61,10 @@ hipError_t launch_stats(int32_t n, const int64_t* rpF, const int32_t* diagF, Pat
 hipError_t launch_depth(bool upper, int32_t n, const int64_t* rpF, const int32_t* ciF,
                         const int32_t* diagF, int32_t* depth, Ctl* ctl, uint64_t spin_limit,
                         int32_t grid, hipStream_t s);
+// grid > 0: wave per row, natural order; grid == 0: one workgroup;
+// grid < 0: lane per row with -grid wavefronts
+hipError_t launch_level_order(int32_t n, int upper, const int32_t* depth, int32_t max_depth, int32_t* hist,
+                              int64_t* off, int64_t* scan_tmp, int32_t* perm, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_max_i32(const int32_t* p, int64_t n, int32_t* out, hipStream_t s);
 
@@ -79,6 +83,9 @@ struct PatDev {
     const int64_t* sptr;  // per F slot: start of its update pairs; [nnz_f + 1]
     const int32_t* sq;    // pair: slot of f_ht in row h
     const int32_t* sp;    // pair: slot of f_jt in row j
+    unsigned long long* trace;  // nullable: per-row start/finish ticks
+    const int32_t* permL;       // nullable: rows in order of forward dependency level
+    const int32_t* permU;       // nullable: rows in order of backward dependency level
 };
 
 // fill `n` doubles with kPending; thread 0 also resets ctl->ticket (and, if

@@ -27,7 +27,9 @@ struct tpilu_ctx_s {
     uint64_t ticks_per_us = 100;
     int64_t skip_row = -1;
     int32_t grid_override = 0;
+    int solver = 0;  // 0 auto, 1 whole device, 2 one workgroup
     bool timing = false;
+    unsigned long long* trace = nullptr;  // per-row timeline buffer (device, 2n), or null
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
     std::string err;
     ~tpilu_ctx_s() {
@@ -42,6 +44,18 @@ struct tpilu_ctx_s {
 namespace {
 
 constexpr uint64_t kDefaultWaitUs = 10000000ull;  // 10 s per dependency wait
+
+// Wavefronts of the persistent kernels.  Every waiting wavefront polls the
+// memory side, so past the parallelism a dependency graph can use, more
+// wavefronts only slow each hand-off down (measured on MI355X: the forward
+// solve of the n=160,000 ILU(2) matrix takes 12 ms with 128 wavefronts and
+// 33 ms with 8192).  Narrow graphs (few rows per level) get few wavefronts.
+constexpr int32_t kSolveWavesNarrow = 128;
+constexpr int32_t kSolveWavesWide = 256;
+constexpr int32_t kNumericWaves = 512;
+constexpr int32_t kAdjointWaves = 512;
+constexpr int64_t kNarrowWidth = 64;   // n / depth below this: narrow
+constexpr int64_t kLongRows = 24;      // average entries per half row at or above this: long
 
 // TPILU_TRACE=1 in the environment prints every host-side step to stderr.
 bool trace_on() {
@@ -116,6 +130,10 @@ struct tpilu_pattern_s {
     int64_t* sptr = nullptr;
     int32_t* sq = nullptr;
     int32_t* sp = nullptr;
+    int32_t* depthL = nullptr;  // dependency level of every row, forward sweep
+    int32_t* depthU = nullptr;  // and backward sweep
+    int32_t* permL = nullptr;   // rows sorted by depthL: the ticket order of numeric and forward
+    int32_t* permU = nullptr;   // rows sorted by depthU: the ticket order of backward
     Ctl* ctl = nullptr;
     // adjoint transposes (built on first use)
     bool have_t = false;
@@ -136,13 +154,15 @@ struct tpilu_pattern_s {
         b.bytes = b.p ? bytes : 0;
         return static_cast<double*>(b.p);
     }
-    PatDev dev() const {
+    PatDev dev(unsigned long long* trace = nullptr) const {
         PatDev d;
+        d.trace = trace;
         d.n = (int32_t)n;
         d.nnz_a = (int32_t)nnz_a;
         d.nnz_f = (int32_t)nnz_f;
         d.rpA = rpA; d.ciA = ciA; d.rpF = rpF; d.ciF = ciF; d.diagF = diagF; d.a2f = a2f;
         d.lsd = lsd; d.sptr = sptr; d.sq = sq; d.sp = sp;
+        d.permL = permL; d.permU = permU;
         return d;
     }
     ~tpilu_pattern_s() {
@@ -249,28 +269,52 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
     if (batch == 1 && (size_t)pat->st.max_row * 8 + 12 * 1024 > kBatchLdsLimit)
         return fail(ctx, TPILU_E_INVAL, "numeric factorization supports rows of at most 6600 entries");
     HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, pat->ctl, true, ctx->stream));
-    const int grid = ctx->grid_override ? ctx->grid_override : numeric_grid(batch, pat->st.max_row, ctx->num_cu);
+    const int grid = ctx->grid_override
+                         ? ctx->grid_override
+                         : std::min(batch == 1 ? kNumericWaves : 1 << 30,
+                                    numeric_grid(batch, pat->st.max_row, ctx->num_cu));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_NUMERIC);
-        HIPCHK(ctx, launch_numeric(pat->dev(), a_val, batch, f_val, pat->ctl, ctx->spin_limit,
+        HIPCHK(ctx, launch_numeric(pat->dev(ctx->trace), a_val, batch, f_val, pat->ctl, ctx->spin_limit,
                                    ctx->skip_row, grid, pat->st.max_row, ctx->stream));
     }
     return TPILU_OK;
 }
 
+// Launch shape of the single-instance solves.  A dependency graph with few
+// rows per level (n / depth small) is a long chain: a single workgroup, whose
+// hand-offs stay inside one CU, beats the whole device, whose hand-offs cross
+// XCDs.  Wide graphs keep the whole device.  Both give the same bits.
+constexpr int64_t kWorkgroupMaxWidth = 0;
+bool use_workgroup(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch) {
+    if (batch != 1) return false;
+    if (ctx->solver == 1) return false;
+    if (ctx->solver == 2) return true;
+    if (ctx->grid_override) return false;
+    const int64_t depth = std::max<int64_t>(1, std::max(pat->depth_l, pat->depth_u));
+    return pat->n / depth < kWorkgroupMaxWidth;  // kWorkgroupMaxWidth 0: never chosen automatically
+}
+
+int32_t solve_waves(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch) {
+    if (ctx->grid_override) return ctx->grid_override;
+    if (batch > 1) return solve_grid(batch, ctx->num_cu);
+    const int64_t depth = std::max<int64_t>(1, std::max(pat->depth_l, pat->depth_u));
+    return pat->n / depth < kNarrowWidth ? kSolveWavesNarrow : kSolveWavesWide;
+}
+
 tpilu_status enqueue_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val, int32_t batch,
                            const double* b, double* y, double* x, bool reset) {
-    const int grid = ctx->grid_override ? ctx->grid_override : solve_grid(batch, ctx->num_cu);
+    const int grid = use_workgroup(ctx, pat, batch) ? 0 : solve_waves(ctx, pat, batch);
     HIPCHK(ctx, launch_fill_pending(x, pat->n * batch, pat->ctl, reset, ctx->stream));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_FORWARD);
-        HIPCHK(ctx, launch_forward(pat->dev(), f_val, batch, b, x, pat->ctl, ctx->spin_limit, grid,
+        HIPCHK(ctx, launch_forward(pat->dev(ctx->trace), f_val, batch, b, x, pat->ctl, ctx->spin_limit, grid,
                                    ctx->stream));
     }
     HIPCHK(ctx, launch_fill_pending(y, pat->n * batch, pat->ctl, false, ctx->stream));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_BACKWARD);
-        HIPCHK(ctx, launch_backward(pat->dev(), f_val, batch, x, y, pat->ctl, ctx->spin_limit, grid,
+        HIPCHK(ctx, launch_backward(pat->dev(ctx->trace), f_val, batch, x, y, pat->ctl, ctx->spin_limit, grid,
                                     ctx->stream));
     }
     return TPILU_OK;
@@ -356,6 +400,19 @@ extern "C" TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t wave
     if (!ctx) return TPILU_E_INVAL;
     if (waves < 0) return fail(ctx, TPILU_E_INVAL, "waves must be >= 0");
     ctx->grid_override = waves;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_trace(tpilu_ctx ctx, uint64_t* rows2n) {
+    if (!ctx) return TPILU_E_INVAL;
+    ctx->trace = reinterpret_cast<unsigned long long*>(rows2n);
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (mode < 0 || mode > 2) return fail(ctx, TPILU_E_INVAL, "solver mode must be 0, 1 or 2");
+    ctx->solver = mode;
     return TPILU_OK;
 }
 
@@ -562,22 +619,42 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
     if (!P->sq || !P->sp) return bail(fail(ctx, TPILU_E_NOMEM, "schedule"));
     HIPCHK(ctx, launch_sched(ni, P->rpF, P->ciF, P->diagF, 1, nullptr, nullptr, P->sptr, P->sq, P->sp,
                              P->st.max_row, s));
-    // ---- dependency depths (reported by tpilu_pattern_info)
-    int32_t* depth = (int32_t*)T.get(sizeof(int32_t) * (size_t)n + 64);
-    if (!depth) return bail(fail(ctx, TPILU_E_NOMEM, "depth"));
-    int32_t* dmax = depth + n;
+    // ---- dependency levels and the level-ordered schedules
+    P->depthL = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
+    P->depthU = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
+    P->permL = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
+    P->permU = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
+    int32_t* dmax = (int32_t*)T.get(64);
+    if (!P->depthL || !P->depthU || !P->permL || !P->permU || !dmax)
+        return bail(fail(ctx, TPILU_E_NOMEM, "levels"));
+    // levels: lane per row (every row in flight) for short rows; a wavefront
+    // per row in natural order when rows are long (one lane scanning a long
+    // row would hold up its whole wavefront)
+    const int32_t lane_waves = (int32_t)std::min<int64_t>((n + 63) / 64, 8192);
     for (int up = 0; up < 2; ++up) {
-        trace("symbolic: depth pass (0 lower, 1 upper)", up);
+        const int64_t half = up ? (nnzf - (int64_t)P->st.nnz_l - n) : (int64_t)P->st.nnz_l;
+        const int32_t dgrid = half >= kLongRows * n ? kSolveWavesNarrow : -lane_waves;
+        trace("symbolic: levels (0 forward, 1 backward)", up);
+        int32_t* depth = up ? P->depthU : P->depthL;
         HIPCHK(ctx, launch_fill_i32(depth, n, -1, s));
         HIPCHK(ctx, launch_fill_i32(dmax, 1, 0, s));
         HIPCHK(ctx, launch_fill_pending(nullptr, 0, P->ctl, true, s));
         HIPCHK(ctx, launch_depth(up == 1, ni, P->rpF, P->ciF, P->diagF, depth, P->ctl, ctx->spin_limit,
-                                 solve_grid(1, ctx->num_cu), s));
+                                 dgrid, s));
         HIPCHK(ctx, launch_max_i32(depth, n, dmax, s));
         int32_t dm = 0;
         HIPCHK(ctx, hipMemcpyAsync(&dm, dmax, sizeof(dm), hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipStreamSynchronize(s));
         (up ? P->depth_u : P->depth_l) = dm;
+        {
+            tpilu_status cs = read_ctl(ctx, P, nullptr, false);
+            if (cs != TPILU_OK) return bail(cs);
+        }
+        int32_t* hist = (int32_t*)T.get(sizeof(int32_t) * 2 * (size_t)std::max(dm, 1));
+        int64_t* off = (int64_t*)T.get(sizeof(int64_t) * ((size_t)std::max(dm, 1) + 1));
+        int64_t* stmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(std::max(dm, 1)));
+        if (!hist || !off || !stmp) return bail(fail(ctx, TPILU_E_NOMEM, "level order"));
+        HIPCHK(ctx, launch_level_order(ni, up, depth, dm, hist, off, stmp, up ? P->permU : P->permL, s));
     }
     tpilu_status st = read_ctl(ctx, P, nullptr, true);
     if (st != TPILU_OK) return bail(st);
@@ -851,7 +928,7 @@ extern "C" TPILU_API tpilu_status tpilu_apply_adjoint(tpilu_ctx ctx, tpilu_patte
     double* z = pat->grow(pat->ws_z, sizeof(double) * (size_t)pat->n * batch);
     if (!z) return fail(ctx, TPILU_E_NOMEM, "adjoint workspace");
     AdjPat T{pat->tpL, pat->tsL, pat->trL, pat->tpU, pat->tsU, pat->trU};
-    const int grid = ctx->grid_override ? ctx->grid_override : solve_grid(batch, ctx->num_cu);
+    const int grid = ctx->grid_override ? ctx->grid_override : kAdjointWaves;
     HIPCHK(ctx, launch_fill_pending(z, pat->n * batch, pat->ctl, true, s));
     HIPCHK(ctx, launch_adj_solve_u(pat->dev(), T, f_val, batch, ybar, z, pat->ctl, ctx->spin_limit, grid, s));
     HIPCHK(ctx, launch_fill_pending(bbar, pat->n * batch, pat->ctl, false, s));
@@ -880,7 +957,7 @@ extern "C" TPILU_API tpilu_status tpilu_numeric_adjoint(tpilu_ctx ctx, tpilu_pat
     HIPCHK(ctx, launch_copy(fin, fbar, nfb, s));
     HIPCHK(ctx, launch_fill_pending(fbar, nfb, pat->ctl, true, s));
     HIPCHK(ctx, launch_fill_pending(lbar, nfb, pat->ctl, false, s));
-    const int grid = ctx->grid_override ? ctx->grid_override : solve_grid(batch, ctx->num_cu);
+    const int grid = ctx->grid_override ? ctx->grid_override : kAdjointWaves;
     HIPCHK(ctx, launch_adj_numeric(pat->dev(), T, f_val, batch, fin, fbar, lbar, abar, pat->ctl,
                                    ctx->spin_limit, grid, pat->st.max_row, s));
     return TPILU_OK;

@@ -25,6 +25,7 @@ def _gpu_guard(request):
     log(f"[gpu] {request.node.nodeid}")
     ctx = T.context(0)
     ctx.set_grid(0)
+    ctx.set_solver(0)
     ctx.set_watchdog(0, -1)
     yield
     torch.cuda.synchronize()
@@ -200,14 +201,36 @@ def test_repeatable_across_launch_shapes():
     ctx = T.context(0)
     ref_f = T.numeric(pat, av)
     ref_y = T.apply(pat, ref_f, bv)
-    for waves in (1, 2, 7, 64, 1000, 0, 40000):
-        ctx.set_grid(waves)
-        for _ in range(3):
-            f = T.numeric(pat, av)
-            y = T.apply(pat, f, bv)
-            assert torch.equal(f.view(torch.int64), ref_f.view(torch.int64)), waves
-            assert torch.equal(y.view(torch.int64), ref_y.view(torch.int64)), waves
+    for solver in (ctx.SOLVER_DEVICE, ctx.SOLVER_WORKGROUP):
+        ctx.set_solver(solver)
+        for waves in (1, 2, 7, 64, 1000, 0, 40000):
+            ctx.set_grid(waves)
+            for _ in range(3):
+                f = T.numeric(pat, av)
+                y = T.apply(pat, f, bv)
+                assert torch.equal(f.view(torch.int64), ref_f.view(torch.int64)), (solver, waves)
+                assert torch.equal(y.view(torch.int64), ref_y.view(torch.int64)), (solver, waves)
     ctx.set_grid(0)
+    ctx.set_solver(0)
+
+
+@pytest.mark.parametrize("cfg", ["c2", "c3k1"])
+def test_solver_shapes_agree_full_size(cfg):
+    """Whole-device and one-workgroup solves: same bits as the oracle."""
+    c = I.config2() if cfg == "c2" else I.config3(k=1)
+    A, b = c["A"], c["b"]
+    pat = T.symbolic(g(A.rowptr), g(A.col), c["k"])
+    f = T.numeric(pat, g(A.val))
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, c["k"])
+    vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
+    x_ref, y_ref = O.apply(A.n, rpF, ciF, vF, b)
+    ctx = T.context(0)
+    for solver in (ctx.SOLVER_DEVICE, ctx.SOLVER_WORKGROUP):
+        ctx.set_solver(solver)
+        y, x = T.apply(pat, f, g(b), return_x=True)
+        assert_bits_equal(x, x_ref, f"x solver {solver}")
+        assert_bits_equal(y, y_ref, f"y solver {solver}")
+    ctx.set_solver(0)
 
 
 def test_repeatable_config2():
