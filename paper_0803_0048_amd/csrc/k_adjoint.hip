@@ -13,6 +13,9 @@
 // travel through kPending-initialised arrays as in the forward kernels.
 //
 // Batches use one task per (row, instance), instances strided in memory.
+// Tasks are handed out by dependency level of the transposed sweep (rows of
+// one level hold no dependencies on each other), so the rows in flight at any
+// moment are ones whose inputs are about to be ready.
 #include "kernels.h"
 
 namespace tpilu {
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(64) void k_adj_solve_u(PatDev P, AdjPat T, const do
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
         if (t >= ntask) break;
-        const int32_t i = (int32_t)(t / (uint32_t)B);
+        const int32_t i = T.permUT[t / (uint32_t)B];
         const int32_t b = (int32_t)(t % (uint32_t)B);
         // rows j < i of column i, taken in ascending j
         const int64_t a0 = T.tpU[i], a1 = T.tpU[i + 1];
@@ -133,7 +136,7 @@ __global__ __launch_bounds__(64) void k_adj_solve_l(PatDev P, AdjPat T, const do
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
         if (t >= ntask) break;
-        const int32_t i = P.n - 1 - (int32_t)(t / (uint32_t)B);
+        const int32_t i = T.permLT[t / (uint32_t)B];
         const int32_t b = (int32_t)(t % (uint32_t)B);
         // rows j > i of column i, taken in descending j
         const int64_t a0 = T.tpL[i], a1 = T.tpL[i + 1];
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(64) void k_adj_numeric(PatDev P, AdjPat T, const do
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
         if (t >= ntask) break;
-        const int32_t j = P.n - 1 - (int32_t)(t / (uint32_t)B);
+        const int32_t j = T.permLT[t / (uint32_t)B];
         const int32_t b = (int32_t)(t % (uint32_t)B);
         const int64_t rs = P.rpF[j], re = P.rpF[j + 1], dj = P.diagF[j];
         const int32_t len = (int32_t)(re - rs);

@@ -546,15 +546,22 @@ __device__ __forceinline__ int32_t wait_depth(const int32_t* p, Ctl* ctl, uint64
     return v;
 }
 
+// The dependencies of node i: mode 0 the strict lower part of row i of F,
+// mode 1 the strict upper part, mode 2 entries [ptr[i], ptr[i+1]) of a
+// column structure (idx = row indices).
+__device__ __forceinline__ void dep_range(const DepGraph& G, int32_t i, int64_t& a, int64_t& b) {
+    if (G.mode == 0) { a = G.ptr[i]; b = G.diag[i]; }
+    else if (G.mode == 1) { a = G.diag[i] + 1; b = G.ptr[i + 1]; }
+    else { a = G.ptr[i]; b = G.ptr[i + 1]; }
+}
+
 template <Scope S>
-__device__ __forceinline__ void depth_row(int upper, const int64_t* __restrict__ rpF,
-                                          const int32_t* __restrict__ ciF,
-                                          const int32_t* __restrict__ diagF, int32_t* depth, Ctl* ctl,
-                                          uint64_t spin_limit, int32_t i) {
+__device__ __forceinline__ void depth_row(const DepGraph& G, int32_t* depth, Ctl* ctl, uint64_t spin_limit,
+                                          int32_t i) {
     const int lane = lane_id();
+    const int32_t* __restrict__ ciF = G.idx;
     int64_t a, b;
-    if (upper) { a = diagF[i] + 1; b = rpF[i + 1]; }
-    else { a = rpF[i]; b = diagF[i]; }
+    dep_range(G, i, a, b);
     int32_t best = 0;
     for (int64_t q = a + lane; q < b; q += kWave)
         best = max(best, wait_depth<S>(depth + ciF[q], ctl, spin_limit));
@@ -567,28 +574,23 @@ __device__ __forceinline__ void depth_row(int upper, const int64_t* __restrict__
     }
 }
 
-__global__ __launch_bounds__(64) void k_depth(int upper, int32_t n, const int64_t* __restrict__ rpF,
-                                              const int32_t* __restrict__ ciF,
-                                              const int32_t* __restrict__ diagF, int32_t* depth,
-                                              Ctl* ctl, uint64_t spin_limit) {
+__global__ __launch_bounds__(64) void k_depth(int desc, int32_t n, DepGraph G, int32_t* depth, Ctl* ctl,
+                                              uint64_t spin_limit) {
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
         if (t >= (uint32_t)n) break;
-        const int32_t i = upper ? n - 1 - (int32_t)t : (int32_t)t;
-        depth_row<Scope::Device>(upper, rpF, ciF, diagF, depth, ctl, spin_limit, i);
+        const int32_t i = desc ? n - 1 - (int32_t)t : (int32_t)t;
+        depth_row<Scope::Device>(G, depth, ctl, spin_limit, i);
     }
 }
 
 // one workgroup, rows dealt round-robin to its 16 wavefronts
-__global__ __launch_bounds__(1024) void k_depth_wg(int upper, int32_t n, const int64_t* __restrict__ rpF,
-                                                   const int32_t* __restrict__ ciF,
-                                                   const int32_t* __restrict__ diagF, int32_t* depth,
-                                                   Ctl* ctl, uint64_t spin_limit) {
+__global__ __launch_bounds__(1024) void k_depth_wg(int desc, int32_t n, DepGraph G, int32_t* depth, Ctl* ctl,
+                                                   uint64_t spin_limit) {
     const int32_t wave = uniform((int32_t)(threadIdx.x >> 6));
     const int32_t nw = (int32_t)(blockDim.x >> 6);
     for (int32_t r = wave; r < n; r += nw)
-        depth_row<Scope::Workgroup>(upper, rpF, ciF, diagF, depth, ctl, spin_limit,
-                                    upper ? n - 1 - r : r);
+        depth_row<Scope::Workgroup>(G, depth, ctl, spin_limit, desc ? n - 1 - r : r);
 }
 
 // Lane per row: a ticket hands a wavefront 64 consecutive rows (in the
@@ -597,22 +599,18 @@ __global__ __launch_bounds__(1024) void k_depth_wg(int upper, int32_t n, const i
 // row's dependencies, at most 8 per round, and stops at the first one not
 // known yet; the wavefront keeps looping until every lane published, so lanes
 // that depend on other lanes of the same wavefront cannot deadlock.
-__global__ __launch_bounds__(64) void k_depth_lanes(int upper, int32_t n, const int64_t* __restrict__ rpF,
-                                                    const int32_t* __restrict__ ciF,
-                                                    const int32_t* __restrict__ diagF, int32_t* depth,
+__global__ __launch_bounds__(64) void k_depth_lanes(int desc, int32_t n, DepGraph G, int32_t* depth,
                                                     Ctl* ctl, uint64_t spin_limit) {
     const int lane = lane_id();
+    const int32_t* __restrict__ ciF = G.idx;
     for (;;) {
         const uint32_t t = wave_ticket(ctl);
         const int64_t r = (int64_t)t * kWave + lane;
         if ((int64_t)t * kWave >= n) break;
         const bool valid = r < n;
-        const int32_t i = valid ? (upper ? n - 1 - (int32_t)r : (int32_t)r) : 0;
+        const int32_t i = valid ? (desc ? n - 1 - (int32_t)r : (int32_t)r) : 0;
         int64_t q = 0, b = 0;
-        if (valid) {
-            if (upper) { q = diagF[i] + 1; b = rpF[i + 1]; }
-            else { q = rpF[i]; b = diagF[i]; }
-        }
+        if (valid) dep_range(G, i, q, b);
         int32_t best = 0;
         bool done = !valid;
         uint32_t polls = 0;
@@ -661,16 +659,15 @@ __global__ void k_level_hist(int32_t n, const int32_t* __restrict__ depth, int32
     if (i < n) atomicAdd(&hist[depth[i] - 1], 1);
 }
 
-__global__ void k_level_scatter(int32_t n, int upper, const int32_t* __restrict__ depth,
+__global__ void k_level_scatter(int32_t n, const int32_t* __restrict__ depth,
                                 const int64_t* __restrict__ off, int32_t* cursor, int32_t* perm) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t d = depth[i] - 1;
     perm[off[d] + atomicAdd(&cursor[d], 1)] = i;
-    (void)upper;
 }
 
-hipError_t launch_level_order(int32_t n, int upper, const int32_t* depth, int32_t max_depth, int32_t* hist,
+hipError_t launch_level_order(int32_t n, const int32_t* depth, int32_t max_depth, int32_t* hist,
                               int64_t* off, int64_t* scan_tmp, int32_t* perm, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipError_t e = launch_fill_i32(hist, 2 * (int64_t)max_depth, 0, s);
@@ -678,24 +675,20 @@ hipError_t launch_level_order(int32_t n, int upper, const int32_t* depth, int32_
     hipLaunchKernelGGL(k_level_hist, dim3((n + 255) / 256), dim3(256), 0, s, n, depth, hist);
     e = launch_scan(hist, max_depth, off, scan_tmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_level_scatter, dim3((n + 255) / 256), dim3(256), 0, s, n, upper, depth, off,
+    hipLaunchKernelGGL(k_level_scatter, dim3((n + 255) / 256), dim3(256), 0, s, n, depth, off,
                        hist + max_depth, perm);
     return hipGetLastError();
 }
 
-// grid <= 0 selects the one-workgroup variant
-hipError_t launch_depth(bool upper, int32_t n, const int64_t* rpF, const int32_t* ciF,
-                        const int32_t* diagF, int32_t* depth, Ctl* ctl, uint64_t spin_limit,
-                        int32_t grid, hipStream_t s) {
+hipError_t launch_depth(int desc, int32_t n, const DepGraph& G, int32_t* depth, Ctl* ctl,
+                        uint64_t spin_limit, int32_t grid, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
     if (grid == 0)
-        hipLaunchKernelGGL(k_depth_wg, dim3(1), dim3(1024), 0, s, upper ? 1 : 0, n, rpF, ciF, diagF,
-                           depth, ctl, spin_limit);
+        hipLaunchKernelGGL(k_depth_wg, dim3(1), dim3(1024), 0, s, desc, n, G, depth, ctl, spin_limit);
     else if (grid < 0)
-        hipLaunchKernelGGL(k_depth_lanes, dim3(-grid), dim3(64), 0, s, upper ? 1 : 0, n, rpF, ciF, diagF,
-                           depth, ctl, spin_limit);
+        hipLaunchKernelGGL(k_depth_lanes, dim3(-grid), dim3(64), 0, s, desc, n, G, depth, ctl, spin_limit);
     else
-        hipLaunchKernelGGL(k_depth, dim3(grid), dim3(64), 0, s, upper ? 1 : 0, n, rpF, ciF, diagF, depth,
-                           ctl, spin_limit);
+        hipLaunchKernelGGL(k_depth, dim3(grid), dim3(64), 0, s, desc, n, G, depth, ctl, spin_limit);
     return hipGetLastError();
 }
 

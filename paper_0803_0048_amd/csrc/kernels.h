@@ -56,14 +56,23 @@ struct PatStats {
 hipError_t launch_stats(int32_t n, const int64_t* rpF, const int32_t* diagF, PatStats* st,
                         hipStream_t s);
 
-// dependency depth of every row (forward over L, backward over U); depth
-// arrays must be pre-filled with -1 by launch_fill_i32
-hipError_t launch_depth(bool upper, int32_t n, const int64_t* rpF, const int32_t* ciF,
-                        const int32_t* diagF, int32_t* depth, Ctl* ctl, uint64_t spin_limit,
-                        int32_t grid, hipStream_t s);
-// grid > 0: wave per row, natural order; grid == 0: one workgroup;
-// grid < 0: lane per row with -grid wavefronts
-hipError_t launch_level_order(int32_t n, int upper, const int32_t* depth, int32_t max_depth, int32_t* hist,
+// Dependency graph whose levels are computed: node i depends on idx[a..b)
+// with (a, b) from the mode (0 strict lower part of row i, 1 strict upper
+// part, 2 a column structure [ptr[i], ptr[i+1])).
+struct DepGraph {
+    const int64_t* ptr;
+    const int32_t* idx;
+    const int32_t* diag;
+    int mode;
+};
+// level of every node (1 + max level of its dependencies), nodes taken in
+// ascending (desc = 0) or descending order; depth pre-filled with -1.
+// grid > 0: wavefront per node, natural order; grid == 0: one workgroup;
+// grid < 0: lane per node with -grid wavefronts
+hipError_t launch_depth(int desc, int32_t n, const DepGraph& G, int32_t* depth, Ctl* ctl,
+                        uint64_t spin_limit, int32_t grid, hipStream_t s);
+// perm = nodes sorted by level (counting sort); hist needs 2 * max_depth ints
+hipError_t launch_level_order(int32_t n, const int32_t* depth, int32_t max_depth, int32_t* hist,
                               int64_t* off, int64_t* scan_tmp, int32_t* perm, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_max_i32(const int32_t* p, int64_t n, int32_t* out, hipStream_t s);
@@ -140,6 +149,9 @@ struct AdjPat {
     const int64_t* tpU;   // CSC of the strict upper part
     const int32_t* tsU;
     const int32_t* trU;
+    const int32_t* permUT;  // rows by level of the U~^T solve (row i waits on column i of U~)
+    const int32_t* permLT;  // rows by level of the L~^T solve and of the reverse sweep
+                            // (row i waits on the rows of column i of L~)
 };
 hipError_t launch_transpose_count(int32_t n, const int64_t* rpF, const int32_t* ciF,
                                   const int32_t* diagF, int32_t* cntL, int32_t* cntU,

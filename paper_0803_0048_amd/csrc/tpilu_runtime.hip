@@ -139,6 +139,7 @@ struct tpilu_pattern_s {
     bool have_t = false;
     int64_t *tpL = nullptr, *tpU = nullptr;
     int32_t *tsL = nullptr, *trL = nullptr, *tsU = nullptr, *trU = nullptr;
+    int32_t *permUT = nullptr, *permLT = nullptr;
     // growable workspaces
     DBuf ws_x, ws_z, ws_fin, ws_lbar, ws_gm;
 
@@ -320,6 +321,51 @@ tpilu_status enqueue_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val
     return TPILU_OK;
 }
 
+// temporaries released when the enclosing call returns
+struct TmpBufs {
+    Alloc al;
+    std::vector<void*> v;
+    void* get(size_t b) {
+        void* p = al.get(b);
+        if (p) v.push_back(p);
+        return p;
+    }
+    ~TmpBufs() { for (void* p : v) al.put(p); }
+};
+
+// Level of every node of a dependency DAG and the nodes sorted by level (the
+// ticket order of the kernel that walks the DAG).  deps = number of edges:
+// with long dependency lists a wavefront per node in natural order, else a
+// lane per node so that every node is in flight at once.
+tpilu_status compute_levels(tpilu_ctx ctx, tpilu_pattern pat, const DepGraph& G, int desc, int64_t deps,
+                            int32_t* depth, int32_t* perm, int32_t* max_depth) {
+    const int32_t n = (int32_t)pat->n;
+    hipStream_t s = ctx->stream;
+    TmpBufs T{pat->al, {}};
+    int32_t* dmax = (int32_t*)T.get(64);
+    if (!dmax) return fail(ctx, TPILU_E_NOMEM, "levels");
+    const int32_t lane_waves = (int32_t)std::min<int64_t>(((int64_t)n + 63) / 64, 8192);
+    const int32_t grid = deps >= kLongRows * (int64_t)n ? kSolveWavesNarrow : -lane_waves;
+    HIPCHK(ctx, launch_fill_i32(depth, n, -1, s));
+    HIPCHK(ctx, launch_fill_i32(dmax, 1, 0, s));
+    HIPCHK(ctx, launch_fill_pending(nullptr, 0, pat->ctl, true, s));
+    HIPCHK(ctx, launch_depth(desc, n, G, depth, pat->ctl, ctx->spin_limit, grid, s));
+    HIPCHK(ctx, launch_max_i32(depth, n, dmax, s));
+    int32_t dm = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&dm, dmax, sizeof(dm), hipMemcpyDeviceToHost, s));
+    tpilu_status cs = read_ctl(ctx, pat, nullptr, false);
+    if (cs != TPILU_OK) return cs;
+    *max_depth = dm;
+    dm = std::max(dm, 1);
+    int32_t* hist = (int32_t*)T.get(sizeof(int32_t) * 2 * (size_t)dm);
+    int64_t* off = (int64_t*)T.get(sizeof(int64_t) * ((size_t)dm + 1));
+    int64_t* stmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(dm));
+    if (!hist || !off || !stmp) return fail(ctx, TPILU_E_NOMEM, "level order");
+    HIPCHK(ctx, launch_level_order(n, depth, dm, hist, off, stmp, perm, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return TPILU_OK;
+}
+
 tpilu_status build_transposes(tpilu_ctx ctx, tpilu_pattern pat) {
     if (pat->have_t) return TPILU_OK;
     const int32_t n = (int32_t)pat->n;
@@ -345,7 +391,18 @@ tpilu_status build_transposes(tpilu_ctx ctx, tpilu_pattern pat) {
                                       pat->tpU, pat->tsU, pat->trU, curL, curU, s));
     HIPCHK(ctx, launch_sort_columns(n, pat->tpL, pat->tsL, pat->trL, s));
     HIPCHK(ctx, launch_sort_columns(n, pat->tpU, pat->tsU, pat->trU, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
+    // level orders of the transposed sweeps: U~^T ascending (row i waits on
+    // the rows of column i of U~), L~^T descending (on those of column i of L~)
+    int32_t* depth = (int32_t*)pat->take(sizeof(int32_t) * (size_t)n);
+    pat->permUT = (int32_t*)pat->take(sizeof(int32_t) * (size_t)n);
+    pat->permLT = (int32_t*)pat->take(sizeof(int32_t) * (size_t)n);
+    if (!depth || !pat->permUT || !pat->permLT) return fail(ctx, TPILU_E_NOMEM, "transpose levels");
+    int32_t dm = 0;
+    tpilu_status st = compute_levels(ctx, pat, DepGraph{pat->tpU, pat->trU, nullptr, 2}, 0, nu, depth,
+                                     pat->permUT, &dm);
+    if (st) return st;
+    st = compute_levels(ctx, pat, DepGraph{pat->tpL, pat->trL, nullptr, 2}, 1, nl, depth, pat->permLT, &dm);
+    if (st) return st;
     pat->have_t = true;
     return TPILU_OK;
 }
@@ -525,17 +582,7 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
     }
     const int32_t ni = (int32_t)n;
     // ---- a2: level-of-fill pattern, count pass
-    Alloc tmpal = P->al;
-    struct Tmp {
-        Alloc al;
-        std::vector<void*> v;
-        void* get(size_t b) {
-            void* p = al.get(b);
-            if (p) v.push_back(p);
-            return p;
-        }
-        ~Tmp() { for (void* p : v) al.put(p); }
-    } T{tmpal, {}};
+    TmpBufs T{P->al, {}};
     int32_t* cnt = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);
     int32_t* over_list = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);
     int32_t* over_n = (int32_t*)T.get(64);
@@ -624,37 +671,17 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
     P->depthU = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
     P->permL = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
     P->permU = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
-    int32_t* dmax = (int32_t*)T.get(64);
-    if (!P->depthL || !P->depthU || !P->permL || !P->permU || !dmax)
-        return bail(fail(ctx, TPILU_E_NOMEM, "levels"));
-    // levels: lane per row (every row in flight) for short rows; a wavefront
-    // per row in natural order when rows are long (one lane scanning a long
-    // row would hold up its whole wavefront)
-    const int32_t lane_waves = (int32_t)std::min<int64_t>((n + 63) / 64, 8192);
-    for (int up = 0; up < 2; ++up) {
-        const int64_t half = up ? (nnzf - (int64_t)P->st.nnz_l - n) : (int64_t)P->st.nnz_l;
-        const int32_t dgrid = half >= kLongRows * n ? kSolveWavesNarrow : -lane_waves;
-        trace("symbolic: levels (0 forward, 1 backward)", up);
-        int32_t* depth = up ? P->depthU : P->depthL;
-        HIPCHK(ctx, launch_fill_i32(depth, n, -1, s));
-        HIPCHK(ctx, launch_fill_i32(dmax, 1, 0, s));
-        HIPCHK(ctx, launch_fill_pending(nullptr, 0, P->ctl, true, s));
-        HIPCHK(ctx, launch_depth(up == 1, ni, P->rpF, P->ciF, P->diagF, depth, P->ctl, ctx->spin_limit,
-                                 dgrid, s));
-        HIPCHK(ctx, launch_max_i32(depth, n, dmax, s));
-        int32_t dm = 0;
-        HIPCHK(ctx, hipMemcpyAsync(&dm, dmax, sizeof(dm), hipMemcpyDeviceToHost, s));
-        HIPCHK(ctx, hipStreamSynchronize(s));
-        (up ? P->depth_u : P->depth_l) = dm;
-        {
-            tpilu_status cs = read_ctl(ctx, P, nullptr, false);
-            if (cs != TPILU_OK) return bail(cs);
-        }
-        int32_t* hist = (int32_t*)T.get(sizeof(int32_t) * 2 * (size_t)std::max(dm, 1));
-        int64_t* off = (int64_t*)T.get(sizeof(int64_t) * ((size_t)std::max(dm, 1) + 1));
-        int64_t* stmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(std::max(dm, 1)));
-        if (!hist || !off || !stmp) return bail(fail(ctx, TPILU_E_NOMEM, "level order"));
-        HIPCHK(ctx, launch_level_order(ni, up, depth, dm, hist, off, stmp, up ? P->permU : P->permL, s));
+    if (!P->depthL || !P->depthU || !P->permL || !P->permU) return bail(fail(ctx, TPILU_E_NOMEM, "levels"));
+    {
+        const int64_t nl = (int64_t)P->st.nnz_l, nu = nnzf - nl - n;
+        trace("symbolic: forward levels");
+        tpilu_status ls = compute_levels(ctx, P, DepGraph{P->rpF, P->ciF, P->diagF, 0}, 0, nl, P->depthL,
+                                         P->permL, &P->depth_l);
+        if (ls != TPILU_OK) return bail(ls);
+        trace("symbolic: backward levels");
+        ls = compute_levels(ctx, P, DepGraph{P->rpF, P->ciF, P->diagF, 1}, 1, nu, P->depthU, P->permU,
+                            &P->depth_u);
+        if (ls != TPILU_OK) return bail(ls);
     }
     tpilu_status st = read_ctl(ctx, P, nullptr, true);
     if (st != TPILU_OK) return bail(st);
@@ -927,7 +954,7 @@ extern "C" TPILU_API tpilu_status tpilu_apply_adjoint(tpilu_ctx ctx, tpilu_patte
     hipStream_t s = ctx->stream;
     double* z = pat->grow(pat->ws_z, sizeof(double) * (size_t)pat->n * batch);
     if (!z) return fail(ctx, TPILU_E_NOMEM, "adjoint workspace");
-    AdjPat T{pat->tpL, pat->tsL, pat->trL, pat->tpU, pat->tsU, pat->trU};
+    AdjPat T{pat->tpL, pat->tsL, pat->trL, pat->tpU, pat->tsU, pat->trU, pat->permUT, pat->permLT};
     const int grid = ctx->grid_override ? ctx->grid_override : kAdjointWaves;
     HIPCHK(ctx, launch_fill_pending(z, pat->n * batch, pat->ctl, true, s));
     HIPCHK(ctx, launch_adj_solve_u(pat->dev(), T, f_val, batch, ybar, z, pat->ctl, ctx->spin_limit, grid, s));
@@ -953,7 +980,7 @@ extern "C" TPILU_API tpilu_status tpilu_numeric_adjoint(tpilu_ctx ctx, tpilu_pat
     if (!fin || !lbar) return fail(ctx, TPILU_E_NOMEM, "adjoint workspace");
     if ((size_t)pat->st.max_row * 8 > kBatchLdsLimit)
         return fail(ctx, TPILU_E_INVAL, "adjoint supports rows of at most 8192 entries");
-    AdjPat T{pat->tpL, pat->tsL, pat->trL, pat->tpU, pat->tsU, pat->trU};
+    AdjPat T{pat->tpL, pat->tsL, pat->trL, pat->tpU, pat->tsU, pat->trU, pat->permUT, pat->permLT};
     HIPCHK(ctx, launch_copy(fin, fbar, nfb, s));
     HIPCHK(ctx, launch_fill_pending(fbar, nfb, pat->ctl, true, s));
     HIPCHK(ctx, launch_fill_pending(lbar, nfb, pat->ctl, false, s));
