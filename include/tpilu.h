@@ -112,6 +112,17 @@ TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t waves);
 enum { TPILU_SOLVER_AUTO = 0, TPILU_SOLVER_DEVICE = 1, TPILU_SOLVER_WORKGROUP = 2 };
 TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode);
 
+/* Kernel of the single-instance numeric factorization: 0 = automatic (the
+ * dataflow kernel when the pattern's rows fit its LDS staging and the strict
+ * lower part holds at least 4n entries, else the pivot-serial one),
+ * 1 = dataflow (lanes own the entries of a row and take
+ * their updates in ascending pivot order; a later tpilu_numeric fails with
+ * TPILU_E_INVAL if the pattern's rows do not fit), 2 = pivot-serial (the
+ * wavefront walks the pivots of a row in ascending order, lanes over one
+ * pivot's updates).  Same bits in every mode. */
+enum { TPILU_NUMERIC_AUTO = 0, TPILU_NUMERIC_FLOW = 1, TPILU_NUMERIC_PIVOT = 2 };
+TPILU_API tpilu_status tpilu_ctx_set_numeric(tpilu_ctx ctx, int mode);
+
 /* Kernel timing.  With timing on, the library brackets the main kernel of
  * every numeric factorization, forward solve and backward solve it launches
  * with a pair of hipEvents recorded on the ctx stream (outside graph
@@ -125,9 +136,12 @@ enum { TPILU_KERNEL_NUMERIC = 0, TPILU_KERNEL_FORWARD = 1, TPILU_KERNEL_BACKWARD
  * numeric factorization and forward solve record, for every row i, the
  * wall-clock tick (s_memrealtime, the device's wall clock rate) at which a
  * wavefront started it in buf[i] and published it in buf[n + i]; the
- * backward solve uses buf[2n + i] and buf[3n + i].  The buffer must hold 4n
- * entries of every pattern used while it is set. */
-TPILU_API tpilu_status tpilu_ctx_set_trace(tpilu_ctx ctx, uint64_t *rows2n);
+ * backward solve uses buf[2n + i] and buf[3n + i].  The numeric
+ * factorization also records in buf[2n + i] when the row's last wait on a
+ * pivot ended (left untouched if it never waited) and in buf[3n + i] when it
+ * began to publish.  The buffer must hold 4n entries of every pattern used
+ * while it is set. */
+TPILU_API tpilu_status tpilu_ctx_set_trace(tpilu_ctx ctx, uint64_t *rows4n);
 TPILU_API tpilu_status tpilu_ctx_set_timing(tpilu_ctx ctx, int on);
 TPILU_API tpilu_status tpilu_ctx_read_timing(tpilu_ctx ctx, int kernel, double *total_ms /* host */,
                                              int64_t *launches /* host */);
@@ -162,6 +176,7 @@ typedef struct {
     int32_t depth_l;     /* rows on the longest dependency chain of L~ (forward order) */
     int32_t depth_u;     /* rows on the longest dependency chain of U~ (backward order) */
     int32_t overflow_rows; /* rows the symbolic pass had to redo in global memory */
+    int32_t flow_ready;  /* 1 if the dataflow numeric kernel can run on this pattern */
 } tpilu_pattern_info_t;
 
 TPILU_API tpilu_status tpilu_pattern_info(tpilu_pattern pat, tpilu_pattern_info_t *info /* host */);

@@ -20,7 +20,7 @@ OK, E_INVAL, E_NOMEM, E_ZEROPIVOT, E_DEVICE, E_NOTCONV, E_TIMEOUT = range(7)
 
 EXPORTED = [
     "tpilu_ctx_create", "tpilu_ctx_set_stream", "tpilu_ctx_destroy", "tpilu_status_string",
-    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
+    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_numeric", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
     "tpilu_pattern_export", "tpilu_pattern_destroy", "tpilu_numeric", "tpilu_pattern_check",
     "tpilu_apply", "tpilu_gmres", "tpilu_spmv", "tpilu_dot", "tpilu_apply_adjoint",
     "tpilu_numeric_adjoint", "tpilu_batched_graph_create", "tpilu_batched_graph_launch",
@@ -43,7 +43,7 @@ class PatternInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz_a", C.c_int64), ("nnz_f", C.c_int64), ("nnz_l", C.c_int64),
                 ("nnz_u", C.c_int64), ("n_updates", C.c_int64), ("k", C.c_int32),
                 ("max_row", C.c_int32), ("max_lrow", C.c_int32), ("depth_l", C.c_int32),
-                ("depth_u", C.c_int32), ("overflow_rows", C.c_int32)]
+                ("depth_u", C.c_int32), ("overflow_rows", C.c_int32), ("flow_ready", C.c_int32)]
 
 
 _lib = None
@@ -70,6 +70,7 @@ def load_library():
             "tpilu_ctx_set_watchdog": ([P, u32, i64], st),
             "tpilu_ctx_set_grid": ([P, i32], st),
             "tpilu_ctx_set_solver": ([P, C.c_int], st),
+            "tpilu_ctx_set_numeric": ([P, C.c_int], st),
             "tpilu_ctx_set_trace": ([P, P], st),
             "tpilu_ctx_set_timing": ([P, C.c_int], st),
             "tpilu_ctx_read_timing": ([P, C.c_int, C.POINTER(dbl), C.POINTER(i64)], st),
@@ -143,6 +144,13 @@ class Context:
 
     def set_solver(self, mode: int = 0):
         self.check(load_library().tpilu_ctx_set_solver(self.h, mode), "set_solver")
+
+    NUMERIC_AUTO, NUMERIC_FLOW, NUMERIC_PIVOT = 0, 1, 2
+
+    def set_numeric(self, mode: int = 0):
+        """Kernel of the single-instance numeric factorization (same bits in
+        every mode): 0 automatic, 1 dataflow, 2 pivot-serial."""
+        self.check(load_library().tpilu_ctx_set_numeric(self.h, mode), "set_numeric")
 
     def set_trace(self, buf=None):
         """Per-row timeline: a uint64/int64 device tensor of 4n entries, or None."""

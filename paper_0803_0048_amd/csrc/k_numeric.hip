@@ -42,34 +42,43 @@ hipError_t launch_fill_pending(double* p, int64_t n, Ctl* ctl, bool reset_status
     return hipGetLastError();
 }
 
-// Wait until pivot row h's diagonal (slot dh) and every value f_ht that the
-// pivot contributes (pairs [ea, eb) of the staged group) are final.  All of
-// them are polled in the same round, so a row that is waiting on h pays one
-// round trip after h is published, not one for the diagonal and another for
-// the rest.  Final values are written back into the staged copies.  Returns
-// the diagonal's bits (a quiet NaN after a watchdog timeout or abort).
-__device__ __forceinline__ uint64_t wait_pivot(const double* F, int32_t dh, uint64_t ub, int32_t ea,
-                                               int32_t eb, const int32_t* pr_q, uint64_t* pr_v,
-                                               Ctl* ctl, uint64_t limit) {
+// Wait until pivot i of the staged group is final: its diagonal and every
+// value f_ht it contributes.  Each polling round also refreshes the pending
+// values of the next few pivots, so pivots whose rows finish while row j
+// waits on an earlier one cost no further round trip of their own.  Final
+// values are written back into the staged copies; after a watchdog timeout
+// or an abort pivot i's diagonal is replaced by a quiet NaN.
+constexpr int kLookahead = 16;
+
+__device__ __forceinline__ void wait_pivot(const double* F, int32_t i, int32_t np,
+                                           const int32_t* piv_dh, uint64_t* piv_u,
+                                           const int32_t* piv_e, const int32_t* pr_q, uint64_t* pr_v,
+                                           Ctl* ctl, uint64_t limit) {
     const int lane = lane_id();
+    const int32_t xe = min(np, i + kLookahead);
+    const int32_t ea = piv_e[i], eb = piv_e[i + 1], ee = piv_e[xe];
     uint32_t polls = 0;
     uint64_t t0 = 0;
     for (;;) {
         bool pend = false;
-        if (ub == kPending) {
-            ub = ld_coherent(F + dh);
-            pend = ub == kPending;
+        for (int32_t x = i + lane; x < xe; x += kWave) {
+            if (piv_u[x] == kPending) {
+                const uint64_t v = ld_coherent(F + piv_dh[x]);
+                if (v != kPending) piv_u[x] = v;
+                else if (x == i) pend = true;
+            }
         }
-        for (int32_t e = ea + lane; e < eb; e += kWave) {
+        for (int32_t e = ea + lane; e < ee; e += kWave) {
             if (pr_v[e] == kPending) {
                 const uint64_t v = ld_coherent(F + pr_q[e]);
                 if (v != kPending) pr_v[e] = v;
-                else pend = true;
+                else if (e < eb) pend = true;
             }
         }
-        if (!__any(pend)) return ub;
+        if (!__any(pend)) break;
         if ((polls & 31u) == 0u) {
-            if ((polls & 255u) == 0u && ld_u32_coherent(&ctl->abort) != 0u) return kQNaN;
+            bool stop = false;
+            if ((polls & 255u) == 0u && ld_u32_coherent(&ctl->abort) != 0u) stop = true;
             const uint64_t now = wall_clock64();
             if (polls == 0) {
                 t0 = now;
@@ -78,12 +87,17 @@ __device__ __forceinline__ uint64_t wait_pivot(const double* F, int32_t dh, uint
                     atomicOr(&ctl->status, kStTimeout);
                     __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                return kQNaN;
+                stop = true;
+            }
+            if (stop) {
+                if (lane == 0) piv_u[i] = kQNaN;
+                break;
             }
         }
         ++polls;
         __builtin_amdgcn_s_sleep(1);
     }
+    wave_sync();
 }
 
 // ----------------------------------------------------------------------------------
@@ -155,7 +169,11 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
                     // the pivot and every value it contributes, polled together
                     bool ok = ub != kPending;
                     for (int32_t e = ea + lane; e < eb; e += kWave) ok = ok && pr_v[e] != kPending;
-                    if (!__all(ok)) ub = wait_pivot(F, piv_dh[i], ub, ea, eb, pr_q, pr_v, ctl, spin_limit);
+                    if (!__all(ok)) {
+                        wait_pivot(F, i, np, piv_dh, piv_u, piv_e, pr_q, pr_v, ctl, spin_limit);
+                        ub = piv_u[i];
+                        trace_mark(P.trace, 2 * (int64_t)n + j);
+                    }
                 } else {
                     ub = as_u64(wait_final(F + piv_dh[i], ub, ctl, spin_limit));
                 }
@@ -181,11 +199,205 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
             s0 += np;
         }
         const int32_t dl = (int32_t)(dj - rs);
+        trace_mark(P.trace, 3 * (int64_t)n + j);
         if (lane == 0 && W[dl] == 0.0) atomicMin(&ctl->bad_row, (unsigned long long)j);
         if ((int64_t)j != skip_row) {
             // U part first: later rows wait on it; the L part is only read by later kernels
             for (int32_t e = dl + lane; e < len; e += kWave) st_publish(F + rs + e, W[e]);
             for (int32_t e = lane; e < dl; e += kWave) F[rs + e] = W[e];
+        }
+        trace_mark(P.trace, (int64_t)n + j);
+        wave_sync();
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// single instance, dataflow form: lanes own target entries of the row
+// ----------------------------------------------------------------------------------
+// Walking the pivots of row j one at a time leaves 60 of 64 lanes idle (a
+// pivot updates only a handful of entries) and puts every pivot's division
+// and LDS round trips on the row's serial path.  Here each lane owns entries
+// f_jt of row j (t = lane, lane + 64, ...) and applies their updates itself,
+// from a target-major copy of the update schedule: per entry, the pivots h
+// that update it in ascending order (the order that fixes the bits).  An
+// update needs l_h = f_jh / f_hh, which the lane owning entry h produces once
+// f_jh has taken all of its own updates; l values are handed between lanes
+// through LDS, initialised to kPending.  A lane finishes its entries in
+// ascending order; the smallest unfinished entry of the row only waits on
+// pivot rows (never on another lane), so the row always makes progress.
+// Values of pivot rows are staged in LDS with optimistic reads; those still
+// pending are re-polled (agent scope) a few at a time per lane, all lanes in
+// one round trip, only when no lane can progress from LDS alone.  Entries of
+// the U part are published the moment they are final, so rows that pivot on
+// row j need not wait for the rest of it.
+constexpr int kFlowCap = 1024;   // staged updates per chunk of targets (at least the longest L part)
+constexpr int kFlowLook = 4;     // staged values re-polled per lane and round
+
+size_t flow_lds_bytes(int32_t max_row, int32_t cap) {
+    return (size_t)max_row * 8 * 3 + (size_t)cap * 8 + (size_t)max_row * 4 + (size_t)cap * 8 +
+           ((size_t)max_row + 1) * 4;
+}
+
+__global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __restrict__ a_val, double* F,
+                                                     Ctl* ctl, uint64_t spin_limit, int64_t skip_row,
+                                                     int32_t max_row, int32_t cap) {
+    extern __shared__ uint64_t lds_u64[];
+    double* Wv = reinterpret_cast<double*>(lds_u64);                  // [max_row] initial values
+    volatile uint64_t* Lb = lds_u64 + max_row;                       // [max_row] l of L entries
+    volatile uint64_t* Ud = lds_u64 + 2 * (size_t)max_row;           // [max_row] pivot diagonals
+    volatile uint64_t* Sv = lds_u64 + 3 * (size_t)max_row;           // [cap] staged f_ht
+    int32_t* Uq = reinterpret_cast<int32_t*>(lds_u64 + 3 * (size_t)max_row + cap);  // [max_row]
+    int32_t* Ss = Uq + max_row;                                      // [cap] pivot entry of update
+    int32_t* Sq = Ss + cap;                                          // [cap] F slot of f_ht
+    int32_t* Tb = Sq + cap;                                          // [max_row + 1] chunk offsets
+    const int lane = lane_id();
+    const int32_t n = P.n;
+    for (;;) {
+        const uint32_t t = wave_ticket(ctl);
+        if (t >= (uint32_t)n) break;
+        const int32_t j = P.permL ? P.permL[t] : (int32_t)t;
+        trace_mark(P.trace, j);
+        const int64_t rs = P.rpF[j], re = P.rpF[j + 1];
+        const int32_t len = (int32_t)(re - rs);
+        const int32_t dl = (int32_t)(P.diagF[j] - rs);
+        const bool publish = (int64_t)j != skip_row;
+        for (int32_t e = lane; e < len; e += kWave) Wv[e] = 0.0;
+        for (int32_t e = lane; e < dl; e += kWave) {
+            const int32_t dh = P.lsd[rs + e];
+            Uq[e] = dh;
+            Ud[e] = ld_cached(F + dh);
+            Lb[e] = kPending;
+        }
+        wave_sync();
+        for (int64_t q = P.rpA[j] + lane; q < P.rpA[j + 1]; q += kWave)
+            Wv[P.a2f[q] - rs] = sanitize_input(a_val[q], ctl);
+        const int64_t row0 = P.tptr[rs];
+        const bool whole = P.tptr[re] - row0 <= cap;
+        bool stop = false;
+        int32_t p0 = 0;
+        while (p0 < len && !stop) {
+            // chunk [p0, p1): the most targets whose updates fit the staging arrays
+            const int64_t c0 = P.tptr[rs + p0];
+            int32_t p1 = len;
+            if (!whole) {
+                p1 = p0 + 1;
+                for (int32_t base = p0 + 1; base <= len; base += kWave) {
+                    const int32_t cand = base + lane;
+                    const bool ok = cand <= len && P.tptr[rs + cand] - c0 <= cap;
+                    const uint64_t m = __ballot(ok);
+                    if (m == 0ull) break;
+                    p1 = base + 63 - __clzll(m);
+                    if (m != ~0ull) break;
+                }
+            }
+            const int32_t nu = (int32_t)(P.tptr[rs + p1] - c0);
+            for (int32_t k = lane; k < nu; k += kWave) {
+                const int32_t q = P.tq[c0 + k];
+                Sq[k] = q;
+                Ss[k] = P.tsl[c0 + k];
+                Sv[k] = ld_cached(F + q);
+            }
+            for (int32_t q = p0 + lane; q <= p1; q += kWave) Tb[q - p0] = (int32_t)(P.tptr[rs + q] - c0);
+            wave_sync();
+
+            int32_t p = p0 + lane;
+            bool have = p < p1;
+            int32_t e = 0, ee = 0;
+            double acc = 0.0;
+            if (have) { e = Tb[p - p0]; ee = Tb[p - p0 + 1]; acc = Wv[p]; }
+            uint32_t polls = 0;
+            uint64_t t0 = 0;
+            for (;;) {
+                // progress from LDS alone until no lane can move
+                for (;;) {
+                    bool prog = false;
+                    if (have) {
+                        while (e < ee) {
+                            const uint64_t lb = Lb[Ss[e]];
+                            const uint64_t vb = Sv[e];
+                            if (lb == kPending || vb == kPending) break;
+                            acc = acc - as_f64(lb) * as_f64(vb);
+                            ++e;
+                            prog = true;
+                        }
+                        if (e >= ee) {
+                            bool fin = true;
+                            if (p < dl) {
+                                const uint64_t ub = Ud[p];
+                                if (ub == kPending) fin = false;
+                                else Lb[p] = as_u64(acc / as_f64(ub));
+                            } else {
+                                if (publish) st_publish(F + rs + p, acc);
+                                if (p == dl && acc == 0.0) atomicMin(&ctl->bad_row, (unsigned long long)j);
+                            }
+                            if (fin) {
+                                prog = true;
+                                p += kWave;
+                                have = p < p1;
+                                if (have) { e = Tb[p - p0]; ee = Tb[p - p0 + 1]; acc = Wv[p]; }
+                            }
+                        }
+                    }
+                    if (!__any(prog)) break;
+                }
+                if (!__any(have)) break;
+                // one round trip for every lane's pending inputs
+                bool got = false;
+                if (have) {
+                    bool need[kFlowLook];
+                    uint64_t v[kFlowLook];
+#pragma unroll
+                    for (int u = 0; u < kFlowLook; ++u) {
+                        const int32_t x = e + u;
+                        need[u] = x < ee && Sv[x] == kPending;
+                        v[u] = need[u] ? ld_coherent(F + Sq[x]) : kPending;
+                    }
+                    const bool needu = p < dl && Ud[p] == kPending;
+                    const uint64_t vu = needu ? ld_coherent(F + Uq[p]) : kPending;
+#pragma unroll
+                    for (int u = 0; u < kFlowLook; ++u)
+                        if (need[u] && v[u] != kPending) { Sv[e + u] = v[u]; got = true; }
+                    if (needu && vu != kPending) { Ud[p] = vu; got = true; }
+                }
+                if (__any(got)) {
+                    trace_mark(P.trace, 2 * (int64_t)n + j);
+                    polls = 0;
+                    continue;
+                }
+                // watchdog: a stall (rounds with no input arriving) is timed
+                // from its 32nd round; the abort flag is read every 256 rounds
+                if ((polls & 31u) == 31u) {
+                    if ((polls & 255u) == 255u && ld_u32_coherent(&ctl->abort) != 0u) stop = true;
+                    const uint64_t now = wall_clock64();
+                    if (polls == 31u) {
+                        t0 = now;
+                    } else if (now - t0 > spin_limit) {
+                        if (lane == 0) {
+                            atomicOr(&ctl->status, kStTimeout);
+                            __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        stop = true;
+                    }
+                    if (__any(stop)) {
+                        stop = true;
+                        break;
+                    }
+                }
+                ++polls;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            wave_sync();
+            p0 = p1;
+        }
+        trace_mark(P.trace, 3 * (int64_t)n + j);
+        if (publish) {
+            for (int32_t q = lane; q < dl; q += kWave) {
+                const uint64_t lb = Lb[q];
+                F[rs + q] = as_f64(lb == kPending ? kQNaN : lb);
+            }
+            // after an abort, release anything that might still wait on this row
+            if (stop)
+                for (int32_t q = dl + lane; q < len; q += kWave) st_publish(F + rs + q, as_f64(kQNaN));
         }
         trace_mark(P.trace, (int64_t)n + j);
         wave_sync();
@@ -291,11 +503,19 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
     }
 }
 
-int numeric_grid(int32_t batch, int32_t max_row, int num_cu) {
+int32_t flow_cap(int32_t max_lrow) { return std::max(kFlowCap, max_lrow); }
+
+bool numeric_flow_fits(int32_t max_row, int32_t max_lrow, size_t lds_limit) {
+    return flow_lds_bytes(std::max(max_row, 1), flow_cap(max_lrow)) <= lds_limit;
+}
+
+int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, int num_cu) {
     // LDS per wavefront bounds how many rows are in flight; aim for the
     // resident maximum so every ready row has a wavefront
     size_t lds;
-    if (batch == 1)
+    if (batch == 1 && flow)
+        lds = flow_lds_bytes(std::max(max_row, 1), flow_cap(max_lrow));
+    else if (batch == 1)
         lds = (size_t)max_row * 8 + (kPivCap + 1) * 4 + kPivCap * 12 + kPairCap * 16;
     else
         lds = (size_t)max_row * 8 * kWave + (kBPivCap + 1) * 4 + kBPivCap * 4 + kBPairCap * 8 +
@@ -307,9 +527,13 @@ int numeric_grid(int32_t batch, int32_t max_row, int num_cu) {
 
 hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, double* f_val,
                           Ctl* ctl, uint64_t spin_limit, int64_t skip_row, int32_t grid,
-                          int32_t max_row, hipStream_t s) {
+                          int32_t max_row, int32_t max_lrow, bool flow, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    if (batch == 1) {
+    if (batch == 1 && flow) {
+        const int32_t mr = std::max(max_row, 1), cap = flow_cap(max_lrow);
+        hipLaunchKernelGGL(k_numeric_flow, dim3(grid), dim3(64), flow_lds_bytes(mr, cap), s, P, a_val, f_val,
+                           ctl, spin_limit, skip_row, mr, cap);
+    } else if (batch == 1) {
         size_t lds = (size_t)std::max(max_row, 1) * sizeof(double);
         hipLaunchKernelGGL(k_numeric_row, dim3(grid), dim3(64), lds, s, P, a_val, f_val, ctl,
                            spin_limit, skip_row);

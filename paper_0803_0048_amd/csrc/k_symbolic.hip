@@ -494,6 +494,68 @@ hipError_t launch_sched(int32_t n, const int64_t* rpF, const int32_t* ciF, const
 }
 
 // ------------------------------------------------------------------------------------
+// Target-major copy of the update schedule: for every F slot p of row j, the
+// updates it receives (row-local slot of the pivot entry f_jh, slot of f_ht)
+// in ascending h.  One wavefront per row.  mode 0 counts per slot into
+// tcount; mode 1 fills, walking the pivots in ascending order so that each
+// slot's list comes out sorted (a pivot updates distinct slots).
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_tsched(int32_t n, const int64_t* __restrict__ rpF,
+                                               const int32_t* __restrict__ diagF,
+                                               const int64_t* __restrict__ sptr,
+                                               const int32_t* __restrict__ sq,
+                                               const int32_t* __restrict__ sp, int mode,
+                                               int32_t* __restrict__ tcount, const int64_t* __restrict__ tptr,
+                                               int32_t* __restrict__ tsl, int32_t* __restrict__ tq) {
+    extern __shared__ int64_t tsh[];
+    const int lane = lane_id();
+    for (int32_t j = blockIdx.x; j < n; j += gridDim.x) {
+        const int64_t rs = rpF[j], re = rpF[j + 1], dj = diagF[j];
+        const int32_t len = (int32_t)(re - rs), dl = (int32_t)(dj - rs);
+        int64_t* Tp = tsh;                                  // [len] tptr of the row's slots
+        int64_t* Sp = tsh + len;                            // [dl + 1] sptr of its L slots
+        int32_t* cur = reinterpret_cast<int32_t*>(tsh + len + dl + 1);  // [len]
+        for (int32_t e = lane; e < len; e += kWave) {
+            cur[e] = 0;
+            if (mode == 1) Tp[e] = tptr[rs + e];
+        }
+        for (int32_t e = lane; e <= dl; e += kWave) Sp[e] = sptr[rs + e];
+        wave_sync();
+        if (mode == 0) {
+            for (int64_t e = Sp[0] + lane; e < Sp[dl]; e += kWave) atomicAdd(&cur[sp[e] - rs], 1);
+            wave_sync();
+            for (int32_t e = lane; e < len; e += kWave) tcount[rs + e] = cur[e];
+        } else {
+            for (int32_t h = 0; h < dl; ++h) {
+                for (int64_t e = Sp[h] + lane; e < Sp[h + 1]; e += kWave) {
+                    const int32_t p = (int32_t)(sp[e] - rs);
+                    const int64_t pos = Tp[p] + cur[p];
+                    cur[p] = cur[p] + 1;
+                    tsl[pos] = h;
+                    tq[pos] = sq[e];
+                }
+                wave_sync();
+            }
+        }
+        wave_sync();
+    }
+}
+
+size_t tsched_lds_bytes(int32_t max_row, int32_t max_lrow) {
+    return (size_t)max_row * 8 + ((size_t)max_lrow + 1) * 8 + (size_t)max_row * 4;
+}
+
+hipError_t launch_tsched(int32_t n, const int64_t* rpF, const int32_t* diagF, const int64_t* sptr,
+                         const int32_t* sq, const int32_t* sp, int mode, int32_t* tcount, const int64_t* tptr,
+                         int32_t* tsl, int32_t* tq, int32_t max_row, int32_t max_lrow, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const size_t lds = tsched_lds_bytes(std::max(max_row, 1), max_lrow);
+    hipLaunchKernelGGL(k_tsched, dim3(std::min(n, 65536)), dim3(64), lds, s, n, rpF, diagF, sptr, sq, sp, mode,
+                       tcount, tptr, tsl, tq);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
 // pattern statistics
 // ------------------------------------------------------------------------------------
 __global__ void k_stats(int32_t n, const int64_t* __restrict__ rpF,

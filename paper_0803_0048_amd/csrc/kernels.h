@@ -95,16 +95,28 @@ struct PatDev {
     unsigned long long* trace;  // nullable: per-row start/finish ticks
     const int32_t* permL;       // nullable: rows in order of forward dependency level
     const int32_t* permU;       // nullable: rows in order of backward dependency level
+    const int64_t* tptr;  // per F slot: start of the updates it receives; [nnz_f + 1]
+    const int32_t* tsl;   // update: row-local slot of the pivot entry f_jh (ascending h per target)
+    const int32_t* tq;    // update: slot of f_ht in row h
 };
 
 // fill `n` doubles with kPending; thread 0 also resets ctl->ticket (and, if
 // reset_status, the sticky status words)
 hipError_t launch_fill_pending(double* p, int64_t n, Ctl* ctl, bool reset_status, hipStream_t s);
 
+// flow: the single-instance dataflow kernel (needs the target-major schedule
+// and numeric_flow_fits); otherwise the pivot-serial one
 hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, double* f_val,
                           Ctl* ctl, uint64_t spin_limit, int64_t skip_row, int32_t grid,
-                          int32_t max_row, hipStream_t s);
-int numeric_grid(int32_t batch, int32_t max_row, int num_cu);
+                          int32_t max_row, int32_t max_lrow, bool flow, hipStream_t s);
+int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, int num_cu);
+bool numeric_flow_fits(int32_t max_row, int32_t max_lrow, size_t lds_limit);
+// target-major update schedule (mode 0 count per slot, mode 1 fill); LDS of
+// tsched_lds_bytes per wavefront
+hipError_t launch_tsched(int32_t n, const int64_t* rpF, const int32_t* diagF, const int64_t* sptr,
+                         const int32_t* sq, const int32_t* sp, int mode, int32_t* tcount, const int64_t* tptr,
+                         int32_t* tsl, int32_t* tq, int32_t max_row, int32_t max_lrow, hipStream_t s);
+size_t tsched_lds_bytes(int32_t max_row, int32_t max_lrow);
 
 // ---- triangular solves -------------------------------------------------------------
 hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, const double* b,

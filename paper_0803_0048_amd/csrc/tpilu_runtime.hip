@@ -28,6 +28,7 @@ struct tpilu_ctx_s {
     int64_t skip_row = -1;
     int32_t grid_override = 0;
     int solver = 0;  // 0 auto, 1 whole device, 2 one workgroup
+    int numeric = 0;  // 0 auto, 1 dataflow, 2 pivot-serial
     bool timing = false;
     unsigned long long* trace = nullptr;  // per-row timeline buffer (device, 2n), or null
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
@@ -53,6 +54,8 @@ constexpr uint64_t kDefaultWaitUs = 10000000ull;  // 10 s per dependency wait
 constexpr int32_t kSolveWavesNarrow = 128;
 constexpr int32_t kSolveWavesWide = 256;
 constexpr int32_t kNumericWaves = 512;
+constexpr int32_t kFlowWaves = 1024;
+constexpr int64_t kFlowMinL = 4;  // dataflow numeric when L rows average at least this many entries
 constexpr int32_t kAdjointWaves = 512;
 constexpr int64_t kNarrowWidth = 64;   // n / depth below this: narrow
 constexpr int64_t kLongRows = 24;      // average entries per half row at or above this: long
@@ -140,6 +143,10 @@ struct tpilu_pattern_s {
     int64_t *tpL = nullptr, *tpU = nullptr;
     int32_t *tsL = nullptr, *trL = nullptr, *tsU = nullptr, *trU = nullptr;
     int32_t *permUT = nullptr, *permLT = nullptr;
+    // target-major update schedule (only when the dataflow numeric kernel fits)
+    bool flow = false;
+    int64_t* tptr = nullptr;
+    int32_t *tsl = nullptr, *tq = nullptr;
     // growable workspaces
     DBuf ws_x, ws_z, ws_fin, ws_lbar, ws_gm;
 
@@ -164,6 +171,7 @@ struct tpilu_pattern_s {
         d.rpA = rpA; d.ciA = ciA; d.rpF = rpF; d.ciF = ciF; d.diagF = diagF; d.a2f = a2f;
         d.lsd = lsd; d.sptr = sptr; d.sq = sq; d.sp = sp;
         d.permL = permL; d.permU = permU;
+        d.tptr = tptr; d.tsl = tsl; d.tq = tq;
         return d;
     }
     ~tpilu_pattern_s() {
@@ -269,15 +277,21 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
                     "batched factorization supports rows of at most 80 entries");
     if (batch == 1 && (size_t)pat->st.max_row * 8 + 12 * 1024 > kBatchLdsLimit)
         return fail(ctx, TPILU_E_INVAL, "numeric factorization supports rows of at most 6600 entries");
+    if (batch == 1 && ctx->numeric == 1 && !pat->flow)
+        return fail(ctx, TPILU_E_INVAL, "the rows of this pattern do not fit the dataflow numeric kernel");
+    // automatic choice: rows with very short L parts (a few pivots each) gain
+    // nothing from spreading a row over lanes and pay for the extra staging
+    const bool auto_flow = (int64_t)pat->st.nnz_l >= kFlowMinL * pat->n;
+    const bool flow = batch == 1 && pat->flow && (ctx->numeric == 1 || (ctx->numeric == 0 && auto_flow));
     HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, pat->ctl, true, ctx->stream));
     const int grid = ctx->grid_override
                          ? ctx->grid_override
-                         : std::min(batch == 1 ? kNumericWaves : 1 << 30,
-                                    numeric_grid(batch, pat->st.max_row, ctx->num_cu));
+                         : std::min(batch == 1 ? (flow ? kFlowWaves : kNumericWaves) : 1 << 30,
+                                    numeric_grid(batch, pat->st.max_row, pat->st.max_lrow, flow, ctx->num_cu));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_NUMERIC);
         HIPCHK(ctx, launch_numeric(pat->dev(ctx->trace), a_val, batch, f_val, pat->ctl, ctx->spin_limit,
-                                   ctx->skip_row, grid, pat->st.max_row, ctx->stream));
+                                   ctx->skip_row, grid, pat->st.max_row, pat->st.max_lrow, flow, ctx->stream));
     }
     return TPILU_OK;
 }
@@ -460,9 +474,9 @@ extern "C" TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t wave
     return TPILU_OK;
 }
 
-extern "C" TPILU_API tpilu_status tpilu_ctx_set_trace(tpilu_ctx ctx, uint64_t* rows2n) {
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_trace(tpilu_ctx ctx, uint64_t* rows4n) {
     if (!ctx) return TPILU_E_INVAL;
-    ctx->trace = reinterpret_cast<unsigned long long*>(rows2n);
+    ctx->trace = reinterpret_cast<unsigned long long*>(rows4n);
     return TPILU_OK;
 }
 
@@ -470,6 +484,13 @@ extern "C" TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode) 
     if (!ctx) return TPILU_E_INVAL;
     if (mode < 0 || mode > 2) return fail(ctx, TPILU_E_INVAL, "solver mode must be 0, 1 or 2");
     ctx->solver = mode;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_numeric(tpilu_ctx ctx, int mode) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (mode < 0 || mode > 2) return fail(ctx, TPILU_E_INVAL, "numeric mode must be 0, 1 or 2");
+    ctx->numeric = mode;
     return TPILU_OK;
 }
 
@@ -666,6 +687,21 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
     if (!P->sq || !P->sp) return bail(fail(ctx, TPILU_E_NOMEM, "schedule"));
     HIPCHK(ctx, launch_sched(ni, P->rpF, P->ciF, P->diagF, 1, nullptr, nullptr, P->sptr, P->sq, P->sp,
                              P->st.max_row, s));
+    // ---- the same schedule by target, for the dataflow numeric kernel
+    if (numeric_flow_fits(P->st.max_row, P->st.max_lrow, kBatchLdsLimit) &&
+        tsched_lds_bytes(P->st.max_row, P->st.max_lrow) <= kBatchLdsLimit) {
+        trace("symbolic: target-major schedule");
+        P->tptr = (int64_t*)P->take(sizeof(int64_t) * (size_t)(nnzf + 1));
+        P->tsl = (int32_t*)P->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nupd, 1));
+        P->tq = (int32_t*)P->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nupd, 1));
+        if (!P->tptr || !P->tsl || !P->tq) return bail(fail(ctx, TPILU_E_NOMEM, "target-major schedule"));
+        HIPCHK(ctx, launch_tsched(ni, P->rpF, P->diagF, P->sptr, P->sq, P->sp, 0, scount, nullptr, nullptr, nullptr,
+                                  P->st.max_row, P->st.max_lrow, s));
+        HIPCHK(ctx, launch_scan(scount, nnzf, P->tptr, scan2, s));
+        HIPCHK(ctx, launch_tsched(ni, P->rpF, P->diagF, P->sptr, P->sq, P->sp, 1, nullptr, P->tptr, P->tsl, P->tq,
+                                  P->st.max_row, P->st.max_lrow, s));
+        P->flow = true;
+    }
     // ---- dependency levels and the level-ordered schedules
     P->depthL = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
     P->depthU = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
@@ -703,6 +739,7 @@ extern "C" TPILU_API tpilu_status tpilu_pattern_info(tpilu_pattern pat, tpilu_pa
     info->depth_l = pat->depth_l;
     info->depth_u = pat->depth_u;
     info->overflow_rows = pat->overflow_rows;
+    info->flow_ready = pat->flow ? 1 : 0;
     return TPILU_OK;
 }
 

@@ -26,6 +26,7 @@ def _gpu_guard(request):
     ctx = T.context(0)
     ctx.set_grid(0)
     ctx.set_solver(0)
+    ctx.set_numeric(0)
     ctx.set_watchdog(0, -1)
     yield
     torch.cuda.synchronize()
@@ -40,6 +41,15 @@ def _full(A, k, b=None, check_gmres=None):
     f = T.numeric(pat, g(A.val), check=False)
     bad_g = T.check(pat) if bad < 0 else None
     assert_bits_equal(f, vF, "F")
+    # both single-instance kernels, whichever the automatic choice was
+    ctx = T.context(0)
+    modes = [ctx.NUMERIC_PIVOT] + ([ctx.NUMERIC_FLOW] if pat.info["flow_ready"] else [])
+    try:
+        for mode in modes:
+            ctx.set_numeric(mode)
+            assert_bits_equal(T.numeric(pat, g(A.val), check=False), vF, f"F (numeric kernel {mode})")
+    finally:
+        ctx.set_numeric(0)
     if b is not None:
         x_ref, y_ref = O.apply(A.n, rpF, ciF, vF, b)
         y, x = T.apply(pat, f, g(b), return_x=True)
@@ -135,6 +145,14 @@ def test_overflow_rows_take_global_path():
     A = I.CSR(n, np.cumsum(rp), cols.astype(np.int32), vals[rows, cols])
     pat, _, _ = _full(A, 2, rng.standard_normal(n))
     assert pat.info["overflow_rows"] >= 1
+    # a 3000-entry row does not fit the dataflow kernel's LDS staging
+    assert pat.info["flow_ready"] == 0
+    ctx = T.context(0)
+    ctx.set_numeric(ctx.NUMERIC_FLOW)
+    with pytest.raises(T.TpiluError) as e:
+        T.numeric(pat, g(A.val))
+    assert e.value.status == T.E_INVAL
+    ctx.set_numeric(0)
 
 
 def test_long_range_fill_k_infinity():
