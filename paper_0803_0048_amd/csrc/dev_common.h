@@ -174,10 +174,11 @@ __device__ __forceinline__ void st_final(double* p, double v) {
 // where lane k holds f_k and the address of v_k (cnt <= 64).  The values are
 // produced by other rows; the chain advances over every prefix of entries
 // whose value is already final, so once the last value arrives only the rest
-// of the chain is left to do.  While blocked it polls only the entry it is
-// blocked on (all pending entries again right after it made progress, and
-// every 8th round): thousands of waiting wavefronts polling every pending
-// value would load the memory side enough to slow every hand-off down.
+// of the chain is left to do.  While blocked, every round re-polls all of the
+// chunk's pending entries at once (one round trip for all of them) with no
+// pause between rounds: entries that land while the chain waits on an earlier
+// one are then already in hand when it gets there.  Polling only the blocking
+// entry, or pausing between rounds, measured slower.
 // The bits are those of the plain sequential loop.  On a watchdog timeout or
 // abort the result is a quiet NaN (the call then reports the timeout).
 template <Scope S>
@@ -194,10 +195,9 @@ __device__ __forceinline__ double chain_sub(double s, int32_t cnt, double f, con
     for (;;) {
         const uint64_t pend = ~__ballot(ready) & (k >= kWave ? 0ull : (~0ull << k));
         const int32_t stop = pend ? min((int32_t)__builtin_ctzll(pend), cnt) : cnt;
-        const bool progressed = stop > k;
         for (; k < stop; ++k) s = s - bcast_lane(prod, k);
         if (k >= cnt) break;
-        if (!ready && (lane == k || progressed || (polls & 7u) == 0u)) {
+        if (!ready) {
             v = ld_poll<S>(src);
             if (v != kPending) {
                 ready = true;
@@ -218,7 +218,6 @@ __device__ __forceinline__ double chain_sub(double s, int32_t cnt, double f, con
             }
         }
         ++polls;
-        __builtin_amdgcn_s_sleep(1);
     }
     return s;
 }

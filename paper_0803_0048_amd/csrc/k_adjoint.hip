@@ -156,12 +156,102 @@ __global__ __launch_bounds__(64) void k_adj_solve_l(PatDev P, AdjPat T, const do
     }
 }
 
+// ----------------------------------------------------------------------------------
+// batches: one wavefront per (row, group of 64 instances), lanes = instances, each
+// lane running the row's sequential chain for its own instance (values are stored
+// entry-major, instance-minor, so the 64 lanes read one contiguous line per entry).
+// One ticket covers a row for 64 instances instead of one.
+// ----------------------------------------------------------------------------------
+constexpr int kAdjChunk = 8;  // chain entries whose inputs are loaded together
+
+__global__ __launch_bounds__(64) void k_adj_solve_u_batch(PatDev P, AdjPat T, const double* __restrict__ F,
+                                                          int32_t B, const double* __restrict__ ybar,
+                                                          double* z, Ctl* ctl, uint64_t spin_limit) {
+    const int lane = lane_id();
+    const int32_t G = (B + kWave - 1) / kWave;
+    const uint32_t ntask = (uint32_t)P.n * (uint32_t)G;
+    for (;;) {
+        const uint32_t t = wave_ticket(ctl);
+        if (t >= ntask) break;
+        const int32_t i = T.permUT[t / (uint32_t)G];
+        const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
+        if (col < B) {
+            const int64_t a0 = T.tpU[i], a1 = T.tpU[i + 1];
+            double s = sanitize_input(ybar[(int64_t)i * B + col], ctl);
+            for (int64_t c = a0; c < a1; c += kAdjChunk) {  // rows j < i of column i, ascending
+                double fv[kAdjChunk];
+                uint64_t zv[kAdjChunk];
+                int32_t jj[kAdjChunk];
+#pragma unroll
+                for (int u = 0; u < kAdjChunk; ++u) {
+                    if (c + u < a1) {
+                        jj[u] = T.trU[c + u];
+                        fv[u] = F[(int64_t)T.tsU[c + u] * B + col];
+                        zv[u] = ld_cached(z + (int64_t)jj[u] * B + col);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kAdjChunk; ++u) {
+                    if (c + u < a1) {
+                        const double zz = wait_final(z + (int64_t)jj[u] * B + col, zv[u], ctl, spin_limit);
+                        s = s - fv[u] * zz;
+                    }
+                }
+            }
+            st_publish(z + (int64_t)i * B + col, s / F[(int64_t)P.diagF[i] * B + col]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void k_adj_solve_l_batch(PatDev P, AdjPat T, const double* __restrict__ F,
+                                                          int32_t B, const double* __restrict__ z,
+                                                          double* w, Ctl* ctl, uint64_t spin_limit) {
+    const int lane = lane_id();
+    const int32_t G = (B + kWave - 1) / kWave;
+    const uint32_t ntask = (uint32_t)P.n * (uint32_t)G;
+    for (;;) {
+        const uint32_t t = wave_ticket(ctl);
+        if (t >= ntask) break;
+        const int32_t i = T.permLT[t / (uint32_t)G];
+        const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
+        if (col < B) {
+            const int64_t a0 = T.tpL[i], a1 = T.tpL[i + 1];
+            double s = z[(int64_t)i * B + col];
+            for (int64_t c = a1 - 1; c >= a0; c -= kAdjChunk) {  // rows j > i of column i, descending
+                double fv[kAdjChunk];
+                uint64_t wv[kAdjChunk];
+                int32_t jj[kAdjChunk];
+#pragma unroll
+                for (int u = 0; u < kAdjChunk; ++u) {
+                    if (c - u >= a0) {
+                        jj[u] = T.trL[c - u];
+                        fv[u] = F[(int64_t)T.tsL[c - u] * B + col];
+                        wv[u] = ld_cached(w + (int64_t)jj[u] * B + col);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kAdjChunk; ++u) {
+                    if (c - u >= a0) {
+                        const double ww = wait_final(w + (int64_t)jj[u] * B + col, wv[u], ctl, spin_limit);
+                        s = s - fv[u] * ww;
+                    }
+                }
+            }
+            st_publish(w + (int64_t)i * B + col, s);
+        }
+    }
+}
+
 hipError_t launch_adj_solve_u(const PatDev& P, const AdjPat& T, const double* f_val,
                               int32_t batch, const double* ybar, double* z, Ctl* ctl,
                               uint64_t spin_limit, int32_t grid, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_solve_u, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, ybar, z, ctl,
-                       spin_limit);
+    if (batch > 1)
+        hipLaunchKernelGGL(k_adj_solve_u_batch, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, ybar, z, ctl,
+                           spin_limit);
+    else
+        hipLaunchKernelGGL(k_adj_solve_u, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, ybar, z, ctl,
+                           spin_limit);
     return hipGetLastError();
 }
 
@@ -169,8 +259,12 @@ hipError_t launch_adj_solve_l(const PatDev& P, const AdjPat& T, const double* f_
                               int32_t batch, const double* z, double* w, Ctl* ctl,
                               uint64_t spin_limit, int32_t grid, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_solve_l, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, z, w, ctl,
-                       spin_limit);
+    if (batch > 1)
+        hipLaunchKernelGGL(k_adj_solve_l_batch, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, z, w, ctl,
+                           spin_limit);
+    else
+        hipLaunchKernelGGL(k_adj_solve_l, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, z, w, ctl,
+                           spin_limit);
     return hipGetLastError();
 }
 
@@ -261,14 +355,89 @@ __global__ __launch_bounds__(64) void k_adj_numeric(PatDev P, AdjPat T, const do
     }
 }
 
+// Reverse sweep for batches: lanes = instances, the working row in LDS as
+// [slot][lane]; the same operations in the same order as k_adj_numeric, each
+// lane on its own instance.
+__global__ __launch_bounds__(64) void k_adj_numeric_batch(PatDev P, AdjPat T, const double* __restrict__ F,
+                                                          int32_t B, const double* __restrict__ fin,
+                                                          double* Gv, double* lbar_out,
+                                                          double* __restrict__ abar, Ctl* ctl,
+                                                          uint64_t spin_limit) {
+    extern __shared__ double W[];  // [len][64]
+    const int lane = lane_id();
+    const int32_t G = (B + kWave - 1) / kWave;
+    const uint32_t ntask = (uint32_t)P.n * (uint32_t)G;
+    for (;;) {
+        const uint32_t t = wave_ticket(ctl);
+        if (t >= ntask) break;
+        const int32_t j = T.permLT[t / (uint32_t)G];
+        const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
+        if (col < B) {
+            const int64_t rs = P.rpF[j], re = P.rpF[j + 1], dj = P.diagF[j];
+            const int32_t len = (int32_t)(re - rs);
+            for (int32_t e = 0; e < len; ++e) W[e * kWave + lane] = sanitize_input(fin[(rs + e) * B + col], ctl);
+            const double ujj = F[dj * B + col];
+            // contributions of the rows i > j that pivot on j, in descending i
+            for (int64_t a = T.tpL[j + 1] - 1; a >= T.tpL[j]; --a) {
+                const int64_t sl = T.tsL[a];  // slot of f_ij in row i
+                const double l = F[sl * B + col];
+                const uint64_t lb0 = ld_cached(lbar_out + sl * B + col);
+                const int64_t e0 = P.sptr[sl], e1 = P.sptr[sl + 1];
+                for (int64_t c = e0; c < e1; c += kAdjChunk) {
+                    uint64_t gv[kAdjChunk];
+                    int32_t pq[kAdjChunk], pp[kAdjChunk];
+#pragma unroll
+                    for (int u = 0; u < kAdjChunk; ++u) {
+                        if (c + u < e1) {
+                            pq[u] = P.sq[c + u];  // slot in row j
+                            pp[u] = P.sp[c + u];  // slot in row i
+                            gv[u] = ld_cached(Gv + (int64_t)pp[u] * B + col);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kAdjChunk; ++u) {
+                        if (c + u < e1) {
+                            const double g = wait_final(Gv + (int64_t)pp[u] * B + col, gv[u], ctl, spin_limit);
+                            const int64_t q = (pq[u] - rs) * kWave + lane;
+                            W[q] = W[q] - g * l;
+                        }
+                    }
+                }
+                const double lb = wait_final(lbar_out + sl * B + col, lb0, ctl, spin_limit);
+                double tmp = lb * l;
+                tmp = tmp / ujj;
+                W[(dj - rs) * kWave + lane] = W[(dj - rs) * kWave + lane] - tmp;
+            }
+            // own pivots, descending
+            for (int64_t sl = dj - 1; sl >= rs; --sl) {
+                double lb = W[(sl - rs) * kWave + lane];
+                for (int64_t e = P.sptr[sl]; e < P.sptr[sl + 1]; ++e)
+                    lb = lb - W[(P.sp[e] - rs) * kWave + lane] * F[(int64_t)P.sq[e] * B + col];
+                st_publish(lbar_out + sl * B + col, lb);
+                W[(sl - rs) * kWave + lane] = lb / F[(int64_t)P.lsd[sl] * B + col];
+            }
+            for (int64_t p = P.rpA[j]; p < P.rpA[j + 1]; ++p)
+                abar[p * B + col] = W[(P.a2f[p] - rs) * kWave + lane];
+            for (int32_t e = 0; e < len; ++e) st_publish(Gv + (rs + e) * B + col, W[e * kWave + lane]);
+        }
+    }
+}
+
 hipError_t launch_adj_numeric(const PatDev& P, const AdjPat& T, const double* f_val,
                               int32_t batch, const double* fbar_in, double* G, double* lbar,
                               double* abar, Ctl* ctl, uint64_t spin_limit, int32_t grid,
                               int32_t max_row, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    size_t lds = (size_t)std::max(max_row, 1) * sizeof(double);
-    hipLaunchKernelGGL(k_adj_numeric, dim3(grid), dim3(64), lds, s, P, T, f_val, batch, fbar_in, G,
-                       lbar, abar, ctl, spin_limit);
+    const size_t lds_batch = (size_t)std::max(max_row, 1) * sizeof(double) * kWave;
+    if (batch > 1 && lds_batch <= 64 * 1024) {  // rows of up to 128 entries
+        const size_t lds = lds_batch;
+        hipLaunchKernelGGL(k_adj_numeric_batch, dim3(grid), dim3(64), lds, s, P, T, f_val, batch, fbar_in, G,
+                           lbar, abar, ctl, spin_limit);
+    } else {
+        size_t lds = (size_t)std::max(max_row, 1) * sizeof(double);
+        hipLaunchKernelGGL(k_adj_numeric, dim3(grid), dim3(64), lds, s, P, T, f_val, batch, fbar_in, G,
+                           lbar, abar, ctl, spin_limit);
+    }
     return hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ constexpr uint64_t kDefaultWaitUs = 10000000ull;  // 10 s per dependency wait
 // wavefronts only slow each hand-off down (measured on MI355X: the forward
 // solve of the n=160,000 ILU(2) matrix takes 12 ms with 128 wavefronts and
 // 33 ms with 8192).  Narrow graphs (few rows per level) get few wavefronts.
-constexpr int32_t kSolveWavesNarrow = 128;
+constexpr int32_t kSolveWavesNarrow = 192;
 constexpr int32_t kSolveWavesWide = 256;
 constexpr int32_t kNumericWaves = 512;
 constexpr int32_t kFlowWaves = 1024;

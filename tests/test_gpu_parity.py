@@ -401,6 +401,51 @@ def test_adjoint_small_bits():
         assert_bits_equal(abar, abar_r, "abar")
 
 
+def _arrow(n, seed):
+    M = np.zeros((n, n), bool)
+    M[np.arange(n), np.arange(n)] = True
+    M[-1, :] = True
+    M[:, -1] = True
+    M[np.arange(1, n), np.arange(n - 1)] = True
+    rows, cols = np.nonzero(M)
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, rows + 1, 1)
+    return I.CSR(n, np.cumsum(rp), cols.astype(np.int32), np.zeros(rows.size))
+
+
+@pytest.mark.parametrize("case", ["groups", "long_rows"])
+def test_adjoint_batched_bits(case):
+    """Reverse mode on batches: every instance equals its own sequential
+    adjoint, with partial instance groups (B=70) and with rows too long for
+    the lanes-as-instances reverse sweep (B=3, 150-entry row)."""
+    rng = np.random.default_rng(12)
+    if case == "groups":
+        A = I.random_pattern(240, 0.02, seed=99)
+        B, k = 70, 2
+    else:
+        A = _arrow(150, 5)
+        B, k = 3, 1
+    vals = rng.uniform(-1, 1, (A.nnz, B))
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    diag = A.col == rows
+    rowsum = np.zeros((A.n, B))
+    np.add.at(rowsum, rows, np.abs(vals))
+    vals[diag] = 1.1 * rowsum + 1.0  # diagonally dominant: no zero pivots
+    rhs, tgt = rng.standard_normal((A.n, B)), rng.standard_normal((A.n, B))
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
+    pat = T.symbolic(g(A.rowptr), g(A.col), k)
+    # factors instance by instance (the batched factorization caps row length)
+    f = torch.stack([T.numeric(pat, g(vals[:, i].copy())) for i in range(B)], dim=1).contiguous()
+    y, x = T.apply(pat, f, g(rhs), return_x=True)
+    bbar, fbar = T.apply_adjoint(pat, f, x, y, 2.0 * (y - g(tgt)))
+    abar, _ = T.numeric_adjoint(pat, f, fbar.clone())
+    for inst in sorted({0, 1, B // 2, B - 1}):
+        abar_r, bbar_r, Fbar_r = _oracle_grads(A, rpF, ciF, vals[:, inst].copy(), rhs[:, inst], tgt[:, inst])
+        assert_bits_equal(bbar[:, inst], bbar_r, f"bbar instance {inst}")
+        assert_bits_equal(fbar[:, inst], Fbar_r, f"Fbar instance {inst}")
+        assert_bits_equal(abar[:, inst], abar_r, f"abar instance {inst}")
+
+
 def test_config5_autograd_against_oracle_and_fd():
     c = I.config5()
     A, rhs, tgt = c["A"], c["b"], c["t"]
