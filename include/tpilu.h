@@ -106,10 +106,11 @@ TPILU_API tpilu_status tpilu_ctx_set_watchdog(tpilu_ctx ctx, uint32_t timeout_us
 TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t waves);
 
 /* Launch shape of the single-instance triangular solves: 0 = automatic
- * (currently always the whole device, the faster shape on every measured
- * workload), 1 = whole device, 2 = one workgroup (16 wavefronts on one CU).
- * Same bits in every mode. */
-enum { TPILU_SOLVER_AUTO = 0, TPILU_SOLVER_DEVICE = 1, TPILU_SOLVER_WORKGROUP = 2 };
+ * (lane per row when a triangle's rows hold at most 40 entries on average
+ * and a dependency level at least 64 rows, else a wavefront per row), 1 = a wavefront per row over the whole device,
+ * 2 = one workgroup (16 wavefronts on one CU), 3 = a lane per row (64 rows per
+ * wavefront) over the whole device.  Same bits in every mode. */
+enum { TPILU_SOLVER_AUTO = 0, TPILU_SOLVER_DEVICE = 1, TPILU_SOLVER_WORKGROUP = 2, TPILU_SOLVER_LANES = 3 };
 TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode);
 
 /* Kernel of the single-instance numeric factorization: 0 = automatic (the

@@ -140,7 +140,7 @@ class Context:
         self.check(load_library().tpilu_ctx_read_timing(self.h, kernel, C.byref(ms), C.byref(cnt)), "read_timing")
         return ms.value, cnt.value
 
-    SOLVER_AUTO, SOLVER_DEVICE, SOLVER_WORKGROUP = 0, 1, 2
+    SOLVER_AUTO, SOLVER_DEVICE, SOLVER_WORKGROUP, SOLVER_LANES = 0, 1, 2, 3
 
     def set_solver(self, mode: int = 0):
         self.check(load_library().tpilu_ctx_set_solver(self.h, mode), "set_solver")

@@ -115,6 +115,131 @@ __global__ __launch_bounds__(1024) void k_backward_wg(PatDev P, const double* __
         backward_row<Scope::Workgroup>(P, F, x, y, ctl, spin_limit, P.permU ? P.permU[r] : P.n - 1 - r);
 }
 
+// lane per row, for wide dependency graphs of short rows (many rows per level,
+// few entries each): one ticket hands out 64 consecutive rows of the level
+// order, one per lane, so the ticket (a single contended atomic) is taken 64
+// times less often.  Each lane runs its row's chain in the fixed order
+// (forward ascending, backward right to left, then the division), with the
+// loads of up to kLaneChunk entries in flight together and every pending one
+// re-polled each round; the wavefront goes round until all its lanes have
+// published.  A lane may wait on the row of another lane of the same
+// wavefront (an earlier position of the level order), which advances in the
+// same rounds, so the wavefront cannot deadlock.
+constexpr int kLaneChunk = 8;
+
+__device__ __forceinline__ void trace_lane(unsigned long long* trace, int64_t slot, bool on) {
+    if (trace && on) trace[slot] = wall_clock64();
+}
+
+template <bool kBackward>
+__global__ __launch_bounds__(64) void k_solve_lanes(PatDev P, const double* __restrict__ F,
+                                                    const double* __restrict__ in, double* out, Ctl* ctl,
+                                                    uint64_t spin_limit) {
+    const int lane = lane_id();
+    const int32_t n = P.n;
+    const int32_t* perm = kBackward ? P.permU : P.permL;
+    const int64_t tr0 = kBackward ? 2 * (int64_t)n : 0;
+    for (;;) {
+        const uint32_t t = wave_ticket(ctl);
+        if ((int64_t)t * kWave >= n) break;
+        const int64_t r = (int64_t)t * kWave + lane;
+        const bool valid = r < n;
+        int32_t i = 0;
+        int64_t q = 0, dslot = 0;
+        int32_t left = 0;
+        double s = 0.0;
+        if (valid) {
+            i = perm ? perm[r] : (kBackward ? n - 1 - (int32_t)r : (int32_t)r);
+            dslot = P.diagF[i];
+            if (kBackward) {
+                q = P.rpF[i + 1] - 1;  // right to left
+                left = (int32_t)(q - dslot);
+                s = in[i];
+            } else {
+                q = P.rpF[i];
+                left = (int32_t)(dslot - q);
+                s = sanitize_input(in[i], ctl);
+            }
+        }
+        trace_lane(P.trace, tr0 + i, valid);
+        bool done = !valid;
+        double fv[kLaneChunk];
+        uint64_t xv[kLaneChunk];
+        int32_t cc[kLaneChunk];
+        int32_t cnt = 0, u = 0;
+        uint32_t polls = 0;
+        uint64_t t0 = 0;
+        for (;;) {
+            bool prog = false;
+            if (!done) {
+                if (u == cnt && left > 0) {  // next chunk of the row
+                    cnt = min(left, kLaneChunk);
+#pragma unroll
+                    for (int k = 0; k < kLaneChunk; ++k) {
+                        if (k < cnt) {
+                            const int64_t slot = kBackward ? q - k : q + k;
+                            cc[k] = P.ciF[slot];
+                            fv[k] = F[slot];
+                            xv[k] = ld_cached(out + cc[k]);
+                        }
+                    }
+                    q = kBackward ? q - cnt : q + cnt;
+                    left -= cnt;
+                    u = 0;
+                }
+                bool blocked = false;
+#pragma unroll
+                for (int k = 0; k < kLaneChunk; ++k) {
+                    if (k >= u && k < cnt && !blocked) {
+                        if (xv[k] == kPending) {
+                            blocked = true;
+                        } else {
+                            s = s - fv[k] * as_f64(xv[k]);
+                            u = k + 1;
+                            prog = true;
+                        }
+                    }
+                }
+                if (u == cnt && left == 0) {
+                    st_publish(out + i, kBackward ? s / F[dslot] : s);
+                    trace_lane(P.trace, tr0 + n + i, true);
+                    done = true;
+                    prog = true;
+                } else if (blocked) {
+#pragma unroll
+                    for (int k = 0; k < kLaneChunk; ++k)
+                        if (k >= u && k < cnt && xv[k] == kPending) xv[k] = ld_coherent(out + cc[k]);
+                }
+            }
+            if (__all(done)) break;
+            if (__any(prog)) {
+                polls = 0;
+                continue;
+            }
+            // watchdog over rounds in which no lane advanced
+            ++polls;
+            if ((polls & 31u) == 0u) {
+                bool stop = (polls & 255u) == 0u && ld_u32_coherent(&ctl->abort) != 0u;
+                const uint64_t now = wall_clock64();
+                if (polls == 32u) {
+                    t0 = now;
+                } else if (now - t0 > spin_limit) {
+                    if (lane == 0) {
+                        atomicOr(&ctl->status, kStTimeout);
+                        __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    stop = true;
+                }
+                if (__any(stop)) {
+                    // release anything waiting on these rows
+                    if (!done) st_publish(out + i, as_f64(kQNaN));
+                    break;
+                }
+            }
+        }
+    }
+}
+
 // batches: lanes are instances; each lane runs the sequential chain of its
 // instance; the loads of a chunk of entries are issued before any of them is
 // waited on
@@ -208,12 +333,15 @@ int solve_grid(int32_t batch, int num_cu) {
     return 16 * num_cu;
 }
 
-// grid <= 0 selects the one-workgroup variant (single instance only)
+// single instance: grid > 0 wavefront per row, grid == 0 one workgroup,
+// grid < 0 lane per row with -grid wavefronts
 hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, const double* b,
                           double* x, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    if (batch == 1 && grid <= 0)
+    if (batch == 1 && grid == 0)
         hipLaunchKernelGGL(k_forward_wg, dim3(1), dim3(1024), 0, s, P, f_val, b, x, ctl, spin_limit);
+    else if (batch == 1 && grid < 0)
+        hipLaunchKernelGGL(k_solve_lanes<false>, dim3(-grid), dim3(64), 0, s, P, f_val, b, x, ctl, spin_limit);
     else if (batch == 1)
         hipLaunchKernelGGL(k_forward_row, dim3(grid), dim3(64), 0, s, P, f_val, b, x, ctl, spin_limit);
     else
@@ -225,8 +353,10 @@ hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, c
 hipError_t launch_backward(const PatDev& P, const double* f_val, int32_t batch, const double* x,
                            double* y, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    if (batch == 1 && grid <= 0)
+    if (batch == 1 && grid == 0)
         hipLaunchKernelGGL(k_backward_wg, dim3(1), dim3(1024), 0, s, P, f_val, x, y, ctl, spin_limit);
+    else if (batch == 1 && grid < 0)
+        hipLaunchKernelGGL(k_solve_lanes<true>, dim3(-grid), dim3(64), 0, s, P, f_val, x, y, ctl, spin_limit);
     else if (batch == 1)
         hipLaunchKernelGGL(k_backward_row, dim3(grid), dim3(64), 0, s, P, f_val, x, y, ctl, spin_limit);
     else

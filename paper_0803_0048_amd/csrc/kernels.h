@@ -119,6 +119,8 @@ hipError_t launch_tsched(int32_t n, const int64_t* rpF, const int32_t* diagF, co
 size_t tsched_lds_bytes(int32_t max_row, int32_t max_lrow);
 
 // ---- triangular solves -------------------------------------------------------------
+// single instance: grid > 0 wavefront per row, 0 one workgroup, < 0 lane per
+// row with -grid wavefronts; batches: lanes = instances with grid wavefronts
 hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, const double* b,
                           double* x, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s);
 hipError_t launch_backward(const PatDev& P, const double* f_val, int32_t batch, const double* x,

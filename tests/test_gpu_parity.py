@@ -219,7 +219,7 @@ def test_repeatable_across_launch_shapes():
     ctx = T.context(0)
     ref_f = T.numeric(pat, av)
     ref_y = T.apply(pat, ref_f, bv)
-    for solver in (ctx.SOLVER_DEVICE, ctx.SOLVER_WORKGROUP):
+    for solver in (ctx.SOLVER_DEVICE, ctx.SOLVER_WORKGROUP, ctx.SOLVER_LANES):
         ctx.set_solver(solver)
         for waves in (1, 2, 7, 64, 1000, 0, 40000):
             ctx.set_grid(waves)
@@ -234,7 +234,7 @@ def test_repeatable_across_launch_shapes():
 
 @pytest.mark.parametrize("cfg", ["c2", "c3k1"])
 def test_solver_shapes_agree_full_size(cfg):
-    """Whole-device and one-workgroup solves: same bits as the oracle."""
+    """Every solve launch shape: same bits as the oracle."""
     c = I.config2() if cfg == "c2" else I.config3(k=1)
     A, b = c["A"], c["b"]
     pat = T.symbolic(g(A.rowptr), g(A.col), c["k"])
@@ -243,7 +243,7 @@ def test_solver_shapes_agree_full_size(cfg):
     vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
     x_ref, y_ref = O.apply(A.n, rpF, ciF, vF, b)
     ctx = T.context(0)
-    for solver in (ctx.SOLVER_DEVICE, ctx.SOLVER_WORKGROUP):
+    for solver in (ctx.SOLVER_DEVICE, ctx.SOLVER_WORKGROUP, ctx.SOLVER_LANES):
         ctx.set_solver(solver)
         y, x = T.apply(pat, f, g(b), return_x=True)
         assert_bits_equal(x, x_ref, f"x solver {solver}")
