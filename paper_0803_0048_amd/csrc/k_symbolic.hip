@@ -577,37 +577,11 @@ hipError_t launch_stats(int32_t n, const int64_t* rpF, const int32_t* diagF, Pat
 }
 
 // ------------------------------------------------------------------------------------
-// dependency depth (informational): depth_i = 1 + max depth_h over the rows h
-// row i needs (L part ascending, or U part descending); -1 = not yet known
+// dependency levels: level_i = 1 + max level_h over the nodes h that node i
+// depends on (-1 = not yet known).  Up to two independent graphs are walked in
+// one launch (the forward and the backward DAG), alternate wavefronts taking
+// nodes of either, so their two dependency chains overlap in time.
 // ------------------------------------------------------------------------------------
-template <Scope S>
-__device__ __forceinline__ int32_t wait_depth(const int32_t* p, Ctl* ctl, uint64_t spin_limit) {
-    int32_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    uint32_t n = 0;
-    uint64_t t0 = 0;
-    while (v < 0) {
-        if constexpr (S == Scope::Device)
-            v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
-            v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (v >= 0) break;
-        if ((n & 31u) == 0u) {
-            if ((n & 255u) == 0u && ld_u32_coherent(&ctl->abort) != 0u) return 0;
-            const uint64_t now = wall_clock64();
-            if (n == 0) {
-                t0 = now;
-            } else if (now - t0 > spin_limit) {
-                atomicOr(&ctl->status, kStTimeout);
-                __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                return 0;
-            }
-        }
-        ++n;
-        __builtin_amdgcn_s_sleep(1);
-    }
-    return v;
-}
-
 // The dependencies of node i: mode 0 the strict lower part of row i of F,
 // mode 1 the strict upper part, mode 2 entries [ptr[i], ptr[i+1]) of a
 // column structure (idx = row indices).
@@ -617,97 +591,134 @@ __device__ __forceinline__ void dep_range(const DepGraph& G, int32_t i, int64_t&
     else { a = G.ptr[i]; b = G.ptr[i + 1]; }
 }
 
-template <Scope S>
-__device__ __forceinline__ void depth_row(const DepGraph& G, int32_t* depth, Ctl* ctl, uint64_t spin_limit,
-                                          int32_t i) {
+__device__ __forceinline__ int32_t ld_level(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// watchdog over polling rounds without progress; true = give up
+__device__ __forceinline__ bool level_watchdog(uint32_t& polls, uint64_t& t0, Ctl* ctl, uint64_t limit) {
+    ++polls;
+    if ((polls & 31u) != 0u) return false;
+    bool stop = (polls & 255u) == 0u && ld_u32_coherent(&ctl->abort) != 0u;
+    const uint64_t now = wall_clock64();
+    if (polls == 32u) {
+        t0 = now;
+    } else if (now - t0 > limit) {
+        if (lane_id() == 0) {
+            atomicOr(&ctl->status, kStTimeout);
+            __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        stop = true;
+    }
+    return __any(stop);
+}
+
+// One node, one wavefront.  The maximum does not depend on order, so every
+// round re-polls all of a chunk's unknown dependencies at once.
+constexpr int kLevelPer = 4;  // dependencies per lane and chunk
+
+__device__ __forceinline__ void level_row(const DepGraph& G, int32_t* depth, Ctl* ctl, uint64_t limit, int32_t i) {
     const int lane = lane_id();
-    const int32_t* __restrict__ ciF = G.idx;
     int64_t a, b;
     dep_range(G, i, a, b);
     int32_t best = 0;
-    for (int64_t q = a + lane; q < b; q += kWave)
-        best = max(best, wait_depth<S>(depth + ciF[q], ctl, spin_limit));
+    bool stop = false;
+    for (int64_t base = a; base < b && !stop; base += kWave * kLevelPer) {
+        int32_t src[kLevelPer], dv[kLevelPer];
+        bool need[kLevelPer];
+#pragma unroll
+        for (int u = 0; u < kLevelPer; ++u) {
+            const int64_t q = base + u * kWave + lane;
+            need[u] = q < b;
+            src[u] = need[u] ? G.idx[q] : 0;
+            dv[u] = need[u] ? __hip_atomic_load(depth + src[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) : 0;
+        }
+        uint32_t polls = 0;
+        uint64_t t0 = 0;
+        for (;;) {
+            bool pend = false;
+#pragma unroll
+            for (int u = 0; u < kLevelPer; ++u) {
+                if (need[u]) {
+                    if (dv[u] >= 0) {
+                        best = max(best, dv[u]);
+                        need[u] = false;
+                    } else {
+                        pend = true;
+                    }
+                }
+            }
+            if (!__any(pend)) break;
+#pragma unroll
+            for (int u = 0; u < kLevelPer; ++u)
+                if (need[u]) dv[u] = ld_level(depth + src[u]);
+            if (level_watchdog(polls, t0, ctl, limit)) {
+                stop = true;
+                break;
+            }
+        }
+    }
     for (int off = 32; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off));
-    if (lane == 0) {
-        if constexpr (S == Scope::Device)
-            __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
-            __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
+    if (lane == 0) __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(64) void k_depth(int desc, int32_t n, DepGraph G, int32_t* depth, Ctl* ctl,
+__global__ __launch_bounds__(64) void k_depth(int32_t n, LevelJob j0, LevelJob j1, int32_t njobs, Ctl* ctl,
                                               uint64_t spin_limit) {
+    const LevelJob J = (njobs > 1 && (blockIdx.x & 1)) ? j1 : j0;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
+        const uint32_t t = wave_ticket(J.tctl);
         if (t >= (uint32_t)n) break;
-        const int32_t i = desc ? n - 1 - (int32_t)t : (int32_t)t;
-        depth_row<Scope::Device>(G, depth, ctl, spin_limit, i);
+        const int32_t i = J.desc ? n - 1 - (int32_t)t : (int32_t)t;
+        level_row(J.G, J.depth, ctl, spin_limit, i);
     }
 }
 
-// one workgroup, rows dealt round-robin to its 16 wavefronts
-__global__ __launch_bounds__(1024) void k_depth_wg(int desc, int32_t n, DepGraph G, int32_t* depth, Ctl* ctl,
-                                                   uint64_t spin_limit) {
-    const int32_t wave = uniform((int32_t)(threadIdx.x >> 6));
-    const int32_t nw = (int32_t)(blockDim.x >> 6);
-    for (int32_t r = wave; r < n; r += nw)
-        depth_row<Scope::Workgroup>(G, depth, ctl, spin_limit, desc ? n - 1 - r : r);
-}
-
-// Lane per row: a ticket hands a wavefront 64 consecutive rows (in the
-// sweep's order), so the whole matrix can be in flight at once and wide
-// dependency graphs are not throttled by the ticket window.  A lane scans its
-// row's dependencies, at most 8 per round, and stops at the first one not
-// known yet; the wavefront keeps looping until every lane published, so lanes
-// that depend on other lanes of the same wavefront cannot deadlock.
-__global__ __launch_bounds__(64) void k_depth_lanes(int desc, int32_t n, DepGraph G, int32_t* depth,
-                                                    Ctl* ctl, uint64_t spin_limit) {
+// Lane per node: a ticket hands a wavefront 64 consecutive nodes (in the
+// sweep's order), so the whole graph can be in flight at once and wide
+// graphs are not throttled by the ticket.  A lane scans its node's
+// dependencies, at most 8 per round, and stops at the first one not known
+// yet; the wavefront keeps looping until every lane published, so lanes that
+// depend on other lanes of the same wavefront cannot deadlock.
+__global__ __launch_bounds__(64) void k_depth_lanes(int32_t n, LevelJob j0, LevelJob j1, int32_t njobs, Ctl* ctl,
+                                                    uint64_t spin_limit) {
     const int lane = lane_id();
-    const int32_t* __restrict__ ciF = G.idx;
+    const LevelJob J = (njobs > 1 && (blockIdx.x & 1)) ? j1 : j0;
+    const int32_t* __restrict__ ciF = J.G.idx;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
+        const uint32_t t = wave_ticket(J.tctl);
         const int64_t r = (int64_t)t * kWave + lane;
         if ((int64_t)t * kWave >= n) break;
         const bool valid = r < n;
-        const int32_t i = valid ? (desc ? n - 1 - (int32_t)r : (int32_t)r) : 0;
+        const int32_t i = valid ? (J.desc ? n - 1 - (int32_t)r : (int32_t)r) : 0;
         int64_t q = 0, b = 0;
-        if (valid) dep_range(G, i, q, b);
+        if (valid) dep_range(J.G, i, q, b);
         int32_t best = 0;
         bool done = !valid;
         uint32_t polls = 0;
         uint64_t t0 = 0;
         for (;;) {
+            bool prog = false;
             if (!done) {
                 for (int step = 0; step < 8 && q < b; ++step) {
-                    const int32_t* src = depth + ciF[q];
+                    const int32_t* src = J.depth + ciF[q];
                     int32_t d = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                    if (d < 0) d = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (d < 0) d = ld_level(src);
                     if (d < 0) break;
                     best = max(best, d);
                     ++q;
+                    prog = true;
                 }
                 if (q >= b) {
-                    __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(J.depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     done = true;
                 }
             }
             if (__all(done)) break;
-            if ((polls & 31u) == 0u) {
-                if ((polls & 255u) == 0u && ld_u32_coherent(&ctl->abort) != 0u) break;
-                const uint64_t now = wall_clock64();
-                if (polls == 0) {
-                    t0 = now;
-                } else if (now - t0 > spin_limit) {
-                    if (lane == 0) {
-                        atomicOr(&ctl->status, kStTimeout);
-                        __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                    break;
-                }
+            if (__any(prog)) {
+                polls = 0;
+                continue;
             }
-            ++polls;
-            __builtin_amdgcn_s_sleep(2);
+            if (level_watchdog(polls, t0, ctl, spin_limit)) break;
         }
     }
 }
@@ -742,15 +753,15 @@ hipError_t launch_level_order(int32_t n, const int32_t* depth, int32_t max_depth
     return hipGetLastError();
 }
 
-hipError_t launch_depth(int desc, int32_t n, const DepGraph& G, int32_t* depth, Ctl* ctl,
-                        uint64_t spin_limit, int32_t grid, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    if (grid == 0)
-        hipLaunchKernelGGL(k_depth_wg, dim3(1), dim3(1024), 0, s, desc, n, G, depth, ctl, spin_limit);
-    else if (grid < 0)
-        hipLaunchKernelGGL(k_depth_lanes, dim3(-grid), dim3(64), 0, s, desc, n, G, depth, ctl, spin_limit);
+hipError_t launch_depth(int32_t n, const LevelJob& j0, const LevelJob* j1, Ctl* ctl, uint64_t spin_limit,
+                        int32_t grid, hipStream_t s) {
+    if (n <= 0 || grid == 0) return hipSuccess;
+    const int32_t njobs = j1 ? 2 : 1;
+    const LevelJob b = j1 ? *j1 : j0;
+    if (grid < 0)
+        hipLaunchKernelGGL(k_depth_lanes, dim3(-grid * njobs), dim3(64), 0, s, n, j0, b, njobs, ctl, spin_limit);
     else
-        hipLaunchKernelGGL(k_depth, dim3(grid), dim3(64), 0, s, desc, n, G, depth, ctl, spin_limit);
+        hipLaunchKernelGGL(k_depth, dim3(grid * njobs), dim3(64), 0, s, n, j0, b, njobs, ctl, spin_limit);
     return hipGetLastError();
 }
 

@@ -65,12 +65,21 @@ struct DepGraph {
     const int32_t* diag;
     int mode;
 };
-// level of every node (1 + max level of its dependencies), nodes taken in
-// ascending (desc = 0) or descending order; depth pre-filled with -1.
-// grid > 0: wavefront per node, natural order; grid == 0: one workgroup;
-// grid < 0: lane per node with -grid wavefronts
-hipError_t launch_depth(int desc, int32_t n, const DepGraph& G, int32_t* depth, Ctl* ctl,
-                        uint64_t spin_limit, int32_t grid, hipStream_t s);
+// One level computation: the graph, its sweep order (ascending, or descending
+// when desc), the level array (pre-filled with -1) and the control block
+// whose ticket hands out its nodes.
+struct LevelJob {
+    DepGraph G;
+    int desc;
+    int32_t* depth;
+    Ctl* tctl;
+};
+// level of every node (1 + max level of its dependencies) for one job, or two
+// independent jobs in one launch (alternate wavefronts; j1 may be null).
+// grid > 0: wavefront per node, grid < 0: lane per node; |grid| wavefronts
+// per job.  Abort and watchdog state live in ctl.
+hipError_t launch_depth(int32_t n, const LevelJob& j0, const LevelJob* j1, Ctl* ctl, uint64_t spin_limit,
+                        int32_t grid, hipStream_t s);
 // perm = nodes sorted by level (counting sort); hist needs 2 * max_depth ints
 hipError_t launch_level_order(int32_t n, const int32_t* depth, int32_t max_depth, int32_t* hist,
                               int64_t* off, int64_t* scan_tmp, int32_t* perm, hipStream_t s);

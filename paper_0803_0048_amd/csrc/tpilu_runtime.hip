@@ -353,35 +353,56 @@ struct TmpBufs {
     ~TmpBufs() { for (void* p : v) al.put(p); }
 };
 
-// Level of every node of a dependency DAG and the nodes sorted by level (the
-// ticket order of the kernel that walks the DAG).  deps = number of edges:
-// with long dependency lists a wavefront per node in natural order, else a
-// lane per node so that every node is in flight at once.
-tpilu_status compute_levels(tpilu_ctx ctx, tpilu_pattern pat, const DepGraph& G, int desc, int64_t deps,
-                            int32_t* depth, int32_t* perm, int32_t* max_depth) {
+// Levels of one or two dependency DAGs (computed in one launch, so their
+// chains overlap) and their nodes sorted by level (the ticket order of the
+// kernels that walk them).  deps = number of edges: with long dependency
+// lists a wavefront per node in natural order, else a lane per node so that
+// every node is in flight at once.
+struct LevelSpec {
+    DepGraph G;
+    int desc;
+    int64_t deps;
+    int32_t* depth;
+    int32_t* perm;
+    int32_t* max_depth;
+};
+
+tpilu_status compute_levels(tpilu_ctx ctx, tpilu_pattern pat, const LevelSpec* js, int njobs) {
     const int32_t n = (int32_t)pat->n;
     hipStream_t s = ctx->stream;
     TmpBufs T{pat->al, {}};
-    int32_t* dmax = (int32_t*)T.get(64);
-    if (!dmax) return fail(ctx, TPILU_E_NOMEM, "levels");
+    int32_t* dmax = (int32_t*)T.get(64 * 2);
+    Ctl* ctl2 = (Ctl*)T.get(sizeof(Ctl));
+    if (!dmax || !ctl2) return fail(ctx, TPILU_E_NOMEM, "levels");
+    int64_t deps = 0;
+    for (int q = 0; q < njobs; ++q) deps = std::max(deps, js[q].deps);
     const int32_t lane_waves = (int32_t)std::min<int64_t>(((int64_t)n + 63) / 64, 8192);
     const int32_t grid = deps >= kLongRows * (int64_t)n ? kSolveWavesNarrow : -lane_waves;
-    HIPCHK(ctx, launch_fill_i32(depth, n, -1, s));
-    HIPCHK(ctx, launch_fill_i32(dmax, 1, 0, s));
+    LevelJob jb[2];
+    for (int q = 0; q < njobs; ++q) {
+        HIPCHK(ctx, launch_fill_i32(js[q].depth, n, -1, s));
+        jb[q] = LevelJob{js[q].G, js[q].desc, js[q].depth, q == 0 ? pat->ctl : ctl2};
+    }
     HIPCHK(ctx, launch_fill_pending(nullptr, 0, pat->ctl, true, s));
-    HIPCHK(ctx, launch_depth(desc, n, G, depth, pat->ctl, ctx->spin_limit, grid, s));
-    HIPCHK(ctx, launch_max_i32(depth, n, dmax, s));
-    int32_t dm = 0;
-    HIPCHK(ctx, hipMemcpyAsync(&dm, dmax, sizeof(dm), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, launch_fill_pending(nullptr, 0, ctl2, false, s));
+    HIPCHK(ctx, launch_depth(n, jb[0], njobs > 1 ? &jb[1] : nullptr, pat->ctl, ctx->spin_limit, grid, s));
+    for (int q = 0; q < njobs; ++q) {
+        HIPCHK(ctx, launch_fill_i32(dmax + 16 * q, 1, 0, s));
+        HIPCHK(ctx, launch_max_i32(js[q].depth, n, dmax + 16 * q, s));
+    }
+    int32_t dm[32] = {0};
+    HIPCHK(ctx, hipMemcpyAsync(dm, dmax, sizeof(int32_t) * 32, hipMemcpyDeviceToHost, s));
     tpilu_status cs = read_ctl(ctx, pat, nullptr, false);
     if (cs != TPILU_OK) return cs;
-    *max_depth = dm;
-    dm = std::max(dm, 1);
-    int32_t* hist = (int32_t*)T.get(sizeof(int32_t) * 2 * (size_t)dm);
-    int64_t* off = (int64_t*)T.get(sizeof(int64_t) * ((size_t)dm + 1));
-    int64_t* stmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(dm));
-    if (!hist || !off || !stmp) return fail(ctx, TPILU_E_NOMEM, "level order");
-    HIPCHK(ctx, launch_level_order(n, depth, dm, hist, off, stmp, perm, s));
+    for (int q = 0; q < njobs; ++q) {
+        const int32_t d = std::max(dm[16 * q], 1);
+        *js[q].max_depth = dm[16 * q];
+        int32_t* hist = (int32_t*)T.get(sizeof(int32_t) * 2 * (size_t)d);
+        int64_t* off = (int64_t*)T.get(sizeof(int64_t) * ((size_t)d + 1));
+        int64_t* stmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(d));
+        if (!hist || !off || !stmp) return fail(ctx, TPILU_E_NOMEM, "level order");
+        HIPCHK(ctx, launch_level_order(n, js[q].depth, d, hist, off, stmp, js[q].perm, s));
+    }
     HIPCHK(ctx, hipStreamSynchronize(s));
     return TPILU_OK;
 }
@@ -417,11 +438,12 @@ tpilu_status build_transposes(tpilu_ctx ctx, tpilu_pattern pat) {
     pat->permUT = (int32_t*)pat->take(sizeof(int32_t) * (size_t)n);
     pat->permLT = (int32_t*)pat->take(sizeof(int32_t) * (size_t)n);
     if (!depth || !pat->permUT || !pat->permLT) return fail(ctx, TPILU_E_NOMEM, "transpose levels");
-    int32_t dm = 0;
-    tpilu_status st = compute_levels(ctx, pat, DepGraph{pat->tpU, pat->trU, nullptr, 2}, 0, nu, depth,
-                                     pat->permUT, &dm);
-    if (st) return st;
-    st = compute_levels(ctx, pat, DepGraph{pat->tpL, pat->trL, nullptr, 2}, 1, nl, depth, pat->permLT, &dm);
+    int32_t* depth2 = (int32_t*)pat->take(sizeof(int32_t) * (size_t)n);
+    if (!depth2) return fail(ctx, TPILU_E_NOMEM, "transpose levels");
+    int32_t dm0 = 0, dm1 = 0;
+    const LevelSpec js[2] = {{DepGraph{pat->tpU, pat->trU, nullptr, 2}, 0, nu, depth, pat->permUT, &dm0},
+                             {DepGraph{pat->tpL, pat->trL, nullptr, 2}, 1, nl, depth2, pat->permLT, &dm1}};
+    tpilu_status st = compute_levels(ctx, pat, js, 2);
     if (st) return st;
     pat->have_t = true;
     return TPILU_OK;
@@ -716,13 +738,10 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
     if (!P->depthL || !P->depthU || !P->permL || !P->permU) return bail(fail(ctx, TPILU_E_NOMEM, "levels"));
     {
         const int64_t nl = (int64_t)P->st.nnz_l, nu = nnzf - nl - n;
-        trace("symbolic: forward levels");
-        tpilu_status ls = compute_levels(ctx, P, DepGraph{P->rpF, P->ciF, P->diagF, 0}, 0, nl, P->depthL,
-                                         P->permL, &P->depth_l);
-        if (ls != TPILU_OK) return bail(ls);
-        trace("symbolic: backward levels");
-        ls = compute_levels(ctx, P, DepGraph{P->rpF, P->ciF, P->diagF, 1}, 1, nu, P->depthU, P->permU,
-                            &P->depth_u);
+        trace("symbolic: forward and backward levels");
+        const LevelSpec js[2] = {{DepGraph{P->rpF, P->ciF, P->diagF, 0}, 0, nl, P->depthL, P->permL, &P->depth_l},
+                                 {DepGraph{P->rpF, P->ciF, P->diagF, 1}, 1, nu, P->depthU, P->permU, &P->depth_u}};
+        tpilu_status ls = compute_levels(ctx, P, js, 2);
         if (ls != TPILU_OK) return bail(ls);
     }
     tpilu_status st = read_ctl(ctx, P, nullptr, true);
