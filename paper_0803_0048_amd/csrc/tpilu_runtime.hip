@@ -32,8 +32,14 @@ struct tpilu_ctx_s {
     bool timing = false;
     unsigned long long* trace = nullptr;  // per-row timeline buffer (device, 2n), or null
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
+    // second stream (default priority) for work that overlaps the main one
+    hipStream_t aux = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     std::string err;
     ~tpilu_ctx_s() {
+        if (aux) (void)hipStreamDestroy(aux);
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (join_ev) (void)hipEventDestroy(join_ev);
         for (auto& v : ev)
             for (auto& p : v) {
                 (void)hipEventDestroy(p.first);
@@ -367,13 +373,17 @@ struct LevelSpec {
     int32_t* max_depth;
 };
 
-tpilu_status compute_levels(tpilu_ctx ctx, tpilu_pattern pat, const LevelSpec* js, int njobs) {
+// Enqueue the level computation on stream s without waiting for it: the
+// level-order sort is sized for the largest possible depth (n), so no host
+// read-back is needed; the maxima land in dmax (16 ints apart).  Temporaries
+// come from T and must outlive the work.
+tpilu_status enqueue_levels(tpilu_ctx ctx, tpilu_pattern pat, const LevelSpec* js, int njobs, hipStream_t s,
+                            TmpBufs& T, int32_t** dmax_out) {
     const int32_t n = (int32_t)pat->n;
-    hipStream_t s = ctx->stream;
-    TmpBufs T{pat->al, {}};
-    int32_t* dmax = (int32_t*)T.get(64 * 2);
+    int32_t* dmax = (int32_t*)T.get(sizeof(int32_t) * 32);
     Ctl* ctl2 = (Ctl*)T.get(sizeof(Ctl));
     if (!dmax || !ctl2) return fail(ctx, TPILU_E_NOMEM, "levels");
+    *dmax_out = dmax;
     int64_t deps = 0;
     for (int q = 0; q < njobs; ++q) deps = std::max(deps, js[q].deps);
     const int32_t lane_waves = (int32_t)std::min<int64_t>(((int64_t)n + 63) / 64, 8192);
@@ -386,25 +396,68 @@ tpilu_status compute_levels(tpilu_ctx ctx, tpilu_pattern pat, const LevelSpec* j
     HIPCHK(ctx, launch_fill_pending(nullptr, 0, pat->ctl, true, s));
     HIPCHK(ctx, launch_fill_pending(nullptr, 0, ctl2, false, s));
     HIPCHK(ctx, launch_depth(n, jb[0], njobs > 1 ? &jb[1] : nullptr, pat->ctl, ctx->spin_limit, grid, s));
+    HIPCHK(ctx, launch_fill_i32(dmax, 32, 0, s));
     for (int q = 0; q < njobs; ++q) {
-        HIPCHK(ctx, launch_fill_i32(dmax + 16 * q, 1, 0, s));
         HIPCHK(ctx, launch_max_i32(js[q].depth, n, dmax + 16 * q, s));
-    }
-    int32_t dm[32] = {0};
-    HIPCHK(ctx, hipMemcpyAsync(dm, dmax, sizeof(int32_t) * 32, hipMemcpyDeviceToHost, s));
-    tpilu_status cs = read_ctl(ctx, pat, nullptr, false);
-    if (cs != TPILU_OK) return cs;
-    for (int q = 0; q < njobs; ++q) {
-        const int32_t d = std::max(dm[16 * q], 1);
-        *js[q].max_depth = dm[16 * q];
-        int32_t* hist = (int32_t*)T.get(sizeof(int32_t) * 2 * (size_t)d);
-        int64_t* off = (int64_t*)T.get(sizeof(int64_t) * ((size_t)d + 1));
-        int64_t* stmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(d));
+        int32_t* hist = (int32_t*)T.get(sizeof(int32_t) * 2 * (size_t)std::max(n, 1));
+        int64_t* off = (int64_t*)T.get(sizeof(int64_t) * ((size_t)n + 1));
+        int64_t* stmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(std::max(n, 1)));
         if (!hist || !off || !stmp) return fail(ctx, TPILU_E_NOMEM, "level order");
-        HIPCHK(ctx, launch_level_order(n, js[q].depth, d, hist, off, stmp, js[q].perm, s));
+        HIPCHK(ctx, launch_level_order(n, js[q].depth, std::max(n, 1), hist, off, stmp, js[q].perm, s));
     }
-    HIPCHK(ctx, hipStreamSynchronize(s));
     return TPILU_OK;
+}
+
+// After the level work has completed: the maxima to the host, and the
+// watchdog / abort status of the level kernels.
+tpilu_status finish_levels(tpilu_ctx ctx, tpilu_pattern pat, const LevelSpec* js, int njobs, const int32_t* dmax) {
+    int32_t dm[32] = {0};
+    HIPCHK(ctx, hipMemcpy(dm, dmax, sizeof(dm), hipMemcpyDeviceToHost));
+    for (int q = 0; q < njobs; ++q) *js[q].max_depth = dm[16 * q];
+    return read_ctl(ctx, pat, nullptr, false);
+}
+
+tpilu_status compute_levels(tpilu_ctx ctx, tpilu_pattern pat, const LevelSpec* js, int njobs) {
+    TmpBufs T{pat->al, {}};
+    int32_t* dmax = nullptr;
+    tpilu_status st = enqueue_levels(ctx, pat, js, njobs, ctx->stream, T, &dmax);
+    if (st != TPILU_OK) return st;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return finish_levels(ctx, pat, js, njobs, dmax);
+}
+
+// waits for the second stream when it goes out of scope (before the
+// temporaries declared ahead of it are released)
+struct AuxJoin {
+    hipStream_t a = nullptr;
+    ~AuxJoin() {
+        if (a) (void)hipStreamSynchronize(a);
+    }
+};
+
+hipError_t ctx_aux(tpilu_ctx ctx) {
+    if (!ctx->aux) {
+        hipError_t e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            ctx->aux = nullptr;
+            return e;
+        }
+    }
+    if (!ctx->fork_ev) {
+        hipError_t e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            ctx->fork_ev = nullptr;
+            return e;
+        }
+    }
+    if (!ctx->join_ev) {
+        hipError_t e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            ctx->join_ev = nullptr;
+            return e;
+        }
+    }
+    return hipSuccess;
 }
 
 tpilu_status build_transposes(tpilu_ctx ctx, tpilu_pattern pat) {
@@ -589,7 +642,9 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
     P->n = n;
     P->nnz_a = nnz;
     P->k = k;
+    bool forked = false;  // work on the second stream may still use P's arrays
     auto bail = [&](tpilu_status st) {
+        if (forked) (void)hipStreamSynchronize(ctx->aux);
         delete P;
         return st;
     };
@@ -697,6 +752,29 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
     HIPCHK(ctx, hipMemcpyAsync(&vs, vstat, sizeof(vs), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (vs) return bail(fail(ctx, TPILU_E_INVAL, "internal: an entry of A is missing from F"));
+    // ---- dependency levels and the level-ordered schedules, on the second
+    // stream: a latency-bound chain on a few wavefronts, overlapped with the
+    // throughput-bound update schedules below
+    P->depthL = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
+    P->depthU = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
+    P->permL = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
+    P->permU = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
+    if (!P->depthL || !P->depthU || !P->permL || !P->permU) return bail(fail(ctx, TPILU_E_NOMEM, "levels"));
+    const int64_t nl_ = (int64_t)P->st.nnz_l, nu_ = nnzf - nl_ - n;
+    const LevelSpec ljobs[2] = {{DepGraph{P->rpF, P->ciF, P->diagF, 0}, 0, nl_, P->depthL, P->permL, &P->depth_l},
+                                {DepGraph{P->rpF, P->ciF, P->diagF, 1}, 1, nu_, P->depthU, P->permU, &P->depth_u}};
+    AuxJoin aux_join;
+    int32_t* ldmax = nullptr;
+    {
+        trace("symbolic: forward and backward levels (second stream)");
+        HIPCHK(ctx, ctx_aux(ctx));
+        HIPCHK(ctx, hipEventRecord(ctx->fork_ev, s));
+        HIPCHK(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
+        aux_join.a = ctx->aux;
+        forked = true;
+        tpilu_status ls = enqueue_levels(ctx, P, ljobs, 2, ctx->aux, T, &ldmax);
+        if (ls != TPILU_OK) return bail(ls);
+    }
     // ---- update schedule for Phase II
     trace("symbolic: schedule count", P->st.max_row, P->st.max_lrow);
     int32_t* scount = (int32_t*)T.get(sizeof(int32_t) * (size_t)nnzf);
@@ -730,18 +808,12 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
                                   P->st.max_row, P->st.max_lrow, s));
         P->flow = true;
     }
-    // ---- dependency levels and the level-ordered schedules
-    P->depthL = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
-    P->depthU = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
-    P->permL = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
-    P->permU = (int32_t*)P->take(sizeof(int32_t) * (size_t)n);
-    if (!P->depthL || !P->depthU || !P->permL || !P->permU) return bail(fail(ctx, TPILU_E_NOMEM, "levels"));
+    // ---- join the level work
+    HIPCHK(ctx, hipEventRecord(ctx->join_ev, ctx->aux));
+    HIPCHK(ctx, hipStreamWaitEvent(s, ctx->join_ev, 0));
+    HIPCHK(ctx, hipStreamSynchronize(s));
     {
-        const int64_t nl = (int64_t)P->st.nnz_l, nu = nnzf - nl - n;
-        trace("symbolic: forward and backward levels");
-        const LevelSpec js[2] = {{DepGraph{P->rpF, P->ciF, P->diagF, 0}, 0, nl, P->depthL, P->permL, &P->depth_l},
-                                 {DepGraph{P->rpF, P->ciF, P->diagF, 1}, 1, nu, P->depthU, P->permU, &P->depth_u}};
-        tpilu_status ls = compute_levels(ctx, P, js, 2);
+        tpilu_status ls = finish_levels(ctx, P, ljobs, 2, ldmax);
         if (ls != TPILU_OK) return bail(ls);
     }
     tpilu_status st = read_ctl(ctx, P, nullptr, true);
