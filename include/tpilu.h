@@ -8,7 +8,7 @@
  *   tpilu_symbolic   Phase I, Sec. 2.2, Algorithm 1 with the levels of Def. 2.3:
  *                    the pattern of the filled matrix F = L~ + U~ - I, every
  *                    entry of level <= k.
- *   tpilu_numeric    Phase II, Eq. 2 and Eqs. 5a/5b: row-wise IKJ elimination
+ *   tpilu_numeric    Phase II, Eq. 2 and Eqs. 6a/6b: row-wise IKJ elimination
  *                    of A restricted to that pattern.
  *   tpilu_apply      y = U~^-1 L~^-1 b, the triangular solves of Eq. 1
  *                    (forward substitution Eq. 3b, then backward substitution).
@@ -191,7 +191,7 @@ TPILU_API tpilu_status tpilu_pattern_export(tpilu_ctx ctx, tpilu_pattern pat, in
 TPILU_API void tpilu_pattern_destroy(tpilu_pattern pat);
 
 /* ---------------------------------------------------------------------------
- * Phase II -- numeric factorization (Eq. 2, Eqs. 5a/5b).
+ * Phase II -- numeric factorization (Eq. 2, Eqs. 6a/6b).
  *
  * a_val[nnz_a * batch]: values of A in the pattern's A order.  f_val[nnz_f *
  * batch] receives F: strictly lower slots hold L~ (unit diagonal implicit),
@@ -268,7 +268,7 @@ TPILU_API tpilu_status tpilu_apply_adjoint(tpilu_ctx ctx, tpilu_pattern pat, con
                                            int32_t batch, const double *x, const double *y,
                                            const double *ybar, double *bbar, double *fbar);
 
-/* Reverse sweep of the elimination (adjoint of Eqs. 5a/5b).  fbar[nnz_f *
+/* Reverse sweep of the elimination (adjoint of Eqs. 6a/6b).  fbar[nnz_f *
  * batch] holds dLoss/dF on entry and is overwritten; abar[nnz_a * batch]
  * receives dLoss/d(values of A).  Rows are undone in descending order; for
  * pivot h of row j with l = f_jh:

@@ -215,7 +215,7 @@ static int find_diag(int64_t n, const int64_t *rpF, const int32_t *ciF, int64_t 
 
 /* ------------------------------------------------------------------------ */
 /* Phase II: numeric factorization, row-wise IKJ (Eq. 2 read as running      */
-/* updates, Eqs. 5a/5b).  F starts as A scattered into the pattern, fill     */
+/* updates, Eqs. 6a/6b).  F starts as A scattered into the pattern, fill     */
 /* entries +0.0.  Row j in ascending order; for each pivot h < j of row j in */
 /* ascending order:  f_jh <- f_jh / f_hh, then for every t > h stored in     */
 /* both row h and row j:  f_jt <- f_jt - f_jh * f_ht.                        */
@@ -520,7 +520,7 @@ int orc_apply_adjoint(int64_t n, const int64_t *rpF, const int32_t *ciF, const d
 }
 
 /* ------------------------------------------------------------------------ */
-/* Adjoint of the numeric factorization (reverse sweep of Eqs. 5a/5b).       */
+/* Adjoint of the numeric factorization (reverse sweep of Eqs. 6a/6b).       */
 /* Fbar holds dL/dF on entry (final factor values); rows are undone in       */
 /* descending order, pivots of a row in descending order.  For pivot h of    */
 /* row j with l = f_jh:                                                      */

@@ -4,7 +4,7 @@ the sequential algorithm (Dong & Cooperman, TPILU(k)).
 Entry points (GPU only; they raise if the HIP library is missing):
 
     pat = symbolic(rowptr, col, k)          # Phase I, Algorithm 1
-    f   = numeric(pat, a_val)               # Phase II, Eqs. 5a/5b
+    f   = numeric(pat, a_val)               # Phase II, Eqs. 6a/6b
     y   = apply(pat, f, b)                  # y = U~^-1 L~^-1 b, Eq. 1
     x, info = gmres(pat, a_val, f, b)       # right-preconditioned GMRES(m)
     ILUApply.apply(a_val, b, pat)           # autograd: d/d a_val, d/d b

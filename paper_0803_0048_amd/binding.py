@@ -262,7 +262,7 @@ def _batch_of(t: torch.Tensor, lead: int, name: str) -> int:
 
 
 def numeric(pat: Pattern, a_val: torch.Tensor, out: torch.Tensor | None = None, check: bool = True):
-    """Phase II (Eqs. 5a/5b): F values, shape [nnz_f] or [nnz_f, batch]."""
+    """Phase II (Eqs. 6a/6b): F values, shape [nnz_f] or [nnz_f, batch]."""
     _need(a_val, torch.float64, "a_val", pat.device)
     B = _batch_of(a_val, pat.nnz_a, "a_val")
     shape = (pat.nnz_f,) if a_val.dim() == 1 else (pat.nnz_f, B)

@@ -1,5 +1,5 @@
 // Reverse mode on gfx950: adjoint of b -> y = U~^-1 L~^-1 b and of the
-// elimination that produced F (reverse sweep of Eqs. 5a/5b).
+// elimination that produced F (reverse sweep of Eqs. 6a/6b).
 //
 // The sequential reverse sweep undoes rows in descending order; the pivot h
 // of row j then scatters fbar_ht -= fbar_jt * l into row h.  A scatter from

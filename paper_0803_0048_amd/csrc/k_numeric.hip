@@ -1,5 +1,5 @@
 // Phase II on gfx950: row-wise IKJ elimination (Eq. 2 read as running
-// updates, Eqs. 5a/5b), bit-identical to the sequential order.
+// updates, Eqs. 6a/6b), bit-identical to the sequential order.
 //
 // The only order that fixes the bits is, per entry f_jt, its updates in
 // ascending pivot h.  A persistent grid hands rows out in ascending order

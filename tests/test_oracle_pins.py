@@ -144,7 +144,7 @@ def test_symbolic_explicit_zero_is_structural():
 
 
 # --------------------------------------------------------------------------
-# Numeric factorization (Eq. 2 / Eqs. 5a-5b)
+# Numeric factorization (Eq. 2 / Eqs. 6a-6b)
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("seed", range(6))
