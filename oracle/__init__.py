@@ -63,6 +63,10 @@ def lib():
         L.orc_nrm2.restype = dbl
         L.orc_gmres.argtypes = [i64, P, P, P, P, P, P, P, P, i32, i32, dbl,
                                 C.POINTER(i32), C.POINTER(dbl), P]
+        L.orc_gmres_inverse.argtypes = [i64, P, P, P, P, P, P, P, P, i32, i32, dbl,
+                                        C.POINTER(i32), C.POINTER(dbl), P]
+        L.orc_inverse.argtypes = [i64, P, P, P, P]
+        L.orc_apply_inverse.argtypes = [i64, P, P, P, P, P, P]
         L.orc_apply_adjoint.argtypes = [i64, P, P, P, P, P, P, P, P]
         L.orc_numeric_adjoint.argtypes = [i64, P, P, P, P, P, P, P]
         _lib = L
@@ -145,8 +149,33 @@ def dot(x, y) -> float:
     return lib().orc_dot(xx.shape[0], _p(xx), _p(yy))
 
 
-def gmres(n, rowptr, col, val, rowptrF, colF, valF, b, x0=None, restart=30, maxit=None, rtol=1e-8):
-    """Right-preconditioned restarted GMRES.  Returns dict(x, iters, relres, status, hist)."""
+def inverse(n, rowptrF, colF, valF):
+    """Level-based incomplete inverses of L~ and U~ on F's pattern (Sec. 3.5).
+    Returns G: inverse of L~ in the strict lower slots, of U~ in the upper ones."""
+    rpF, ciF, vF = _c(rowptrF, np.int64), _c(colF, np.int32), _c(valF, np.float64)
+    vG = np.empty(ciF.shape[0], dtype=np.float64)
+    st = lib().orc_inverse(n, _p(rpF), _p(ciF), _p(vF), _p(vG))
+    if st:
+        raise OracleError(st, "inverse")
+    return vG
+
+
+def apply_inverse(n, rowptrF, colF, valG, p):
+    """y = U~~^-1 L~~^-1 p by two products.  Returns (x = L~~^-1 p, y)."""
+    rpF, ciF, vG = _c(rowptrF, np.int64), _c(colF, np.int32), _c(valG, np.float64)
+    pp = _c(p, np.float64)
+    x = np.empty(n, dtype=np.float64)
+    y = np.empty(n, dtype=np.float64)
+    st = lib().orc_apply_inverse(n, _p(rpF), _p(ciF), _p(vG), _p(pp), _p(x), _p(y))
+    if st:
+        raise OracleError(st, "apply_inverse")
+    return x, y
+
+
+def gmres(n, rowptr, col, val, rowptrF, colF, valF, b, x0=None, restart=30, maxit=None, rtol=1e-8,
+          inverse=False):
+    """Right-preconditioned restarted GMRES.  Returns dict(x, iters, relres, status, hist).
+    inverse=True: valF holds the incomplete inverses G and M^-1 is applied by products."""
     rp, ci, v = _c(rowptr, np.int64), _c(col, np.int32), _c(val, np.float64)
     rpF, ciF, vF = _c(rowptrF, np.int64), _c(colF, np.int32), _c(valF, np.float64)
     bb = _c(b, np.float64)
@@ -156,8 +185,9 @@ def gmres(n, rowptr, col, val, rowptrF, colF, valF, b, x0=None, restart=30, maxi
     hist = np.zeros(max(maxit, 1), dtype=np.float64)
     it = C.c_int32(0)
     rr = C.c_double(0.0)
-    st = lib().orc_gmres(n, _p(rp), _p(ci), _p(v), _p(rpF), _p(ciF), _p(vF), _p(bb), _p(x),
-                         int(restart), int(maxit), float(rtol), C.byref(it), C.byref(rr), _p(hist))
+    fn = lib().orc_gmres_inverse if inverse else lib().orc_gmres
+    st = fn(n, _p(rp), _p(ci), _p(v), _p(rpF), _p(ciF), _p(vF), _p(bb), _p(x),
+            int(restart), int(maxit), float(rtol), C.byref(it), C.byref(rr), _p(hist))
     if st not in (OK, ENOTCONV):
         raise OracleError(st, "gmres")
     return {"x": x, "iters": int(it.value), "relres": float(rr.value), "status": st,

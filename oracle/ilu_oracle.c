@@ -338,10 +338,22 @@ double orc_nrm2(int64_t n, const double *x) { return sqrt(orc_dot(n, x, x)); }
 /* iterations over all cycles.  x holds x0 on entry.  hist (nullable, maxit  */
 /* entries) receives |g_{j+1}| after every inner iteration.                  */
 /* ------------------------------------------------------------------------ */
-int orc_gmres(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
-              const int64_t *rpF, const int32_t *ciF, const double *vF,
-              const double *b, double *x, int32_t m, int32_t maxit, double rtol,
-              int32_t *iters_out, double *relres_out, double *hist)
+int orc_apply_inverse(int64_t n, const int64_t *rpF, const int32_t *ciF, const double *vG,
+                      const double *p, double *x, double *y);
+
+/* z = M^-1 v: the two substitutions (vM = F), or the two products with the
+   incomplete inverses (vM = G) */
+static void apply_m(int64_t n, const int64_t *rpF, const int32_t *ciF, const double *vM, int inverse,
+                    const double *v, double *t, double *z)
+{
+    if (inverse) orc_apply_inverse(n, rpF, ciF, vM, v, t, z);
+    else orc_apply(n, rpF, ciF, vM, v, t, z);
+}
+
+static int gmres_impl(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
+                      const int64_t *rpF, const int32_t *ciF, const double *vF, int inverse,
+                      const double *b, double *x, int32_t m, int32_t maxit, double rtol,
+                      int32_t *iters_out, double *relres_out, double *hist)
 {
     *iters_out = 0;
     *relres_out = 0.0;
@@ -380,7 +392,7 @@ int orc_gmres(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *v
         int32_t jj = 0;
         for (int32_t j = 0; j < m; ++j) {
             double *vj = V + (size_t)j * N;
-            orc_apply(n, rpF, ciF, vF, vj, t, z);
+            apply_m(n, rpF, ciF, vF, inverse, vj, t, z);
             orc_spmv(n, rpA, ciA, vA, z, w);
             for (int32_t i = 0; i <= j; ++i) {
                 double *vi = V + (size_t)i * N;
@@ -424,7 +436,7 @@ int orc_gmres(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *v
             for (int32_t i = 0; i < jj; ++i) s = s + yv[i] * V[(size_t)i * N + (size_t)e];
             w[e] = s;
         }
-        orc_apply(n, rpF, ciF, vF, w, t, z);
+        apply_m(n, rpF, ciF, vF, inverse, w, t, z);
         for (int64_t e = 0; e < n; ++e) x[e] = x[e] + z[e];
     }
     orc_spmv(n, rpA, ciA, vA, x, w);
@@ -436,6 +448,23 @@ done:
 #undef HH
     free(V); free(w); free(z); free(t); free(H); free(cs); free(sn); free(g); free(yv);
     return st;
+}
+
+int orc_gmres(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
+              const int64_t *rpF, const int32_t *ciF, const double *vF,
+              const double *b, double *x, int32_t m, int32_t maxit, double rtol,
+              int32_t *iters_out, double *relres_out, double *hist)
+{
+    return gmres_impl(n, rpA, ciA, vA, rpF, ciF, vF, 0, b, x, m, maxit, rtol, iters_out, relres_out, hist);
+}
+
+/* the same GMRES(m) with M^-1 applied through the incomplete inverses vG */
+int orc_gmres_inverse(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
+                      const int64_t *rpF, const int32_t *ciF, const double *vG,
+                      const double *b, double *x, int32_t m, int32_t maxit, double rtol,
+                      int32_t *iters_out, double *relres_out, double *hist)
+{
+    return gmres_impl(n, rpA, ciA, vA, rpF, ciF, vG, 1, b, x, m, maxit, rtol, iters_out, relres_out, hist);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -571,4 +600,111 @@ int orc_numeric_adjoint(int64_t n, const int64_t *rpA, const int32_t *ciA, const
     free(slot_of);
     free(diag);
     return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level-based incomplete inverses (Sec. 3.5).                               */
+/*                                                                           */
+/* L~^-1 has a unit diagonal and the entries -beta_it below it (Eq. 3a),     */
+/* where beta_it = f_it - sum over t < h < i of f_ih beta_ht (Eq. 5).  Rows  */
+/* in ascending order, each after the ILU rows it needs; row i starts from   */
+/* beta_it = f_it and, for its pivots h in ascending order and every column  */
+/* t < h stored in both row h and row i, takes beta_it <- beta_it - f_ih     */
+/* beta_ht (Eq. 6c); the stored inverse entries are -beta_it (Eq. 6d).       */
+/* Level-based: only the pattern of L~ is kept, contributions to positions   */
+/* outside it are dropped.                                                   */
+/*                                                                           */
+/* U~^-1 (the paper omits the details and names only the order: rows from    */
+/* the last to the first, right to left within a row).  Row i of the inverse */
+/* is (e_i - sum over pivots j > i of row i of u_ij (row j of the inverse))  */
+/* / u_ii: the working row starts as e_i on row i's upper pattern, the       */
+/* pivots j are taken from right to left, each subtracting u_ij g_jt at      */
+/* every column t stored in both row j's inverse and row i, and finally      */
+/* every entry is divided by u_ii.  Kept: the pattern of U~.                 */
+/*                                                                           */
+/* vG receives both, in F's slots: inverse of L~ in the strict lower slots,  */
+/* inverse of U~ in the upper slots (diagonal included).                     */
+/* ------------------------------------------------------------------------ */
+int orc_inverse(int64_t n, const int64_t *rpF, const int32_t *ciF, const double *vF, double *vG)
+{
+    const int64_t nnz = n > 0 ? rpF[n] : 0;
+    int64_t *slot_of = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *diag = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    double *beta = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    if (!slot_of || !diag || !beta) { free(slot_of); free(diag); free(beta); return ORC_ENOMEM; }
+    int st = find_diag(n, rpF, ciF, diag);
+    if (st) { free(slot_of); free(diag); free(beta); return st; }
+    for (int64_t t = 0; t < n; ++t) slot_of[t] = -1;
+
+    /* L~: rows ascending, beta kept unflipped until every row is done */
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t s = rpF[i]; s < diag[i]; ++s) {
+            slot_of[ciF[s]] = s;
+            beta[s] = vF[s];
+        }
+        for (int64_t s = rpF[i]; s < diag[i]; ++s) {
+            const int64_t h = ciF[s];
+            const double fih = vF[s];
+            for (int64_t q = rpF[h]; q < diag[h]; ++q) {
+                const int64_t p = slot_of[ciF[q]];
+                if (p >= 0) beta[p] = beta[p] - fih * beta[q];
+            }
+        }
+        for (int64_t s = rpF[i]; s < diag[i]; ++s) slot_of[ciF[s]] = -1;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t s = rpF[i]; s < diag[i]; ++s) vG[s] = -beta[s];
+
+    /* U~: rows descending, pivots right to left, then the division */
+    for (int64_t i = n - 1; i >= 0; --i) {
+        for (int64_t s = diag[i]; s < rpF[i + 1]; ++s) {
+            slot_of[ciF[s]] = s;
+            vG[s] = 0.0;
+        }
+        vG[diag[i]] = 1.0;
+        for (int64_t s = rpF[i + 1] - 1; s > diag[i]; --s) {
+            const int64_t j = ciF[s];
+            const double uij = vF[s];
+            for (int64_t q = diag[j]; q < rpF[j + 1]; ++q) {
+                const int64_t p = slot_of[ciF[q]];
+                if (p >= 0) vG[p] = vG[p] - uij * vG[q];
+            }
+        }
+        for (int64_t s = diag[i]; s < rpF[i + 1]; ++s) {
+            vG[s] = vG[s] / vF[diag[i]];
+            slot_of[ciF[s]] = -1;
+        }
+    }
+    free(slot_of);
+    free(diag);
+    free(beta);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Applying the incomplete inverses (Sec. 3.5: the triangular solve stage    */
+/* becomes two matrix-vector products).  x = L~~^-1 p as Eq. 3a writes it:   */
+/* the sum over t < i of (L~~^-1)_it p_t, from +0.0 in ascending t, then     */
+/* + p_i.  y = U~~^-1 x: the sum over t >= i, from +0.0 in ascending t (the  */
+/* SpMV order).                                                              */
+/* ------------------------------------------------------------------------ */
+int orc_apply_inverse(int64_t n, const int64_t *rpF, const int32_t *ciF, const double *vG,
+                      const double *p, double *x, double *y)
+{
+    int64_t *diag = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!diag) return ORC_ENOMEM;
+    int st = find_diag(n, rpF, ciF, diag);
+    if (st) { free(diag); return st; }
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t q = rpF[i]; q < diag[i]; ++q) s = s + vG[q] * p[ciF[q]];
+        x[i] = s + p[i];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t q = diag[i]; q < rpF[i + 1]; ++q) s = s + vG[q] * x[ciF[q]];
+        y[i] = s;
+    }
+    free(diag);
+    return ORC_OK;
 }

@@ -576,3 +576,194 @@ def test_adjoint_against_dense_autograd():
         gb = bt.grad.numpy()
         assert np.abs(ga - abar).max() <= 1e-12 * max(1.0, np.abs(ga).max())
         assert np.abs(gb - bbar).max() <= 1e-12 * max(1.0, np.abs(gb).max())
+
+
+# --------------------------------------------------------------------------
+# Level-based incomplete inverses (Sec. 3.5: Eqs. 3a, 5, 6c, 6d)
+# --------------------------------------------------------------------------
+
+def _lower_upper(n, rpF, ciF, vals):
+    D = sp.csr_matrix((vals, ciF, rpF), shape=(n, n)).toarray()
+    return np.tril(D, -1), np.triu(D)
+
+
+def _dense_problem(n, seed):
+    rng = np.random.default_rng(seed)
+    M = np.ones((n, n), dtype=bool)
+    vals = rng.uniform(-1.0, 1.0, (n, n))
+    vals[np.arange(n), np.arange(n)] = np.abs(vals).sum(axis=1) + 1.0
+    rp, ci, v = P.csr_from_dense_mask(M, vals)
+    rpF, ciF, _ = O.symbolic(n, rp, ci, 0)
+    vF, bad = O.numeric(n, rp, ci, v, rpF, ciF)
+    assert bad == -1
+    return rp, ci, v, rpF, ciF, vF, vals
+
+
+def test_inverse_full_pattern_is_exact_inverse():
+    """With every position kept the incomplete inverses are the inverses of
+    L~ (unit diagonal) and U~, and applying them solves A y = b."""
+    for seed in range(4):
+        n = 30
+        rp, ci, v, rpF, ciF, vF, Ad = _dense_problem(n, 70 + seed)
+        vG = O.inverse(n, rpF, ciF, vF)
+        Lf, Uf = _lower_upper(n, rpF, ciF, vF)
+        GL, GU = _lower_upper(n, rpF, ciF, vG)
+        L = Lf + np.eye(n)
+        assert np.abs(GL + np.eye(n) - np.linalg.inv(L)).max() <= 1e-12 * np.abs(np.linalg.inv(L)).max()
+        assert np.abs(GU - np.linalg.inv(Uf)).max() <= 1e-12 * np.abs(np.linalg.inv(Uf)).max()
+        b = np.random.default_rng(seed).standard_normal(n)
+        _, y = O.apply_inverse(n, rpF, ciF, vG, b)
+        ref = np.linalg.solve(Ad, b)
+        assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_inverse_exact_dyadic():
+    """Full pattern, integer L~, U~ with integer off-diagonals and power-of-two
+    pivots: every intermediate is an exact dyadic rational, so the result
+    equals the exact inverse exactly."""
+    rng = np.random.default_rng(8)
+    for case in range(20):
+        n = int(rng.integers(2, 8))
+        Fi = rng.integers(-2, 3, size=(n, n)).astype(np.float64)
+        Fi[np.arange(n), np.arange(n)] = rng.choice([1.0, -1.0, 2.0, -2.0, 4.0, 0.5], size=n)
+        M = np.ones((n, n), dtype=bool)
+        rp, ci, v = P.csr_from_dense_mask(M, Fi)
+        vG = O.inverse(n, rp, ci, v)
+        Lq = [[Fraction(int(Fi[i, t])) if t < i else Fraction(int(i == t)) for t in range(n)] for i in range(n)]
+        Uq = [[Fraction(Fi[i, t]) if t >= i else Fraction(0) for t in range(n)] for i in range(n)]
+        # exact inverses by substitution on the columns of the identity
+        Li = [[Fraction(0)] * n for _ in range(n)]
+        Ui = [[Fraction(0)] * n for _ in range(n)]
+        for c in range(n):
+            for i in range(n):
+                Li[i][c] = Fraction(int(i == c)) - sum(Lq[i][h] * Li[h][c] for h in range(i))
+            for i in reversed(range(n)):
+                Ui[i][c] = (Fraction(int(i == c)) - sum(Uq[i][j] * Ui[j][c] for j in range(i + 1, n))) / Uq[i][i]
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        want = np.array([float(Li[i][t]) if t < i else float(Ui[i][t]) for i, t in zip(rows, ci)])
+        assert all(Fraction(w) == (Li[i][t] if t < i else Ui[i][t]) for w, i, t in zip(want, rows, ci))
+        # values (the flip of Eq. 6d makes -0.0 from +0.0; exact rationals have no signed zero)
+        assert np.array_equal(vG, want), (case, n)
+
+
+def test_inverse_order_of_updates():
+    """L~: pivots in ascending order (Eq. 6c); U~: pivots from right to left.
+    Entries whose terms round differently in another order expose it."""
+    n = 4
+    M = np.ones((n, n), dtype=bool)
+    # L~ rows: f10 = 2^53; f20 = 0, f21 = 1; f30 = f31 = f32 = 1; U~ = I
+    F = np.eye(n)
+    F[1, 0] = 2.0**53
+    F[2, 1] = 1.0
+    F[3, :3] = 1.0
+    rp, ci, v = P.csr_from_dense_mask(M, F)
+    vG = O.inverse(n, rp, ci, v)
+    G = sp.csr_matrix((vG, ci, rp), shape=(n, n)).toarray()
+    # beta_20 = -2^53; beta_30 = (1 - 1*2^53) - 1*(-2^53) = 1 ascending (descending: 0)
+    assert G[2, 0] == 2.0**53 and G[3, 0] == -1.0
+    # U~ row 0 = (1, 1, 1, 1); row 1: u12 = 1; row 2: u23 = -2^53; unit pivots, L~ = I
+    F2 = np.eye(n)
+    F2[0, 1:] = 1.0
+    F2[1, 2] = 1.0
+    F2[2, 3] = -(2.0**53)
+    rp2, ci2, v2 = P.csr_from_dense_mask(M, F2)
+    G2 = sp.csr_matrix((O.inverse(n, rp2, ci2, v2), ci2, rp2), shape=(n, n)).toarray()
+    # g23 = 2^53, g13 = -2^53, g33 = 1; row 0, column 3, pivots j = 3, 2, 1:
+    # ((0 - 1) - 2^53) - (-2^53) = 0 (the middle step rounds); left to right gives -1
+    assert G2[2, 3] == 2.0**53 and G2[1, 3] == -(2.0**53) and G2[0, 3] == 0.0
+
+
+def test_inverse_incomplete_defining_property():
+    """On every kept position, (L~ X)_it = delta_it with X = I + (inverse of
+    L~), and (U~ G)_it = delta_it: the level-based inverse is exact on its
+    own pattern (Eq. 5 restricted to it)."""
+    u = 2.0**-53
+    cases = [(I.config1()["A"], k) for k in (0, 1, 2)]
+    cases += [(I.random_pattern(120, 0.04, seed=90 + s, diag_dominant=True), s % 3) for s in range(3)]
+    for A, k in cases:
+        rpF, ciF, _, vF, bad = O.ilu(A, k)
+        assert bad == -1
+        n = A.n
+        vG = O.inverse(n, rpF, ciF, vF)
+        Lf, Uf = _lower_upper(n, rpF, ciF, vF)
+        GL, GU = _lower_upper(n, rpF, ciF, vG)
+        L, X = Lf + np.eye(n), GL + np.eye(n)
+        rows = np.repeat(np.arange(n), np.diff(rpF))
+        low = ciF < rows
+        R = L @ X
+        B = np.abs(L) @ np.abs(X)
+        r, c = rows[low], ciF[low]
+        assert np.all(np.abs(R[r, c]) <= 8 * n * u * B[r, c] + 1e-300), (k,)
+        R2 = Uf @ GU - np.eye(n)
+        B2 = np.abs(Uf) @ np.abs(GU)
+        r, c = rows[~low], ciF[~low]
+        assert np.all(np.abs(R2[r, c]) <= 8 * n * u * B2[r, c] + 1e-300), (k,)
+
+
+def test_inverse_tridiagonal_closed_form():
+    """Tridiagonal A, k = 0: bidiagonal factors; the kept inverse entries are
+    -l_i (bit for bit), 1/u_i (bit for bit) and -c_i / (u_i u_{i+1})."""
+    rng = np.random.default_rng(4)
+    n = 100
+    M = np.zeros((n, n), dtype=bool)
+    for d in (-1, 0, 1):
+        M[np.arange(max(0, -d), n - max(0, d)), np.arange(max(0, -d), n - max(0, d)) + d] = True
+    vals = rng.uniform(-1, 1, (n, n))
+    vals[np.arange(n), np.arange(n)] = 3.0 + rng.random(n)
+    rp, ci, v = P.csr_from_dense_mask(M, vals)
+    rpF, ciF, _ = O.symbolic(n, rp, ci, 0)
+    vF, _ = O.numeric(n, rp, ci, v, rpF, ciF)
+    vG = O.inverse(n, rpF, ciF, vF)
+    F = sp.csr_matrix((vF, ciF, rpF), shape=(n, n)).toarray()
+    G = sp.csr_matrix((vG, ciF, rpF), shape=(n, n)).toarray()
+    i = np.arange(1, n)
+    assert np.array_equal(P.bits(G[i, i - 1]), P.bits(-F[i, i - 1]))
+    d = np.arange(n)
+    assert np.array_equal(P.bits(G[d, d]), P.bits(1.0 / F[d, d]))
+    j = np.arange(n - 1)
+    want = -F[j, j + 1] / (F[j, j] * F[j + 1, j + 1])
+    assert np.all(np.abs(G[j, j + 1] - want) <= 4 * 2.0**-53 * np.abs(want))
+
+
+def test_apply_inverse_sum_order():
+    """x = L~~^-1 p as Eq. 3a writes it: the products summed from +0.0 in
+    ascending column order, then + p_i; y = U~~^-1 x summed in ascending order."""
+    n = 3
+    M = np.ones((n, n), dtype=bool)
+    Gv = np.zeros((n, n))
+    Gv[2, 0] = Gv[2, 1] = 1.0
+    Gv[np.arange(n), np.arange(n)] = 1.0
+    rp, ci, v = P.csr_from_dense_mask(M, Gv)
+    x, _ = O.apply_inverse(n, rp, ci, v, np.array([2.0**53, -(2.0**53), 1.0]))
+    # ((0 + 2^53) - 2^53) + 1 = 1; with p_2 first: (1 + 2^53) - 2^53 = 0
+    assert x[2] == 1.0
+    Gu = np.zeros((n, n))
+    Gu[0, :] = 1.0
+    Gu[1, 1] = Gu[2, 2] = 1.0
+    rp2, ci2, v2 = P.csr_from_dense_mask(M, Gu)
+    # p with L part zero: x = p
+    _, y = O.apply_inverse(n, rp2, ci2, v2, np.array([1.0, 2.0**53, -(2.0**53)]))
+    # ((0 + 1) + 2^53) - 2^53 = 0 in ascending order (descending: 1)
+    assert y[0] == 0.0
+
+
+def test_gmres_with_inverse():
+    """Full pattern: the incomplete inverses are exact, one iteration.  On the
+    64x64 stencil: converges, residuals non-increasing within a cycle."""
+    n = 30
+    rp, ci, v, rpF, ciF, vF, Ad = _dense_problem(n, 77)
+    vG = O.inverse(n, rpF, ciF, vF)
+    b = np.random.default_rng(1).standard_normal(n)
+    r = O.gmres(n, rp, ci, v, rpF, ciF, vG, b, restart=10, maxit=20, rtol=1e-10, inverse=True)
+    assert r["iters"] == 1 and r["relres"] <= 1e-10
+    c = I.config1()
+    A = c["A"]
+    rpF, ciF, _, vF, _ = O.ilu(A, 1)
+    vG = O.inverse(A.n, rpF, ciF, vF)
+    r = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vG, c["b"], restart=30, maxit=2000, rtol=1e-8,
+                inverse=True)
+    assert r["relres"] <= 1e-8
+    h = r["hist"]
+    for s in range(0, h.size, 30):
+        seg = h[s:s + 30]
+        assert np.all(np.diff(seg) <= 1e-12 * seg[0])
