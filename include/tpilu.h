@@ -245,6 +245,45 @@ TPILU_API tpilu_status tpilu_gmres(tpilu_ctx ctx, tpilu_pattern pat, const doubl
                                    int32_t restart, int32_t maxit, double rtol, int32_t *iters,
                                    double *relres, double *hist);
 
+/* ---------------------------------------------------------------------------
+ * Level-based incomplete inverses (Sec. 3.5, the optional TPIILU(k) step):
+ * the triangular solve stage becomes two matrix-vector products.
+ *
+ * tpilu_inverse computes, from a factor F of this pattern, G shaped like F:
+ *   strict lower slots: the inverse of L~ kept on L~'s pattern, entry (i, t)
+ *     = -beta_it, beta_it = f_it - sum over the pivots h of row i with t < h,
+ *     in ascending h, of f_ih beta_ht (Eqs. 5, 6c, 6d); contributions to
+ *     positions outside the pattern are dropped;
+ *   upper slots (diagonal included): the inverse of U~ kept on U~'s pattern,
+ *     rows from the last to the first, row i = (e_i - sum over the pivots
+ *     j > i of row i, from right to left, of u_ij * (row j of the inverse)) /
+ *     u_ii (the paper omits these details; this is its order for the U~
+ *     stage).
+ * Rows run in dependency-level order; the result is bit-identical to the
+ * sequential recurrence.  f_val, g_val: [nnz_f] device arrays, no aliasing;
+ * batch must be 1.  The first call on a pattern builds the update lists
+ * (kept with the pattern).  Waits for the stream; reports a watchdog timeout
+ * like the factorization.
+ * ------------------------------------------------------------------------- */
+TPILU_API tpilu_status tpilu_inverse(tpilu_ctx ctx, tpilu_pattern pat, const double *f_val, int32_t batch,
+                                     double *g_val);
+
+/* y = U~~^-1 (L~~^-1 b) with the incomplete inverses G (Eq. 3a):
+ *   x_i = (sum over t < i of G_it b_t, from +0.0 in ascending t) + b_i,
+ *   y_i = sum over t >= i of G_it x_t, from +0.0 in ascending t.
+ * Fully parallel (two products).  g_val [nnz_f], b, y [n], x_out (nullable,
+ * [n]) receives x; no two vectors may alias; batch must be 1. */
+TPILU_API tpilu_status tpilu_apply_inverse(tpilu_ctx ctx, tpilu_pattern pat, const double *g_val,
+                                           int32_t batch, const double *b, double *y, double *x_out);
+
+/* tpilu_gmres with M^-1 applied through the incomplete inverses g_val
+ * (tpilu_apply_inverse) instead of the two substitutions; every other step,
+ * argument and result as for tpilu_gmres. */
+TPILU_API tpilu_status tpilu_gmres_inverse(tpilu_ctx ctx, tpilu_pattern pat, const double *a_val,
+                                           const double *g_val, const double *b, double *x, int32_t restart,
+                                           int32_t maxit, double rtol, int32_t *iters, double *relres,
+                                           double *hist);
+
 /* Building blocks exposed for testing and reuse (single instance). */
 /* y = A x with the pattern's A structure. */
 TPILU_API tpilu_status tpilu_spmv(tpilu_ctx ctx, tpilu_pattern pat, const double *a_val,

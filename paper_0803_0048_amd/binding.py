@@ -20,7 +20,7 @@ OK, E_INVAL, E_NOMEM, E_ZEROPIVOT, E_DEVICE, E_NOTCONV, E_TIMEOUT = range(7)
 
 EXPORTED = [
     "tpilu_ctx_create", "tpilu_ctx_set_stream", "tpilu_ctx_destroy", "tpilu_status_string",
-    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_numeric", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
+    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_numeric", "tpilu_inverse", "tpilu_apply_inverse", "tpilu_gmres_inverse", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
     "tpilu_pattern_export", "tpilu_pattern_destroy", "tpilu_numeric", "tpilu_pattern_check",
     "tpilu_apply", "tpilu_gmres", "tpilu_spmv", "tpilu_dot", "tpilu_apply_adjoint",
     "tpilu_numeric_adjoint", "tpilu_batched_graph_create", "tpilu_batched_graph_launch",
@@ -82,6 +82,9 @@ def load_library():
             "tpilu_pattern_check": ([P, P, C.POINTER(i64)], st),
             "tpilu_apply": ([P, P, P, i32, P, P, P], st),
             "tpilu_gmres": ([P, P, P, P, P, P, i32, i32, dbl, C.POINTER(i32), C.POINTER(dbl), P], st),
+            "tpilu_gmres_inverse": ([P, P, P, P, P, P, i32, i32, dbl, C.POINTER(i32), C.POINTER(dbl), P], st),
+            "tpilu_inverse": ([P, P, P, i32, P], st),
+            "tpilu_apply_inverse": ([P, P, P, i32, P, P, P], st),
             "tpilu_spmv": ([P, P, P, P, P], st),
             "tpilu_dot": ([P, i64, P, P, C.POINTER(dbl)], st),
             "tpilu_apply_adjoint": ([P, P, P, i32, P, P, P, P, P], st),
@@ -299,6 +302,32 @@ def apply(pat: Pattern, f_val: torch.Tensor, b: torch.Tensor, out: torch.Tensor 
     return (y, x) if return_x else y
 
 
+def inverse(pat: Pattern, f_val: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Level-based incomplete inverses of L~ and U~ (Sec. 3.5), shaped like F."""
+    _need(f_val, torch.float64, "f_val", pat.device)
+    if _batch_of(f_val, pat.nnz_f, "f_val") != 1:
+        raise ValueError("incomplete inverses: one instance only")
+    g = torch.empty_like(f_val) if out is None else _need(out, torch.float64, "out", pat.device)
+    ctx = context(pat.device)
+    ctx.check(load_library().tpilu_inverse(ctx.h, pat.h, _ptr(f_val), 1, _ptr(g)), "inverse")
+    return g
+
+
+def apply_inverse(pat: Pattern, g_val: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None,
+                  return_x: bool = False):
+    """y = U~~^-1 L~~^-1 b with the incomplete inverses (two products, Eq. 3a)."""
+    _need(g_val, torch.float64, "g_val", pat.device)
+    _need(b, torch.float64, "b", pat.device)
+    if _batch_of(b, pat.n, "b") != 1:
+        raise ValueError("incomplete inverses: one instance only")
+    y = torch.empty_like(b) if out is None else _need(out, torch.float64, "out", pat.device)
+    x = torch.empty_like(b) if return_x else None
+    ctx = context(pat.device)
+    st = load_library().tpilu_apply_inverse(ctx.h, pat.h, _ptr(g_val), 1, _ptr(b), _ptr(y), _ptr(x))
+    ctx.check(st, "apply_inverse")
+    return (y, x) if return_x else y
+
+
 def spmv(pat: Pattern, a_val: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
     _need(a_val, torch.float64, "a_val", pat.device)
     _need(x, torch.float64, "x", pat.device)
@@ -319,8 +348,11 @@ def dot(x: torch.Tensor, y: torch.Tensor) -> float:
 
 
 def gmres(pat: Pattern, a_val: torch.Tensor, f_val: torch.Tensor, b: torch.Tensor, x0: torch.Tensor | None = None,
-          restart: int = 30, maxit: int | None = None, rtol: float = 1e-8, raise_notconv: bool = False):
-    """Right-preconditioned restarted GMRES.  Returns (x, info)."""
+          restart: int = 30, maxit: int | None = None, rtol: float = 1e-8, raise_notconv: bool = False,
+          inverse: bool = False):
+    """Right-preconditioned restarted GMRES.  Returns (x, info).  inverse=True:
+    f_val holds the incomplete inverses (from inverse()) and M^-1 is applied by
+    two products."""
     _need(a_val, torch.float64, "a_val", pat.device)
     _need(f_val, torch.float64, "f_val", pat.device)
     _need(b, torch.float64, "b", pat.device)
@@ -331,8 +363,9 @@ def gmres(pat: Pattern, a_val: torch.Tensor, f_val: torch.Tensor, b: torch.Tenso
     it = C.c_int32(0)
     rr = C.c_double(0.0)
     ctx = context(pat.device)
-    st = load_library().tpilu_gmres(ctx.h, pat.h, _ptr(a_val), _ptr(f_val), _ptr(b), _ptr(x), restart, maxit,
-                                    rtol, C.byref(it), C.byref(rr), hist)
+    fn = load_library().tpilu_gmres_inverse if inverse else load_library().tpilu_gmres
+    st = fn(ctx.h, pat.h, _ptr(a_val), _ptr(f_val), _ptr(b), _ptr(x), restart, maxit, rtol, C.byref(it),
+            C.byref(rr), hist)
     if st != E_NOTCONV or raise_notconv:
         ctx.check(st, "gmres")
     info = {"iters": it.value, "relres": rr.value, "status": st, "hist": list(hist[: it.value])}

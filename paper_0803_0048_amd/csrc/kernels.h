@@ -200,4 +200,27 @@ hipError_t launch_adj_numeric(const PatDev& P, const AdjPat& T, const double* f_
                               int32_t max_row, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 
+// ---- level-based incomplete inverses ---------------------------------------------------
+// per kept entry p of F's pattern: its updates [ptr[p], ptr[p+1]), each the
+// row-local slot of the multiplier (s) and the slot of the partner entry in
+// the other row (q); ascending pivot order for the strict lower part,
+// descending for the upper part
+struct InvSched {
+    const int64_t* ptr;
+    const int32_t* s;
+    const int32_t* q;
+};
+// upper 0: lists of the strict lower entries, 1: of the upper entries; pass 0
+// counts into tcount, pass 1 fills (tptr = scan of the counts)
+hipError_t launch_isched(int32_t n, const int64_t* rpF, const int32_t* ciF, const int32_t* diagF, int upper,
+                         int pass, int32_t* tcount, const int64_t* tptr, int32_t* ps, int32_t* pq,
+                         int32_t max_row, hipStream_t s);
+size_t isched_lds_bytes(int32_t max_row);
+// one half of G from F (G pre-filled with kPending; ctl ticket reset)
+hipError_t launch_inverse(const PatDev& P, const InvSched& S, const double* f_val, double* g_val, bool upper,
+                          Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s);
+// x = L~~^-1 b, y = U~~^-1 x
+hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const double* b, double* x, double* y,
+                                hipStream_t s);
+
 }  // namespace tpilu

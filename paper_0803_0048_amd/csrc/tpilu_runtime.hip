@@ -63,6 +63,7 @@ constexpr int32_t kNumericWaves = 512;
 constexpr int32_t kFlowWaves = 1024;
 constexpr int64_t kFlowMinL = 4;  // dataflow numeric when L rows average at least this many entries
 constexpr int32_t kAdjointWaves = 512;
+constexpr int32_t kInverseWaves = 512;
 constexpr int64_t kNarrowWidth = 64;   // n / depth below this: narrow
 constexpr int64_t kLongRows = 24;      // average entries per half row at or above this: long
 
@@ -149,6 +150,11 @@ struct tpilu_pattern_s {
     int64_t *tpL = nullptr, *tpU = nullptr;
     int32_t *tsL = nullptr, *trL = nullptr, *tsU = nullptr, *trU = nullptr;
     int32_t *permUT = nullptr, *permLT = nullptr;
+    // update lists of the incomplete inverses (built on first use)
+    bool have_inv = false;
+    int64_t* iptr = nullptr;
+    int32_t *is_s = nullptr, *is_q = nullptr;
+    int64_t n_inv_updates = 0;
     // target-major update schedule (only when the dataflow numeric kernel fits)
     bool flow = false;
     int64_t* tptr = nullptr;
@@ -424,6 +430,40 @@ tpilu_status compute_levels(tpilu_ctx ctx, tpilu_pattern pat, const LevelSpec* j
     if (st != TPILU_OK) return st;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return finish_levels(ctx, pat, js, njobs, dmax);
+}
+
+tpilu_status build_inverse_sched(tpilu_ctx ctx, tpilu_pattern pat) {
+    if (pat->have_inv) return TPILU_OK;
+    if (isched_lds_bytes(pat->st.max_row) > kBatchLdsLimit)
+        return fail(ctx, TPILU_E_INVAL, "incomplete inverses support rows of at most 4096 entries");
+    const int32_t n = (int32_t)pat->n;
+    const int64_t nnzf = pat->nnz_f;
+    hipStream_t s = ctx->stream;
+    TmpBufs T{pat->al, {}};
+    int32_t* cnt = (int32_t*)T.get(sizeof(int32_t) * (size_t)nnzf);
+    int64_t* stmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(nnzf));
+    int64_t* iptr = (int64_t*)pat->take(sizeof(int64_t) * (size_t)(nnzf + 1));
+    if (!cnt || !stmp || !iptr) return fail(ctx, TPILU_E_NOMEM, "inverse schedule");
+    for (int up = 0; up < 2; ++up)
+        HIPCHK(ctx, launch_isched(n, pat->rpF, pat->ciF, pat->diagF, up, 0, cnt, nullptr, nullptr, nullptr,
+                                  pat->st.max_row, s));
+    HIPCHK(ctx, launch_scan(cnt, nnzf, iptr, stmp, s));
+    int64_t total = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&total, iptr + nnzf, sizeof(total), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    int32_t* ps = (int32_t*)pat->take(sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1));
+    int32_t* pq = (int32_t*)pat->take(sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1));
+    if (!ps || !pq) return fail(ctx, TPILU_E_NOMEM, "inverse schedule");
+    for (int up = 0; up < 2; ++up)
+        HIPCHK(ctx, launch_isched(n, pat->rpF, pat->ciF, pat->diagF, up, 1, nullptr, iptr, ps, pq,
+                                  pat->st.max_row, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    pat->iptr = iptr;
+    pat->is_s = ps;
+    pat->is_q = pq;
+    pat->n_inv_updates = total;
+    pat->have_inv = true;
+    return TPILU_OK;
 }
 
 // waits for the second stream when it goes out of scope (before the
@@ -920,6 +960,46 @@ extern "C" TPILU_API tpilu_status tpilu_apply(tpilu_ctx ctx, tpilu_pattern pat, 
     return enqueue_apply(ctx, pat, f_val, batch, b, y, x, true);
 }
 
+extern "C" TPILU_API tpilu_status tpilu_inverse(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val,
+                                                int32_t batch, double* g_val) {
+    tpilu_status st = check_common(ctx, pat, batch);
+    if (st) return st;
+    if (batch != 1) return fail(ctx, TPILU_E_INVAL, "incomplete inverses: batch must be 1");
+    if (pat->n == 0) return TPILU_OK;
+    if (!f_val || !g_val) return fail(ctx, TPILU_E_INVAL, "null array");
+    if (f_val == g_val) return fail(ctx, TPILU_E_INVAL, "f_val and g_val alias");
+    DeviceGuard dg(ctx->device);
+    trace("inverse", pat->n);
+    st = build_inverse_sched(ctx, pat);
+    if (st) return st;
+    hipStream_t s = ctx->stream;
+    const InvSched S{pat->iptr, pat->is_s, pat->is_q};
+    const int grid = ctx->grid_override ? ctx->grid_override : kInverseWaves;
+    HIPCHK(ctx, launch_fill_pending(g_val, pat->nnz_f, pat->ctl, true, s));
+    HIPCHK(ctx, launch_inverse(pat->dev(), S, f_val, g_val, false, pat->ctl, ctx->spin_limit, grid, s));
+    HIPCHK(ctx, launch_fill_pending(nullptr, 0, pat->ctl, false, s));
+    HIPCHK(ctx, launch_inverse(pat->dev(), S, f_val, g_val, true, pat->ctl, ctx->spin_limit, grid, s));
+    return read_ctl(ctx, pat, nullptr, false);
+}
+
+extern "C" TPILU_API tpilu_status tpilu_apply_inverse(tpilu_ctx ctx, tpilu_pattern pat, const double* g_val,
+                                                      int32_t batch, const double* b, double* y, double* x_out) {
+    tpilu_status st = check_common(ctx, pat, batch);
+    if (st) return st;
+    if (batch != 1) return fail(ctx, TPILU_E_INVAL, "incomplete inverses: batch must be 1");
+    if (pat->n == 0) return TPILU_OK;
+    if (!g_val || !b || !y) return fail(ctx, TPILU_E_INVAL, "null array");
+    if (b == y || (x_out && (x_out == b || x_out == y))) return fail(ctx, TPILU_E_INVAL, "vectors alias");
+    DeviceGuard dg(ctx->device);
+    double* x = x_out;
+    if (!x) {
+        x = pat->grow(pat->ws_x, sizeof(double) * (size_t)pat->n);
+        if (!x) return fail(ctx, TPILU_E_NOMEM, "apply workspace");
+    }
+    HIPCHK(ctx, launch_apply_inverse(pat->dev(), g_val, b, x, y, ctx->stream));
+    return TPILU_OK;
+}
+
 extern "C" TPILU_API tpilu_status tpilu_spmv(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val,
                                              const double* x, double* y) {
     tpilu_status st = check_common(ctx, pat, 1);
@@ -956,10 +1036,19 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
         p[i] = v;
 }
 
-extern "C" TPILU_API tpilu_status tpilu_gmres(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val,
-                                              const double* f_val, const double* b, double* x,
-                                              int32_t restart, int32_t maxit, double rtol, int32_t* iters,
-                                              double* relres, double* hist) {
+namespace {
+// z = M^-1 v: the two substitutions with F, or the two products with G
+tpilu_status enqueue_precond(tpilu_ctx ctx, tpilu_pattern pat, const double* m_val, bool inverse,
+                             const double* v, double* z, double* t, bool reset) {
+    if (!inverse) return enqueue_apply(ctx, pat, m_val, 1, v, z, t, reset);
+    if (reset) HIPCHK(ctx, launch_fill_pending(nullptr, 0, pat->ctl, true, ctx->stream));
+    HIPCHK(ctx, launch_apply_inverse(pat->dev(), m_val, v, t, z, ctx->stream));
+    return TPILU_OK;
+}
+
+tpilu_status gmres_impl(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val, const double* f_val, bool inverse,
+                        const double* b, double* x, int32_t restart, int32_t maxit, double rtol, int32_t* iters,
+                        double* relres, double* hist) {
     tpilu_status st = check_common(ctx, pat, 1);
     if (st) return st;
     if (!iters || !relres) return fail(ctx, TPILU_E_INVAL, "null host output");
@@ -1032,7 +1121,7 @@ extern "C" TPILU_API tpilu_status tpilu_gmres(tpilu_ctx ctx, tpilu_pattern pat, 
         int32_t jj = 0;
         for (int32_t j = 0; j < m; ++j) {
             double* vj = V + (size_t)j * nn;
-            st = enqueue_apply(ctx, pat, f_val, 1, vj, z, t, reset);
+            st = enqueue_precond(ctx, pat, f_val, inverse, vj, z, t, reset);
             reset = false;
             if (st) return st;
             HIPCHK(ctx, launch_spmv(ni, pat->rpA, pat->ciA, a_val, z, nullptr, w, s));
@@ -1053,7 +1142,7 @@ extern "C" TPILU_API tpilu_status tpilu_gmres(tpilu_ctx ctx, tpilu_pattern pat, 
         }
         HIPCHK(ctx, launch_gm_backsub(H, g, yv, m, jj, s));
         HIPCHK(ctx, launch_gm_combine(n, V, yv, jj, u, s));
-        st = enqueue_apply(ctx, pat, f_val, 1, u, z, t, false);
+        st = enqueue_precond(ctx, pat, f_val, inverse, u, z, t, false);
         if (st) return st;
         HIPCHK(ctx, launch_axpy1(n, x, z, s));
     }
@@ -1070,6 +1159,21 @@ extern "C" TPILU_API tpilu_status tpilu_gmres(tpilu_ctx ctx, tpilu_pattern pat, 
     if (st) return st;
     if (!(*relres <= rtol)) return fail(ctx, TPILU_E_NOTCONV, "GMRES reached maxit");
     return TPILU_OK;
+}
+}  // namespace
+
+extern "C" TPILU_API tpilu_status tpilu_gmres(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val,
+                                              const double* f_val, const double* b, double* x,
+                                              int32_t restart, int32_t maxit, double rtol, int32_t* iters,
+                                              double* relres, double* hist) {
+    return gmres_impl(ctx, pat, a_val, f_val, false, b, x, restart, maxit, rtol, iters, relres, hist);
+}
+
+extern "C" TPILU_API tpilu_status tpilu_gmres_inverse(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val,
+                                                      const double* g_val, const double* b, double* x,
+                                                      int32_t restart, int32_t maxit, double rtol,
+                                                      int32_t* iters, double* relres, double* hist) {
+    return gmres_impl(ctx, pat, a_val, g_val, true, b, x, restart, maxit, rtol, iters, relres, hist);
 }
 
 // =====================================================================================

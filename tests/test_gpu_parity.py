@@ -485,3 +485,62 @@ def test_config5_autograd_against_oracle_and_fd():
         yp, ym = y_of(vp, inst), y_of(vm, inst)
         fd = math.fsum((yp - ym) * (yp + ym - 2.0 * tgt[:, inst])) / (vp[p] - vm[p])
         assert abs(fd - ga[p, inst]) <= 1e-5 * max(abs(fd), 1e-9 * scale) + 1e-9 * scale, (inst, p, fd, ga[p, inst])
+
+
+# ----------------------------------------------------------------------------------
+# level-based incomplete inverses (Sec. 3.5)
+# ----------------------------------------------------------------------------------
+def _inverse_parity(A, k, b, waves=0):
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
+    vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
+    vG = O.inverse(A.n, rpF, ciF, vF)
+    x_ref, y_ref = O.apply_inverse(A.n, rpF, ciF, vG, b)
+    pat = T.symbolic(g(A.rowptr), g(A.col), k)
+    f = T.numeric(pat, g(A.val), check=False)
+    assert_bits_equal(f, vF, "F")
+    ctx = T.context(0)
+    ctx.set_grid(waves)
+    try:
+        G = T.inverse(pat, f)
+    finally:
+        ctx.set_grid(0)
+    assert_bits_equal(G, vG, "G")
+    y, x = T.apply_inverse(pat, G, g(b), return_x=True)
+    assert_bits_equal(x, x_ref, "x = L~~^-1 b")
+    assert_bits_equal(y, y_ref, "y = U~~^-1 x")
+    return pat, f, G, (rpF, ciF, vF, vG)
+
+
+def test_inverse_small_sweep():
+    rng = np.random.default_rng(21)
+    for case in range(40):
+        n = int(rng.integers(1, 300))
+        A = I.random_pattern(n, float(rng.choice([0.005, 0.02, 0.06])), seed=int(rng.integers(1 << 30)),
+                             diag_dominant=bool(rng.integers(2)))
+        if case % 7 == 0 and A.nnz > 3:
+            A.val[1] = -0.0
+        k = int(rng.choice([0, 1, 2, 3, n]))
+        _inverse_parity(A, k, rng.standard_normal(n), waves=int(rng.choice([0, 1, 5, 64])))
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c3k1", "c3k2"])
+def test_inverse_stencils(cfg):
+    c = I.config1() if cfg == "c1" else I.config3(k=int(cfg[-1]))
+    _inverse_parity(c["A"], c["k"] if cfg == "c1" else int(cfg[-1]), c["b"])
+
+
+def test_inverse_config2_full_size():
+    c = I.config2()
+    _inverse_parity(c["A"], c["k"], c["b"])
+
+
+def test_gmres_inverse_bits():
+    c = I.config1()
+    A = c["A"]
+    pat, f, G, (rpF, ciF, vF, vG) = _inverse_parity(A, 1, c["b"])
+    ref = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vG, c["b"], restart=30, maxit=400, rtol=1e-8,
+                  inverse=True)
+    x, info = T.gmres(pat, g(A.val), G, g(c["b"]), restart=30, maxit=400, rtol=1e-8, inverse=True)
+    assert info["iters"] == ref["iters"]
+    assert_bits_equal(np.array(info["hist"]), ref["hist"], "GMRES |g| history (inverse)")
+    assert_bits_equal(x, ref["x"], "GMRES x (inverse)")
