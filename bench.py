@@ -227,6 +227,8 @@ def main():
 
     if not args.no_extras:
         out["extras"] = extras(T, I, torch, np, dev, ctx)
+        out["extras"]["incomplete_inverse"] = inverse_extra(T, torch, pat, av, fout, bv, restart, rtol, maxit,
+                                                            gmres_ms, ginfo, n, nnz_f, nnz_l)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, k, np)
@@ -311,6 +313,56 @@ def extras(T, I, torch, np, dev, ctx):
     res["reverse_mode"] = {"instances": A5.batch, "n": A5.n, "forward_ms": fms, "backward_ms": bms,
                            "backward_over_forward": bms / fms}
     return res
+
+
+def inverse_extra(T, torch, pat, av, f, bv, restart, rtol, maxit, gmres_ms, ginfo, n, nnz_f, nnz_l):
+    """The optional level-based incomplete inverses (Sec. 3.5) on the same
+    n=160000 ILU(2) factor: building them, applying M^-1 by two products next
+    to the two substitutions, and GMRES(30) with them next to GMRES(30) with
+    the substitutions.  The products are bandwidth-bound: their roofline."""
+    log("incomplete inverses on the n=160000 factor")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    G = T.inverse(pat, f)
+    per = []
+    for _ in range(5):
+        e0.record()
+        T.inverse(pat, f, out=G)
+        e1.record()
+        torch.cuda.synchronize()
+        per.append(e0.elapsed_time(e1))
+    y = torch.empty_like(bv)
+    x = torch.empty_like(bv)
+    reps = 50
+    T.apply_inverse(pat, G, bv, out=y)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        T.apply_inverse(pat, G, bv, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    app_ms = e0.elapsed_time(e1) / reps
+    e0.record()
+    for _ in range(5):
+        T.apply(pat, f, bv, out=x)
+    e1.record()
+    torch.cuda.synchronize()
+    tri_ms = e0.elapsed_time(e1) / 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = T.gmres(pat, av, G, bv, restart=restart, maxit=maxit, rtol=rtol, inverse=True)
+    torch.cuda.synchronize()
+    gi_ms = (time.perf_counter() - t0) * 1e3
+    # compulsory bytes of the two products: G and its columns once, row
+    # pointers and diagonal slots, b read twice (gathered and added), x
+    # written then gathered, y written
+    app_bytes = 12 * nnz_f + 8 * (n + 1) + 4 * n + 5 * 8 * n
+    gbs = app_bytes / (app_ms * 1e-3) / 1e9
+    return {"inverse_ms": statistics.median(per), "apply_ms": app_ms, "triangular_apply_ms": tri_ms,
+            "apply_speedup": tri_ms / app_ms,
+            "apply_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": app_bytes},
+            "gmres_iters": info["iters"], "gmres_relres": info["relres"], "gmres_ms": gi_ms,
+            "gmres_with_substitutions": {"iters": ginfo["iters"], "ms": gmres_ms}}
 
 
 def cpu_baseline(A, k, np):

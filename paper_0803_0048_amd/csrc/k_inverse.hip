@@ -22,8 +22,9 @@
 // the moment they are final.  G starts as kPending.
 //
 // Applying them (Eq. 3a): x_i = sum_{t<i} G_it p_t + p_i, y_i = sum_{t>=i}
-// G_it x_t, each row summed from +0.0 in ascending column order: a wavefront
-// per row forms the products in parallel and adds them in that order.
+// G_it x_t, each row summed from +0.0 in ascending column order, either by one
+// thread per row or by a wavefront per row (products in parallel, added in
+// that order); both give the same bits.
 #include "kernels.h"
 
 namespace tpilu {
@@ -239,12 +240,36 @@ __global__ __launch_bounds__(64) void k_apply_inverse(PatDev P, const double* __
     }
 }
 
+// one thread per row: the row's products and their sum in order, no
+// cross-lane traffic (rows of a wavefront are consecutive, so each thread's
+// consecutive entries share cache lines across iterations)
+template <bool kUpper>
+__global__ __launch_bounds__(256) void k_apply_inverse_rows(PatDev P, const double* __restrict__ G,
+                                                            const double* __restrict__ in,
+                                                            double* __restrict__ out) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    const int64_t dj = P.diagF[i];
+    const int64_t a = kUpper ? dj : P.rpF[i], b = kUpper ? P.rpF[i + 1] : dj;
+    double s = 0.0;
+    for (int64_t q = a; q < b; ++q) s = s + G[q] * in[P.ciF[q]];
+    if (!kUpper) s = s + in[i];
+    out[i] = s;
+}
+
+// thread_rows: one thread per row, else a wavefront per row
 hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const double* b, double* x, double* y,
-                                hipStream_t s) {
+                                bool thread_rows, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    const int grid = std::min(P.n, 65536);
-    hipLaunchKernelGGL(k_apply_inverse<false>, dim3(grid), dim3(64), 0, s, P, g_val, b, x);
-    hipLaunchKernelGGL(k_apply_inverse<true>, dim3(grid), dim3(64), 0, s, P, g_val, x, y);
+    if (thread_rows) {
+        const int grid = (P.n + 255) / 256;
+        hipLaunchKernelGGL(k_apply_inverse_rows<false>, dim3(grid), dim3(256), 0, s, P, g_val, b, x);
+        hipLaunchKernelGGL(k_apply_inverse_rows<true>, dim3(grid), dim3(256), 0, s, P, g_val, x, y);
+    } else {
+        const int grid = std::min(P.n, 65536);
+        hipLaunchKernelGGL(k_apply_inverse<false>, dim3(grid), dim3(64), 0, s, P, g_val, b, x);
+        hipLaunchKernelGGL(k_apply_inverse<true>, dim3(grid), dim3(64), 0, s, P, g_val, x, y);
+    }
     return hipGetLastError();
 }
 

@@ -505,9 +505,15 @@ def _inverse_parity(A, k, b, waves=0):
     finally:
         ctx.set_grid(0)
     assert_bits_equal(G, vG, "G")
-    y, x = T.apply_inverse(pat, G, g(b), return_x=True)
-    assert_bits_equal(x, x_ref, "x = L~~^-1 b")
-    assert_bits_equal(y, y_ref, "y = U~~^-1 x")
+    # both shapes of the two products (wavefront per row, thread per row)
+    for solver in (ctx.SOLVER_DEVICE, ctx.SOLVER_LANES, 0):
+        ctx.set_solver(solver)
+        try:
+            y, x = T.apply_inverse(pat, G, g(b), return_x=True)
+        finally:
+            ctx.set_solver(0)
+        assert_bits_equal(x, x_ref, "x = L~~^-1 b")
+        assert_bits_equal(y, y_ref, "y = U~~^-1 x")
     return pat, f, G, (rpF, ciF, vF, vG)
 
 
