@@ -66,6 +66,8 @@ def lib():
         L.orc_gmres_inverse.argtypes = [i64, P, P, P, P, P, P, P, P, i32, i32, dbl,
                                         C.POINTER(i32), C.POINTER(dbl), P]
         L.orc_inverse.argtypes = [i64, P, P, P, P]
+        L.orc_bicgstab.argtypes = [i64, P, P, P, P, P, P, i32, P, P, i32, dbl,
+                                   C.POINTER(i32), C.POINTER(dbl), P]
         L.orc_apply_inverse.argtypes = [i64, P, P, P, P, P, P]
         L.orc_apply_adjoint.argtypes = [i64, P, P, P, P, P, P, P, P]
         L.orc_numeric_adjoint.argtypes = [i64, P, P, P, P, P, P, P]
@@ -190,6 +192,26 @@ def gmres(n, rowptr, col, val, rowptrF, colF, valF, b, x0=None, restart=30, maxi
             int(restart), int(maxit), float(rtol), C.byref(it), C.byref(rr), _p(hist))
     if st not in (OK, ENOTCONV):
         raise OracleError(st, "gmres")
+    return {"x": x, "iters": int(it.value), "relres": float(rr.value), "status": st,
+            "hist": hist[: it.value].copy()}
+
+
+def bicgstab(n, rowptr, col, val, rowptrF, colF, valM, b, x0=None, maxit=None, rtol=1e-8, inverse=False):
+    """Right-preconditioned BiCGSTAB.  maxit and iters count half steps (one
+    per preconditioner application).  Returns dict(x, iters, relres, status, hist)."""
+    rp, ci, v = _c(rowptr, np.int64), _c(col, np.int32), _c(val, np.float64)
+    rpF, ciF, vM = _c(rowptrF, np.int64), _c(colF, np.int32), _c(valM, np.float64)
+    bb = _c(b, np.float64)
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    if maxit is None:
+        maxit = min(10 * n, 100000)
+    hist = np.zeros(max(maxit, 1), dtype=np.float64)
+    it = C.c_int32(0)
+    rr = C.c_double(0.0)
+    st = lib().orc_bicgstab(n, _p(rp), _p(ci), _p(v), _p(rpF), _p(ciF), _p(vM), int(bool(inverse)), _p(bb),
+                            _p(x), int(maxit), float(rtol), C.byref(it), C.byref(rr), _p(hist))
+    if st not in (OK, ENOTCONV):
+        raise OracleError(st, "bicgstab")
     return {"x": x, "iters": int(it.value), "relres": float(rr.value), "status": st,
             "hist": hist[: it.value].copy()}
 

@@ -458,6 +458,130 @@ int orc_gmres(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *v
     return gmres_impl(n, rpA, ciA, vA, rpF, ciF, vF, 0, b, x, m, maxit, rtol, iters_out, relres_out, hist);
 }
 
+/* ------------------------------------------------------------------------ */
+/* BiCGSTAB, the Krylov method the paper runs (through Hypre, Sec. 4), right */
+/* preconditioned (the solver works on A M^-1, Sec. 2), in the textbook form */
+/* of van der Vorst with the shadow residual fixed to the first residual.   */
+/* Every scalar and vector step is one fixed expression, rounded step by    */
+/* step as written:                                                          */
+/*   r = b - A x, rs = r, rho_old = alpha = omega = 1, v = p = 0             */
+/*   loop: rho = (rs, r); stop on rho == 0 (breakdown)                        */
+/*     first pass p = r, else beta = (rho / rho_old) * (alpha / omega) and    */
+/*       p_e = r_e + beta * (p_e - omega * v_e)                               */
+/*     ph = M^-1 p; v = A ph; alpha = rho / (rs, v) (breakdown on 0)          */
+/*     s_e = r_e - alpha * v_e; iters++; hist = ||s||                         */
+/*     if ||s|| <= rtol ||b||: x_e = x_e + alpha * ph_e, stop                 */
+/*     sh = M^-1 s; t = A sh; omega = (t, s) / (t, t) (breakdown on 0)        */
+/*     x_e = (x_e + alpha * ph_e) + omega * sh_e; r_e = s_e - omega * t_e     */
+/*     hist = ||r||; stop if ||r|| <= rtol ||b|| or iters >= maxit            */
+/*     rho_old = rho                                                          */
+/* iters counts half steps (each ph and each sh), so hist has one entry per */
+/* preconditioner application.  Returns the true relative residual.         */
+/* ------------------------------------------------------------------------ */
+static int bicgstab_impl(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
+                         const int64_t *rpF, const int32_t *ciF, const double *vM, int inverse,
+                         const double *b, double *x, int32_t maxit, double rtol,
+                         int32_t *iters_out, double *relres_out, double *hist)
+{
+    *iters_out = 0;
+    *relres_out = 0.0;
+    if (maxit < 0) return ORC_EINVAL;
+    size_t N = (size_t)(n > 0 ? n : 1);
+    double *r = (double *)malloc(N * sizeof(double));
+    double *rs = (double *)malloc(N * sizeof(double));
+    double *p = (double *)malloc(N * sizeof(double));
+    double *v = (double *)malloc(N * sizeof(double));
+    double *ph = (double *)malloc(N * sizeof(double));
+    double *sv = (double *)malloc(N * sizeof(double));
+    double *sh = (double *)malloc(N * sizeof(double));
+    double *t = (double *)malloc(N * sizeof(double));
+    double *tmp = (double *)malloc(N * sizeof(double));
+    if (!r || !rs || !p || !v || !ph || !sv || !sh || !t || !tmp) {
+        free(r); free(rs); free(p); free(v); free(ph); free(sv); free(sh); free(t); free(tmp);
+        return ORC_ENOMEM;
+    }
+    int st = ORC_OK;
+    int32_t iters = 0;
+    double bnorm = orc_nrm2(n, b);
+    if (bnorm == 0.0) {
+        for (int64_t e = 0; e < n; ++e) x[e] = 0.0;
+        goto done;
+    }
+    double tol = rtol * bnorm;
+    orc_spmv(n, rpA, ciA, vA, x, r);
+    for (int64_t e = 0; e < n; ++e) {
+        r[e] = b[e] - r[e];
+        rs[e] = r[e];
+        p[e] = 0.0;
+        v[e] = 0.0;
+    }
+    if (orc_nrm2(n, r) <= tol) goto finish;
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    int first = 1;
+    while (iters < maxit) {
+        double rho = orc_dot(n, rs, r);
+        if (rho == 0.0) { st = ORC_ENOTCONV; break; }
+        if (first) {
+            for (int64_t e = 0; e < n; ++e) p[e] = r[e];
+            first = 0;
+        } else {
+            double beta = (rho / rho_old) * (alpha / omega);
+            for (int64_t e = 0; e < n; ++e) p[e] = r[e] + beta * (p[e] - omega * v[e]);
+        }
+        apply_m(n, rpF, ciF, vM, inverse, p, tmp, ph);
+        orc_spmv(n, rpA, ciA, vA, ph, v);
+        double rv = orc_dot(n, rs, v);
+        if (rv == 0.0) { st = ORC_ENOTCONV; break; }
+        alpha = rho / rv;
+        for (int64_t e = 0; e < n; ++e) sv[e] = r[e] - alpha * v[e];
+        double snorm = orc_nrm2(n, sv);
+        if (hist) hist[iters] = snorm;
+        ++iters;
+        if (snorm <= tol) {
+            for (int64_t e = 0; e < n; ++e) x[e] = x[e] + alpha * ph[e];
+            break;
+        }
+        if (iters >= maxit) {
+            for (int64_t e = 0; e < n; ++e) x[e] = x[e] + alpha * ph[e];
+            break;
+        }
+        apply_m(n, rpF, ciF, vM, inverse, sv, tmp, sh);
+        orc_spmv(n, rpA, ciA, vA, sh, t);
+        double ts = orc_dot(n, t, sv);
+        double tt = orc_dot(n, t, t);
+        if (tt == 0.0) { st = ORC_ENOTCONV; break; }
+        omega = ts / tt;
+        for (int64_t e = 0; e < n; ++e) {
+            x[e] = (x[e] + alpha * ph[e]) + omega * sh[e];
+            r[e] = sv[e] - omega * t[e];
+        }
+        double rnorm = orc_nrm2(n, r);
+        if (hist) hist[iters] = rnorm;
+        ++iters;
+        if (rnorm <= tol) break;
+        if (omega == 0.0) { st = ORC_ENOTCONV; break; }
+        rho_old = rho;
+    }
+finish:
+    orc_spmv(n, rpA, ciA, vA, x, tmp);
+    for (int64_t e = 0; e < n; ++e) tmp[e] = b[e] - tmp[e];
+    *relres_out = orc_nrm2(n, tmp) / bnorm;
+    if (!(*relres_out <= rtol)) st = ORC_ENOTCONV;
+done:
+    *iters_out = iters;
+    free(r); free(rs); free(p); free(v); free(ph); free(sv); free(sh); free(t); free(tmp);
+    return st;
+}
+
+int orc_bicgstab(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
+                 const int64_t *rpF, const int32_t *ciF, const double *vM, int32_t inverse,
+                 const double *b, double *x, int32_t maxit, double rtol,
+                 int32_t *iters_out, double *relres_out, double *hist)
+{
+    return bicgstab_impl(n, rpA, ciA, vA, rpF, ciF, vM, inverse != 0, b, x, maxit, rtol, iters_out,
+                         relres_out, hist);
+}
+
 /* the same GMRES(m) with M^-1 applied through the incomplete inverses vG */
 int orc_gmres_inverse(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
                       const int64_t *rpF, const int32_t *ciF, const double *vG,

@@ -767,3 +767,57 @@ def test_gmres_with_inverse():
     for s in range(0, h.size, 30):
         seg = h[s:s + 30]
         assert np.all(np.diff(seg) <= 1e-12 * seg[0])
+
+
+# --------------------------------------------------------------------------
+# BiCGSTAB (the Krylov method of the paper's experiments, Sec. 4)
+# --------------------------------------------------------------------------
+
+def test_bicgstab_iterates_match_scipy():
+    """The same right-preconditioned BiCGSTAB as scipy's: the iterate after k
+    full steps agrees to rounding (only the inner products' summation order
+    differs), for both preconditioners."""
+    from scipy.sparse.linalg import LinearOperator, bicgstab as sp_bicgstab
+
+    c = I.config1()
+    A = c["A"]
+    rpF, ciF, _, vF, _ = O.ilu(A, 1)
+    vG = O.inverse(A.n, rpF, ciF, vF)
+    As = sp.csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n))
+    b = c["b"]
+    for inverse, vals in ((False, vF), (True, vG)):
+        if inverse:
+            M = LinearOperator((A.n, A.n), matvec=lambda p: O.apply_inverse(A.n, rpF, ciF, vG, p)[1])
+        else:
+            M = LinearOperator((A.n, A.n), matvec=lambda p: O.apply(A.n, rpF, ciF, vF, p)[1])
+        for k in (1, 2, 3, 6):
+            xs = []
+            sp_bicgstab(As, b, rtol=1e-30, atol=0.0, maxiter=k, M=M, callback=lambda xk: xs.append(xk.copy()))
+            r = O.bicgstab(A.n, A.rowptr, A.col, A.val, rpF, ciF, vals, b, maxit=2 * k, rtol=1e-30,
+                           inverse=inverse)
+            assert r["iters"] == 2 * k
+            assert np.linalg.norm(r["x"] - xs[-1]) <= 1e-11 * np.linalg.norm(xs[-1]), (inverse, k)
+
+
+def test_bicgstab_exact_preconditioner_one_half_step():
+    """M = A (full pattern): p_hat = A^-1 b, v = b, alpha = 1, s = 0 -- done
+    after the first half step."""
+    n = 30
+    rp, ci, v, rpF, ciF, vF, Ad = _dense_problem(n, 78)
+    b = np.random.default_rng(2).standard_normal(n)
+    r = O.bicgstab(n, rp, ci, v, rpF, ciF, vF, b, maxit=10, rtol=1e-10)
+    assert r["iters"] == 1 and r["relres"] <= 1e-12
+    assert np.linalg.norm(r["x"] - np.linalg.solve(Ad, b)) <= 1e-12 * np.linalg.norm(r["x"])
+
+
+def test_bicgstab_converges_and_edge_cases():
+    c = I.config1()
+    A = c["A"]
+    rpF, ciF, _, vF, _ = O.ilu(A, 1)
+    r = O.bicgstab(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, c["b"], maxit=400, rtol=1e-8)
+    assert r["status"] == O.OK and r["relres"] <= 1e-8
+    assert r["hist"][-1] <= 1e-8 * np.linalg.norm(c["b"])
+    z = O.bicgstab(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, np.zeros(A.n), maxit=10, rtol=1e-8)
+    assert z["iters"] == 0 and not z["x"].any()
+    m = O.bicgstab(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, c["b"], maxit=3, rtol=1e-14)
+    assert m["iters"] == 3 and m["status"] == O.ENOTCONV
