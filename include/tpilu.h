@@ -279,6 +279,25 @@ TPILU_API tpilu_status tpilu_inverse(tpilu_ctx ctx, tpilu_pattern pat, const dou
 TPILU_API tpilu_status tpilu_apply_inverse(tpilu_ctx ctx, tpilu_pattern pat, const double *g_val,
                                            int32_t batch, const double *b, double *y, double *x_out);
 
+/* ---------------------------------------------------------------------------
+ * BiCGSTAB, the Krylov method of the paper's experiments (Sec. 4), right
+ * preconditioned like tpilu_gmres: the textbook iteration with the shadow
+ * residual fixed to the first residual, every scalar and vector step one
+ * fixed expression (beta = (rho / rho_old) * (alpha / omega);
+ * p = r + beta * (p - omega * v); s = r - alpha * v; x = (x + alpha * ph) +
+ * omega * sh; r = s - omega * t), inner products of the fixed shape above.
+ * m_val: the factor F (inverse = 0, M^-1 by the two substitutions) or the
+ * incomplete inverses G (inverse != 0, by two products).  maxit and *iters
+ * count half steps (one per preconditioner application); hist (host,
+ * nullable, maxit entries) gets ||s|| or ||r|| after each half step.  Stops
+ * when that norm <= rtol ||b||.  Returns TPILU_E_NOTCONV on a breakdown (a
+ * zero rho, (rs, v), (t, t) or omega) or when maxit is reached, with the last
+ * x, *iters and the true *relres = ||b - A x|| / ||b||.
+ * ------------------------------------------------------------------------- */
+TPILU_API tpilu_status tpilu_bicgstab(tpilu_ctx ctx, tpilu_pattern pat, const double *a_val,
+                                      const double *m_val, int32_t inverse, const double *b, double *x,
+                                      int32_t maxit, double rtol, int32_t *iters, double *relres, double *hist);
+
 /* tpilu_gmres with M^-1 applied through the incomplete inverses g_val
  * (tpilu_apply_inverse) instead of the two substitutions; every other step,
  * argument and result as for tpilu_gmres. */

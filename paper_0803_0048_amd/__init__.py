@@ -9,6 +9,7 @@ Entry points (GPU only; they raise if the HIP library is missing):
     x, info = gmres(pat, a_val, f, b)       # right-preconditioned GMRES(m)
     g   = inverse(pat, f)                   # level-based incomplete inverses, Sec. 3.5
     y   = apply_inverse(pat, g, b)          # M^-1 b by two products, Eq. 3a
+    x, info = bicgstab(pat, a_val, f, b)    # right-preconditioned BiCGSTAB (Sec. 4)
     ILUApply.apply(a_val, b, pat)           # autograd: d/d a_val, d/d b
     BatchedGraph(pat, a_vals, bs).launch()  # batch in one HIP graph
 
@@ -17,7 +18,7 @@ Entry points (GPU only; they raise if the HIP library is missing):
 
 _BINDING_NAMES = {
     "symbolic", "numeric", "apply", "gmres", "spmv", "dot", "apply_adjoint", "numeric_adjoint",
-    "inverse", "apply_inverse",
+    "inverse", "apply_inverse", "bicgstab",
     "check", "BatchedGraph", "ILUApply", "Pattern", "TpiluError", "ZeroPivotError", "context",
     "load_library", "LIB_PATH",
 }

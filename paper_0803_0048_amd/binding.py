@@ -20,7 +20,7 @@ OK, E_INVAL, E_NOMEM, E_ZEROPIVOT, E_DEVICE, E_NOTCONV, E_TIMEOUT = range(7)
 
 EXPORTED = [
     "tpilu_ctx_create", "tpilu_ctx_set_stream", "tpilu_ctx_destroy", "tpilu_status_string",
-    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_numeric", "tpilu_inverse", "tpilu_apply_inverse", "tpilu_gmres_inverse", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
+    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_numeric", "tpilu_inverse", "tpilu_apply_inverse", "tpilu_gmres_inverse", "tpilu_bicgstab", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
     "tpilu_pattern_export", "tpilu_pattern_destroy", "tpilu_numeric", "tpilu_pattern_check",
     "tpilu_apply", "tpilu_gmres", "tpilu_spmv", "tpilu_dot", "tpilu_apply_adjoint",
     "tpilu_numeric_adjoint", "tpilu_batched_graph_create", "tpilu_batched_graph_launch",
@@ -84,6 +84,7 @@ def load_library():
             "tpilu_gmres": ([P, P, P, P, P, P, i32, i32, dbl, C.POINTER(i32), C.POINTER(dbl), P], st),
             "tpilu_gmres_inverse": ([P, P, P, P, P, P, i32, i32, dbl, C.POINTER(i32), C.POINTER(dbl), P], st),
             "tpilu_inverse": ([P, P, P, i32, P], st),
+            "tpilu_bicgstab": ([P, P, P, P, i32, P, P, i32, dbl, C.POINTER(i32), C.POINTER(dbl), P], st),
             "tpilu_apply_inverse": ([P, P, P, i32, P, P, P], st),
             "tpilu_spmv": ([P, P, P, P, P], st),
             "tpilu_dot": ([P, i64, P, P, C.POINTER(dbl)], st),
@@ -368,6 +369,30 @@ def gmres(pat: Pattern, a_val: torch.Tensor, f_val: torch.Tensor, b: torch.Tenso
             C.byref(rr), hist)
     if st != E_NOTCONV or raise_notconv:
         ctx.check(st, "gmres")
+    info = {"iters": it.value, "relres": rr.value, "status": st, "hist": list(hist[: it.value])}
+    return x, info
+
+
+def bicgstab(pat: Pattern, a_val: torch.Tensor, m_val: torch.Tensor, b: torch.Tensor,
+             x0: torch.Tensor | None = None, maxit: int | None = None, rtol: float = 1e-8,
+             inverse: bool = False, raise_notconv: bool = False):
+    """Right-preconditioned BiCGSTAB (Sec. 4's solver).  m_val: the factor, or
+    the incomplete inverses with inverse=True.  maxit / iters count half steps.
+    Returns (x, info)."""
+    _need(a_val, torch.float64, "a_val", pat.device)
+    _need(m_val, torch.float64, "m_val", pat.device)
+    _need(b, torch.float64, "b", pat.device)
+    x = torch.zeros_like(b) if x0 is None else _need(x0, torch.float64, "x0", pat.device).clone()
+    if maxit is None:
+        maxit = min(10 * pat.n, 100000)
+    hist = (C.c_double * max(maxit, 1))()
+    it = C.c_int32(0)
+    rr = C.c_double(0.0)
+    ctx = context(pat.device)
+    st = load_library().tpilu_bicgstab(ctx.h, pat.h, _ptr(a_val), _ptr(m_val), 1 if inverse else 0, _ptr(b),
+                                       _ptr(x), maxit, rtol, C.byref(it), C.byref(rr), hist)
+    if st != E_NOTCONV or raise_notconv:
+        ctx.check(st, "bicgstab")
     info = {"iters": it.value, "relres": rr.value, "status": st, "hist": list(hist[: it.value])}
     return x, info
 

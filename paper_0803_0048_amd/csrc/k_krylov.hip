@@ -1,4 +1,5 @@
-// Krylov building blocks for right-preconditioned restarted GMRES on gfx950.
+// Krylov building blocks for right-preconditioned restarted GMRES and
+// BiCGSTAB on gfx950.
 //
 // The paper keeps inner products sequential so that their bits do not depend
 // on the number of threads (Sec. 3.5).  Here every reduction instead has one
@@ -256,6 +257,117 @@ hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s)
     if (n <= 0) return hipSuccess;
     int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
     hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+}  // namespace tpilu
+
+namespace tpilu {
+
+// ----------------------------------------------------------------------------------
+// BiCGSTAB steps.  Scalars live in sc[] on the device (kBi* slots); every
+// thread that needs one derives it from the same stored values with the same
+// expression, so all of them hold the same bits.
+// ----------------------------------------------------------------------------------
+// rho_old <- rho, rho <- (rs, r) from its partials
+__global__ void k_bi_rho(const double* __restrict__ partial, double* sc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        sc[kBiRhoOld] = sc[kBiRho];
+        sc[kBiRho] = tree64(partial);
+    }
+}
+
+// p <- r (first pass) or p_e <- r_e + beta * (p_e - omega * v_e),
+// beta = (rho / rho_old) * (alpha / omega)
+__global__ __launch_bounds__(256) void k_bi_p(int64_t n, int first, const double* __restrict__ sc,
+                                              const double* __restrict__ r, double* __restrict__ p,
+                                              const double* __restrict__ v) {
+    const double omega = sc[kBiOmega];
+    const double beta = (sc[kBiRho] / sc[kBiRhoOld]) * (sc[kBiAlpha] / omega);
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = first ? r[e] : r[e] + beta * (p[e] - omega * v[e]);
+}
+
+// rv = (rs, v); alpha = rho / rv (rv == 0: breakdown flag, alpha left alone)
+__global__ void k_bi_alpha(const double* __restrict__ partial, double* sc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double rv = tree64(partial);
+        sc[kBiRv] = rv;
+        if (rv != 0.0) sc[kBiAlpha] = sc[kBiRho] / rv;
+    }
+}
+
+// s_e = r_e - alpha * v_e (skipped after a breakdown)
+__global__ __launch_bounds__(256) void k_bi_s(int64_t n, const double* __restrict__ sc, const double* __restrict__ r,
+                                              const double* __restrict__ v, double* __restrict__ s) {
+    if (sc[kBiRv] == 0.0) return;
+    const double alpha = sc[kBiAlpha];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        s[e] = r[e] - alpha * v[e];
+}
+
+// x_e = x_e + alpha * ph_e (the exit after the first half of a step)
+__global__ __launch_bounds__(256) void k_bi_x_half(int64_t n, const double* __restrict__ sc, double* __restrict__ x,
+                                                   const double* __restrict__ ph) {
+    const double alpha = sc[kBiAlpha];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        x[e] = x[e] + alpha * ph[e];
+}
+
+// ts = (t, s), tt = (t, t); omega = ts / tt (tt == 0: breakdown, omega left alone)
+__global__ void k_bi_omega(const double* __restrict__ pts, const double* __restrict__ ptt, double* sc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double ts = tree64(pts), tt = tree64(ptt);
+        sc[kBiTt] = tt;
+        if (tt != 0.0) sc[kBiOmega] = ts / tt;
+    }
+}
+
+// x_e = (x_e + alpha * ph_e) + omega * sh_e; r_e = s_e - omega * t_e (skipped after a breakdown)
+__global__ __launch_bounds__(256) void k_bi_xr(int64_t n, const double* __restrict__ sc, double* __restrict__ x,
+                                               double* __restrict__ r, const double* __restrict__ ph,
+                                               const double* __restrict__ sh, const double* __restrict__ s,
+                                               const double* __restrict__ t) {
+    if (sc[kBiTt] == 0.0) return;
+    const double alpha = sc[kBiAlpha], omega = sc[kBiOmega];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        x[e] = (x[e] + alpha * ph[e]) + omega * sh[e];
+        r[e] = s[e] - omega * t[e];
+    }
+}
+
+namespace {
+int vec_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
+}  // namespace
+
+hipError_t launch_bi(int op, int64_t n, int first, const double* pa, const double* pb, double* sc, double* x,
+                     double* r, const double* a1, const double* a2, const double* a3, const double* a4,
+                     hipStream_t s) {
+    switch (op) {
+        case kBiOpRho:
+            hipLaunchKernelGGL(k_bi_rho, dim3(1), dim3(64), 0, s, pa, sc);
+            break;
+        case kBiOpP:  // r = a1, p = x (in/out), v = a2
+            hipLaunchKernelGGL(k_bi_p, dim3(vec_blocks(n)), dim3(256), 0, s, n, first, sc, a1, x, a2);
+            break;
+        case kBiOpAlpha:
+            hipLaunchKernelGGL(k_bi_alpha, dim3(1), dim3(64), 0, s, pa, sc);
+            break;
+        case kBiOpS:  // r = a1, v = a2, s = x
+            hipLaunchKernelGGL(k_bi_s, dim3(vec_blocks(n)), dim3(256), 0, s, n, sc, a1, a2, x);
+            break;
+        case kBiOpXHalf:  // x, ph = a1
+            hipLaunchKernelGGL(k_bi_x_half, dim3(vec_blocks(n)), dim3(256), 0, s, n, sc, x, a1);
+            break;
+        case kBiOpOmega:
+            hipLaunchKernelGGL(k_bi_omega, dim3(1), dim3(64), 0, s, pa, pb, sc);
+            break;
+        case kBiOpXR:  // x, r, ph = a1, sh = a2, s = a3, t = a4
+            hipLaunchKernelGGL(k_bi_xr, dim3(vec_blocks(n)), dim3(256), 0, s, n, sc, x, r, a1, a2, a3, a4);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

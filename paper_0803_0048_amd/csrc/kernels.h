@@ -200,6 +200,15 @@ hipError_t launch_adj_numeric(const PatDev& P, const AdjPat& T, const double* f_
                               int32_t max_row, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 
+// ---- BiCGSTAB steps ----------------------------------------------------------------------
+// device scalar slots
+enum { kBiRho = 0, kBiRhoOld = 1, kBiAlpha = 2, kBiOmega = 3, kBiRv = 4, kBiTt = 5, kBiSlots = 8 };
+enum { kBiOpRho = 0, kBiOpP = 1, kBiOpAlpha = 2, kBiOpS = 3, kBiOpXHalf = 4, kBiOpOmega = 5, kBiOpXR = 6 };
+// one step of the iteration (see k_krylov.hip for the operands of each op)
+hipError_t launch_bi(int op, int64_t n, int first, const double* pa, const double* pb, double* sc, double* x,
+                     double* r, const double* a1, const double* a2, const double* a3, const double* a4,
+                     hipStream_t s);
+
 // ---- level-based incomplete inverses ---------------------------------------------------
 // per kept entry p of F's pattern: its updates [ptr[p], ptr[p+1]), each the
 // row-local slot of the multiplier (s) and the slot of the partner entry in

@@ -160,7 +160,7 @@ struct tpilu_pattern_s {
     int64_t* tptr = nullptr;
     int32_t *tsl = nullptr, *tq = nullptr;
     // growable workspaces
-    DBuf ws_x, ws_z, ws_fin, ws_lbar, ws_gm;
+    DBuf ws_x, ws_z, ws_fin, ws_lbar, ws_gm, ws_bi;
 
     void* take(size_t bytes) {
         void* p = al.get(bytes);
@@ -188,7 +188,7 @@ struct tpilu_pattern_s {
     }
     ~tpilu_pattern_s() {
         for (auto& b : owned) al.put(b.p);
-        al.put(ws_x.p); al.put(ws_z.p); al.put(ws_fin.p); al.put(ws_lbar.p); al.put(ws_gm.p);
+        al.put(ws_x.p); al.put(ws_z.p); al.put(ws_fin.p); al.put(ws_lbar.p); al.put(ws_gm.p); al.put(ws_bi.p);
     }
 };
 
@@ -1186,6 +1186,137 @@ extern "C" TPILU_API tpilu_status tpilu_gmres_inverse(tpilu_ctx ctx, tpilu_patte
                                                       int32_t restart, int32_t maxit, double rtol,
                                                       int32_t* iters, double* relres, double* hist) {
     return gmres_impl(ctx, pat, a_val, g_val, true, b, x, restart, maxit, rtol, iters, relres, hist);
+}
+
+// =====================================================================================
+// BiCGSTAB
+// =====================================================================================
+extern "C" TPILU_API tpilu_status tpilu_bicgstab(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val,
+                                                 const double* m_val, int32_t inverse, const double* b, double* x,
+                                                 int32_t maxit, double rtol, int32_t* iters, double* relres,
+                                                 double* hist) {
+    tpilu_status st = check_common(ctx, pat, 1);
+    if (st) return st;
+    if (!iters || !relres) return fail(ctx, TPILU_E_INVAL, "null host output");
+    *iters = 0;
+    *relres = 0.0;
+    if (maxit < 0) return fail(ctx, TPILU_E_INVAL, "maxit >= 0 required");
+    const int64_t n = pat->n;
+    if (n == 0) return TPILU_OK;
+    if (!a_val || !m_val || !b || !x) return fail(ctx, TPILU_E_INVAL, "null array");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = ctx->stream;
+    const bool inv = inverse != 0;
+    // workspace: r rs p v ph sv sh t tmp (n each) | 3 partial blocks | scalars
+    const size_t nn = (size_t)n;
+    double* wsd = pat->grow(pat->ws_bi, sizeof(double) * (9 * nn + 3 * kDotBlocks + 16));
+    if (!wsd) return fail(ctx, TPILU_E_NOMEM, "bicgstab workspace");
+    double *r = wsd, *rs = r + nn, *p = rs + nn, *v = p + nn, *ph = v + nn, *sv = ph + nn, *sh = sv + nn,
+           *t = sh + nn, *tmp = t + nn;
+    double *pa = tmp + nn, *pb = pa + kDotBlocks, *pc = pb + kDotBlocks, *sc = pc + kDotBlocks;
+    const int32_t ni = (int32_t)n;
+    auto nrm = [&](const double* vec, double* out_host) -> tpilu_status {
+        HIPCHK(ctx, launch_dot_partial(n, vec, vec, pc, s));
+        HIPCHK(ctx, launch_dot_final(pc, sc + 8, 1, s));
+        HIPCHK(ctx, hipMemcpyAsync(out_host, sc + 8, sizeof(double), hipMemcpyDeviceToHost, s));
+        return TPILU_OK;
+    };
+    double bnorm = 0.0;
+    st = nrm(b, &bnorm);
+    if (st) return st;
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (bnorm == 0.0) {
+        hipLaunchKernelGGL(k_fill_f64, dim3(256), dim3(256), 0, s, x, n, 0.0);
+        HIPCHK(ctx, hipGetLastError());
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        return TPILU_OK;
+    }
+    const double tol = rtol * bnorm;
+    // r = b - A x, rs = r, p = v = 0, rho = alpha = omega = 1
+    HIPCHK(ctx, launch_spmv(ni, pat->rpA, pat->ciA, a_val, x, b, r, s));
+    HIPCHK(ctx, launch_copy(rs, r, n, s));
+    {
+        const double init[8] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 0.0, 0.0};
+        HIPCHK(ctx, hipMemcpyAsync(sc, init, sizeof(init), hipMemcpyHostToDevice, s));
+    }
+    double r0 = 0.0;
+    st = nrm(r, &r0);
+    if (st) return st;
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    int32_t it = 0;
+    bool breakdown = false, first = true, reset = true;
+    if (!(r0 <= tol)) {
+        // rho for the first step
+        HIPCHK(ctx, launch_dot_partial(n, rs, r, pa, s));
+        HIPCHK(ctx, launch_bi(kBiOpRho, n, 0, pa, nullptr, sc, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              nullptr, s));
+        while (it < maxit) {
+            double hs[2] = {0, 0};
+            HIPCHK(ctx, hipMemcpyAsync(hs, sc + kBiRho, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipStreamSynchronize(s));
+            if (hs[0] == 0.0) { breakdown = true; break; }
+            HIPCHK(ctx, launch_bi(kBiOpP, n, first ? 1 : 0, nullptr, nullptr, sc, p, nullptr, r, v, nullptr,
+                                  nullptr, s));
+            first = false;
+            st = enqueue_precond(ctx, pat, m_val, inv, p, ph, tmp, reset);
+            reset = false;
+            if (st) return st;
+            HIPCHK(ctx, launch_spmv(ni, pat->rpA, pat->ciA, a_val, ph, nullptr, v, s));
+            HIPCHK(ctx, launch_dot_partial(n, rs, v, pa, s));
+            HIPCHK(ctx, launch_bi(kBiOpAlpha, n, 0, pa, nullptr, sc, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                  nullptr, s));
+            HIPCHK(ctx, launch_bi(kBiOpS, n, 0, nullptr, nullptr, sc, sv, nullptr, r, v, nullptr, nullptr, s));
+            double snorm = 0.0, rv = 0.0;
+            st = nrm(sv, &snorm);
+            if (st) return st;
+            HIPCHK(ctx, hipMemcpyAsync(&rv, sc + kBiRv, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipStreamSynchronize(s));
+            if (rv == 0.0) { breakdown = true; break; }
+            if (hist) hist[it] = snorm;
+            ++it;
+            if (snorm <= tol || it >= maxit) {
+                HIPCHK(ctx, launch_bi(kBiOpXHalf, n, 0, nullptr, nullptr, sc, x, nullptr, ph, nullptr, nullptr,
+                                      nullptr, s));
+                break;
+            }
+            st = enqueue_precond(ctx, pat, m_val, inv, sv, sh, tmp, false);
+            if (st) return st;
+            HIPCHK(ctx, launch_spmv(ni, pat->rpA, pat->ciA, a_val, sh, nullptr, t, s));
+            HIPCHK(ctx, launch_dot_partial(n, t, sv, pa, s));
+            HIPCHK(ctx, launch_dot_partial(n, t, t, pb, s));
+            HIPCHK(ctx, launch_bi(kBiOpOmega, n, 0, pa, pb, sc, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                  nullptr, s));
+            HIPCHK(ctx, launch_bi(kBiOpXR, n, 0, nullptr, nullptr, sc, x, r, ph, sh, sv, t, s));
+            double rnorm = 0.0;
+            st = nrm(r, &rnorm);
+            if (st) return st;
+            // rho for the next step, read with the residual (rho_old <- rho inside)
+            HIPCHK(ctx, launch_dot_partial(n, rs, r, pa, s));
+            HIPCHK(ctx, launch_bi(kBiOpRho, n, 0, pa, nullptr, sc, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                  nullptr, s));
+            double so[2] = {0, 0};  // tt, omega
+            HIPCHK(ctx, hipMemcpyAsync(&so[0], sc + kBiTt, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipMemcpyAsync(&so[1], sc + kBiOmega, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipStreamSynchronize(s));
+            if (so[0] == 0.0) { breakdown = true; break; }
+            if (hist) hist[it] = rnorm;
+            ++it;
+            if (rnorm <= tol) break;
+            if (so[1] == 0.0) { breakdown = true; break; }
+        }
+    }
+    // true residual
+    HIPCHK(ctx, launch_spmv(ni, pat->rpA, pat->ciA, a_val, x, b, tmp, s));
+    double rn = 0.0;
+    st = nrm(tmp, &rn);
+    if (st) return st;
+    st = read_ctl(ctx, pat, nullptr, false);
+    *iters = it;
+    *relres = rn / bnorm;
+    if (st) return st;
+    if (breakdown) return fail(ctx, TPILU_E_NOTCONV, "BiCGSTAB breakdown");
+    if (!(*relres <= rtol)) return fail(ctx, TPILU_E_NOTCONV, "BiCGSTAB reached maxit");
+    return TPILU_OK;
 }
 
 // =====================================================================================

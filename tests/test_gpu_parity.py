@@ -550,3 +550,31 @@ def test_gmres_inverse_bits():
     assert info["iters"] == ref["iters"]
     assert_bits_equal(np.array(info["hist"]), ref["hist"], "GMRES |g| history (inverse)")
     assert_bits_equal(x, ref["x"], "GMRES x (inverse)")
+
+
+# ----------------------------------------------------------------------------------
+# BiCGSTAB (Sec. 4's Krylov method)
+# ----------------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["c1_ilu", "c1_inverse", "c3k1_ilu", "c2_ilu", "c2_inverse"])
+def test_bicgstab_bits(case):
+    name, prec = case.split("_")
+    c = I.config1() if name == "c1" else (I.config3(k=1) if name == "c3k1" else I.config2())
+    A, k = c["A"], (1 if name != "c2" else c["k"])
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
+    vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
+    pat = T.symbolic(g(A.rowptr), g(A.col), k)
+    f = T.numeric(pat, g(A.val))
+    inv = prec == "inverse"
+    if inv:
+        vM = O.inverse(A.n, rpF, ciF, vF)
+        M = T.inverse(pat, f)
+    else:
+        vM, M = vF, f
+    maxit = 200
+    ref = O.bicgstab(A.n, A.rowptr, A.col, A.val, rpF, ciF, vM, c["b"], maxit=maxit, rtol=1e-8, inverse=inv)
+    x, info = T.bicgstab(pat, g(A.val), M, g(c["b"]), maxit=maxit, rtol=1e-8, inverse=inv)
+    assert info["iters"] == ref["iters"], (info["iters"], ref["iters"])
+    assert info["status"] == ref["status"]
+    assert_bits_equal(np.array(info["hist"]), ref["hist"], "BiCGSTAB residual history")
+    assert_bits_equal(x, ref["x"], "BiCGSTAB x")
+    assert bits(np.array([info["relres"]]))[0] == bits(np.array([ref["relres"]]))[0]
