@@ -318,8 +318,9 @@ def extras(T, I, torch, np, dev, ctx):
 def inverse_extra(T, torch, pat, av, f, bv, restart, rtol, maxit, gmres_ms, ginfo, n, nnz_f, nnz_l):
     """The optional level-based incomplete inverses (Sec. 3.5) on the same
     n=160000 ILU(2) factor: building them, applying M^-1 by two products next
-    to the two substitutions, and GMRES(30) with them next to GMRES(30) with
-    the substitutions.  The products are bandwidth-bound: their roofline."""
+    to the two substitutions, GMRES(30) with them next to GMRES(30) with the
+    substitutions, and BiCGSTAB (the paper's solver) with either.  The
+    products are bandwidth-bound: their roofline."""
     log("incomplete inverses on the n=160000 factor")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     G = T.inverse(pat, f)
@@ -357,7 +358,17 @@ def inverse_extra(T, torch, pat, av, f, bv, restart, rtol, maxit, gmres_ms, ginf
     # written then gathered, y written
     app_bytes = 12 * nnz_f + 8 * (n + 1) + 4 * n + 5 * 8 * n
     gbs = app_bytes / (app_ms * 1e-3) / 1e9
-    return {"inverse_ms": statistics.median(per), "apply_ms": app_ms, "triangular_apply_ms": tri_ms,
+    # BiCGSTAB (the paper's solver) with either preconditioner
+    bi = {}
+    for name, mval, inv in (("substitutions", f, False), ("incomplete_inverse", G, True)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, binfo = T.bicgstab(pat, av, mval, bv, maxit=2 * maxit, rtol=rtol, inverse=inv)
+        torch.cuda.synchronize()
+        bi[name] = {"half_steps": binfo["iters"], "relres": binfo["relres"],
+                    "ms": (time.perf_counter() - t0) * 1e3}
+    return {"bicgstab": bi,
+            "inverse_ms": statistics.median(per), "apply_ms": app_ms, "triangular_apply_ms": tri_ms,
             "apply_speedup": tri_ms / app_ms,
             "apply_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": app_bytes},
