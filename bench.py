@@ -229,6 +229,7 @@ def main():
         out["extras"] = extras(T, I, torch, np, dev, ctx)
         out["extras"]["incomplete_inverse"] = inverse_extra(T, torch, pat, av, fout, bv, restart, rtol, maxit,
                                                             gmres_ms, ginfo, n, nnz_f, nnz_l)
+        out["extras"]["stencil27"] = stencil27_extra(T, I, torch, dev, ctx)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, k, np)
@@ -313,6 +314,48 @@ def extras(T, I, torch, np, dev, ctx):
     res["reverse_mode"] = {"instances": A5.batch, "n": A5.n, "forward_ms": fms, "backward_ms": bms,
                            "backward_over_forward": bms / fms}
     return res
+
+
+def stencil27_extra(T, I, torch, dev, ctx):
+    """The 27-point 3-D stencil of Sec. 4.2 at 50^3 (k = 0..3) and 90^3 (k = 1):
+    symbolic (host clock), numeric and the two solves (HIP events around each
+    kernel, median of 3)."""
+    out = []
+    for m, k in ((50, 0), (50, 1), (50, 2), (50, 3), (90, 1)):
+        log(f"27-point stencil {m}^3 ILU({k})")
+        c = I.config_stencil27(m=m, k=k)
+        A = c["A"]
+        rp = torch.from_numpy(A.rowptr).to(dev)
+        ci = torch.from_numpy(A.col).to(dev)
+        av = torch.from_numpy(A.val).to(dev)
+        bv = torch.from_numpy(c["b"]).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pat = T.symbolic(rp, ci, k)
+        torch.cuda.synchronize()
+        sym_ms = (time.perf_counter() - t0) * 1e3
+        f = T.numeric(pat, av)
+        y = torch.empty_like(bv)
+        T.apply(pat, f, bv, out=y)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        for kk in range(3):
+            ctx.read_timing(kk)
+        num, fwd, bwd = [], [], []
+        for _ in range(3):
+            T.numeric(pat, av, out=f, check=False)
+            T.apply(pat, f, bv, out=y)
+            num.append(ctx.read_timing(ctx.KERNEL_NUMERIC)[0])
+            fwd.append(ctx.read_timing(ctx.KERNEL_FORWARD)[0])
+            bwd.append(ctx.read_timing(ctx.KERNEL_BACKWARD)[0])
+        ctx.set_timing(False)
+        T.check(pat)
+        info = pat.info
+        out.append({"m": m, "k": k, "n": info["n"], "nnz_a": info["nnz_a"], "nnz_f": info["nnz_f"],
+                    "depth_l": info["depth_l"], "symbolic_ms": sym_ms, "numeric_ms": statistics.median(num),
+                    "forward_ms": statistics.median(fwd), "backward_ms": statistics.median(bwd)})
+        del pat, f, y, av, bv, rp, ci
+    return out
 
 
 def inverse_extra(T, torch, pat, av, f, bv, restart, rtol, maxit, gmres_ms, ginfo, n, nnz_f, nnz_l):

@@ -23,6 +23,9 @@ them):
   multiplied by h^2.  With cell Peclet number |b_c| h / (2 eps) > 1 the matrix
   is not diagonally dominant (stand-in for the paper's driven-cavity and 3-D
   stencil problems, Sec. 4.1-4.2).
+* ``stencil27_3d``: the 27-point 3-D stencil (diffusion on all 26 neighbours,
+  convection on the 6 face neighbours), stand-in for the 27-point central
+  differencing problem of Sec. 4.2.
 * ``random_banded``: general sparse non-symmetric matrix, a fixed number of
   off-diagonal columns per row drawn uniformly inside a band plus a few drawn
   anywhere, values U(-1, 1), diagonal 1.1 x the row's absolute sum, so the
@@ -41,6 +44,8 @@ __all__ = [
     "conv_diff_3d",
     "random_banded",
     "random_pattern",
+    "stencil27_3d",
+    "config_stencil27",
     "config1",
     "config2",
     "config3",
@@ -155,6 +160,57 @@ def conv_diff_3d(m: int, eps, bvec) -> CSR:
     rowptr, col, kind, sign = _stencil_pattern((m, m, m))
     val = _stencil_values(kind, sign, np.asarray(eps, dtype=np.float64), np.asarray(bvec, dtype=np.float64), h, 3)
     return CSR(m**3, rowptr, col, val, {"kind": "conv_diff_3d", "m": m, "h": h})
+
+
+def stencil27_3d(m: int, eps: float, bvec) -> CSR:
+    """3-D 27-point stencil on an m^3 grid, natural order: the diffusion part of
+    the 27-point central-difference Laplacian (every one of the 26 neighbours
+    -eps, the diagonal 26 eps) plus central-difference convection b.grad on
+    the six face neighbours (+-b_a h / 2), all times h^2 like the 7-point
+    stencils.  Stand-in for the 27-point central differencing problem of
+    Sec. 4.2 (50^3 to 90^3)."""
+    h = 1.0 / (m + 1)
+    n = m**3
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % m
+    y = (idx // m) % m
+    z = idx // (m * m)
+    bvec = np.asarray(bvec, dtype=np.float64)
+    cols, vals, valid = [], [], []
+    for dz in (-1, 0, 1):  # lexicographic (dz, dy, dx) = ascending column order
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                ok = (x + dx >= 0) & (x + dx < m) & (y + dy >= 0) & (y + dy < m) & (z + dz >= 0) & (z + dz < m)
+                c = idx + dz * m * m + dy * m + dx
+                if dx == dy == dz == 0:
+                    v = np.full(n, 26.0 * eps)
+                else:
+                    v = np.full(n, -eps)
+                    if abs(dx) + abs(dy) + abs(dz) == 1:  # face neighbour: convection
+                        a = 0 if dx else (1 if dy else 2)
+                        v = v + (dx + dy + dz) * bvec[a] * (h / 2.0)
+                cols.append(c)
+                vals.append(v)
+                valid.append(ok)
+    C = np.stack(cols, axis=1)
+    V = np.stack(vals, axis=1)
+    M = np.stack(valid, axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    rowptr[1:] = np.cumsum(M.sum(axis=1))
+    col = C[M].astype(np.int32)
+    val = V[M] * (h * h)
+    return CSR(n, rowptr, col, val, {"kind": "stencil27_3d", "m": m, "h": h})
+
+
+def config_stencil27(m: int = 50, k: int = 1, seed: int = 1006):
+    """3-D 27-point stencil (next-step workload, Sec. 4.2's 50^3 to 90^3),
+    eps = 1, b ~ U[-10, 10]^3 (convection mild enough to keep the diagonal
+    dominant), rhs ~ N(0, 1); ILU(k) for k = 0..3."""
+    rng = np.random.default_rng(seed)
+    bvec = rng.uniform(-10.0, 10.0, size=3)
+    A = stencil27_3d(m, 1.0, bvec)
+    b = rng.standard_normal(A.n)
+    return {"name": f"stencil27_3d_{m}cubed_ilu{k}", "A": A, "b": b, "k": k, "restart": 50, "rtol": 1e-8}
 
 
 def _first_distinct(cand: np.ndarray, forbid: np.ndarray, need: int) -> tuple[np.ndarray, np.ndarray]:

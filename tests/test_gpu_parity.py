@@ -578,3 +578,22 @@ def test_bicgstab_bits(case):
     assert_bits_equal(np.array(info["hist"]), ref["hist"], "BiCGSTAB residual history")
     assert_bits_equal(x, ref["x"], "BiCGSTAB x")
     assert bits(np.array([info["relres"]]))[0] == bits(np.array([ref["relres"]]))[0]
+
+
+# ----------------------------------------------------------------------------------
+# 27-point 3-D stencil (Sec. 4.2's problem), k = 0..3
+# ----------------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_stencil27_small(k):
+    c = I.config_stencil27(m=12, k=k)
+    pat, f, ref = _full(c["A"], k, c["b"])
+    if k == 1:
+        _gmres_parity(pat, (f, ref), c["A"], c["b"], 50, 200, 1e-8)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_stencil27_50cubed(k):
+    """At the paper's smallest size (50^3 = 125,000 rows): pattern, factor and
+    both solves bit for bit."""
+    c = I.config_stencil27(m=50, k=k)
+    _full(c["A"], k, c["b"])
