@@ -117,8 +117,9 @@ enum { TPILU_SOLVER_AUTO = 0, TPILU_SOLVER_DEVICE = 1, TPILU_SOLVER_WORKGROUP = 
 TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode);
 
 /* Kernel of the single-instance numeric factorization: 0 = automatic (the
- * dataflow kernel when the pattern's rows fit its LDS staging and the strict
- * lower part holds at least 4n entries, else the pivot-serial one),
+ * dataflow kernel when the pattern's rows fit its LDS staging, the strict
+ * lower part holds at least 4n entries and an entry receives fewer than 12
+ * updates on average, else the pivot-serial one),
  * 1 = dataflow (lanes own the entries of a row and take
  * their updates in ascending pivot order; a later tpilu_numeric fails with
  * TPILU_E_INVAL if the pattern's rows do not fit), 2 = pivot-serial (the
