@@ -128,6 +128,17 @@ TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode);
 enum { TPILU_NUMERIC_AUTO = 0, TPILU_NUMERIC_FLOW = 1, TPILU_NUMERIC_PIVOT = 2 };
 TPILU_API tpilu_status tpilu_ctx_set_numeric(tpilu_ctx ctx, int mode);
 
+/* Rows per ticket of the kernels that give a wavefront one row at a time
+ * (numeric factorization, wavefront-per-row solves, incomplete inverses):
+ * a wavefront takes `rows` consecutive positions of the dependency-level
+ * order from the shared counter and works through them in order.  0 =
+ * automatic, else 1 to 64.  Automatic: 1 for the numeric factorization
+ * (its kernels overlap a row's work with the wait on earlier levels, which
+ * a group would serialise); for the solves 1, 2 or 3 and for the inverses 1
+ * or 2, growing with the average rows per dependency level.  Same bits for every value;
+ * it only changes speed.  Returns TPILU_E_INVAL outside [0, 64]. */
+TPILU_API tpilu_status tpilu_ctx_set_group(tpilu_ctx ctx, int32_t rows);
+
 /* Kernel timing.  With timing on, the library brackets the main kernel of
  * every numeric factorization, forward solve and backward solve it launches
  * with a pair of hipEvents recorded on the ctx stream (outside graph

@@ -141,6 +141,26 @@ __device__ __forceinline__ uint32_t wave_ticket(Ctl* ctl) {
     return __builtin_amdgcn_readfirstlane(s_ticket);
 }
 
+// Positions of a level order handed out `group` consecutive ones per ticket;
+// the wavefront works through its group in order.  Still deadlock-free: a
+// position only depends on earlier ones, which sit in earlier groups (held by
+// running wavefronts) or earlier in the same group (already done).  Grouping
+// divides the ticket traffic on the one shared counter by `group`; the price
+// is that a group's rows run one after another.
+struct PosRun {
+    uint32_t next = 0, end = 0;
+};
+__device__ __forceinline__ bool next_pos(Ctl* ctl, uint32_t n, uint32_t group, PosRun& r, uint32_t& pos) {
+    if (r.next == r.end) {
+        const uint64_t first = (uint64_t)wave_ticket(ctl) * group;
+        if (first >= n) return false;
+        r.next = (uint32_t)first;
+        r.end = (uint32_t)(first + group < n ? first + group : n);
+    }
+    pos = r.next++;
+    return true;
+}
+
 __device__ __forceinline__ double bcast_lane(double v, int src) {
     uint64_t u = as_u64(v);
     uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(u), src);

@@ -118,9 +118,10 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
     __shared__ uint64_t pr_v[kPairCap];
     const int lane = lane_id();
     const int32_t n = P.n;
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= (uint32_t)n) break;
+        uint32_t t;
+        if (!next_pos(ctl, (uint32_t)n, (uint32_t)P.groupL, run, t)) break;
         const int32_t j = P.permL ? P.permL[t] : (int32_t)t;
         trace_mark(P.trace, j);
         const int64_t rs = P.rpF[j], re = P.rpF[j + 1];
@@ -252,9 +253,10 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
     int32_t* Tb = Sq + cap;                                          // [max_row + 1] chunk offsets
     const int lane = lane_id();
     const int32_t n = P.n;
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= (uint32_t)n) break;
+        uint32_t t;
+        if (!next_pos(ctl, (uint32_t)n, (uint32_t)P.groupL, run, t)) break;
         const int32_t j = P.permL ? P.permL[t] : (int32_t)t;
         trace_mark(P.trace, j);
         const int64_t rs = P.rpF[j], re = P.rpF[j + 1];

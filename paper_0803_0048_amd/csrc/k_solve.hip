@@ -75,9 +75,10 @@ __device__ __forceinline__ void backward_row(const PatDev& P, const double* __re
 __global__ __launch_bounds__(64) void k_forward_row(PatDev P, const double* __restrict__ F,
                                                     const double* __restrict__ b, double* x,
                                                     Ctl* ctl, uint64_t spin_limit) {
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= (uint32_t)P.n) break;
+        uint32_t t;
+        if (!next_pos(ctl, (uint32_t)P.n, (uint32_t)P.groupL, run, t)) break;
         forward_row<Scope::Device>(P, F, b, x, ctl, spin_limit, P.permL ? P.permL[t] : (int32_t)t);
     }
 }
@@ -85,9 +86,10 @@ __global__ __launch_bounds__(64) void k_forward_row(PatDev P, const double* __re
 __global__ __launch_bounds__(64) void k_backward_row(PatDev P, const double* __restrict__ F,
                                                      const double* __restrict__ x, double* y,
                                                      Ctl* ctl, uint64_t spin_limit) {
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= (uint32_t)P.n) break;
+        uint32_t t;
+        if (!next_pos(ctl, (uint32_t)P.n, (uint32_t)P.groupU, run, t)) break;
         backward_row<Scope::Device>(P, F, x, y, ctl, spin_limit, P.permU ? P.permU[t] : P.n - 1 - (int32_t)t);
     }
 }

@@ -29,6 +29,7 @@ struct tpilu_ctx_s {
     int32_t grid_override = 0;
     int solver = 0;  // 0 auto, 1 wavefront per row, 2 one workgroup, 3 lane per row
     int numeric = 0;  // 0 auto, 1 dataflow, 2 pivot-serial
+    int32_t group = 0;  // level-order positions per ticket of the row kernels; 0 auto
     bool timing = false;
     unsigned long long* trace = nullptr;  // per-row timeline buffer (device, 2n), or null
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
@@ -124,6 +125,24 @@ struct DeviceGuard {
 
 }  // namespace
 
+// Level-order positions a wavefront takes per ticket in the wavefront-per-row
+// kernels.  Every ticket is one atomic on one address (about 11 ns each,
+// serialised), which on wide levels caps how fast rows can be handed out;
+// grouping divides that traffic but runs a group's rows back to back.  The
+// numeric kernels overlap a row's work with its wait on earlier levels, so
+// there a group costs a whole row time per level (c2: 8.5 -> 147 ms at 2
+// rows): always 1.  Solves and inverses gain on wide levels (7-point 64^3,
+// ILU(1), 692 rows per level: wavefront-per-row forward 5.5 -> 3.3 ms at 3
+// rows, inverse 6.6 -> 4.0 ms at 2 rows) and lose on narrow ones.
+enum class RowKernel { Numeric, Solve, Inverse };
+
+int32_t row_group(RowKernel kind, int64_t n, int64_t depth) {
+    if (depth <= 0 || kind == RowKernel::Numeric) return 1;
+    const int64_t width = std::max<int64_t>(n, 1) / depth;
+    if (kind == RowKernel::Solve) return width >= 512 ? 3 : width >= 128 ? 2 : 1;
+    return width >= 512 ? 2 : 1;
+}
+
 struct tpilu_pattern_s {
     Alloc al;
     int device = 0;
@@ -178,9 +197,11 @@ struct tpilu_pattern_s {
         b.bytes = b.p ? bytes : 0;
         return static_cast<double*>(b.p);
     }
-    PatDev dev(unsigned long long* trace = nullptr) const {
+    PatDev dev(unsigned long long* trace = nullptr, RowKernel kind = RowKernel::Numeric, int32_t group = 0) const {
         PatDev d;
         d.trace = trace;
+        d.groupL = group ? group : row_group(kind, n, depth_l);
+        d.groupU = group ? group : row_group(kind, n, depth_u);
         d.n = (int32_t)n;
         d.nnz_a = (int32_t)nnz_a;
         d.nnz_f = (int32_t)nnz_f;
@@ -195,6 +216,10 @@ struct tpilu_pattern_s {
         al.put(ws_x.p); al.put(ws_z.p); al.put(ws_fin.p); al.put(ws_lbar.p); al.put(ws_gm.p); al.put(ws_bi.p);
     }
 };
+
+PatDev pdev(tpilu_ctx ctx, tpilu_pattern pat, RowKernel kind = RowKernel::Numeric, bool trace = false) {
+    return pat->dev(trace ? ctx->trace : nullptr, kind, ctx->group);
+}
 
 struct tpilu_graph_s {
     hipGraph_t graph = nullptr;
@@ -312,8 +337,9 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
                                     numeric_grid(batch, pat->st.max_row, pat->st.max_lrow, flow, ctx->num_cu));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_NUMERIC);
-        HIPCHK(ctx, launch_numeric(pat->dev(ctx->trace), a_val, batch, f_val, pat->ctl, ctx->spin_limit,
-                                   ctx->skip_row, grid, pat->st.max_row, pat->st.max_lrow, flow, ctx->stream));
+        HIPCHK(ctx, launch_numeric(pdev(ctx, pat, RowKernel::Numeric, true), a_val, batch, f_val, pat->ctl,
+                                   ctx->spin_limit, ctx->skip_row, grid, pat->st.max_row, pat->st.max_lrow, flow,
+                                   ctx->stream));
     }
     return TPILU_OK;
 }
@@ -348,17 +374,16 @@ int32_t solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool backwa
 tpilu_status enqueue_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val, int32_t batch,
                            const double* b, double* y, double* x, bool reset) {
     const int32_t gf = solve_shape(ctx, pat, batch, false), gb = solve_shape(ctx, pat, batch, true);
+    const PatDev P = pdev(ctx, pat, RowKernel::Solve, true);
     HIPCHK(ctx, launch_fill_pending(x, pat->n * batch, pat->ctl, reset, ctx->stream));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_FORWARD);
-        HIPCHK(ctx, launch_forward(pat->dev(ctx->trace), f_val, batch, b, x, pat->ctl, ctx->spin_limit, gf,
-                                   ctx->stream));
+        HIPCHK(ctx, launch_forward(P, f_val, batch, b, x, pat->ctl, ctx->spin_limit, gf, ctx->stream));
     }
     HIPCHK(ctx, launch_fill_pending(y, pat->n * batch, pat->ctl, false, ctx->stream));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_BACKWARD);
-        HIPCHK(ctx, launch_backward(pat->dev(ctx->trace), f_val, batch, x, y, pat->ctl, ctx->spin_limit, gb,
-                                    ctx->stream));
+        HIPCHK(ctx, launch_backward(P, f_val, batch, x, y, pat->ctl, ctx->spin_limit, gb, ctx->stream));
     }
     return TPILU_OK;
 }
@@ -624,6 +649,13 @@ extern "C" TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t wave
     if (!ctx) return TPILU_E_INVAL;
     if (waves < 0) return fail(ctx, TPILU_E_INVAL, "waves must be >= 0");
     ctx->grid_override = waves;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_group(tpilu_ctx ctx, int32_t rows) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (rows < 0 || rows > 64) return fail(ctx, TPILU_E_INVAL, "rows per ticket must be in [0, 64]");
+    ctx->group = rows;
     return TPILU_OK;
 }
 
@@ -1007,10 +1039,11 @@ extern "C" TPILU_API tpilu_status tpilu_inverse(tpilu_ctx ctx, tpilu_pattern pat
     hipStream_t s = ctx->stream;
     const InvSched S{pat->iptr, pat->is_s, pat->is_q};
     const int grid = ctx->grid_override ? ctx->grid_override : kInverseWaves;
+    const PatDev P = pdev(ctx, pat, RowKernel::Inverse);
     HIPCHK(ctx, launch_fill_pending(g_val, pat->nnz_f, pat->ctl, true, s));
-    HIPCHK(ctx, launch_inverse(pat->dev(), S, f_val, g_val, false, pat->ctl, ctx->spin_limit, grid, s));
+    HIPCHK(ctx, launch_inverse(P, S, f_val, g_val, false, pat->ctl, ctx->spin_limit, grid, s));
     HIPCHK(ctx, launch_fill_pending(nullptr, 0, pat->ctl, false, s));
-    HIPCHK(ctx, launch_inverse(pat->dev(), S, f_val, g_val, true, pat->ctl, ctx->spin_limit, grid, s));
+    HIPCHK(ctx, launch_inverse(P, S, f_val, g_val, true, pat->ctl, ctx->spin_limit, grid, s));
     return read_ctl(ctx, pat, nullptr, false);
 }
 
@@ -1028,7 +1061,7 @@ extern "C" TPILU_API tpilu_status tpilu_apply_inverse(tpilu_ctx ctx, tpilu_patte
         x = pat->grow(pat->ws_x, sizeof(double) * (size_t)pat->n);
         if (!x) return fail(ctx, TPILU_E_NOMEM, "apply workspace");
     }
-    HIPCHK(ctx, launch_apply_inverse(pat->dev(), g_val, b, x, y, inverse_thread_rows(ctx, pat), ctx->stream));
+    HIPCHK(ctx, launch_apply_inverse(pdev(ctx, pat), g_val, b, x, y, inverse_thread_rows(ctx, pat), ctx->stream));
     return TPILU_OK;
 }
 
@@ -1074,7 +1107,7 @@ tpilu_status enqueue_precond(tpilu_ctx ctx, tpilu_pattern pat, const double* m_v
                              const double* v, double* z, double* t, bool reset) {
     if (!inverse) return enqueue_apply(ctx, pat, m_val, 1, v, z, t, reset);
     if (reset) HIPCHK(ctx, launch_fill_pending(nullptr, 0, pat->ctl, true, ctx->stream));
-    HIPCHK(ctx, launch_apply_inverse(pat->dev(), m_val, v, t, z, inverse_thread_rows(ctx, pat), ctx->stream));
+    HIPCHK(ctx, launch_apply_inverse(pdev(ctx, pat), m_val, v, t, z, inverse_thread_rows(ctx, pat), ctx->stream));
     return TPILU_OK;
 }
 
@@ -1358,10 +1391,10 @@ extern "C" TPILU_API tpilu_status tpilu_apply_adjoint(tpilu_ctx ctx, tpilu_patte
     AdjPat T{pat->tpL, pat->tsL, pat->trL, pat->tpU, pat->tsU, pat->trU, pat->permUT, pat->permLT};
     const int grid = ctx->grid_override ? ctx->grid_override : kAdjointWaves;
     HIPCHK(ctx, launch_fill_pending(z, pat->n * batch, pat->ctl, true, s));
-    HIPCHK(ctx, launch_adj_solve_u(pat->dev(), T, f_val, batch, ybar, z, pat->ctl, ctx->spin_limit, grid, s));
+    HIPCHK(ctx, launch_adj_solve_u(pdev(ctx, pat), T, f_val, batch, ybar, z, pat->ctl, ctx->spin_limit, grid, s));
     HIPCHK(ctx, launch_fill_pending(bbar, pat->n * batch, pat->ctl, false, s));
-    HIPCHK(ctx, launch_adj_solve_l(pat->dev(), T, f_val, batch, z, bbar, pat->ctl, ctx->spin_limit, grid, s));
-    HIPCHK(ctx, launch_adj_fbar(pat->dev(), batch, x, y, z, bbar, fbar, s));
+    HIPCHK(ctx, launch_adj_solve_l(pdev(ctx, pat), T, f_val, batch, z, bbar, pat->ctl, ctx->spin_limit, grid, s));
+    HIPCHK(ctx, launch_adj_fbar(pdev(ctx, pat), batch, x, y, z, bbar, fbar, s));
     return TPILU_OK;
 }
 
@@ -1386,7 +1419,7 @@ extern "C" TPILU_API tpilu_status tpilu_numeric_adjoint(tpilu_ctx ctx, tpilu_pat
     HIPCHK(ctx, launch_fill_pending(fbar, nfb, pat->ctl, true, s));
     HIPCHK(ctx, launch_fill_pending(lbar, nfb, pat->ctl, false, s));
     const int grid = ctx->grid_override ? ctx->grid_override : kAdjointWaves;
-    HIPCHK(ctx, launch_adj_numeric(pat->dev(), T, f_val, batch, fin, fbar, lbar, abar, pat->ctl,
+    HIPCHK(ctx, launch_adj_numeric(pdev(ctx, pat), T, f_val, batch, fin, fbar, lbar, abar, pat->ctl,
                                    ctx->spin_limit, grid, pat->st.max_row, s));
     return TPILU_OK;
 }

@@ -27,6 +27,7 @@ def _gpu_guard(request):
     ctx.set_grid(0)
     ctx.set_solver(0)
     ctx.set_numeric(0)
+    ctx.set_group(0)
     ctx.set_watchdog(0, -1)
     yield
     torch.cuda.synchronize()
@@ -221,15 +222,48 @@ def test_repeatable_across_launch_shapes():
     ref_y = T.apply(pat, ref_f, bv)
     for solver in (ctx.SOLVER_DEVICE, ctx.SOLVER_WORKGROUP, ctx.SOLVER_LANES):
         ctx.set_solver(solver)
-        for waves in (1, 2, 7, 64, 1000, 0, 40000):
+        for waves, group in ((1, 1), (2, 3), (7, 0), (64, 64), (1000, 2), (0, 0), (40000, 5)):
             ctx.set_grid(waves)
+            ctx.set_group(group)
             for _ in range(3):
                 f = T.numeric(pat, av)
                 y = T.apply(pat, f, bv)
-                assert torch.equal(f.view(torch.int64), ref_f.view(torch.int64)), (solver, waves)
-                assert torch.equal(y.view(torch.int64), ref_y.view(torch.int64)), (solver, waves)
+                assert torch.equal(f.view(torch.int64), ref_f.view(torch.int64)), (solver, waves, group)
+                assert torch.equal(y.view(torch.int64), ref_y.view(torch.int64)), (solver, waves, group)
     ctx.set_grid(0)
+    ctx.set_group(0)
     ctx.set_solver(0)
+
+
+@pytest.mark.parametrize("cfg", ["c3k1", "s27k1"])
+def test_row_groups_agree_full_size(cfg):
+    """Rows per ticket of the row kernels (numeric, wavefront-per-row solves,
+    inverses): the oracle's bits for every group size."""
+    c = I.config3(k=1) if cfg == "c3k1" else I.config_stencil27(m=50, k=1)
+    A, b, k = c["A"], c["b"], 1
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
+    vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
+    x_ref, y_ref = O.apply(A.n, rpF, ciF, vF, b)
+    vG = O.inverse(A.n, rpF, ciF, vF)
+    pat = T.symbolic(g(A.rowptr), g(A.col), k)
+    ctx = T.context(0)
+    modes = [ctx.NUMERIC_PIVOT] + ([ctx.NUMERIC_FLOW] if pat.info["flow_ready"] else [])
+    try:
+        ctx.set_solver(ctx.SOLVER_DEVICE)
+        for group in (1, 2, 5, 8, 64):
+            ctx.set_group(group)
+            for mode in modes:
+                ctx.set_numeric(mode)
+                f = T.numeric(pat, g(A.val))
+                assert_bits_equal(f, vF, f"F group {group} kernel {mode}")
+            y, x = T.apply(pat, f, g(b), return_x=True)
+            assert_bits_equal(x, x_ref, f"x group {group}")
+            assert_bits_equal(y, y_ref, f"y group {group}")
+            assert_bits_equal(T.inverse(pat, f), vG, f"G group {group}")
+    finally:
+        ctx.set_group(0)
+        ctx.set_numeric(0)
+        ctx.set_solver(0)
 
 
 @pytest.mark.parametrize("cfg", ["c2", "c3k1"])
