@@ -107,7 +107,8 @@ TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t waves);
 
 /* Launch shape of the single-instance triangular solves: 0 = automatic
  * (lane per row when a triangle's rows hold at most 40 entries on average
- * and a dependency level at least 64 rows, else a wavefront per row), 1 = a wavefront per row over the whole device,
+ * and a dependency level at least max(64, 16 x that average) rows, else a
+ * wavefront per row), 1 = a wavefront per row over the whole device,
  * 2 = one workgroup (16 wavefronts on one CU), 3 = a lane per row (64 rows per
  * wavefront) over the whole device.  The same setting picks the shape of the
  * two products of tpilu_apply_inverse: 1 a wavefront per row, 3 a thread per
@@ -118,8 +119,9 @@ TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode);
 
 /* Kernel of the single-instance numeric factorization: 0 = automatic (the
  * dataflow kernel when the pattern's rows fit its LDS staging, the strict
- * lower part holds at least 4n entries and an entry receives fewer than 12
- * updates on average, else the pivot-serial one),
+ * lower part holds at least 4n entries, an entry receives fewer than 12
+ * updates on average and a dependency level holds fewer than 64 rows on
+ * average, else the pivot-serial one),
  * 1 = dataflow (lanes own the entries of a row and take
  * their updates in ascending pivot order; a later tpilu_numeric fails with
  * TPILU_E_INVAL if the pattern's rows do not fit), 2 = pivot-serial (the
@@ -138,6 +140,13 @@ TPILU_API tpilu_status tpilu_ctx_set_numeric(tpilu_ctx ctx, int mode);
  * or 2, growing with the average rows per dependency level.  Same bits for every value;
  * it only changes speed.  Returns TPILU_E_INVAL outside [0, 64]. */
 TPILU_API tpilu_status tpilu_ctx_set_group(tpilu_ctx ctx, int32_t rows);
+
+/* Task counters the same kernels draw their groups of rows from: groups are
+ * dealt round robin to `counters` counters on separate cache lines, so that
+ * wide dependency levels are not held up by the atomics on one address.
+ * 0 = automatic, else 1 to 8 (never more than the launch's wavefronts).
+ * Same bits for every value.  Returns TPILU_E_INVAL outside [0, 8]. */
+TPILU_API tpilu_status tpilu_ctx_set_tickets(tpilu_ctx ctx, int32_t counters);
 
 /* Kernel timing.  With timing on, the library brackets the main kernel of
  * every numeric factorization, forward solve and backward solve it launches

@@ -20,7 +20,7 @@ OK, E_INVAL, E_NOMEM, E_ZEROPIVOT, E_DEVICE, E_NOTCONV, E_TIMEOUT = range(7)
 
 EXPORTED = [
     "tpilu_ctx_create", "tpilu_ctx_set_stream", "tpilu_ctx_destroy", "tpilu_status_string",
-    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_numeric", "tpilu_ctx_set_group", "tpilu_inverse", "tpilu_apply_inverse", "tpilu_gmres_inverse", "tpilu_bicgstab", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
+    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_numeric", "tpilu_ctx_set_group", "tpilu_ctx_set_tickets", "tpilu_inverse", "tpilu_apply_inverse", "tpilu_gmres_inverse", "tpilu_bicgstab", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
     "tpilu_pattern_export", "tpilu_pattern_destroy", "tpilu_numeric", "tpilu_pattern_check",
     "tpilu_apply", "tpilu_gmres", "tpilu_spmv", "tpilu_dot", "tpilu_apply_adjoint",
     "tpilu_numeric_adjoint", "tpilu_batched_graph_create", "tpilu_batched_graph_launch",
@@ -72,6 +72,7 @@ def load_library():
             "tpilu_ctx_set_solver": ([P, C.c_int], st),
             "tpilu_ctx_set_numeric": ([P, C.c_int], st),
             "tpilu_ctx_set_group": ([P, C.c_int32], st),
+            "tpilu_ctx_set_tickets": ([P, C.c_int32], st),
             "tpilu_ctx_set_trace": ([P, P], st),
             "tpilu_ctx_set_timing": ([P, C.c_int], st),
             "tpilu_ctx_read_timing": ([P, C.c_int, C.POINTER(dbl), C.POINTER(i64)], st),
@@ -161,6 +162,11 @@ class Context:
         """Level-order rows per ticket of the wavefront-per-row kernels
         (0 automatic, else 1..64); same bits for every value."""
         self.check(load_library().tpilu_ctx_set_group(self.h, rows), "set_group")
+
+    def set_tickets(self, counters: int = 0):
+        """Task counters of the wavefront-per-row kernels (0 automatic, else
+        1..8); same bits for every value."""
+        self.check(load_library().tpilu_ctx_set_tickets(self.h, counters), "set_tickets")
 
     def set_trace(self, buf=None):
         """Per-row timeline: a uint64/int64 device tensor of 4n entries, or None."""

@@ -38,12 +38,20 @@ constexpr int kWave = 64;
 constexpr uint32_t kStTimeout = 1u;
 constexpr uint32_t kStReservedNaN = 2u;
 
+// Counters of the row kernels' level-order positions, each on its own 256-byte
+// line: one counter serialises its atomics (about 11 ns each), several on
+// separate lines proceed in parallel.
+constexpr int kTicketParts = 8;
+constexpr int kTicketStride = 64;  // uint32 words between two counters
+
 struct Ctl {
     uint32_t ticket;        // next task of the running persistent kernel
     uint32_t abort;         // set once any wait ran out
     uint32_t status;        // kSt* bits
     uint32_t pad;
     unsigned long long bad_row;  // smallest row with a zero final pivot, or ~0
+    uint32_t pad2[58];
+    uint32_t part[kTicketParts * kTicketStride];  // position counters (next_pos)
 };
 
 __device__ __forceinline__ uint64_t as_u64(double d) { return __builtin_bit_cast(uint64_t, d); }
@@ -141,18 +149,33 @@ __device__ __forceinline__ uint32_t wave_ticket(Ctl* ctl) {
     return __builtin_amdgcn_readfirstlane(s_ticket);
 }
 
-// Positions of a level order handed out `group` consecutive ones per ticket;
-// the wavefront works through its group in order.  Still deadlock-free: a
-// position only depends on earlier ones, which sit in earlier groups (held by
-// running wavefronts) or earlier in the same group (already done).  Grouping
-// divides the ticket traffic on the one shared counter by `group`; the price
-// is that a group's rows run one after another.
+// Positions of a level order handed to wavefronts `group` consecutive ones at a
+// time, the wavefront working through its group in order.  Groups are dealt
+// round robin to `parts` counters (group g to counter g mod parts; wavefront
+// w draws from counter w mod parts), so that wide levels are not held up by
+// one counter.  Deadlock-free: a position only depends on earlier ones.  The
+// smallest unfinished position is either held by a running wavefront, which
+// has finished everything before it in its group and so is working on it,
+// or not yet drawn; then every wavefront of its counter holds only smaller,
+// finished positions of that counter (a counter deals in increasing order)
+// and will draw it next.  Every counter has at least one wavefront
+// (parts <= grid), and the waves that are not resident yet only wait for
+// resident ones to finish, which needs nothing from them.
 struct PosRun {
     uint32_t next = 0, end = 0;
 };
-__device__ __forceinline__ bool next_pos(Ctl* ctl, uint32_t n, uint32_t group, PosRun& r, uint32_t& pos) {
+__device__ __forceinline__ bool next_pos(Ctl* ctl, uint32_t n, uint32_t group, uint32_t parts, PosRun& r,
+                                         uint32_t& pos) {
     if (r.next == r.end) {
-        const uint64_t first = (uint64_t)wave_ticket(ctl) * group;
+        __shared__ uint32_t s_ticket;
+        if (parts > gridDim.x) parts = gridDim.x;
+        if (parts == 0) parts = 1;
+        const uint32_t x = blockIdx.x % parts;
+        __syncthreads();
+        if (lane_id() == 0) s_ticket = atomicAdd(&ctl->part[x * kTicketStride], 1u);
+        __syncthreads();
+        const uint64_t v = __builtin_amdgcn_readfirstlane(s_ticket);
+        const uint64_t first = (v * parts + x) * group;
         if (first >= n) return false;
         r.next = (uint32_t)first;
         r.end = (uint32_t)(first + group < n ? first + group : n);

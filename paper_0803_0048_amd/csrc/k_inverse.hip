@@ -116,7 +116,7 @@ __global__ __launch_bounds__(64) void k_inverse(PatDev P, InvSched S, const doub
     PosRun run;
     for (;;) {
         uint32_t tk;
-        if (!next_pos(ctl, (uint32_t)n, (uint32_t)(kUpper ? P.groupU : P.groupL), run, tk)) break;
+        if (!next_pos(ctl, (uint32_t)n, (uint32_t)(kUpper ? P.groupU : P.groupL), (uint32_t)P.parts, run, tk)) break;
         const int32_t i = perm ? perm[tk] : (kUpper ? n - 1 - (int32_t)tk : (int32_t)tk);
         const int64_t rs = P.rpF[i], dj = P.diagF[i];
         const int64_t p0 = kUpper ? dj : rs, p1 = kUpper ? P.rpF[i + 1] : dj;

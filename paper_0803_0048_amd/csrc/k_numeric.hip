@@ -21,6 +21,7 @@
 namespace tpilu {
 
 __global__ void k_fill_pending(double* __restrict__ p, int64_t n, Ctl* ctl, int reset_status) {
+    if (blockIdx.x == 0 && threadIdx.x < kTicketParts) ctl->part[threadIdx.x * kTicketStride] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->ticket = 0;
         if (reset_status) {
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, (uint32_t)n, (uint32_t)P.groupL, run, t)) break;
+        if (!next_pos(ctl, (uint32_t)n, (uint32_t)P.groupL, (uint32_t)P.parts, run, t)) break;
         const int32_t j = P.permL ? P.permL[t] : (int32_t)t;
         trace_mark(P.trace, j);
         const int64_t rs = P.rpF[j], re = P.rpF[j + 1];
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, (uint32_t)n, (uint32_t)P.groupL, run, t)) break;
+        if (!next_pos(ctl, (uint32_t)n, (uint32_t)P.groupL, (uint32_t)P.parts, run, t)) break;
         const int32_t j = P.permL ? P.permL[t] : (int32_t)t;
         trace_mark(P.trace, j);
         const int64_t rs = P.rpF[j], re = P.rpF[j + 1];

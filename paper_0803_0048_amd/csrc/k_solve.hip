@@ -78,7 +78,7 @@ __global__ __launch_bounds__(64) void k_forward_row(PatDev P, const double* __re
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, (uint32_t)P.n, (uint32_t)P.groupL, run, t)) break;
+        if (!next_pos(ctl, (uint32_t)P.n, (uint32_t)P.groupL, (uint32_t)P.parts, run, t)) break;
         forward_row<Scope::Device>(P, F, b, x, ctl, spin_limit, P.permL ? P.permL[t] : (int32_t)t);
     }
 }
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64) void k_backward_row(PatDev P, const double* __r
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, (uint32_t)P.n, (uint32_t)P.groupU, run, t)) break;
+        if (!next_pos(ctl, (uint32_t)P.n, (uint32_t)P.groupU, (uint32_t)P.parts, run, t)) break;
         backward_row<Scope::Device>(P, F, x, y, ctl, spin_limit, P.permU ? P.permU[t] : P.n - 1 - (int32_t)t);
     }
 }

@@ -105,6 +105,7 @@ struct PatDev {
     const int32_t* permL;       // nullable: rows in order of forward dependency level
     const int32_t* permU;       // nullable: rows in order of backward dependency level
     int32_t groupL, groupU;     // positions of permL / permU per ticket (>= 1)
+    int32_t parts;              // position counters the row kernels draw from (1..kTicketParts, <= grid)
     const int64_t* tptr;  // per F slot: start of the updates it receives; [nnz_f + 1]
     const int32_t* tsl;   // update: row-local slot of the pivot entry f_jh (ascending h per target)
     const int32_t* tq;    // update: slot of f_ht in row h

@@ -30,6 +30,7 @@ struct tpilu_ctx_s {
     int solver = 0;  // 0 auto, 1 wavefront per row, 2 one workgroup, 3 lane per row
     int numeric = 0;  // 0 auto, 1 dataflow, 2 pivot-serial
     int32_t group = 0;  // level-order positions per ticket of the row kernels; 0 auto
+    int32_t tickets = 0;  // position counters of the row kernels; 0 auto
     bool timing = false;
     unsigned long long* trace = nullptr;  // per-row timeline buffer (device, 2n), or null
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
@@ -62,8 +63,16 @@ constexpr int32_t kSolveWavesNarrow = 192;
 constexpr int32_t kSolveWavesWide = 256;
 constexpr int32_t kNumericWaves = 1024;
 constexpr int32_t kFlowWaves = 1024;
-constexpr int64_t kFlowMinL = 4;      // dataflow numeric when L rows average at least this many entries
-constexpr int64_t kFlowMaxChain = 12;  // ... and an entry receives fewer than this many updates on average
+// Dataflow numeric kernel (automatic choice) when the L rows average at least
+// kFlowMinL entries, an entry receives fewer than kFlowMaxChain updates on
+// average and a dependency level holds fewer than kFlowMaxWidth rows.  On
+// narrow graphs the dataflow kernel's short hand-off wins (random banded
+// n=160,000: ILU(1) 1.4 vs 4.8 ms, ILU(2) 8.5 vs 21 ms); on wide ones the
+// pivot-serial kernel's cheaper rows do (27-point 30^3 ILU(1), 71 rows per
+// level: 1.4 vs 2.1 ms; 7-point 64^3 ILU(2): 3.0 vs 4.3 ms).
+constexpr int64_t kFlowMinL = 4;
+constexpr int64_t kFlowMaxChain = 12;
+constexpr int64_t kFlowMaxWidth = 64;
 constexpr int32_t kAdjointWaves = 512;
 constexpr int32_t kInverseWaves = 512;
 constexpr int64_t kNarrowWidth = 64;   // n / depth below this: narrow
@@ -143,6 +152,9 @@ int32_t row_group(RowKernel kind, int64_t n, int64_t depth) {
     return width >= 512 ? 2 : 1;
 }
 
+// Position counters the row kernels draw from (see next_pos).
+int32_t ticket_parts(RowKernel, int64_t, int64_t) { return kTicketParts; }
+
 struct tpilu_pattern_s {
     Alloc al;
     int device = 0;
@@ -197,9 +209,11 @@ struct tpilu_pattern_s {
         b.bytes = b.p ? bytes : 0;
         return static_cast<double*>(b.p);
     }
-    PatDev dev(unsigned long long* trace = nullptr, RowKernel kind = RowKernel::Numeric, int32_t group = 0) const {
+    PatDev dev(unsigned long long* trace = nullptr, RowKernel kind = RowKernel::Numeric, int32_t group = 0,
+               int32_t tickets = 0) const {
         PatDev d;
         d.trace = trace;
+        d.parts = tickets ? tickets : ticket_parts(kind, n, depth_l);
         d.groupL = group ? group : row_group(kind, n, depth_l);
         d.groupU = group ? group : row_group(kind, n, depth_u);
         d.n = (int32_t)n;
@@ -218,7 +232,7 @@ struct tpilu_pattern_s {
 };
 
 PatDev pdev(tpilu_ctx ctx, tpilu_pattern pat, RowKernel kind = RowKernel::Numeric, bool trace = false) {
-    return pat->dev(trace ? ctx->trace : nullptr, kind, ctx->group);
+    return pat->dev(trace ? ctx->trace : nullptr, kind, ctx->group, ctx->tickets);
 }
 
 struct tpilu_graph_s {
@@ -328,7 +342,8 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
     // 8.3 ms dataflow vs 25 ms pivot-serial; 27-point 50^3 ILU(2) and ILU(3)
     // (16.5 and 26 per entry) 21 and 41 ms dataflow vs 12 and 21 ms.
     const bool auto_flow = (int64_t)pat->st.nnz_l >= kFlowMinL * pat->n &&
-                           pat->n_updates < kFlowMaxChain * pat->nnz_f;
+                           pat->n_updates < kFlowMaxChain * pat->nnz_f &&
+                           pat->n < kFlowMaxWidth * std::max<int64_t>(pat->depth_l, 1);
     const bool flow = batch == 1 && pat->flow && (ctx->numeric == 1 || (ctx->numeric == 0 && auto_flow));
     HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, pat->ctl, true, ctx->stream));
     const int grid = ctx->grid_override
@@ -348,14 +363,19 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
 // argument of launch_forward / launch_backward): > 0 wavefront per row with
 // that many wavefronts, 0 one workgroup, < 0 lane per row with -grid
 // wavefronts.  Automatic choice: lane per row when the rows are short and a
-// dependency level holds at least a wavefront's worth of rows (a lane runs a
-// whole chain, and one ticket covers 64 rows), else a wavefront per row; few
-// rows per level want fewer wavefronts (hand-offs dominate), many rows more.
-// Measured: 64^3 7-point stencils ILU(0..3) 2-9x faster by lane, the random
-// banded n=160,000 ILU(2) (82 entries per row half) 3x slower, the 64^2
-// stencil (21 rows per level) 1.3x slower.
+// dependency level is wide next to the row length (a lane runs a whole row
+// alone, so it needs many rows per level to beat 64 lanes on one row),
+// namely rows per level >= max(64, 16 x average entries per row half); else
+// a wavefront per row; few rows per level want fewer wavefronts (hand-offs
+// dominate), many rows more.  Measured on MI355X: 7-point 64^3 ILU(1) (692
+// rows per level, 6 entries per half) 0.8 vs 2.1 ms by lane; 27-point 90^3
+// ILU(1) (630 rows, 30 entries) 6.3 vs 8.2 ms by lane; 27-point 70^3 ILU(1)
+// (382 rows, 30 entries) 3.9 vs 4.3 ms by wavefront; 27-point 30^3 ILU(1)
+// (71 rows) 0.46 vs 1.6 ms by wavefront; random banded n=160,000 ILU(2) (82
+// entries per half) 3x faster by wavefront.
 constexpr int64_t kLaneMaxAvg = 40;    // average entries per row half at or below
 constexpr int64_t kLaneMinWidth = 64;  // rows per dependency level at or above
+constexpr int64_t kLaneWidthPerEntry = 16;  // ... and at or above this many per entry of a row half
 constexpr int32_t kLaneWaves = 128;
 
 int32_t solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool backward) {
@@ -364,7 +384,12 @@ int32_t solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool backwa
     const int64_t half = backward ? pat->nnz_f - (int64_t)pat->st.nnz_l - pat->n : (int64_t)pat->st.nnz_l;
     const int64_t depth = std::max<int64_t>(1, backward ? pat->depth_u : pat->depth_l);
     int mode = ctx->solver;
-    if (mode == 0) mode = (half <= kLaneMaxAvg * n && n / depth >= kLaneMinWidth) ? 3 : 1;
+    if (mode == 0) {
+        const int64_t width = n / depth;
+        const bool lanes = half <= kLaneMaxAvg * n && width >= kLaneMinWidth &&
+                           width * n >= kLaneWidthPerEntry * half;
+        mode = lanes ? 3 : 1;
+    }
     if (mode == 2) return 0;
     if (mode == 3) return -(ctx->grid_override ? ctx->grid_override : kLaneWaves);
     if (ctx->grid_override) return ctx->grid_override;
@@ -656,6 +681,14 @@ extern "C" TPILU_API tpilu_status tpilu_ctx_set_group(tpilu_ctx ctx, int32_t row
     if (!ctx) return TPILU_E_INVAL;
     if (rows < 0 || rows > 64) return fail(ctx, TPILU_E_INVAL, "rows per ticket must be in [0, 64]");
     ctx->group = rows;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_tickets(tpilu_ctx ctx, int32_t counters) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (counters < 0 || counters > kTicketParts)
+        return fail(ctx, TPILU_E_INVAL, "task counters must be in [0, 8]");
+    ctx->tickets = counters;
     return TPILU_OK;
 }
 

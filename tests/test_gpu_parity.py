@@ -28,6 +28,7 @@ def _gpu_guard(request):
     ctx.set_solver(0)
     ctx.set_numeric(0)
     ctx.set_group(0)
+    ctx.set_tickets(0)
     ctx.set_watchdog(0, -1)
     yield
     torch.cuda.synchronize()
@@ -222,23 +223,27 @@ def test_repeatable_across_launch_shapes():
     ref_y = T.apply(pat, ref_f, bv)
     for solver in (ctx.SOLVER_DEVICE, ctx.SOLVER_WORKGROUP, ctx.SOLVER_LANES):
         ctx.set_solver(solver)
-        for waves, group in ((1, 1), (2, 3), (7, 0), (64, 64), (1000, 2), (0, 0), (40000, 5)):
+        for waves, group, tickets in ((1, 1, 8), (2, 3, 8), (7, 0, 3), (64, 64, 1), (1000, 2, 5), (0, 0, 0),
+                                      (40000, 5, 8)):
             ctx.set_grid(waves)
             ctx.set_group(group)
+            ctx.set_tickets(tickets)
             for _ in range(3):
                 f = T.numeric(pat, av)
                 y = T.apply(pat, f, bv)
-                assert torch.equal(f.view(torch.int64), ref_f.view(torch.int64)), (solver, waves, group)
-                assert torch.equal(y.view(torch.int64), ref_y.view(torch.int64)), (solver, waves, group)
+                key = (solver, waves, group, tickets)
+                assert torch.equal(f.view(torch.int64), ref_f.view(torch.int64)), key
+                assert torch.equal(y.view(torch.int64), ref_y.view(torch.int64)), key
     ctx.set_grid(0)
     ctx.set_group(0)
+    ctx.set_tickets(0)
     ctx.set_solver(0)
 
 
 @pytest.mark.parametrize("cfg", ["c3k1", "s27k1"])
 def test_row_groups_agree_full_size(cfg):
-    """Rows per ticket of the row kernels (numeric, wavefront-per-row solves,
-    inverses): the oracle's bits for every group size."""
+    """Rows per ticket and task counters of the row kernels (numeric,
+    wavefront-per-row solves, inverses): the oracle's bits for every setting."""
     c = I.config3(k=1) if cfg == "c3k1" else I.config_stencil27(m=50, k=1)
     A, b, k = c["A"], c["b"], 1
     rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
@@ -250,8 +255,9 @@ def test_row_groups_agree_full_size(cfg):
     modes = [ctx.NUMERIC_PIVOT] + ([ctx.NUMERIC_FLOW] if pat.info["flow_ready"] else [])
     try:
         ctx.set_solver(ctx.SOLVER_DEVICE)
-        for group in (1, 2, 5, 8, 64):
+        for group, tickets in ((1, 1), (1, 8), (2, 3), (5, 8), (8, 2), (64, 8)):
             ctx.set_group(group)
+            ctx.set_tickets(tickets)
             for mode in modes:
                 ctx.set_numeric(mode)
                 f = T.numeric(pat, g(A.val))
@@ -262,6 +268,7 @@ def test_row_groups_agree_full_size(cfg):
             assert_bits_equal(T.inverse(pat, f), vG, f"G group {group}")
     finally:
         ctx.set_group(0)
+        ctx.set_tickets(0)
         ctx.set_numeric(0)
         ctx.set_solver(0)
 
