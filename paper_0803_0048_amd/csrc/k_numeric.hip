@@ -125,22 +125,40 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
         if (!next_pos(ctl, (uint32_t)n, (uint32_t)P.groupL, (uint32_t)P.parts, run, t)) break;
         const int32_t j = P.permL ? P.permL[t] : (int32_t)t;
         trace_mark(P.trace, j);
+        // The loads of a row are issued level by level of their address
+        // dependencies (row bounds -> pivot offsets and diagonal slots ->
+        // pair lists and pivot diagonals -> pivot values), each level in one
+        // round trip: a row whose pivots are all final then costs a handful
+        // of memory latencies, not one per 64 staged values.
         const int64_t rs = P.rpF[j], re = P.rpF[j + 1];
         const int32_t len = (int32_t)(re - rs);
         const int64_t dj = P.diagF[j];
+        const int64_t a0 = P.rpA[j], a1 = P.rpA[j + 1];
+        // zeros first, then the values of A (one wavefront: its LDS writes land in order)
         for (int32_t e = lane; e < len; e += kWave) W[e] = 0.0;
-        wave_sync();
-        for (int64_t p = P.rpA[j] + lane; p < P.rpA[j + 1]; p += kWave)
-            W[P.a2f[p] - rs] = sanitize_input(a_val[p], ctl);
+        for (int64_t p = a0 + lane; p < a1; p += kWave) W[P.a2f[p] - rs] = sanitize_input(a_val[p], ctl);
         wave_sync();
 
         int64_t s0 = rs;
         while (s0 < dj) {
             int32_t np = (int32_t)std::min<int64_t>(dj - s0, kPivCap);
             const int64_t e0 = P.sptr[s0];
-            for (int32_t i = lane; i <= np; i += kWave) {
-                int64_t v = P.sptr[s0 + i] - e0;
-                piv_e[i] = (int32_t)std::min<int64_t>(v, 0x7fffffff);
+            {
+                constexpr int kSlots = (kPivCap + kWave) / kWave;  // covers i = 0..np
+                int64_t off[kSlots];
+                int32_t dh[kSlots];
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) {
+                    const int32_t i = lane + u * kWave;
+                    off[u] = i <= np ? P.sptr[s0 + i] : 0;
+                    dh[u] = i < np ? P.lsd[s0 + i] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) {
+                    const int32_t i = lane + u * kWave;
+                    if (i <= np) piv_e[i] = (int32_t)std::min<int64_t>(off[u] - e0, 0x7fffffff);
+                    if (i < np) piv_dh[i] = dh[u];
+                }
             }
             wave_sync();
             int32_t fit = 0;
@@ -149,17 +167,38 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
             np = uniform(fit > 0 ? fit : 1);
             const int32_t npair = uniform(piv_e[np]);
             const bool big = npair > kPairCap;  // a single pivot with more pairs than fit
-            for (int32_t i = lane; i < np; i += kWave) {
-                const int32_t dh = P.lsd[s0 + i];
-                piv_dh[i] = dh;
-                piv_u[i] = ld_cached(F + dh);
-            }
-            if (!big) {
-                for (int32_t e = lane; e < npair; e += kWave) {
-                    const int32_t q = P.sq[e0 + e];
-                    pr_q[e] = q;
-                    pr_p[e] = (int32_t)(P.sp[e0 + e] - rs);
-                    pr_v[e] = ld_cached(F + q);
+            {
+                constexpr int kPS = kPairCap / kWave;
+                constexpr int kPv = kPivCap / kWave;
+                const int32_t nst = big ? 0 : npair;
+                int32_t q[kPS], pp[kPS], dh[kPv];
+#pragma unroll
+                for (int u = 0; u < kPS; ++u) {
+                    const int32_t e = lane + u * kWave;
+                    q[u] = e < nst ? P.sq[e0 + e] : 0;
+                    pp[u] = e < nst ? P.sp[e0 + e] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < kPv; ++u) {
+                    const int32_t i = lane + u * kWave;
+                    dh[u] = i < np ? piv_dh[i] : 0;
+                }
+                uint64_t v[kPS], ud[kPv];
+#pragma unroll
+                for (int u = 0; u < kPv; ++u) ud[u] = lane + u * kWave < np ? ld_cached(F + dh[u]) : 0ull;
+#pragma unroll
+                for (int u = 0; u < kPS; ++u) v[u] = lane + u * kWave < nst ? ld_cached(F + q[u]) : 0ull;
+#pragma unroll
+                for (int u = 0; u < kPv; ++u)
+                    if (lane + u * kWave < np) piv_u[lane + u * kWave] = ud[u];
+#pragma unroll
+                for (int u = 0; u < kPS; ++u) {
+                    const int32_t e = lane + u * kWave;
+                    if (e < nst) {
+                        pr_q[e] = q[u];
+                        pr_p[e] = (int32_t)(pp[u] - rs);
+                        pr_v[e] = v[u];
+                    }
                 }
             }
             wave_sync();
