@@ -330,11 +330,6 @@ __global__ __launch_bounds__(64) void k_backward_batch(PatDev P, const double* _
     }
 }
 
-int solve_grid(int32_t batch, int num_cu) {
-    (void)batch;
-    return 16 * num_cu;
-}
-
 // single instance: grid > 0 wavefront per row, grid == 0 one workgroup,
 // grid < 0 lane per row with -grid wavefronts
 hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, const double* b,

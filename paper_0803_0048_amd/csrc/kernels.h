@@ -136,7 +136,6 @@ hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, c
                           double* x, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s);
 hipError_t launch_backward(const PatDev& P, const double* f_val, int32_t batch, const double* x,
                            double* y, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s);
-int solve_grid(int32_t batch, int num_cu);
 
 // ---- Krylov building blocks ---------------------------------------------------
 constexpr int kDotLanes = 16384;  // fixed shape of every inner product
