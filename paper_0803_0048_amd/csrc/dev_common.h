@@ -184,6 +184,13 @@ __device__ __forceinline__ bool next_pos(Ctl* ctl, uint32_t n, uint32_t group, u
     return true;
 }
 
+__device__ __forceinline__ int64_t bcast_i64(int64_t v, int src) {
+    const uint64_t u = static_cast<uint64_t>(v);
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(u), src);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(u >> 32), src);
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 __device__ __forceinline__ double bcast_lane(double v, int src) {
     uint64_t u = as_u64(v);
     uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(u), src);

@@ -453,6 +453,8 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
 // ----------------------------------------------------------------------------------
 constexpr int kBPivCap = 8;
 constexpr int kBPairCap = 32;
+constexpr int kBAChunk = 8;  // A entries loaded per round trip
+constexpr int kBLook = 8;    // pending pair values re-read per polling round
 
 __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __restrict__ a_val,
                                                       int32_t B, double* F, Ctl* ctl,
@@ -476,40 +478,134 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
         const int32_t g = (int32_t)(t % (uint32_t)G);
         const int32_t col = g * kWave + lane;
         const bool act = col < B;
+        const int32_t colc = act ? col : B - 1;  // an in-bounds column for inactive lanes
         const int64_t rs = P.rpF[j], re = P.rpF[j + 1];
         const int32_t len = (int32_t)(re - rs);
         const int64_t dj = P.diagF[j];
+        // Loads are issued a dependency level at a time (A row; pivot offsets
+        // and diagonal slots; pair lists; pivot values), each level in one
+        // round trip, so a task whose pivots are final costs a few memory
+        // latencies rather than one per staged value.
+        const int64_t a0 = P.rpA[j], a1 = P.rpA[j + 1];
         for (int32_t e = 0; e < len; ++e) W[e * kWave + lane] = 0.0;
-        for (int64_t p = P.rpA[j]; p < P.rpA[j + 1]; ++p) {
-            const int64_t sl = P.a2f[p] - rs;
-            if (act) W[sl * kWave + lane] = sanitize_input(a_val[p * B + col], ctl);
+        for (int64_t p0 = a0; p0 < a1; p0 += kBAChunk) {
+            // unconditional loads at clamped, in-bounds indices keep the
+            // compiler from waiting on each one; the extra values are unused
+            int32_t sl[kBAChunk];
+            double av[kBAChunk];
+#pragma unroll
+            for (int u = 0; u < kBAChunk; ++u) {
+                const int64_t p = std::min<int64_t>(p0 + u, a1 - 1);
+                sl[u] = P.a2f[p] - (int32_t)rs;
+                av[u] = a_val[p * B + colc];
+            }
+#pragma unroll
+            for (int u = 0; u < kBAChunk; ++u)
+                if (p0 + u < a1 && act) W[(int64_t)sl[u] * kWave + lane] = sanitize_input(av[u], ctl);
         }
         int64_t s0 = rs;
         while (s0 < dj) {
             int32_t np = (int32_t)std::min<int64_t>(dj - s0, kBPivCap);
             const int64_t e0 = P.sptr[s0];
+            // lane i: pair offset of pivot i of the group and its diagonal slot
+            const int64_t offl = lane <= np ? P.sptr[s0 + lane] - e0 : 0;
+            const int32_t dhl = lane < np ? P.lsd[s0 + lane] : 0;
+            // offsets never decrease: the pivots whose pairs fit are a prefix
+            const int32_t fit = __popcll(__ballot(lane >= 1 && lane <= np && offl <= kBPairCap));
+            np = fit > 0 ? fit : 1;
+            const int32_t npair = (int32_t)std::min<int64_t>(bcast_i64(offl, np), 0x7fffffff);
+            const bool big = npair > kBPairCap;  // a single pivot with more pairs than fit
             wave_sync();
-            if (lane <= np) piv_e[lane] = (int32_t)std::min<int64_t>(P.sptr[s0 + lane] - e0, 0x7fffffff);
-            wave_sync();
-            int32_t fit = 0;
-            for (int32_t i = 1; i <= np; ++i) fit += piv_e[i] <= kBPairCap ? 1 : 0;
-            np = uniform(fit > 0 ? fit : 1);
-            const int32_t npair = uniform(piv_e[np]);
-            const bool big = npair > kBPairCap;
-            if (lane < np) piv_dh[lane] = P.lsd[s0 + lane];
-            if (!big && lane < npair) {
-                pr_q[lane] = P.sq[e0 + lane];
-                pr_p[lane] = (int32_t)(P.sp[e0 + lane] - rs);
+            if (lane <= np) piv_e[lane] = (int32_t)std::min<int64_t>(offl, 0x7fffffff);
+            if (lane < np) piv_dh[lane] = dhl;
+            const int32_t nst = big ? 0 : npair;
+            const int32_t ql = lane < nst ? P.sq[e0 + lane] : 0;
+            const int32_t pl = lane < nst ? P.sp[e0 + lane] : 0;
+            if (lane < nst) {
+                pr_q[lane] = ql;
+                pr_p[lane] = (int32_t)(pl - rs);
+            }
+            // every lane (instance) needs every pivot's and pair's slot: read them
+            // out of the lanes that loaded them while the whole wavefront is active
+            int32_t dhs[kBPivCap], qs[kBPairCap];
+#pragma unroll
+            for (int i = 0; i < kBPivCap; ++i) dhs[i] = __builtin_amdgcn_readlane(dhl, i);
+#pragma unroll
+            for (int e = 0; e < kBPairCap; ++e) qs[e] = __builtin_amdgcn_readlane(ql, e);
+            if (act) {
+                uint64_t u8[kBPivCap], v32[kBPairCap];
+#pragma unroll
+                for (int i = 0; i < kBPivCap; ++i) u8[i] = ld_cached(F + (int64_t)dhs[i] * B + col);
+#pragma unroll
+                for (int e = 0; e < kBPairCap; ++e) v32[e] = ld_cached(F + (int64_t)qs[e] * B + col);
+#pragma unroll
+                for (int i = 0; i < kBPivCap; ++i)
+                    if (i < np) vu[i * kWave + lane] = u8[i];
+#pragma unroll
+                for (int e = 0; e < kBPairCap; ++e)
+                    if (e < nst) vv[e * kWave + lane] = v32[e];
             }
             wave_sync();
-            if (act) {
-                for (int32_t i = 0; i < np; ++i)
-                    vu[i * kWave + lane] = ld_cached(F + (int64_t)piv_dh[i] * B + col);
-                if (!big)
-                    for (int32_t e = 0; e < npair; ++e)
-                        vv[e * kWave + lane] = ld_cached(F + (int64_t)pr_q[e] * B + col);
-            }
-            if (act) {
+            if (act && !big) {
+                // Pivots in ascending order, each once its diagonal and all of
+                // its pair values are final in this lane's staged copy.  A
+                // round of polls re-reads the pivot's diagonal and up to
+                // kBLook of its pending pairs together (one round trip), so a
+                // pivot row that has just been published costs one latency,
+                // not one per value.
+                int32_t i = 0;
+                uint32_t polls = 0;
+                uint64_t t0 = 0;
+                while (i < np) {
+                    const int32_t ea = piv_e[i], eb = piv_e[i + 1];
+                    const bool ur = vu[i * kWave + lane] != kPending;
+                    int32_t ep = ea;
+                    while (ep < eb && vv[ep * kWave + lane] != kPending) ++ep;
+                    if (ur && ep == eb) {
+                        const int64_t sl = s0 + i - rs;
+                        const double l = W[sl * kWave + lane] / as_f64(vu[i * kWave + lane]);
+                        W[sl * kWave + lane] = l;
+                        for (int32_t e = ea; e < eb; ++e) {
+                            const int32_t p = pr_p[e];
+                            W[p * kWave + lane] = W[p * kWave + lane] - l * as_f64(vv[e * kWave + lane]);
+                        }
+                        ++i;
+                        polls = 0;
+                        continue;
+                    }
+                    const double* du = F + (int64_t)piv_dh[i] * B + col;
+                    const uint64_t nu = ld_coherent(du);
+                    uint64_t nv[kBLook];
+#pragma unroll
+                    for (int k = 0; k < kBLook; ++k) {
+                        const int32_t e = ep + k;
+                        // entries past the pivot's pairs read the diagonal's line again
+                        nv[k] = ld_coherent(e < eb ? F + (int64_t)pr_q[e] * B + col : du);
+                    }
+                    if (!ur && nu != kPending) vu[i * kWave + lane] = nu;
+#pragma unroll
+                    for (int k = 0; k < kBLook; ++k)
+                        if (ep + k < eb && nv[k] != kPending) vv[(ep + k) * kWave + lane] = nv[k];
+                    if ((polls & 31u) == 31u) {
+                        bool stop = (polls & 255u) == 255u && ld_u32_coherent(&ctl->abort) != 0u;
+                        const uint64_t now = wall_clock64();
+                        if (polls == 31u) {
+                            t0 = now;
+                        } else if (now - t0 > spin_limit) {
+                            atomicOr(&ctl->status, kStTimeout);
+                            __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            stop = true;
+                        }
+                        if (stop) {
+                            // give up on this pivot: its values become quiet NaNs
+                            if (vu[i * kWave + lane] == kPending) vu[i * kWave + lane] = kQNaN;
+                            for (int32_t e = ea; e < eb; ++e)
+                                if (vv[e * kWave + lane] == kPending) vv[e * kWave + lane] = kQNaN;
+                        }
+                    }
+                    ++polls;
+                }
+            } else if (act) {
                 for (int32_t i = 0; i < np; ++i) {
                     const int64_t sl = s0 + i - rs;
                     const double u = wait_final(F + (int64_t)piv_dh[i] * B + col, vu[i * kWave + lane], ctl,
