@@ -109,6 +109,47 @@ __device__ __forceinline__ double wait_final(const double* p, Ctl* ctl, uint64_t
     return wait_final(p, ld_cached(p), ctl, limit);
 }
 
+// Make every staged value of a chunk final: the pending ones are re-read
+// together, one round trip per round, until none is left; after a timeout or
+// an abort they become quiet NaNs.  Unused entries must hold a final value
+// and a valid index.
+template <int K>
+__device__ __forceinline__ void settle(const double* v, const int32_t (&idx)[K], uint64_t (&val)[K], int32_t B,
+                                       int32_t col, Ctl* ctl, uint64_t limit) {
+    uint32_t n = 0;
+    uint64_t t0 = 0;
+    for (;;) {
+        bool pend = false;
+#pragma unroll
+        for (int u = 0; u < K; ++u) pend = pend || val[u] == kPending;
+        if (!pend) return;
+        uint64_t nv[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) nv[u] = ld_coherent(v + (int64_t)idx[u] * B + col);
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+            if (val[u] == kPending) val[u] = nv[u];
+        if ((n & 31u) == 31u) {
+            bool stop = (n & 255u) == 255u && ld_u32_coherent(&ctl->abort) != 0u;
+            const uint64_t now = wall_clock64();
+            if (n == 31u) {
+                t0 = now;
+            } else if (now - t0 > limit) {
+                atomicOr(&ctl->status, kStTimeout);
+                __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                stop = true;
+            }
+            if (stop) {
+#pragma unroll
+                for (int u = 0; u < K; ++u)
+                    if (val[u] == kPending) val[u] = kQNaN;
+                return;
+            }
+        }
+        ++n;
+    }
+}
+
 // A caller-supplied value that happens to carry the reserved pattern is
 // replaced by the quiet NaN (and reported), so it can never be mistaken for
 // "not written yet".

@@ -182,21 +182,22 @@ __global__ __launch_bounds__(64) void k_adj_solve_u_batch(PatDev P, AdjPat T, co
                 double fv[kAdjChunk];
                 uint64_t zv[kAdjChunk];
                 int32_t jj[kAdjChunk];
+                // unconditional loads at clamped entries (the extra ones unused),
+                // pending values re-read together
 #pragma unroll
                 for (int u = 0; u < kAdjChunk; ++u) {
-                    if (c + u < a1) {
-                        jj[u] = T.trU[c + u];
-                        fv[u] = F[(int64_t)T.tsU[c + u] * B + col];
-                        zv[u] = ld_cached(z + (int64_t)jj[u] * B + col);
-                    }
+                    const int64_t cc = std::min<int64_t>(c + u, a1 - 1);
+                    jj[u] = T.trU[cc];
+                    fv[u] = F[(int64_t)T.tsU[cc] * B + col];
+                    zv[u] = ld_cached(z + (int64_t)jj[u] * B + col);
                 }
 #pragma unroll
-                for (int u = 0; u < kAdjChunk; ++u) {
-                    if (c + u < a1) {
-                        const double zz = wait_final(z + (int64_t)jj[u] * B + col, zv[u], ctl, spin_limit);
-                        s = s - fv[u] * zz;
-                    }
-                }
+                for (int u = 0; u < kAdjChunk; ++u)
+                    if (c + u >= a1) zv[u] = 0ull;
+                settle(z, jj, zv, B, col, ctl, spin_limit);
+#pragma unroll
+                for (int u = 0; u < kAdjChunk; ++u)
+                    if (c + u < a1) s = s - fv[u] * as_f64(zv[u]);
             }
             st_publish(z + (int64_t)i * B + col, s / F[(int64_t)P.diagF[i] * B + col]);
         }
@@ -223,19 +224,18 @@ __global__ __launch_bounds__(64) void k_adj_solve_l_batch(PatDev P, AdjPat T, co
                 int32_t jj[kAdjChunk];
 #pragma unroll
                 for (int u = 0; u < kAdjChunk; ++u) {
-                    if (c - u >= a0) {
-                        jj[u] = T.trL[c - u];
-                        fv[u] = F[(int64_t)T.tsL[c - u] * B + col];
-                        wv[u] = ld_cached(w + (int64_t)jj[u] * B + col);
-                    }
+                    const int64_t cc = std::max<int64_t>(c - u, a0);
+                    jj[u] = T.trL[cc];
+                    fv[u] = F[(int64_t)T.tsL[cc] * B + col];
+                    wv[u] = ld_cached(w + (int64_t)jj[u] * B + col);
                 }
 #pragma unroll
-                for (int u = 0; u < kAdjChunk; ++u) {
-                    if (c - u >= a0) {
-                        const double ww = wait_final(w + (int64_t)jj[u] * B + col, wv[u], ctl, spin_limit);
-                        s = s - fv[u] * ww;
-                    }
-                }
+                for (int u = 0; u < kAdjChunk; ++u)
+                    if (c - u < a0) wv[u] = 0ull;
+                settle(w, jj, wv, B, col, ctl, spin_limit);
+#pragma unroll
+                for (int u = 0; u < kAdjChunk; ++u)
+                    if (c - u >= a0) s = s - fv[u] * as_f64(wv[u]);
             }
             st_publish(w + (int64_t)i * B + col, s);
         }
@@ -388,18 +388,20 @@ __global__ __launch_bounds__(64) void k_adj_numeric_batch(PatDev P, AdjPat T, co
                     int32_t pq[kAdjChunk], pp[kAdjChunk];
 #pragma unroll
                     for (int u = 0; u < kAdjChunk; ++u) {
-                        if (c + u < e1) {
-                            pq[u] = P.sq[c + u];  // slot in row j
-                            pp[u] = P.sp[c + u];  // slot in row i
-                            gv[u] = ld_cached(Gv + (int64_t)pp[u] * B + col);
-                        }
+                        const int64_t cc = std::min<int64_t>(c + u, e1 - 1);
+                        pq[u] = P.sq[cc];  // slot in row j
+                        pp[u] = P.sp[cc];  // slot in row i
+                        gv[u] = ld_cached(Gv + (int64_t)pp[u] * B + col);
                     }
+#pragma unroll
+                    for (int u = 0; u < kAdjChunk; ++u)
+                        if (c + u >= e1) gv[u] = 0ull;
+                    settle(Gv, pp, gv, B, col, ctl, spin_limit);
 #pragma unroll
                     for (int u = 0; u < kAdjChunk; ++u) {
                         if (c + u < e1) {
-                            const double g = wait_final(Gv + (int64_t)pp[u] * B + col, gv[u], ctl, spin_limit);
                             const int64_t q = (pq[u] - rs) * kWave + lane;
-                            W[q] = W[q] - g * l;
+                            W[q] = W[q] - as_f64(gv[u]) * l;
                         }
                     }
                 }

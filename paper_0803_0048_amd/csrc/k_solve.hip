@@ -267,21 +267,21 @@ __global__ __launch_bounds__(64) void k_forward_batch(PatDev P, const double* __
                 double fv[kSolveChunk];
                 uint64_t xv[kSolveChunk];
                 int32_t hh[kSolveChunk];
+                // unconditional loads at clamped slots (the extra ones unused)
 #pragma unroll
                 for (int u = 0; u < kSolveChunk; ++u) {
-                    if (c + u < dj) {
-                        hh[u] = P.ciF[c + u];
-                        fv[u] = F[(c + u) * B + col];
-                        xv[u] = ld_cached(x + (int64_t)hh[u] * B + col);
-                    }
+                    const int64_t cc = std::min<int64_t>(c + u, dj - 1);
+                    hh[u] = P.ciF[cc];
+                    fv[u] = F[cc * B + col];
+                    xv[u] = ld_cached(x + (int64_t)hh[u] * B + col);
                 }
 #pragma unroll
-                for (int u = 0; u < kSolveChunk; ++u) {
-                    if (c + u < dj) {
-                        const double xx = wait_final(x + (int64_t)hh[u] * B + col, xv[u], ctl, spin_limit);
-                        s = s - fv[u] * xx;
-                    }
-                }
+                for (int u = 0; u < kSolveChunk; ++u)
+                    if (c + u >= dj) xv[u] = 0ull;
+                settle(x, hh, xv, B, col, ctl, spin_limit);
+#pragma unroll
+                for (int u = 0; u < kSolveChunk; ++u)
+                    if (c + u < dj) s = s - fv[u] * as_f64(xv[u]);
             }
             st_publish(x + (int64_t)i * B + col, s);
         }
@@ -311,19 +311,18 @@ __global__ __launch_bounds__(64) void k_backward_batch(PatDev P, const double* _
                 int32_t jj[kSolveChunk];
 #pragma unroll
                 for (int u = 0; u < kSolveChunk; ++u) {
-                    if (c - u > dj) {
-                        jj[u] = P.ciF[c - u];
-                        fv[u] = F[(c - u) * B + col];
-                        yv[u] = ld_cached(y + (int64_t)jj[u] * B + col);
-                    }
+                    const int64_t cc = std::max<int64_t>(c - u, dj + 1);
+                    jj[u] = P.ciF[cc];
+                    fv[u] = F[cc * B + col];
+                    yv[u] = ld_cached(y + (int64_t)jj[u] * B + col);
                 }
 #pragma unroll
-                for (int u = 0; u < kSolveChunk; ++u) {
-                    if (c - u > dj) {
-                        const double yy = wait_final(y + (int64_t)jj[u] * B + col, yv[u], ctl, spin_limit);
-                        s = s - fv[u] * yy;
-                    }
-                }
+                for (int u = 0; u < kSolveChunk; ++u)
+                    if (c - u <= dj) yv[u] = 0ull;
+                settle(y, jj, yv, B, col, ctl, spin_limit);
+#pragma unroll
+                for (int u = 0; u < kSolveChunk; ++u)
+                    if (c - u > dj) s = s - fv[u] * as_f64(yv[u]);
             }
             st_publish(y + (int64_t)i * B + col, s / F[dj * B + col]);
         }

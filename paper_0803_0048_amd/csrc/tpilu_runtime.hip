@@ -152,26 +152,13 @@ int32_t row_group(RowKernel kind, int64_t n, int64_t depth) {
     return width >= 512 ? 2 : 1;
 }
 
-// Wavefronts of the batched kernels (a task is one row for 64 instances),
-// from the tasks of one dependency level, W = ceil(n / depth) x ceil(B / 64).
-// Waiting wavefronts poll, and past what the levels can use they slow every
-// hand-off down, so the batched kernels get far fewer than the resident
-// maximum.  Measured on MI355X (solves / numeric, best grid): 2-D 5-point
-// 128^2 ILU(2) x256 (W = 132) 192 / 384-512; x512 ILU(1) (W = 344) 192-256 /
-// 640; 3-D 7-point 32^3 ILU(1) x16 (W = 176) 192-256 / 512-640; 64^3 x64
-// (W = 692) 320 / >= 1536; 48^3 ILU(2) x256 (W = 856) 512 / >= 1024.  The
-// resident maximum ran 1.5-4x slower on the narrow ones.
-int64_t batch_width(int64_t n, int64_t depth, int32_t batch) {
-    const int64_t d = std::max<int64_t>(depth, 1);
-    return std::max<int64_t>(1, (n + d - 1) / d) * (((int64_t)batch + 63) / 64);
-}
-int32_t batch_solve_waves(int64_t W) {
-    return (int32_t)std::min<int64_t>(std::max<int64_t>({64, std::min<int64_t>(3 * W / 2, 192), W / 2}), 8192);
-}
-int32_t batch_numeric_waves(int64_t W) {
-    const int64_t hi = std::max<int64_t>(640, 3 * W / 2);
-    return (int32_t)std::min<int64_t>(std::max<int64_t>(7 * W / 2, 256), std::min<int64_t>(hi, 8192));
-}
+// Wavefronts of the batched kernels (a task is one row for 64 instances).
+// Their waits re-read all pending values of a chunk in one round trip, and
+// then extra wavefronts cost little: measured on MI355X, the batched solves
+// are flat from 256-384 wavefronts on (2-D 5-point 128^2 ILU(2) x256, x512
+// ILU(1); 3-D 7-point 32^3 ILU(1) x16, 64^3 x64) and the numeric kernel
+// improves up to the resident maximum.
+constexpr int32_t kBatchSolveWaves = 512;
 
 // Position counters the row kernels draw from (see next_pos).
 int32_t ticket_parts(RowKernel, int64_t, int64_t) { return kTicketParts; }
@@ -183,7 +170,6 @@ struct tpilu_pattern_s {
     int32_t k = 0;
     PatStats st{};
     int32_t depth_l = 0, depth_u = 0, overflow_rows = 0;
-    int32_t depth_ut = 0, depth_lt = 0;  // of the transposed sweeps (set with the transposes)
     std::vector<DBuf> owned;
     // device arrays
     int64_t* rpA = nullptr;
@@ -370,8 +356,7 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
     HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, pat->ctl, true, ctx->stream));
     const int grid = ctx->grid_override
                          ? ctx->grid_override
-                         : std::min(batch == 1 ? (flow ? kFlowWaves : kNumericWaves)
-                                               : batch_numeric_waves(batch_width(pat->n, pat->depth_l, batch)),
+                         : std::min(batch == 1 ? (flow ? kFlowWaves : kNumericWaves) : 1 << 30,
                                     numeric_grid(batch, pat->st.max_row, pat->st.max_lrow, flow, ctx->num_cu));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_NUMERIC);
@@ -402,10 +387,7 @@ constexpr int64_t kLaneWidthPerEntry = 16;  // ... and at or above this many per
 constexpr int32_t kLaneWaves = 128;
 
 int32_t solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool backward) {
-    if (batch > 1) {
-        if (ctx->grid_override) return ctx->grid_override;
-        return batch_solve_waves(batch_width(pat->n, backward ? pat->depth_u : pat->depth_l, batch));
-    }
+    if (batch > 1) return ctx->grid_override ? ctx->grid_override : kBatchSolveWaves;
     const int64_t n = std::max<int64_t>(pat->n, 1);
     const int64_t half = backward ? pat->nnz_f - (int64_t)pat->st.nnz_l - pat->n : (int64_t)pat->st.nnz_l;
     const int64_t depth = std::max<int64_t>(1, backward ? pat->depth_u : pat->depth_l);
@@ -646,8 +628,6 @@ tpilu_status build_transposes(tpilu_ctx ctx, tpilu_pattern pat) {
                              {DepGraph{pat->tpL, pat->trL, nullptr, 2}, 1, nl, depth2, pat->permLT, &dm1}};
     tpilu_status st = compute_levels(ctx, pat, js, 2);
     if (st) return st;
-    pat->depth_ut = dm0;
-    pat->depth_lt = dm1;
     pat->have_t = true;
     return TPILU_OK;
 }
@@ -1450,16 +1430,11 @@ extern "C" TPILU_API tpilu_status tpilu_apply_adjoint(tpilu_ctx ctx, tpilu_patte
     double* z = pat->grow(pat->ws_z, sizeof(double) * (size_t)pat->n * batch);
     if (!z) return fail(ctx, TPILU_E_NOMEM, "adjoint workspace");
     AdjPat T{pat->tpL, pat->tsL, pat->trL, pat->tpU, pat->tsU, pat->trU, pat->permUT, pat->permLT};
-    auto adj_grid = [&](int32_t depth) {
-        if (ctx->grid_override) return (int)ctx->grid_override;
-        return batch > 1 ? (int)batch_solve_waves(batch_width(pat->n, depth, batch)) : (int)kAdjointWaves;
-    };
+    const int grid = ctx->grid_override ? ctx->grid_override : batch > 1 ? kBatchSolveWaves : kAdjointWaves;
     HIPCHK(ctx, launch_fill_pending(z, pat->n * batch, pat->ctl, true, s));
-    HIPCHK(ctx, launch_adj_solve_u(pdev(ctx, pat), T, f_val, batch, ybar, z, pat->ctl, ctx->spin_limit,
-                                   adj_grid(pat->depth_ut), s));
+    HIPCHK(ctx, launch_adj_solve_u(pdev(ctx, pat), T, f_val, batch, ybar, z, pat->ctl, ctx->spin_limit, grid, s));
     HIPCHK(ctx, launch_fill_pending(bbar, pat->n * batch, pat->ctl, false, s));
-    HIPCHK(ctx, launch_adj_solve_l(pdev(ctx, pat), T, f_val, batch, z, bbar, pat->ctl, ctx->spin_limit,
-                                   adj_grid(pat->depth_lt), s));
+    HIPCHK(ctx, launch_adj_solve_l(pdev(ctx, pat), T, f_val, batch, z, bbar, pat->ctl, ctx->spin_limit, grid, s));
     HIPCHK(ctx, launch_adj_fbar(pdev(ctx, pat), batch, x, y, z, bbar, fbar, s));
     return TPILU_OK;
 }
@@ -1484,9 +1459,7 @@ extern "C" TPILU_API tpilu_status tpilu_numeric_adjoint(tpilu_ctx ctx, tpilu_pat
     HIPCHK(ctx, launch_copy(fin, fbar, nfb, s));
     HIPCHK(ctx, launch_fill_pending(fbar, nfb, pat->ctl, true, s));
     HIPCHK(ctx, launch_fill_pending(lbar, nfb, pat->ctl, false, s));
-    const int grid = ctx->grid_override ? ctx->grid_override
-                     : batch > 1            ? batch_numeric_waves(batch_width(pat->n, pat->depth_l, batch))
-                                            : kAdjointWaves;
+    const int grid = ctx->grid_override ? ctx->grid_override : kAdjointWaves;
     HIPCHK(ctx, launch_adj_numeric(pdev(ctx, pat), T, f_val, batch, fin, fbar, lbar, abar, pat->ctl,
                                    ctx->spin_limit, grid, pat->st.max_row, s));
     return TPILU_OK;
