@@ -358,12 +358,35 @@ __global__ __launch_bounds__(64) void k_adj_numeric(PatDev P, AdjPat T, const do
 // Reverse sweep for batches: lanes = instances, the working row in LDS as
 // [slot][lane]; the same operations in the same order as k_adj_numeric, each
 // lane on its own instance.
+// Inputs of a task that no other task writes (the row's own pivot
+// diagonals and update values, the l of the rows that pivot on it) are staged
+// in LDS at the start, a batch of loads per round trip, so that once the last
+// dependency has arrived only the polled values remain on the task's path.
+constexpr int kAdjPairCap = 32;  // own update pairs staged
+constexpr int kAdjRowCap = 16;   // rows pivoting on the task's row staged
+constexpr int kAdjLCap = 64;     // own pivots staged
+constexpr int kAdjRPairCap = 64; // update pairs of the staged rows
+
+size_t adj_numeric_batch_lds(int32_t max_row, bool stage) {
+    const size_t rows = (size_t)std::max(max_row, 1) * (stage ? 2 : 1) + (stage ? kAdjPairCap + kAdjRowCap : 0);
+    return rows * sizeof(double) * kWave;
+}
+
 __global__ __launch_bounds__(64) void k_adj_numeric_batch(PatDev P, AdjPat T, const double* __restrict__ F,
                                                           int32_t B, const double* __restrict__ fin,
                                                           double* Gv, double* lbar_out,
                                                           double* __restrict__ abar, Ctl* ctl,
-                                                          uint64_t spin_limit) {
-    extern __shared__ double W[];  // [len][64]
+                                                          uint64_t spin_limit, int32_t max_row, int32_t stage) {
+    extern __shared__ double W[];  // [max_row][64]; staged: Ud [max_row][64], Pv [pairs][64], La [rows][64]
+    double* Ud = W + (size_t)std::max(max_row, 1) * kWave;
+    double* Pv = Ud + (size_t)std::max(max_row, 1) * kWave;
+    double* La = Pv + (size_t)kAdjPairCap * kWave;
+    __shared__ int32_t sla[kAdjRowCap];       // slot of f_ij of the staged rows i
+    __shared__ int32_t psp[kAdjPairCap];      // own pairs: slot in row j minus its start
+    __shared__ int32_t pof[kAdjLCap + 1];     // own pivots: first pair, relative
+    __shared__ int32_t rq[kAdjRPairCap];      // pairs of the staged rows: slot in row j minus its start
+    __shared__ int32_t rp[kAdjRPairCap];      // ... and slot in row i
+    __shared__ int32_t rof[kAdjRowCap + 1];   // first pair of each staged row, relative
     const int lane = lane_id();
     const int32_t G = (B + kWave - 1) / kWave;
     const uint32_t ntask = (uint32_t)P.n * (uint32_t)G;
@@ -372,16 +395,127 @@ __global__ __launch_bounds__(64) void k_adj_numeric_batch(PatDev P, AdjPat T, co
         if (t >= ntask) break;
         const int32_t j = T.permLT[t / (uint32_t)G];
         const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
+        const int64_t rs = P.rpF[j], re = P.rpF[j + 1], dj = P.diagF[j];
+        const int32_t len = (int32_t)(re - rs);
+        const int64_t a0 = T.tpL[j], a1 = T.tpL[j + 1];
+        const int64_t q0 = P.sptr[rs], q1 = P.sptr[dj];
+        const bool st_own = stage && q1 - q0 <= kAdjPairCap && dj - rs <= kAdjLCap;
+        bool st_rows = stage && a1 - a0 <= kAdjRowCap;
+        // uniform metadata first, with the whole wavefront active
+        if (st_own) {
+            for (int64_t e = q0 + lane; e < q1; e += kWave) psp[e - q0] = P.sp[e] - (int32_t)rs;
+            for (int64_t sl = rs + lane; sl <= dj; sl += kWave) pof[sl - rs] = (int32_t)(P.sptr[sl] - q0);
+        }
+        if (st_rows) {
+            // lane k < a1 - a0: row a0 + k, its slot and its pair range
+            const int32_t k = lane;
+            const bool in = k < a1 - a0;
+            const int32_t slk = in ? T.tsL[a0 + k] : 0;
+            const int64_t pb = in ? P.sptr[slk] : 0, pe = in ? P.sptr[slk + 1] : 0;
+            // exclusive prefix of the pair counts, lanes in order
+            int32_t cnt = (int32_t)(pe - pb), pre = cnt;
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int32_t o = __shfl_up(pre, off);
+                if (k >= off) pre += o;
+            }
+            const int32_t total = __shfl(pre, kWave - 1);
+            pre -= cnt;
+            if (total > kAdjRPairCap) {
+                st_rows = false;
+            } else {
+                if (in) {
+                    sla[k] = slk;
+                    rof[k] = pre;
+                }
+                if (k == 0) rof[a1 - a0] = total;
+                wave_sync();
+                for (int32_t r = 0; r < (int32_t)(a1 - a0); ++r) {
+                    const int64_t b0 = P.sptr[sla[r]];
+                    const int32_t o0 = rof[r], o1 = rof[r + 1];
+                    if (lane < o1 - o0) {
+                        rq[o0 + lane] = P.sq[b0 + lane] - (int32_t)rs;
+                        rp[o0 + lane] = P.sp[b0 + lane];
+                    }
+                }
+            }
+        }
+        wave_sync();
         if (col < B) {
-            const int64_t rs = P.rpF[j], re = P.rpF[j + 1], dj = P.diagF[j];
-            const int32_t len = (int32_t)(re - rs);
-            for (int32_t e = 0; e < len; ++e) W[e * kWave + lane] = sanitize_input(fin[(rs + e) * B + col], ctl);
+            for (int32_t e0 = 0; e0 < len; e0 += kAdjChunk) {
+                double v[kAdjChunk];
+#pragma unroll
+                for (int u = 0; u < kAdjChunk; ++u) v[u] = fin[(rs + std::min(e0 + u, len - 1)) * B + col];
+#pragma unroll
+                for (int u = 0; u < kAdjChunk; ++u)
+                    if (e0 + u < len) W[(e0 + u) * kWave + lane] = sanitize_input(v[u], ctl);
+            }
             const double ujj = F[dj * B + col];
+            if (stage) {
+                for (int64_t c = rs; c < dj; c += kAdjChunk) {
+                    double v[kAdjChunk];
+#pragma unroll
+                    for (int u = 0; u < kAdjChunk; ++u)
+                        v[u] = F[(int64_t)P.lsd[std::min<int64_t>(c + u, dj - 1)] * B + col];
+#pragma unroll
+                    for (int u = 0; u < kAdjChunk; ++u)
+                        if (c + u < dj) Ud[(c + u - rs) * kWave + lane] = v[u];
+                }
+            }
+            if (st_own) {
+                for (int64_t c = q0; c < q1; c += kAdjChunk) {
+                    double v[kAdjChunk];
+#pragma unroll
+                    for (int u = 0; u < kAdjChunk; ++u)
+                        v[u] = F[(int64_t)P.sq[std::min<int64_t>(c + u, q1 - 1)] * B + col];
+#pragma unroll
+                    for (int u = 0; u < kAdjChunk; ++u)
+                        if (c + u < q1) Pv[(c + u - q0) * kWave + lane] = v[u];
+                }
+            }
+            if (st_rows) {
+                for (int64_t c = a0; c < a1; c += kAdjChunk) {
+                    double v[kAdjChunk];
+#pragma unroll
+                    for (int u = 0; u < kAdjChunk; ++u)
+                        v[u] = F[(int64_t)sla[std::min<int64_t>(c + u, a1 - 1) - a0] * B + col];
+#pragma unroll
+                    for (int u = 0; u < kAdjChunk; ++u)
+                        if (c + u < a1) La[(c + u - a0) * kWave + lane] = v[u];
+                }
+            }
             // contributions of the rows i > j that pivot on j, in descending i
-            for (int64_t a = T.tpL[j + 1] - 1; a >= T.tpL[j]; --a) {
-                const int64_t sl = T.tsL[a];  // slot of f_ij in row i
-                const double l = F[sl * B + col];
+            for (int64_t a = a1 - 1; a >= a0; --a) {
+                const int64_t sl = st_rows ? sla[a - a0] : T.tsL[a];  // slot of f_ij in row i
+                const double l = st_rows ? La[(a - a0) * kWave + lane] : F[sl * B + col];
                 const uint64_t lb0 = ld_cached(lbar_out + sl * B + col);
+                if (st_rows) {
+                    const int32_t o0 = rof[a - a0], o1 = rof[a - a0 + 1];
+                    for (int32_t c = o0; c < o1; c += kAdjChunk) {
+                        uint64_t gv[kAdjChunk];
+                        int32_t pp[kAdjChunk];
+#pragma unroll
+                        for (int u = 0; u < kAdjChunk; ++u) {
+                            pp[u] = rp[std::min(c + u, o1 - 1)];
+                            gv[u] = ld_cached(Gv + (int64_t)pp[u] * B + col);
+                        }
+#pragma unroll
+                        for (int u = 0; u < kAdjChunk; ++u)
+                            if (c + u >= o1) gv[u] = 0ull;
+                        settle(Gv, pp, gv, B, col, ctl, spin_limit);
+#pragma unroll
+                        for (int u = 0; u < kAdjChunk; ++u) {
+                            if (c + u < o1) {
+                                const int32_t q = rq[c + u] * kWave + lane;
+                                W[q] = W[q] - as_f64(gv[u]) * l;
+                            }
+                        }
+                    }
+                    const double lb = wait_final(lbar_out + sl * B + col, lb0, ctl, spin_limit);
+                    double tmp = lb * l;
+                    tmp = tmp / ujj;
+                    W[(dj - rs) * kWave + lane] = W[(dj - rs) * kWave + lane] - tmp;
+                    continue;
+                }
                 const int64_t e0 = P.sptr[sl], e1 = P.sptr[sl + 1];
                 for (int64_t c = e0; c < e1; c += kAdjChunk) {
                     uint64_t gv[kAdjChunk];
@@ -413,15 +547,22 @@ __global__ __launch_bounds__(64) void k_adj_numeric_batch(PatDev P, AdjPat T, co
             // own pivots, descending
             for (int64_t sl = dj - 1; sl >= rs; --sl) {
                 double lb = W[(sl - rs) * kWave + lane];
-                for (int64_t e = P.sptr[sl]; e < P.sptr[sl + 1]; ++e)
-                    lb = lb - W[(P.sp[e] - rs) * kWave + lane] * F[(int64_t)P.sq[e] * B + col];
+                if (st_own) {
+                    for (int32_t e = pof[sl - rs]; e < pof[sl - rs + 1]; ++e)
+                        lb = lb - W[psp[e] * kWave + lane] * Pv[e * kWave + lane];
+                } else {
+                    for (int64_t e = P.sptr[sl]; e < P.sptr[sl + 1]; ++e)
+                        lb = lb - W[(P.sp[e] - rs) * kWave + lane] * F[(int64_t)P.sq[e] * B + col];
+                }
                 st_publish(lbar_out + sl * B + col, lb);
-                W[(sl - rs) * kWave + lane] = lb / F[(int64_t)P.lsd[sl] * B + col];
+                const double u = stage ? Ud[(sl - rs) * kWave + lane] : F[(int64_t)P.lsd[sl] * B + col];
+                W[(sl - rs) * kWave + lane] = lb / u;
             }
             for (int64_t p = P.rpA[j]; p < P.rpA[j + 1]; ++p)
                 abar[p * B + col] = W[(P.a2f[p] - rs) * kWave + lane];
             for (int32_t e = 0; e < len; ++e) st_publish(Gv + (rs + e) * B + col, W[e * kWave + lane]);
         }
+        wave_sync();
     }
 }
 
@@ -430,11 +571,11 @@ hipError_t launch_adj_numeric(const PatDev& P, const AdjPat& T, const double* f_
                               double* abar, Ctl* ctl, uint64_t spin_limit, int32_t grid,
                               int32_t max_row, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    const size_t lds_batch = (size_t)std::max(max_row, 1) * sizeof(double) * kWave;
+    const bool stage = adj_numeric_batch_lds(max_row, true) <= 64 * 1024;  // rows of up to 40 entries
+    const size_t lds_batch = adj_numeric_batch_lds(max_row, stage);
     if (batch > 1 && lds_batch <= 64 * 1024) {  // rows of up to 128 entries
-        const size_t lds = lds_batch;
-        hipLaunchKernelGGL(k_adj_numeric_batch, dim3(grid), dim3(64), lds, s, P, T, f_val, batch, fbar_in, G,
-                           lbar, abar, ctl, spin_limit);
+        hipLaunchKernelGGL(k_adj_numeric_batch, dim3(grid), dim3(64), lds_batch, s, P, T, f_val, batch, fbar_in,
+                           G, lbar, abar, ctl, spin_limit, max_row, stage ? 1 : 0);
     } else {
         size_t lds = (size_t)std::max(max_row, 1) * sizeof(double);
         hipLaunchKernelGGL(k_adj_numeric, dim3(grid), dim3(64), lds, s, P, T, f_val, batch, fbar_in, G,

@@ -74,6 +74,7 @@ constexpr int64_t kFlowMinL = 4;
 constexpr int64_t kFlowMaxChain = 12;
 constexpr int64_t kFlowMaxWidth = 64;
 constexpr int32_t kAdjointWaves = 512;
+constexpr int32_t kAdjointBatchWaves = 1024;  // batched reverse elimination (3-D 7-point 32^3 x16: 1.9 ms, 2.2 at 512)
 constexpr int32_t kInverseWaves = 512;
 constexpr int64_t kNarrowWidth = 64;   // n / depth below this: narrow
 constexpr int64_t kLevelLaneMax = 14;  // level computation: lane per node below this many dependencies
@@ -1459,7 +1460,7 @@ extern "C" TPILU_API tpilu_status tpilu_numeric_adjoint(tpilu_ctx ctx, tpilu_pat
     HIPCHK(ctx, launch_copy(fin, fbar, nfb, s));
     HIPCHK(ctx, launch_fill_pending(fbar, nfb, pat->ctl, true, s));
     HIPCHK(ctx, launch_fill_pending(lbar, nfb, pat->ctl, false, s));
-    const int grid = ctx->grid_override ? ctx->grid_override : kAdjointWaves;
+    const int grid = ctx->grid_override ? ctx->grid_override : batch > 1 ? kAdjointBatchWaves : kAdjointWaves;
     HIPCHK(ctx, launch_adj_numeric(pdev(ctx, pat), T, f_val, batch, fin, fbar, lbar, abar, pat->ctl,
                                    ctx->spin_limit, grid, pat->st.max_row, s));
     return TPILU_OK;
