@@ -202,6 +202,7 @@ typedef struct {
     int32_t depth_u;     /* rows on the longest dependency chain of U~ (backward order) */
     int32_t overflow_rows; /* rows the symbolic pass had to redo in global memory */
     int32_t flow_ready;  /* 1 if the dataflow numeric kernel can run on this pattern */
+    int32_t long_rows;   /* rows the symbolic pass redid with its larger LDS maps */
 } tpilu_pattern_info_t;
 
 TPILU_API tpilu_status tpilu_pattern_info(tpilu_pattern pat, tpilu_pattern_info_t *info /* host */);

@@ -54,6 +54,7 @@ def lib():
         L.orc_symbolic.argtypes = [i64, P, P, i32, C.POINTER(_Pattern)]
         L.orc_pattern_free.argtypes = [C.POINTER(_Pattern)]
         L.orc_numeric.argtypes = [i64, P, P, P, P, P, P, C.POINTER(i64)]
+        L.orc_numeric_rows.argtypes = [i64, P, P, P, P, P, P, i64, P, P]
         L.orc_apply.argtypes = [i64, P, P, P, P, P, P]
         L.orc_spmv.argtypes = [i64, P, P, P, P, P]
         L.orc_spmv.restype = None
@@ -125,6 +126,21 @@ def numeric(n, rowptr, col, val, rowptrF, colF):
     if st not in (OK, EZEROPIVOT):
         raise OracleError(st, "numeric")
     return vF, int(bad.value)
+
+
+def numeric_rows(n, rowptr, col, val, rowptrF, colF, valF, rows):
+    """The listed rows alone, each eliminated exactly as in ``numeric`` but
+    against the pivot rows given in ``valF`` (e.g. a factor computed
+    elsewhere).  Returns one array per row, in the order of ``rows``."""
+    rp, ci, v = _c(rowptr, np.int64), _c(col, np.int32), _c(val, np.float64)
+    rpF, ciF, vF = _c(rowptrF, np.int64), _c(colF, np.int32), _c(valF, np.float64)
+    rr = _c(rows, np.int64)
+    lens = rpF[rr + 1] - rpF[rr]
+    out = np.empty(int(lens.sum()), dtype=np.float64)
+    st = lib().orc_numeric_rows(n, _p(rp), _p(ci), _p(v), _p(rpF), _p(ciF), _p(vF), rr.shape[0], _p(rr), _p(out))
+    if st:
+        raise OracleError(st, "numeric_rows")
+    return np.split(out, np.cumsum(lens)[:-1])
 
 
 def apply(n, rowptrF, colF, valF, p):

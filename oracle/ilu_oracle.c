@@ -223,6 +223,42 @@ static int find_diag(int64_t n, const int64_t *rpF, const int32_t *ciF, int64_t 
 /* NaN); *bad_row receives the smallest row whose final pivot f_jj is +-0,   */
 /* or -1.                                                                    */
 /* ------------------------------------------------------------------------ */
+/* Row j of the factor (Eq. 2 restricted to the pattern, IKJ order): A's row
+ * scattered into F's pattern, then for every pivot h < j of the row in
+ * ascending column order l = f_jh / u_hh and f_jt -= l * u_ht for the t of
+ * U~'s row h that lie in row j's pattern.  `row` receives row j's values
+ * (its slots rpF[j]..rpF[j+1]-1); pivot rows are read from `vpiv` at their
+ * own slots.  slot_of must be all -1 on entry and is left so. */
+static int eliminate_row(int64_t j, const int64_t *rpA, const int32_t *ciA, const double *vA,
+                         const int64_t *rpF, const int32_t *ciF, const int64_t *diag,
+                         int64_t *slot_of, const double *vpiv, double *row)
+{
+    const int64_t r0 = rpF[j];
+    int st = ORC_OK;
+    for (int64_t s = r0; s < rpF[j + 1]; ++s) {
+        slot_of[ciF[s]] = s - r0;
+        row[s - r0] = 0.0;
+    }
+    for (int64_t p = rpA[j]; p < rpA[j + 1]; ++p) {
+        int64_t s = slot_of[ciA[p]];
+        if (s < 0) { st = ORC_EINVAL; break; }
+        row[s] = vA[p];
+    }
+    if (st == ORC_OK) {
+        for (int64_t s = r0; s < diag[j]; ++s) {
+            int64_t h = ciF[s];
+            row[s - r0] = row[s - r0] / vpiv[diag[h]];
+            double l = row[s - r0];
+            for (int64_t q = diag[h] + 1; q < rpF[h + 1]; ++q) {
+                int64_t p = slot_of[ciF[q]];
+                if (p >= 0) row[p] = row[p] - l * vpiv[q];
+            }
+        }
+    }
+    for (int64_t s = r0; s < rpF[j + 1]; ++s) slot_of[ciF[s]] = -1;
+    return st;
+}
+
 int orc_numeric(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
                 const int64_t *rpF, const int32_t *ciF, double *vF, int64_t *bad_row)
 {
@@ -235,32 +271,39 @@ int orc_numeric(int64_t n, const int64_t *rpA, const int32_t *ciA, const double 
     for (int64_t t = 0; t < n; ++t) slot_of[t] = -1;
 
     for (int64_t j = 0; j < n; ++j) {
-        for (int64_t s = rpF[j]; s < rpF[j + 1]; ++s) {
-            slot_of[ciF[s]] = s;
-            vF[s] = 0.0;
-        }
-        for (int64_t p = rpA[j]; p < rpA[j + 1]; ++p) {
-            int64_t s = slot_of[ciA[p]];
-            if (s < 0) { st = ORC_EINVAL; break; }
-            vF[s] = vA[p];
-        }
+        /* rows are produced in order, so every pivot row is final in vF */
+        st = eliminate_row(j, rpA, ciA, vA, rpF, ciF, diag, slot_of, vF, vF + rpF[j]);
         if (st) break;
-        for (int64_t s = rpF[j]; s < diag[j]; ++s) {
-            int64_t h = ciF[s];
-            vF[s] = vF[s] / vF[diag[h]];
-            double l = vF[s];
-            for (int64_t q = diag[h] + 1; q < rpF[h + 1]; ++q) {
-                int64_t p = slot_of[ciF[q]];
-                if (p >= 0) vF[p] = vF[p] - l * vF[q];
-            }
-        }
         if (vF[diag[j]] == 0.0 && *bad_row < 0) *bad_row = j;
-        for (int64_t s = rpF[j]; s < rpF[j + 1]; ++s) slot_of[ciF[s]] = -1;
     }
     free(slot_of);
     free(diag);
     if (st) return st;
     return *bad_row >= 0 ? ORC_EZEROPIVOT : ORC_OK;
+}
+
+/* The listed rows alone, each eliminated against the pivot rows given in
+ * vF (for instance a factor computed elsewhere): row rows[r] goes to
+ * out[off[r] .. off[r+1]), off[r] = sum of the lengths of the rows before. */
+int orc_numeric_rows(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
+                     const int64_t *rpF, const int32_t *ciF, const double *vF, int64_t nrows,
+                     const int64_t *rows, double *out)
+{
+    int64_t *slot_of = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *diag = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!slot_of || !diag) { free(slot_of); free(diag); return ORC_ENOMEM; }
+    int st = find_diag(n, rpF, ciF, diag);
+    for (int64_t t = 0; t < n; ++t) slot_of[t] = -1;
+    int64_t o = 0;
+    for (int64_t r = 0; r < nrows && st == ORC_OK; ++r) {
+        const int64_t j = rows[r];
+        if (j < 0 || j >= n) { st = ORC_EINVAL; break; }
+        st = eliminate_row(j, rpA, ciA, vA, rpF, ciF, diag, slot_of, vF, out + o);
+        o += rpF[j + 1] - rpF[j];
+    }
+    free(slot_of);
+    free(diag);
+    return st;
 }
 
 /* ------------------------------------------------------------------------ */

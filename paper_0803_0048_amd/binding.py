@@ -43,7 +43,8 @@ class PatternInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz_a", C.c_int64), ("nnz_f", C.c_int64), ("nnz_l", C.c_int64),
                 ("nnz_u", C.c_int64), ("n_updates", C.c_int64), ("k", C.c_int32),
                 ("max_row", C.c_int32), ("max_lrow", C.c_int32), ("depth_l", C.c_int32),
-                ("depth_u", C.c_int32), ("overflow_rows", C.c_int32), ("flow_ready", C.c_int32)]
+                ("depth_u", C.c_int32), ("overflow_rows", C.c_int32), ("flow_ready", C.c_int32),
+                ("long_rows", C.c_int32)]
 
 
 _lib = None

@@ -204,17 +204,41 @@ __device__ __forceinline__ void sym_row(int32_t i, const int64_t* __restrict__ r
         if (lane == 0) cnt[i] = len;
         return;
     }
+    // sort (column, level) by column: bitonic network over the next power of
+    // two, padded with kBig (it fits: the map's capacity is a power of two)
+    uint32_t np2 = 1;
+    while (np2 < (uint32_t)len) np2 <<= 1;
+    for (uint32_t e = len + lane; e < np2; e += kWave) { W.ok[e] = kBig; W.ol[e] = 0; }
+    wave_sync();
+    for (uint32_t kk = 2; kk <= np2; kk <<= 1) {
+        for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (uint32_t e = lane; e < np2; e += kWave) {
+                const uint32_t f = e ^ jj;
+                if (f > e) {
+                    const int32_t a = W.ok[e], b = W.ok[f];
+                    if ((a > b) == ((e & kk) == 0)) {
+                        W.ok[e] = b;
+                        W.ok[f] = a;
+                        const int32_t la = W.ol[e];
+                        W.ol[e] = W.ol[f];
+                        W.ol[f] = la;
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
     const int64_t base = rpF[i];
     for (int32_t e = lane; e < len; e += kWave) {
-        int32_t key = W.ok[e];
-        int32_t rank = 0;
-        for (int32_t f = 0; f < len; ++f) rank += (W.ok[f] < key) ? 1 : 0;
-        ciF[base + rank] = key;
-        lvF[base + rank] = static_cast<uint8_t>(min(W.ol[e], 255));
-        if (key == i) diagF[i] = static_cast<int32_t>(base + rank);
+        const int32_t key = W.ok[e];
+        ciF[base + e] = key;
+        lvF[base + e] = static_cast<uint8_t>(min(W.ol[e], 255));
+        if (key == i) diagF[i] = static_cast<int32_t>(base + e);
     }
 }
 
+// kEnd: capacity of the endpoint map (and of the compacted row)
+template <int kEnd>
 __global__ __launch_bounds__(64) void k_sym_rows_lds(int32_t n, const int64_t* __restrict__ rpA,
                                                      const int32_t* __restrict__ ciA, int32_t k,
                                                      const int32_t* __restrict__ row_list,
@@ -223,20 +247,21 @@ __global__ __launch_bounds__(64) void k_sym_rows_lds(int32_t n, const int64_t* _
                                                      const int64_t* __restrict__ rpF,
                                                      int32_t* __restrict__ ciF,
                                                      uint8_t* __restrict__ lvF,
-                                                     int32_t* __restrict__ diagF) {
-    __shared__ int32_t ek[kSymEndCap], ev[kSymEndCap];
+                                                     int32_t* __restrict__ diagF,
+                                                     const uint8_t* __restrict__ tier_of, int tier) {
+    __shared__ int32_t ek[kEnd], ev[kEnd];
     __shared__ int32_t bk[kSymFrontCap], bv[kSymFrontCap], ck[kSymFrontCap], cv[kSymFrontCap];
     __shared__ int32_t f0v[kSymFrontCap], f0m[kSymFrontCap], f1v[kSymFrontCap], f1m[kSymFrontCap];
-    __shared__ int32_t ok[kSymEndCap], ol[kSymEndCap];
+    __shared__ int32_t ok[kEnd], ol[kEnd];
     __shared__ int32_t ctr[4];
     SymWs W;
     W.ek = ek; W.ev = ev; W.bk = bk; W.bv = bv; W.ck = ck; W.cv = cv;
     W.fv[0] = f0v; W.fm[0] = f0m; W.fv[1] = f1v; W.fm[1] = f1m;
     W.ok = ok; W.ol = ol; W.ctr = ctr;
-    W.emask = kSymEndCap - 1; W.fmask = kSymFrontCap - 1; W.fcap = kSymFrontCap;
+    W.emask = kEnd - 1; W.fmask = kSymFrontCap - 1; W.fcap = kSymFrontCap;
     for (int32_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
         int32_t i = row_list ? row_list[r] : r;
-        if (mode == 1 && cnt[i] < 0) continue;  // built by the global path
+        if (mode == 1 && tier_of && tier_of[i] != tier) continue;  // built by another tier
         sym_row(i, rpA, ciA, k, mode, cnt, rpF, ciF, lvF, diagF, W);
         wave_sync();
     }
@@ -257,7 +282,8 @@ __global__ __launch_bounds__(64) void k_sym_rows_global(int32_t n, const int64_t
                                                         int32_t* __restrict__ ciF,
                                                         uint8_t* __restrict__ lvF,
                                                         int32_t* __restrict__ diagF,
-                                                        int32_t* gscratch, uint32_t gcap) {
+                                                        int32_t* gscratch, uint32_t gcap,
+                                                        const uint8_t* __restrict__ tier_of) {
     int32_t* base = gscratch + (size_t)blockIdx.x * sym_global_scratch_ints(n, gcap);
     SymWs W;
     W.ek = base; W.ev = base + gcap;
@@ -270,37 +296,48 @@ __global__ __launch_bounds__(64) void k_sym_rows_global(int32_t n, const int64_t
     W.emask = gcap - 1; W.fmask = gcap - 1; W.fcap = (uint32_t)n;
     for (int32_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
         int32_t i = row_list ? row_list[r] : r;
+        if (mode == 1 && tier_of && tier_of[i] != 2) continue;
         sym_row(i, rpA, ciA, k, mode, cnt, rpF, ciF, lvF, diagF, W);
         wave_sync();
     }
 }
 
-hipError_t launch_sym_rows(bool global, int32_t n, const int64_t* rpA, const int32_t* ciA,
+hipError_t launch_sym_rows(int tier, int32_t n, const int64_t* rpA, const int32_t* ciA,
                            int32_t k, const int32_t* row_list, int32_t n_rows, int mode,
                            int32_t* cnt, const int64_t* rpF, int32_t* ciF, uint8_t* lvF,
-                           int32_t* diagF, int32_t* gscratch, uint32_t gcap, int32_t grid,
-                           hipStream_t s) {
+                           int32_t* diagF, const uint8_t* tier_of, int32_t* gscratch, uint32_t gcap,
+                           int32_t grid, hipStream_t s) {
     if (n_rows <= 0) return hipSuccess;
-    if (global) {
+    if (tier == 2) {
         hipLaunchKernelGGL(k_sym_rows_global, dim3(grid), dim3(64), 0, s, n, rpA, ciA, k,
-                           row_list, n_rows, mode, cnt, rpF, ciF, lvF, diagF, gscratch, gcap);
+                           row_list, n_rows, mode, cnt, rpF, ciF, lvF, diagF, gscratch, gcap, tier_of);
+    } else if (tier == 1) {
+        hipLaunchKernelGGL(k_sym_rows_lds<kSymEndCapLong>, dim3(grid), dim3(64), 0, s, n, rpA, ciA, k,
+                           row_list, n_rows, mode, cnt, rpF, ciF, lvF, diagF, tier_of, 1);
     } else {
-        hipLaunchKernelGGL(k_sym_rows_lds, dim3(grid), dim3(64), 0, s, n, rpA, ciA, k, row_list,
-                           n_rows, mode, cnt, rpF, ciF, lvF, diagF);
+        hipLaunchKernelGGL(k_sym_rows_lds<kSymEndCap>, dim3(grid), dim3(64), 0, s, n, rpA, ciA, k,
+                           row_list, n_rows, mode, cnt, rpF, ciF, lvF, diagF, tier_of, 0);
     }
     return hipGetLastError();
 }
 
-__global__ void k_collect_overflow(int32_t n, const int32_t* __restrict__ cnt, int32_t* row_list,
-                                   int32_t* n_over) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && cnt[i] < 0) row_list[atomicAdd(n_over, 1)] = i;
+__global__ void k_collect_overflow(int32_t n_rows, const int32_t* __restrict__ list,
+                                   const int32_t* __restrict__ cnt, int32_t* row_list, int32_t* n_over,
+                                   uint8_t* tier_of, int tier) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int32_t i = list ? list[r] : r;
+    if (cnt[i] < 0) {
+        row_list[atomicAdd(n_over, 1)] = i;
+        tier_of[i] = static_cast<uint8_t>(tier);
+    }
 }
 
-hipError_t launch_collect_overflow(int32_t n, const int32_t* cnt, int32_t* row_list,
-                                   int32_t* n_over, hipStream_t s) {
-    hipLaunchKernelGGL(k_collect_overflow, dim3((n + 255) / 256), dim3(256), 0, s, n, cnt,
-                       row_list, n_over);
+hipError_t launch_collect_overflow(int32_t n_rows, const int32_t* list, const int32_t* cnt, int32_t* row_list,
+                                   int32_t* n_over, uint8_t* tier_of, int tier, hipStream_t s) {
+    if (n_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_collect_overflow, dim3((n_rows + 255) / 256), dim3(256), 0, s, n_rows, list, cnt,
+                       row_list, n_over, tier_of, tier);
     return hipGetLastError();
 }
 

@@ -15,23 +15,27 @@ constexpr uint32_t kValBadRowptr = 1u, kValBadCol = 2u, kValUnsorted = 4u, kValN
 hipError_t launch_validate(int32_t n, int64_t nnz, const int64_t* rp, const int32_t* ci,
                            uint32_t* status, hipStream_t s);
 
-// LDS capacities of the fast symbolic path
-constexpr int kSymEndCap = 1024;   // endpoint map (row of F being built)
-constexpr int kSymFrontCap = 512;  // frontier maps and lists
+// LDS capacities of the symbolic paths: tier 0 for rows of up to about a
+// thousand entries, tier 1 (80 KB of LDS per wavefront) up to about four
+// thousand; longer rows use maps in global memory (tier 2)
+constexpr int kSymEndCap = 1024;      // endpoint map (row of F being built), tier 0
+constexpr int kSymEndCapLong = 4096;  // the same, tier 1
+constexpr int kSymFrontCap = 512;     // frontier maps and lists
 
 // Count (mode 0) or fill (mode 1) the level-<=k pattern of rows [0, n) (or of
-// the rows in row_list when non-null).  Fast path: maps in LDS; a row that
-// does not fit gets cnt = -1.  Global path: maps in `gscratch`.
-hipError_t launch_sym_rows(bool global, int32_t n, const int64_t* rpA, const int32_t* ciA,
+// the rows in row_list when non-null) with the maps of `tier`; a row that
+// does not fit gets cnt = -1 (mode 0).  In mode 1 a row is only built by the
+// tier that tier_of (nullable: tier 0 for all) records for it.
+hipError_t launch_sym_rows(int tier, int32_t n, const int64_t* rpA, const int32_t* ciA,
                            int32_t k, const int32_t* row_list, int32_t n_rows, int mode,
                            int32_t* cnt, const int64_t* rpF, int32_t* ciF, uint8_t* lvF,
-                           int32_t* diagF, int32_t* gscratch, uint32_t gcap, int32_t grid,
-                           hipStream_t s);
+                           int32_t* diagF, const uint8_t* tier_of, int32_t* gscratch, uint32_t gcap,
+                           int32_t grid, hipStream_t s);
 __host__ __device__ size_t sym_global_scratch_ints(int32_t n, uint32_t gcap);  // per block
 
-// rows with cnt < 0 -> row_list, *n_over
-hipError_t launch_collect_overflow(int32_t n, const int32_t* cnt, int32_t* row_list,
-                                   int32_t* n_over, hipStream_t s);
+// rows (of `list`, or 0..n_rows-1) with cnt < 0 -> row_list, *n_over; tier_of[row] = tier
+hipError_t launch_collect_overflow(int32_t n_rows, const int32_t* list, const int32_t* cnt, int32_t* row_list,
+                                   int32_t* n_over, uint8_t* tier_of, int tier, hipStream_t s);
 
 // exclusive scan of int32 counts into int64 offsets out[0..n], out[n] = total
 hipError_t launch_scan(const int32_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);

@@ -170,7 +170,7 @@ struct tpilu_pattern_s {
     int64_t n = 0, nnz_a = 0, nnz_f = 0, n_updates = 0;
     int32_t k = 0;
     PatStats st{};
-    int32_t depth_l = 0, depth_u = 0, overflow_rows = 0;
+    int32_t depth_l = 0, depth_u = 0, overflow_rows = 0, long_rows = 0;
     std::vector<DBuf> owned;
     // device arrays
     int64_t* rpA = nullptr;
@@ -834,30 +834,43 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
     // ---- a2: level-of-fill pattern, count pass
     TmpBufs T{P->al, {}};
     int32_t* cnt = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);
-    int32_t* over_list = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);
+    int32_t* over_list = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);  // rows past tier 0
+    int32_t* over2_list = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);  // rows past tier 1
     int32_t* over_n = (int32_t*)T.get(64);
+    uint8_t* tier_of = (uint8_t*)T.get((size_t)n + 4);
     int64_t* scan_tmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(n));
-    if (!cnt || !over_list || !over_n || !scan_tmp) return bail(fail(ctx, TPILU_E_NOMEM, "symbolic scratch"));
+    if (!cnt || !over_list || !over2_list || !over_n || !tier_of || !scan_tmp)
+        return bail(fail(ctx, TPILU_E_NOMEM, "symbolic scratch"));
+    HIPCHK(ctx, launch_fill_i32((int32_t*)tier_of, (n + 4) / 4, 0, s));
     const int sym_grid = std::min<int64_t>(n, (int64_t)ctx->num_cu * 4);
     trace("symbolic: count pass", n, k);
-    HIPCHK(ctx, launch_sym_rows(false, ni, P->rpA, P->ciA, k, nullptr, ni, 0, cnt, nullptr, nullptr,
-                                nullptr, nullptr, nullptr, 0, sym_grid, s));
-    HIPCHK(ctx, launch_fill_i32(over_n, 1, 0, s));
-    HIPCHK(ctx, launch_collect_overflow(ni, cnt, over_list, over_n, s));
-    int32_t n_over = 0;
+    HIPCHK(ctx, launch_sym_rows(0, ni, P->rpA, P->ciA, k, nullptr, ni, 0, cnt, nullptr, nullptr,
+                                nullptr, nullptr, nullptr, nullptr, 0, sym_grid, s));
+    HIPCHK(ctx, launch_fill_i32(over_n, 2, 0, s));
+    HIPCHK(ctx, launch_collect_overflow(ni, nullptr, cnt, over_list, over_n, tier_of, 1, s));
+    int32_t n_over = 0, n_over2 = 0;
     HIPCHK(ctx, hipMemcpyAsync(&n_over, over_n, sizeof(n_over), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
-    P->overflow_rows = n_over;
-    trace("symbolic: overflow rows", n_over);
+    if (n_over > 0) {
+        // long rows: the same construction with four times the map capacity
+        HIPCHK(ctx, launch_sym_rows(1, ni, P->rpA, P->ciA, k, over_list, n_over, 0, cnt, nullptr, nullptr,
+                                    nullptr, nullptr, nullptr, nullptr, 0, std::min(n_over, sym_grid), s));
+        HIPCHK(ctx, launch_collect_overflow(n_over, over_list, cnt, over2_list, over_n + 1, tier_of, 2, s));
+        HIPCHK(ctx, hipMemcpyAsync(&n_over2, over_n + 1, sizeof(n_over2), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+    }
+    P->long_rows = n_over - n_over2;
+    P->overflow_rows = n_over2;
+    trace("symbolic: long rows, overflow rows", n_over - n_over2, n_over2);
     int32_t* gscr = nullptr;
     uint32_t gcap = 0;
     int ggrid = 0;
-    if (n_over > 0) {
+    if (n_over2 > 0) {
         gcap = next_pow2(2 * (uint64_t)n + 2);
-        ggrid = std::min(n_over, 32);
+        ggrid = std::min(n_over2, 32);
         gscr = (int32_t*)T.get(sizeof(int32_t) * sym_global_scratch_ints(ni, gcap) * (size_t)ggrid);
         if (!gscr) return bail(fail(ctx, TPILU_E_NOMEM, "symbolic global scratch"));
-        HIPCHK(ctx, launch_sym_rows(true, ni, P->rpA, P->ciA, k, over_list, n_over, 0, cnt, nullptr,
+        HIPCHK(ctx, launch_sym_rows(2, ni, P->rpA, P->ciA, k, over2_list, n_over2, 0, cnt, nullptr, nullptr,
                                     nullptr, nullptr, nullptr, gscr, gcap, ggrid, s));
     }
     P->rpF = (int64_t*)P->take(sizeof(int64_t) * (size_t)(n + 1));
@@ -878,11 +891,14 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
     if (!P->ciF || !P->lvF || !P->diagF || !P->a2f || !P->lsd || !P->sptr)
         return bail(fail(ctx, TPILU_E_NOMEM, "pattern arrays"));
     // fill pass
-    HIPCHK(ctx, launch_sym_rows(false, ni, P->rpA, P->ciA, k, nullptr, ni, 1, cnt, P->rpF, P->ciF, P->lvF,
-                                P->diagF, nullptr, 0, sym_grid, s));
+    HIPCHK(ctx, launch_sym_rows(0, ni, P->rpA, P->ciA, k, nullptr, ni, 1, cnt, P->rpF, P->ciF, P->lvF,
+                                P->diagF, tier_of, nullptr, 0, sym_grid, s));
     if (n_over > 0)
-        HIPCHK(ctx, launch_sym_rows(true, ni, P->rpA, P->ciA, k, over_list, n_over, 1, cnt, P->rpF, P->ciF,
-                                    P->lvF, P->diagF, gscr, gcap, ggrid, s));
+        HIPCHK(ctx, launch_sym_rows(1, ni, P->rpA, P->ciA, k, over_list, n_over, 1, cnt, P->rpF, P->ciF,
+                                    P->lvF, P->diagF, tier_of, nullptr, 0, std::min(n_over, sym_grid), s));
+    if (n_over2 > 0)
+        HIPCHK(ctx, launch_sym_rows(2, ni, P->rpA, P->ciA, k, over2_list, n_over2, 1, cnt, P->rpF, P->ciF,
+                                    P->lvF, P->diagF, tier_of, gscr, gcap, ggrid, s));
     // A -> F map
     HIPCHK(ctx, launch_fill_i32((int32_t*)vstat, 16, 0, s));
     HIPCHK(ctx, launch_a2f(ni, P->rpA, P->ciA, P->rpF, P->ciF, P->a2f, vstat, s));
@@ -982,6 +998,7 @@ extern "C" TPILU_API tpilu_status tpilu_pattern_info(tpilu_pattern pat, tpilu_pa
     info->depth_l = pat->depth_l;
     info->depth_u = pat->depth_u;
     info->overflow_rows = pat->overflow_rows;
+    info->long_rows = pat->long_rows;
     info->flow_ready = pat->flow ? 1 : 0;
     return TPILU_OK;
 }

@@ -26,6 +26,9 @@ them):
 * ``stencil27_3d``: the 27-point 3-D stencil (diffusion on all 26 neighbours,
   convection on the 6 face neighbours), stand-in for the 27-point central
   differencing problem of Sec. 4.2.
+* ``random_uniform``: general sparse non-symmetric matrix with a given entry
+  count, columns uniform over the whole row (stand-in for the generated
+  matrices of the paper's Table 3, whose counts it matches).
 * ``random_banded``: general sparse non-symmetric matrix, a fixed number of
   off-diagonal columns per row drawn uniformly inside a band plus a few drawn
   anywhere, values U(-1, 1), diagonal 1.1 x the row's absolute sum, so the
@@ -279,6 +282,50 @@ def random_banded(n: int, seed: int, band: int = 2000, n_band: int = 8, n_any: i
                {"kind": "random_banded", "band": band, "n_band": n_band, "n_any": n_any})
 
 
+def random_uniform(n: int, nnz: int, seed: int, dominance: float = 1.1) -> CSR:
+    """General sparse non-symmetric, strictly diagonally dominant matrix with
+    exactly ``nnz`` stored entries, columns uniform over the whole row.
+
+    Row i holds its diagonal and c_i - 1 distinct off-diagonal columns drawn
+    uniformly from [0, n) minus {i}, c_i = nnz // n, plus one for the first
+    nnz % n rows.  Off-diagonal values are U(-1, 1); a_ii = dominance x the
+    row's absolute sum.  With d entries per row, ILU(1) keeps about d^2 / 3
+    per row (a pivot h < j contributes its upper part, d (1 - h/n) entries on
+    average, and column h is stored in d (1 - h/n) of the later rows).
+    """
+    rng = np.random.default_rng(seed)
+    base, extra = divmod(int(nnz), int(n))
+    cnt = np.full(n, base, dtype=np.int64)
+    cnt[:extra] += 1
+    if (cnt < 1).any() or (cnt > n).any():
+        raise ValueError("nnz must give every row 1..n entries")
+    off = cnt - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), off)
+    cols = rng.integers(0, n - 1, size=rows.size)
+    cols += cols >= rows  # skip the diagonal
+    # redraw repeated columns inside a row until every row's are distinct
+    while True:
+        order = np.lexsort((cols, rows))
+        rows, cols = rows[order], cols[order]
+        dup = np.zeros(rows.size, dtype=bool)
+        dup[1:] = (rows[1:] == rows[:-1]) & (cols[1:] == cols[:-1])
+        nd = int(dup.sum())
+        if nd == 0:
+            break
+        c = rng.integers(0, n - 1, size=nd)
+        cols[dup] = c + (c >= rows[dup])
+    offv = rng.uniform(-1.0, 1.0, size=rows.size)
+    absum = np.zeros(n)
+    np.add.at(absum, rows, np.abs(offv))
+    allr = np.concatenate([rows, np.arange(n, dtype=np.int64)])
+    allc = np.concatenate([cols, np.arange(n, dtype=np.int64)])
+    allv = np.concatenate([offv, dominance * absum])
+    order = np.lexsort((allc, allr))
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    rowptr[1:] = np.cumsum(cnt)
+    return CSR(n, rowptr, allc[order].astype(np.int32), allv[order].copy(), {"kind": "random_uniform", "nnz": int(nnz)})
+
+
 def random_pattern(n: int, density: float, seed: int, *, diag_dominant: bool = True,
                    batch: int | None = None, explicit_zeros: float = 0.0) -> CSR:
     """Small random non-symmetric matrix for sweeps and edge cases.
@@ -335,6 +382,28 @@ def config2(seed: int = 1002, n: int = 160_000):
     rng = np.random.default_rng(seed + 7919)
     b = rng.standard_normal(n)
     return {"name": f"random_banded_n{n}_ilu2", "A": A, "b": b, "k": 2, "restart": 30, "rtol": 1e-8}
+
+
+# Table 3 of the paper (ILU(1) on its generated general sparse matrices):
+# n -> (initial entries, final entries)
+PAPER_K1_COUNTS = {40_000: (5_120_950, 196_223_519), 80_000: (6_960_983, 195_202_037),
+                   160_000: (9_832_794, 198_969_083), 320_000: (14_090_553, 206_489_590)}
+
+
+def config_paper_k1(n: int = 160_000, seed: int = 1007, per_row: float | None = None):
+    """Paper-scale ILU(1): a uniform random sparse matrix with Table 3's entry
+    count for this n (the generator behind the table is not available, so the
+    count is matched, not the matrix).  ``per_row`` overrides the entries per
+    row (smaller n at the same row length, for parity tests)."""
+    if per_row is None:
+        nnz = PAPER_K1_COUNTS[n][0]
+    else:
+        nnz = int(round(per_row * n))
+    A = random_uniform(n, nnz, seed)
+    rng = np.random.default_rng(seed + 7919)
+    b = rng.standard_normal(n)
+    return {"name": f"paper_scale_random_n{n}_ilu1", "A": A, "b": b, "k": 1,
+            "paper_final_entries": PAPER_K1_COUNTS.get(n, (None, None))[1]}
 
 
 def config3(seed: int = 1003, m: int = 64, k: int = 2):

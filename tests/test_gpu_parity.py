@@ -130,10 +130,11 @@ def test_small_random_sweep(seed):
         _full(A, k, b)
 
 
-def test_overflow_rows_take_global_path():
-    """An arrow matrix (dense last row and column) makes rows longer than the
-    LDS maps of the fast symbolic path; they are rebuilt in global memory."""
-    n = 3000
+@pytest.mark.parametrize("n", [3000, 5000])
+def test_overflow_rows_take_global_path(n):
+    """An arrow matrix (dense last row and column) makes a row longer than the
+    LDS maps of the fast symbolic path: at 3,000 entries it is rebuilt with
+    the larger LDS maps, at 5,000 in global memory."""
     M = np.zeros((n, n), bool)
     M[np.arange(n), np.arange(n)] = True
     M[-1, :] = True
@@ -146,7 +147,10 @@ def test_overflow_rows_take_global_path():
     np.add.at(rp, rows + 1, 1)
     A = I.CSR(n, np.cumsum(rp), cols.astype(np.int32), vals[rows, cols])
     pat, _, _ = _full(A, 2, rng.standard_normal(n))
-    assert pat.info["overflow_rows"] >= 1
+    if n <= 4000:
+        assert pat.info["long_rows"] >= 1 and pat.info["overflow_rows"] == 0
+    else:
+        assert pat.info["overflow_rows"] >= 1
     # a 3000-entry row does not fit the dataflow kernel's LDS staging
     assert pat.info["flow_ready"] == 0
     ctx = T.context(0)
@@ -638,3 +642,60 @@ def test_stencil27_50cubed(k):
     both solves bit for bit."""
     c = I.config_stencil27(m=50, k=k)
     _full(c["A"], k, c["b"])
+
+
+# ----------------------------------------------------------------------------------
+# Paper-scale ILU(1) (Table 3's general sparse matrices, about 1,250 entries per row
+# of F): long rows through the larger symbolic maps and the pivot-serial kernel
+# ----------------------------------------------------------------------------------
+PAPER_ROW = 9_832_794 / 160_000  # entries per row of A in Table 3's 160K matrix
+
+
+def test_paper_scale_rows_small_bits():
+    """Rows of the paper's length (~1,000 entries of F, up to ~1,550) on a
+    3,000-row matrix: pattern, factor and both solves bit for bit."""
+    c = I.config_paper_k1(n=3000, per_row=PAPER_ROW)
+    pat, _, _ = _full(c["A"], 1, c["b"])
+    assert pat.info["long_rows"] > 0
+
+
+def _k1_row_pattern(A, j):
+    """Level <= 1 pattern of row j from the definition of the levels: an entry
+    has level 1 exactly when it is reached through a pivot h < j of level 0
+    with a level-0 entry (h, t), t > h; stored entries have level 0."""
+    a = A.col[A.rowptr[j]:A.rowptr[j + 1]].astype(np.int64)
+    lev = {int(t): 0 for t in a}
+    for h in a[a < j]:
+        ah = A.col[A.rowptr[h]:A.rowptr[h + 1]].astype(np.int64)
+        for t in ah[ah > h]:
+            lev.setdefault(int(t), 1)
+    cols = np.array(sorted(lev), dtype=np.int64)
+    return cols, np.array([lev[int(t)] for t in cols], dtype=np.uint8)
+
+
+def test_paper_scale_160k_sampled_rows():
+    """Table 3's 160K size at full scale (~2 x 10^8 entries of F): sampled
+    rows' patterns against the level definition, and their factor rows
+    against the oracle's elimination of that row on the GPU's pivot rows
+    (a row of F depends only on A's row and its pivots' final U rows)."""
+    c = I.config_paper_k1()
+    A = c["A"]
+    pat = T.symbolic(g(A.rowptr), g(A.col), 1)
+    info = pat.info
+    log(f"[gpu] paper-scale 160K: nnz_f {info['nnz_f']} long rows {info['long_rows']} "
+        f"overflow {info['overflow_rows']} depth {info['depth_l']}")
+    f = T.numeric(pat, g(A.val))
+    ex = pat.export()
+    rpF = ex["rowptr"].cpu().numpy()
+    ciF = ex["col"].cpu().numpy()
+    lvF = ex["level"].cpu().numpy()
+    vF = f.cpu().numpy()
+    rng = np.random.default_rng(160)
+    rows = np.unique(np.concatenate([[0, 1, A.n // 2, A.n - 1], rng.integers(0, A.n, 60)]))
+    for j in rows:
+        cols, lev = _k1_row_pattern(A, j)
+        assert np.array_equal(ciF[rpF[j]:rpF[j + 1]], cols), f"pattern of row {j}"
+        assert np.array_equal(lvF[rpF[j]:rpF[j + 1]], lev), f"levels of row {j}"
+    ref = O.numeric_rows(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, rows)
+    for j, r in zip(rows, ref):
+        assert np.array_equal(vF[rpF[j]:rpF[j + 1]].view(np.int64), r.view(np.int64)), f"factor row {j}"

@@ -821,3 +821,15 @@ def test_bicgstab_converges_and_edge_cases():
     assert z["iters"] == 0 and not z["x"].any()
     m = O.bicgstab(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, c["b"], maxit=3, rtol=1e-14)
     assert m["iters"] == 3 and m["status"] == O.ENOTCONV
+
+
+def test_numeric_rows_reproduces_rows_of_the_factor():
+    """Eliminating single rows against the finished factor gives that factor's
+    rows (a row of F depends only on A's row and the final U rows of its
+    pivots), in any order of the rows."""
+    A = I.random_pattern(200, 0.04, seed=31)
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, 2)
+    vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
+    rows = np.array([199, 0, 57, 123, 57])
+    for j, r in zip(rows, O.numeric_rows(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, rows)):
+        assert np.array_equal(r.view(np.int64), vF[rpF[j]:rpF[j + 1]].view(np.int64))
