@@ -230,6 +230,7 @@ def main():
         out["extras"]["incomplete_inverse"] = inverse_extra(T, torch, pat, av, fout, bv, restart, rtol, maxit,
                                                             gmres_ms, ginfo, n, nnz_f, nnz_l)
         out["extras"]["stencil27"] = stencil27_extra(T, I, torch, dev, ctx)
+        out["extras"]["paper_scale_ilu1"] = paper_scale_extra(T, I, torch, dev, ctx)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, k, np)
@@ -313,6 +314,51 @@ def extras(T, I, torch, np, dev, ctx):
     T.check(pat5)
     res["reverse_mode"] = {"instances": A5.batch, "n": A5.n, "forward_ms": fms, "backward_ms": bms,
                            "backward_over_forward": bms / fms}
+    return res
+
+
+def paper_scale_extra(T, I, torch, dev, ctx):
+    """ILU(1) at the size of the paper's Table 3 (n = 160,000, 9,832,794
+    entries, uniform random columns; the paper's factor has 198,969,083
+    entries): symbolic (host clock), numeric and the two solves (HIP events,
+    median of 3).  The paper's figures for its own matrix (Tables 3 and 4,
+    2008-era CPUs) are context, not a baseline."""
+    log("paper-scale ILU(1), n = 160,000")
+    c = I.config_paper_k1()
+    A = c["A"]
+    rp = torch.from_numpy(A.rowptr).to(dev)
+    ci = torch.from_numpy(A.col).to(dev)
+    av = torch.from_numpy(A.val).to(dev)
+    bv = torch.from_numpy(c["b"]).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pat = T.symbolic(rp, ci, 1)
+    torch.cuda.synchronize()
+    sym_ms = (time.perf_counter() - t0) * 1e3
+    f = T.numeric(pat, av)
+    y = torch.empty_like(bv)
+    T.apply(pat, f, bv, out=y)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    for kk in range(3):
+        ctx.read_timing(kk)
+    num, fwd, bwd = [], [], []
+    for _ in range(3):
+        T.numeric(pat, av, out=f, check=False)
+        T.apply(pat, f, bv, out=y)
+        num.append(ctx.read_timing(ctx.KERNEL_NUMERIC)[0])
+        fwd.append(ctx.read_timing(ctx.KERNEL_FORWARD)[0])
+        bwd.append(ctx.read_timing(ctx.KERNEL_BACKWARD)[0])
+    ctx.set_timing(False)
+    T.check(pat)
+    info = pat.info
+    res = {"n": info["n"], "nnz_a": info["nnz_a"], "nnz_f": info["nnz_f"],
+           "paper_nnz_f": c["paper_final_entries"], "updates": info["n_updates"], "max_row": info["max_row"],
+           "depth_l": info["depth_l"], "symbolic_ms": sym_ms, "numeric_ms": statistics.median(num),
+           "forward_ms": statistics.median(fwd), "backward_ms": statistics.median(bwd),
+           "paper_context_s": {"sequential_symbolic": 140.2, "sequential_numeric": 2112.7,
+                               "tpilu_60_cores_symbolic": 2.5, "tpilu_60_cores_numeric": 64.4}}
+    del pat, f, y, av, bv, rp, ci
     return res
 
 
