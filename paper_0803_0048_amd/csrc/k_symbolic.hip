@@ -468,6 +468,9 @@ hipError_t launch_a2f(int32_t n, const int64_t* rpA, const int32_t* ciA, const i
 // One wavefront per row j; row j's columns are staged in LDS and every
 // candidate t of the pivot row is binary-searched there.
 // ------------------------------------------------------------------------------------
+constexpr int kSchedDir = 256;   // buckets of the column directory of row j
+constexpr int kSchedUnroll = 8;  // 64-column chunks of a pivot row loaded per round
+
 __global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restrict__ rpF,
                                               const int32_t* __restrict__ ciF,
                                               const int32_t* __restrict__ diagF, int mode,
@@ -475,6 +478,13 @@ __global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restri
                                               const int64_t* __restrict__ sptr,
                                               int32_t* __restrict__ sq, int32_t* __restrict__ sp) {
     extern __shared__ int32_t colsj[];
+    // Row j's sorted columns get a directory: bucket b of [c_min, c_max]
+    // holds the columns at positions dir[b] .. dir[b+1]-1, so a candidate t
+    // is searched among a handful of columns instead of the whole row.
+    __shared__ int32_t dir[kSchedDir + 1];
+    // the pivots of the row, 64 at a time: diagonal slot and row end of each
+    __shared__ int32_t pdh[kWave], phe[kWave];
+    __shared__ int64_t pout[kWave];
     const int lane = lane_id();
     for (int32_t j = blockIdx.x; j < n; j += gridDim.x) {
         const int64_t rs = rpF[j], re = rpF[j + 1];
@@ -484,36 +494,73 @@ __global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restri
         if (mode == 0)
             for (int64_t s = dj + lane; s < re; s += kWave) scount[s] = 0;
         wave_sync();
-        for (int64_t s = rs; s < dj; ++s) {
-            const int32_t h = ciF[s];
-            const int64_t dh = diagF[h];
-            const int64_t he = rpF[h + 1];
-            if (mode == 0 && lane == 0) lsd[s] = static_cast<int32_t>(dh);
-            int32_t found = 0;
-            int64_t out = mode == 1 ? sptr[s] : 0;
-            for (int64_t q0 = dh + 1; q0 < he; q0 += kWave) {
-                const int64_t q = q0 + lane;
-                int32_t pos = -1;
-                if (q < he) {
-                    const int32_t t = ciF[q];
-                    int32_t lo = static_cast<int32_t>(s - rs) + 1, hi = len - 1;
-                    while (lo <= hi) {
-                        int32_t mid = (lo + hi) >> 1;
-                        int32_t c = colsj[mid];
-                        if (c == t) { pos = mid; break; }
-                        if (c < t) lo = mid + 1;
-                        else hi = mid - 1;
+        const int32_t cmin = colsj[0];
+        const int64_t range = (int64_t)colsj[len - 1] - cmin + 1;
+        for (int32_t b = lane; b <= kSchedDir; b += kWave) {
+            // first position whose bucket is >= b
+            int32_t lo = 0, hi = len;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                const int64_t bm = ((int64_t)colsj[mid] - cmin) * kSchedDir / range;
+                if (bm < b) lo = mid + 1;
+                else hi = mid;
+            }
+            dir[b] = lo;
+        }
+        wave_sync();
+        for (int64_t s0 = rs; s0 < dj; s0 += kWave) {
+            const int32_t np = static_cast<int32_t>(min<int64_t>(kWave, dj - s0));
+            if (lane < np) {
+                const int32_t h = ciF[s0 + lane];
+                const int32_t dh = diagF[h];
+                pdh[lane] = dh;
+                phe[lane] = static_cast<int32_t>(rpF[h + 1]);
+                pout[lane] = mode == 1 ? sptr[s0 + lane] : 0;
+                if (mode == 0) lsd[s0 + lane] = dh;
+            }
+            wave_sync();
+            for (int32_t p = 0; p < np; ++p) {
+                const int64_t s = s0 + p;
+                const int64_t dh = pdh[p], he = phe[p];
+                const int64_t out = pout[p];
+                const int32_t lo0 = static_cast<int32_t>(s - rs) + 1;
+                int32_t found = 0;
+                // kSchedUnroll chunks of the pivot row per round: their column
+                // loads are issued together (clamped, in bounds; extras unused)
+                for (int64_t q0 = dh + 1; q0 < he; q0 += kSchedUnroll * kWave) {
+                    int32_t tv[kSchedUnroll];
+#pragma unroll
+                    for (int u = 0; u < kSchedUnroll; ++u)
+                        tv[u] = ciF[min<int64_t>(q0 + u * kWave + lane, he - 1)];
+#pragma unroll
+                    for (int u = 0; u < kSchedUnroll; ++u) {
+                        const int64_t q = q0 + u * kWave + lane;
+                        int32_t pos = -1;
+                        const int64_t off = (int64_t)tv[u] - cmin;
+                        if (q < he && off >= 0 && off < range) {
+                            const int32_t t = tv[u];
+                            const int32_t b = static_cast<int32_t>(off * kSchedDir / range);
+                            int32_t lo = max(lo0, dir[b]), hi = dir[b + 1] - 1;
+                            while (lo <= hi) {
+                                const int32_t mid = (lo + hi) >> 1;
+                                const int32_t c = colsj[mid];
+                                if (c == t) { pos = mid; break; }
+                                if (c < t) lo = mid + 1;
+                                else hi = mid - 1;
+                            }
+                        }
+                        const uint64_t m = __ballot(pos >= 0);
+                        if (mode == 1 && pos >= 0) {
+                            const int32_t rank = __popcll(m & ((1ull << lane) - 1ull));
+                            sq[out + found + rank] = static_cast<int32_t>(q);
+                            sp[out + found + rank] = static_cast<int32_t>(rs + pos);
+                        }
+                        found += __popcll(m);
                     }
                 }
-                const uint64_t m = __ballot(pos >= 0);
-                if (mode == 1 && pos >= 0) {
-                    const int32_t rank = __popcll(m & ((1ull << lane) - 1ull));
-                    sq[out + found + rank] = static_cast<int32_t>(q);
-                    sp[out + found + rank] = static_cast<int32_t>(rs + pos);
-                }
-                found += __popcll(m);
+                if (mode == 0 && lane == 0) scount[s] = found;
             }
-            if (mode == 0 && lane == 0) scount[s] = found;
+            wave_sync();
         }
         wave_sync();
     }

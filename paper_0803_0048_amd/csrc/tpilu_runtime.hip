@@ -54,15 +54,23 @@ namespace {
 
 constexpr uint64_t kDefaultWaitUs = 10000000ull;  // 10 s per dependency wait
 
-// Wavefronts of the persistent kernels.  Every waiting wavefront polls the
-// memory side, so past the parallelism a dependency graph can use, more
-// wavefronts only slow each hand-off down (measured on MI355X: the forward
-// solve of the n=160,000 ILU(2) matrix takes 12 ms with 128 wavefronts and
-// 33 ms with 8192).  Narrow graphs (few rows per level) get few wavefronts.
-constexpr int32_t kSolveWavesNarrow = 192;
-constexpr int32_t kSolveWavesWide = 256;
-constexpr int32_t kNumericWaves = 1024;
-constexpr int32_t kFlowWaves = 1024;
+// Wavefronts of the wavefront-per-row solves.  Every waiting wavefront polls
+// the memory side, so past the parallelism a dependency graph can use, more
+// wavefronts only slow each hand-off down; long rows, on the other hand,
+// keep a wavefront busy and want more rows in flight.  Measured on MI355X
+// (forward solve, best grid): random banded n=160,000 ILU(2), 13 rows per
+// level, 12 ms at 128-192 and 33 ms at 8192; the same ILU(1), 46 rows per
+// level and 18 entries per row half: 3.1 ms at 256, 3.5 at 1024; paper-scale
+// random ILU(1), 40 rows per level and 640 entries per half: 5.2 ms at 1024,
+// 22 at 192; 27-point 50^3 ILU(3): 1.9 ms at 1024, 3.2 at 256.
+constexpr int32_t kSolveWavesNarrow = 192;   // fewer than kNarrowWidth rows per level
+constexpr int32_t kSolveWavesMid = 256;      // fewer than 64 rows per level, short rows
+constexpr int32_t kSolveWavesWide = 1024;
+// The numeric kernels run every resident wavefront: with their loads batched
+// a row is short, and the rows in flight set the rate (1024 wavefronts ->
+// resident maximum, pivot-serial: 27-point 90^3 ILU(1) 15.7 -> 8.4 ms,
+// 7-point 64^3 ILU(1) 1.9 -> 1.2 ms, paper-scale random ILU(1) 69.7 ->
+// 58.5 ms; dataflow: random banded ILU(1) 1.37 -> 0.83 ms, ILU(2) unchanged).
 // Dataflow numeric kernel (automatic choice) when the L rows average at least
 // kFlowMinL entries, an entry receives fewer than kFlowMaxChain updates on
 // average and a dependency level holds fewer than kFlowMaxWidth rows.  On
@@ -75,8 +83,8 @@ constexpr int64_t kFlowMaxChain = 12;
 constexpr int64_t kFlowMaxWidth = 64;
 constexpr int32_t kAdjointWaves = 512;
 constexpr int32_t kAdjointBatchWaves = 1024;  // batched reverse elimination (3-D 7-point 32^3 x16: 1.9 ms, 2.2 at 512)
-constexpr int32_t kInverseWaves = 512;
-constexpr int64_t kNarrowWidth = 64;   // n / depth below this: narrow
+constexpr int32_t kInverseWaves = 1024;  // incomplete inverses (n=160,000 ILU(2): 7.0 ms, 8.3 at 512)
+constexpr int64_t kNarrowWidth = 32;   // n / depth below this: narrow
 constexpr int64_t kLevelLaneMax = 14;  // level computation: lane per node below this many dependencies
 constexpr int64_t kLevelWideMax = 60;  // wavefront per node: the wide window below this, else the narrow one
 constexpr int32_t kLevelWavesWide = 768;
@@ -357,8 +365,7 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
     HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, pat->ctl, true, ctx->stream));
     const int grid = ctx->grid_override
                          ? ctx->grid_override
-                         : std::min(batch == 1 ? (flow ? kFlowWaves : kNumericWaves) : 1 << 30,
-                                    numeric_grid(batch, pat->st.max_row, pat->st.max_lrow, flow, ctx->num_cu));
+                         : numeric_grid(batch, pat->st.max_row, pat->st.max_lrow, flow, ctx->num_cu);
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_NUMERIC);
         HIPCHK(ctx, launch_numeric(pdev(ctx, pat, RowKernel::Numeric, true), a_val, batch, f_val, pat->ctl,
@@ -402,7 +409,10 @@ int32_t solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool backwa
     if (mode == 2) return 0;
     if (mode == 3) return -(ctx->grid_override ? ctx->grid_override : kLaneWaves);
     if (ctx->grid_override) return ctx->grid_override;
-    return n / depth < kNarrowWidth ? kSolveWavesNarrow : kSolveWavesWide;
+    const int64_t width = n / depth;
+    if (width < kNarrowWidth) return kSolveWavesNarrow;
+    if (width < 64 && half < 64 * n) return kSolveWavesMid;
+    return kSolveWavesWide;
 }
 
 tpilu_status enqueue_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val, int32_t batch,
