@@ -104,9 +104,10 @@ __global__ __launch_bounds__(64) void k_adj_solve_u(PatDev P, AdjPat T, const do
                                                     double* z, Ctl* ctl, uint64_t spin_limit) {
     const int lane = lane_id();
     const uint32_t ntask = (uint32_t)P.n * (uint32_t)B;
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= ntask) break;
+        uint32_t t;
+        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
         const int32_t i = T.permUT[t / (uint32_t)B];
         const int32_t b = (int32_t)(t % (uint32_t)B);
         // rows j < i of column i, taken in ascending j
@@ -133,9 +134,10 @@ __global__ __launch_bounds__(64) void k_adj_solve_l(PatDev P, AdjPat T, const do
                                                     double* w, Ctl* ctl, uint64_t spin_limit) {
     const int lane = lane_id();
     const uint32_t ntask = (uint32_t)P.n * (uint32_t)B;
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= ntask) break;
+        uint32_t t;
+        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
         const int32_t i = T.permLT[t / (uint32_t)B];
         const int32_t b = (int32_t)(t % (uint32_t)B);
         // rows j > i of column i, taken in descending j
@@ -170,9 +172,10 @@ __global__ __launch_bounds__(64) void k_adj_solve_u_batch(PatDev P, AdjPat T, co
     const int lane = lane_id();
     const int32_t G = (B + kWave - 1) / kWave;
     const uint32_t ntask = (uint32_t)P.n * (uint32_t)G;
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= ntask) break;
+        uint32_t t;
+        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
         const int32_t i = T.permUT[t / (uint32_t)G];
         const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
         if (col < B) {
@@ -210,9 +213,10 @@ __global__ __launch_bounds__(64) void k_adj_solve_l_batch(PatDev P, AdjPat T, co
     const int lane = lane_id();
     const int32_t G = (B + kWave - 1) / kWave;
     const uint32_t ntask = (uint32_t)P.n * (uint32_t)G;
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= ntask) break;
+        uint32_t t;
+        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
         const int32_t i = T.permLT[t / (uint32_t)G];
         const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
         if (col < B) {
@@ -302,9 +306,10 @@ __global__ __launch_bounds__(64) void k_adj_numeric(PatDev P, AdjPat T, const do
     extern __shared__ double W[];
     const int lane = lane_id();
     const uint32_t ntask = (uint32_t)P.n * (uint32_t)B;
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= ntask) break;
+        uint32_t t;
+        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
         const int32_t j = T.permLT[t / (uint32_t)B];
         const int32_t b = (int32_t)(t % (uint32_t)B);
         const int64_t rs = P.rpF[j], re = P.rpF[j + 1], dj = P.diagF[j];
@@ -390,9 +395,10 @@ __global__ __launch_bounds__(64) void k_adj_numeric_batch(PatDev P, AdjPat T, co
     const int lane = lane_id();
     const int32_t G = (B + kWave - 1) / kWave;
     const uint32_t ntask = (uint32_t)P.n * (uint32_t)G;
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= ntask) break;
+        uint32_t t;
+        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
         const int32_t j = T.permLT[t / (uint32_t)G];
         const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
         const int64_t rs = P.rpF[j], re = P.rpF[j + 1], dj = P.diagF[j];

@@ -470,9 +470,10 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
     const int32_t n = P.n;
     const int32_t G = (B + kWave - 1) / kWave;
     const uint32_t ntask = (uint32_t)n * (uint32_t)G;
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= ntask) break;
+        uint32_t t;
+        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
         const int32_t jr = (int32_t)(t / (uint32_t)G);
         const int32_t j = P.permL ? P.permL[jr] : jr;
         const int32_t g = (int32_t)(t % (uint32_t)G);

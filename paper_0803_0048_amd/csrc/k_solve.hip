@@ -141,9 +141,11 @@ __global__ __launch_bounds__(64) void k_solve_lanes(PatDev P, const double* __re
     const int32_t n = P.n;
     const int32_t* perm = kBackward ? P.permU : P.permL;
     const int64_t tr0 = kBackward ? 2 * (int64_t)n : 0;
+    const uint32_t nchunk = (uint32_t)(((int64_t)n + kWave - 1) / kWave);
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if ((int64_t)t * kWave >= n) break;
+        uint32_t t;
+        if (!next_pos(ctl, nchunk, 1u, (uint32_t)P.parts, run, t)) break;
         const int64_t r = (int64_t)t * kWave + lane;
         const bool valid = r < n;
         int32_t i = 0;
@@ -254,9 +256,10 @@ __global__ __launch_bounds__(64) void k_forward_batch(PatDev P, const double* __
     const int32_t n = P.n;
     const int32_t G = (B + kWave - 1) / kWave;
     const uint32_t ntask = (uint32_t)n * (uint32_t)G;
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= ntask) break;
+        uint32_t t;
+        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
         const int32_t ir = (int32_t)(t / (uint32_t)G);
         const int32_t i = P.permL ? P.permL[ir] : ir;
         const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
@@ -295,9 +298,10 @@ __global__ __launch_bounds__(64) void k_backward_batch(PatDev P, const double* _
     const int32_t n = P.n;
     const int32_t G = (B + kWave - 1) / kWave;
     const uint32_t ntask = (uint32_t)n * (uint32_t)G;
+    PosRun run;
     for (;;) {
-        const uint32_t t = wave_ticket(ctl);
-        if (t >= ntask) break;
+        uint32_t t;
+        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
         const int32_t ir = (int32_t)(t / (uint32_t)G);
         const int32_t i = P.permU ? P.permU[ir] : n - 1 - ir;
         const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;

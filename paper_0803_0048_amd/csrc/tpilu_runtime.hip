@@ -162,12 +162,14 @@ int32_t row_group(RowKernel kind, int64_t n, int64_t depth) {
 }
 
 // Wavefronts of the batched kernels (a task is one row for 64 instances).
-// Their waits re-read all pending values of a chunk in one round trip, and
-// then extra wavefronts cost little: measured on MI355X, the batched solves
-// are flat from 256-384 wavefronts on (2-D 5-point 128^2 ILU(2) x256, x512
-// ILU(1); 3-D 7-point 32^3 ILU(1) x16, 64^3 x64) and the numeric kernel
-// improves up to the resident maximum.
-constexpr int32_t kBatchSolveWaves = 512;
+// Their waits re-read all pending values of a chunk in one round trip and
+// their tasks come from the eight counters, and then extra wavefronts cost
+// little: measured on MI355X, the batched solves are flat from 256-384
+// wavefronts on (2-D 5-point 128^2 ILU(2) x256, x512 ILU(1); 3-D 7-point
+// 32^3 ILU(1) x16, 64^3 x64) and the transposed ones best at 1024 (32^3
+// x16: 0.59 ms, 0.70 at 512); the numeric kernel improves up to the
+// resident maximum.
+constexpr int32_t kBatchSolveWaves = 1024;
 
 // Position counters the row kernels draw from (see next_pos).
 int32_t ticket_parts(RowKernel, int64_t, int64_t) { return kTicketParts; }
