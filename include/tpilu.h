@@ -112,8 +112,9 @@ TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t waves);
  * 2 = one workgroup (16 wavefronts on one CU), 3 = a lane per row (64 rows per
  * wavefront) over the whole device.  The same setting picks the shape of the
  * two products of tpilu_apply_inverse: 1 a wavefront per row, 3 a thread per
- * row, 0 by row length (thread per row below 32 entries per row of F on
- * average).  Same bits in every mode. */
+ * row, 0 automatic (64 rows per wavefront staged through LDS when the
+ * longest row of F is at most 1.5 x the average and the average at most 512
+ * entries, else a wavefront per row).  Same bits in every mode. */
 enum { TPILU_SOLVER_AUTO = 0, TPILU_SOLVER_DEVICE = 1, TPILU_SOLVER_WORKGROUP = 2, TPILU_SOLVER_LANES = 3 };
 TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode);
 

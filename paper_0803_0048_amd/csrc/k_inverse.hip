@@ -222,9 +222,11 @@ hipError_t launch_inverse(const PatDev& P, const InvSched& S, const double* f_va
 // ----------------------------------------------------------------------------------
 // applying them: two products
 // ----------------------------------------------------------------------------------
+// one wavefront per row: products in parallel, their sum in order (one
+// lane's chain broadcast across the wavefront; best for long, uneven rows)
 template <bool kUpper>
-__global__ __launch_bounds__(64) void k_apply_inverse(PatDev P, const double* __restrict__ G,
-                                                      const double* __restrict__ in, double* __restrict__ out) {
+__global__ __launch_bounds__(64) void k_apply_inverse_wave(PatDev P, const double* __restrict__ G,
+                                                           const double* __restrict__ in, double* __restrict__ out) {
     const int lane = lane_id();
     for (int32_t i = blockIdx.x; i < P.n; i += gridDim.x) {
         const int64_t dj = P.diagF[i];
@@ -238,6 +240,65 @@ __global__ __launch_bounds__(64) void k_apply_inverse(PatDev P, const double* __
         }
         if (!kUpper) s = s + in[i];
         if (lane == 0) out[i] = s;
+    }
+}
+
+// 64 rows per wavefront, lane r owning row r0 + r and adding its products in
+// order.  The wavefront stages the next kTile entries of all 64 rows in LDS
+// with coalesced loads (each load instruction covers kTile consecutive
+// entries of 64 / kTile rows), then every lane walks its own row there: the
+// in-order sum of a row is one lane's chain, so the wavefront's 64 chains run
+// side by side instead of one at a time.
+constexpr int kTile = 16;
+constexpr int kTileStride = kTile + 1;  // odd stride: lanes reading their rows hit distinct banks
+
+template <bool kUpper>
+__global__ __launch_bounds__(64) void k_apply_inverse_tile(PatDev P, const double* __restrict__ G,
+                                                      const double* __restrict__ in, double* __restrict__ out) {
+    __shared__ double tv[kWave * kTileStride];
+    __shared__ int32_t tc[kWave * kTileStride];
+    const int lane = lane_id();
+    for (int64_t r0 = (int64_t)blockIdx.x * kWave; r0 < P.n; r0 += (int64_t)gridDim.x * kWave) {
+        const int64_t i = r0 + lane;
+        const bool has = i < P.n;
+        int64_t a = 0, b = 0;
+        if (has) {
+            const int64_t dj = P.diagF[i];
+            a = kUpper ? dj : P.rpF[i];
+            b = kUpper ? P.rpF[i + 1] : dj;
+        }
+        int64_t len = b - a, maxlen = len;
+        for (int off = 32; off > 0; off >>= 1) maxlen = max(maxlen, (int64_t)__shfl_xor(maxlen, off));
+        double s = 0.0;
+        for (int64_t k0 = 0; k0 < maxlen; k0 += kTile) {
+            // stage entries k0 .. k0+kTile-1 of every row: instruction u loads
+            // rows u*(64/kTile) .. +(64/kTile)-1, kTile entries each
+#pragma unroll
+            for (int u = 0; u < kTile; ++u) {
+                const int rr = u * (kWave / kTile) + lane / kTile;  // row of the tile
+                const int kk = lane % kTile;                        // entry of that row's slice
+                const int64_t ar = __shfl(a, rr), br = __shfl(b, rr);
+                const int64_t e = ar + k0 + kk;
+                if (e < br) {
+                    tv[rr * kTileStride + kk] = G[e];
+                    tc[rr * kTileStride + kk] = P.ciF[e];
+                }
+            }
+            wave_sync();
+            const int32_t cnt = (int32_t)max<int64_t>(0, min<int64_t>(kTile, len - k0));
+            double prod[kTile];
+#pragma unroll
+            for (int kk = 0; kk < kTile; ++kk)
+                prod[kk] = kk < cnt ? tv[lane * kTileStride + kk] * in[tc[lane * kTileStride + kk]] : 0.0;
+#pragma unroll
+            for (int kk = 0; kk < kTile; ++kk)
+                if (kk < cnt) s = s + prod[kk];
+            wave_sync();
+        }
+        if (has) {
+            if (!kUpper) s = s + in[i];
+            out[i] = s;
+        }
     }
 }
 
@@ -258,18 +319,21 @@ __global__ __launch_bounds__(256) void k_apply_inverse_rows(PatDev P, const doub
     out[i] = s;
 }
 
-// thread_rows: one thread per row, else a wavefront per row
 hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const double* b, double* x, double* y,
-                                bool thread_rows, hipStream_t s) {
+                                int shape, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    if (thread_rows) {
+    if (shape == kProdThreadRows) {
         const int grid = (P.n + 255) / 256;
         hipLaunchKernelGGL(k_apply_inverse_rows<false>, dim3(grid), dim3(256), 0, s, P, g_val, b, x);
         hipLaunchKernelGGL(k_apply_inverse_rows<true>, dim3(grid), dim3(256), 0, s, P, g_val, x, y);
+    } else if (shape == kProdTile) {
+        const int grid = std::min((P.n + kWave - 1) / kWave, 65536);
+        hipLaunchKernelGGL(k_apply_inverse_tile<false>, dim3(grid), dim3(64), 0, s, P, g_val, b, x);
+        hipLaunchKernelGGL(k_apply_inverse_tile<true>, dim3(grid), dim3(64), 0, s, P, g_val, x, y);
     } else {
         const int grid = std::min(P.n, 65536);
-        hipLaunchKernelGGL(k_apply_inverse<false>, dim3(grid), dim3(64), 0, s, P, g_val, b, x);
-        hipLaunchKernelGGL(k_apply_inverse<true>, dim3(grid), dim3(64), 0, s, P, g_val, x, y);
+        hipLaunchKernelGGL(k_apply_inverse_wave<false>, dim3(grid), dim3(64), 0, s, P, g_val, b, x);
+        hipLaunchKernelGGL(k_apply_inverse_wave<true>, dim3(grid), dim3(64), 0, s, P, g_val, x, y);
     }
     return hipGetLastError();
 }

@@ -234,7 +234,9 @@ size_t isched_lds_bytes(int32_t max_row);
 hipError_t launch_inverse(const PatDev& P, const InvSched& S, const double* f_val, double* g_val, bool upper,
                           Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s);
 // x = L~~^-1 b, y = U~~^-1 x; thread_rows: one thread per row, else a wavefront
+// shapes of the two products of the incomplete inverses
+enum { kProdWaveRows = 0, kProdThreadRows = 1, kProdTile = 2 };
 hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const double* b, double* x, double* y,
-                                bool thread_rows, hipStream_t s);
+                                int shape, hipStream_t s);
 
 }  // namespace tpilu

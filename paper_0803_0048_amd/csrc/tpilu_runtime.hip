@@ -523,16 +523,23 @@ tpilu_status compute_levels(tpilu_ctx ctx, tpilu_pattern pat, const LevelSpec* j
     return finish_levels(ctx, pat, js, njobs, dmax);
 }
 
-// Shape of the two products: one thread per row for short rows, a wavefront
-// per row for long ones (automatic: fewer than 32 entries per row of F on
-// average), or as the solver mode asks (1 wavefront, 3 lane per row).
-// Measured: 64^3 ILU(1) (12.7 per row) 0.062 ms by thread vs 0.116 ms by
-// wavefront; n=160,000 ILU(2) (164 per row) 0.29 ms by wavefront vs 0.91 ms.
-constexpr int64_t kInvThreadMaxAvg = 32;
-bool inverse_thread_rows(tpilu_ctx ctx, tpilu_pattern pat) {
-    if (ctx->solver == 1) return false;
-    if (ctx->solver == 3) return true;
-    return pat->nnz_f < kInvThreadMaxAvg * std::max<int64_t>(pat->n, 1);
+// Shape of the two products (kProd*): as the solver mode asks (1 a wavefront
+// per row, 3 a thread per row) or automatically: 64 rows per wavefront
+// staged through LDS (each lane one row's in-order sum) when the rows are of
+// even length (longest row at most 1.5 x the average) and not very long,
+// else a wavefront per row.  Measured on MI355X (both products): 7-point
+// 64^3 ILU(1), 13 entries per row: 0.042 ms tiled, 0.061 by thread, 0.165
+// by wavefront; 27-point 50^3 ILU(3), 165 per row (longest 183): 0.147 vs
+// 0.225 ms by wavefront; random banded n=160,000 ILU(2), 164 per row (longest
+// 419): 0.29 ms by wavefront, 0.35 tiled; paper-scale ILU(1), 1,276 per row:
+// 1.9 ms by wavefront, 2.8 tiled.
+constexpr int64_t kInvTileMaxAvg = 512;
+int inverse_product_shape(tpilu_ctx ctx, tpilu_pattern pat) {
+    if (ctx->solver == 1) return kProdWaveRows;
+    if (ctx->solver == 3) return kProdThreadRows;
+    const int64_t n = std::max<int64_t>(pat->n, 1);
+    const bool even = 2 * (int64_t)pat->st.max_row * n <= 3 * pat->nnz_f;
+    return even && pat->nnz_f <= kInvTileMaxAvg * n ? kProdTile : kProdWaveRows;
 }
 
 tpilu_status build_inverse_sched(tpilu_ctx ctx, tpilu_pattern pat) {
@@ -1132,7 +1139,8 @@ extern "C" TPILU_API tpilu_status tpilu_apply_inverse(tpilu_ctx ctx, tpilu_patte
         x = pat->grow(pat->ws_x, sizeof(double) * (size_t)pat->n);
         if (!x) return fail(ctx, TPILU_E_NOMEM, "apply workspace");
     }
-    HIPCHK(ctx, launch_apply_inverse(pdev(ctx, pat), g_val, b, x, y, inverse_thread_rows(ctx, pat), ctx->stream));
+    HIPCHK(ctx, launch_apply_inverse(pdev(ctx, pat), g_val, b, x, y, inverse_product_shape(ctx, pat),
+                                     ctx->stream));
     return TPILU_OK;
 }
 
@@ -1178,7 +1186,8 @@ tpilu_status enqueue_precond(tpilu_ctx ctx, tpilu_pattern pat, const double* m_v
                              const double* v, double* z, double* t, bool reset) {
     if (!inverse) return enqueue_apply(ctx, pat, m_val, 1, v, z, t, reset);
     if (reset) HIPCHK(ctx, launch_fill_pending(nullptr, 0, pat->ctl, true, ctx->stream));
-    HIPCHK(ctx, launch_apply_inverse(pdev(ctx, pat), m_val, v, t, z, inverse_thread_rows(ctx, pat), ctx->stream));
+    HIPCHK(ctx, launch_apply_inverse(pdev(ctx, pat), m_val, v, t, z, inverse_product_shape(ctx, pat),
+                                     ctx->stream));
     return TPILU_OK;
 }
 
