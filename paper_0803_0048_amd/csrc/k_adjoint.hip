@@ -162,7 +162,7 @@ __global__ __launch_bounds__(64) void k_adj_solve_l(PatDev P, AdjPat T, const do
 // batches: one wavefront per (row, group of 64 instances), lanes = instances, each
 // lane running the row's sequential chain for its own instance (values are stored
 // entry-major, instance-minor, so the 64 lanes read one contiguous line per entry).
-// One ticket covers a row for 64 instances instead of one.
+// One draw from the task counters covers a row for 64 instances instead of one.
 // ----------------------------------------------------------------------------------
 constexpr int kAdjChunk = 8;  // chain entries whose inputs are loaded together
 

@@ -14,7 +14,7 @@
 // column of a pivot row's half is binary-searched there.
 //
 // Values: a persistent grid walks the rows in dependency-level order (the
-// forward DAG for L~, the backward DAG for U~) through an atomic ticket.
+// forward DAG for L~, the backward DAG for U~) through the task counters.
 // Unlike the elimination, the entries of one row do not depend on each other
 // here, so each lane owns entries of the row and runs their chains alone:
 // loads of up to kInvChunk partners in flight together, pending ones (rows

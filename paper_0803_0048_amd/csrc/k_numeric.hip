@@ -2,9 +2,10 @@
 // updates, Eqs. 6a/6b), bit-identical to the sequential order.
 //
 // The only order that fixes the bits is, per entry f_jt, its updates in
-// ascending pivot h.  A persistent grid hands rows out in ascending order
-// through an atomic ticket, so a wavefront only ever waits on rows that some
-// running wavefront already holds (no deadlock for any grid size).  One
+// ascending pivot h.  A persistent grid hands rows out in dependency-level
+// order through atomic task counters (next_pos in dev_common.h), so a
+// wavefront only ever waits on rows that some running wavefront already holds
+// (no deadlock for any grid size).  One
 // wavefront owns row j: it scatters A's row into an LDS working row indexed by
 // F slot (fills +0.0), then for every pivot h < j of row j in ascending order
 // divides f_jh by the final pivot f_hh and applies that pivot's updates

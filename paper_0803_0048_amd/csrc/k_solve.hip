@@ -12,8 +12,9 @@
 // advancing as the needed values arrive, which keeps every bit of the
 // sequential result.  With these orders the value that arrives last (the
 // nearest row) is the last term of the chain.  Two launch shapes give the
-// same bits: a persistent grid over the whole device (rows handed out by an
-// atomic ticket) and a single workgroup whose 16 wavefronts share one CU.
+// same bits: a persistent grid over the whole device (rows handed out by
+// atomic task counters) and a single workgroup whose 16 wavefronts share one
+// CU; for wide levels of short rows also a lane per row.
 // For batches the lanes are instances and each lane runs its own chain.
 // x and y start as kPending and each slot is written once.
 #include "kernels.h"
@@ -71,7 +72,7 @@ __device__ __forceinline__ void backward_row(const PatDev& P, const double* __re
     trace_mark(P.trace, 3 * (int64_t)P.n + i);
 }
 
-// whole device: persistent grid, rows handed out by an atomic ticket
+// whole device: persistent grid, rows handed out by the task counters
 __global__ __launch_bounds__(64) void k_forward_row(PatDev P, const double* __restrict__ F,
                                                     const double* __restrict__ b, double* x,
                                                     Ctl* ctl, uint64_t spin_limit) {
@@ -118,9 +119,9 @@ __global__ __launch_bounds__(1024) void k_backward_wg(PatDev P, const double* __
 }
 
 // lane per row, for wide dependency graphs of short rows (many rows per level,
-// few entries each): one ticket hands out 64 consecutive rows of the level
-// order, one per lane, so the ticket (a single contended atomic) is taken 64
-// times less often.  Each lane runs its row's chain in the fixed order
+// few entries each): one draw from the task counters hands out 64
+// consecutive rows of the level order, one per lane, so the counters are
+// taken 64 times less often.  Each lane runs its row's chain in the fixed order
 // (forward ascending, backward right to left, then the division), with the
 // loads of up to kLaneChunk entries in flight together and every pending one
 // re-polled each round; the wavefront goes round until all its lanes have

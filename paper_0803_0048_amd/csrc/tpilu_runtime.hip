@@ -171,8 +171,6 @@ int32_t row_group(RowKernel kind, int64_t n, int64_t depth) {
 // resident maximum.
 constexpr int32_t kBatchSolveWaves = 1024;
 
-// Position counters the row kernels draw from (see next_pos).
-int32_t ticket_parts(RowKernel, int64_t, int64_t) { return kTicketParts; }
 
 struct tpilu_pattern_s {
     Alloc al;
@@ -232,7 +230,7 @@ struct tpilu_pattern_s {
                int32_t tickets = 0) const {
         PatDev d;
         d.trace = trace;
-        d.parts = tickets ? tickets : ticket_parts(kind, n, depth_l);
+        d.parts = tickets ? tickets : kTicketParts;  // task counters (see next_pos)
         d.groupL = group ? group : row_group(kind, n, depth_l);
         d.groupU = group ? group : row_group(kind, n, depth_u);
         d.n = (int32_t)n;
