@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--extra", choices=["batched", "reverse", "stencil27", "paper_scale"],
+                    help="run only this extra workload and print its figures (no bench step)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -119,6 +121,16 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x 256 MiB device-to-device copies done")
         del src, dst
+    if args.extra:
+        ctx = T.context(0)
+        if args.extra == "stencil27":
+            res = stencil27_extra(T, I, torch, dev, ctx)
+        elif args.extra == "paper_scale":
+            res = paper_scale_extra(T, I, torch, dev, ctx)
+        else:
+            res = extras(T, I, torch, np, dev, ctx, only=args.extra)
+        print(json.dumps({"extra": args.extra, "result": res}), flush=True)
+        return
     log("building the n=160000 workload")
     cfg = I.config2()
     A, k, restart, rtol = cfg["A"], cfg["k"], cfg["restart"], cfg["rtol"]
@@ -238,9 +250,12 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def extras(T, I, torch, np, dev, ctx):
-    """Batched graph and reverse mode next to the plain single-matrix path."""
+def extras(T, I, torch, np, dev, ctx, only=None):
+    """Batched graph and reverse mode next to the plain single-matrix path
+    (``only``: "batched" or "reverse" for one of the two)."""
     res = {}
+    if only not in (None, "batched"):
+        return res | reverse_extra(T, I, torch, dev)
     log("batched: 256 x 128^2 ILU(2) in one graph")
     c4 = I.config4()
     A4 = c4["A"]
@@ -277,7 +292,16 @@ def extras(T, I, torch, np, dev, ctx):
     B = A4.batch
     res["batched"] = {"instances": B, "n": A4.n, "graph_ms": gms, "per_instance_ms": gms / B,
                       "plain_single_instance_ms": pms, "speedup_per_instance_vs_plain": pms / (gms / B)}
+    if only == "batched":
+        return res
+    return res | reverse_extra(T, I, torch, dev)
 
+
+def reverse_extra(T, I, torch, dev):
+    """Reverse mode of 16 x 32^3 ILU(1): forward pass next to backward pass."""
+    res = {}
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     log("reverse mode: 16 x 32^3 ILU(1)")
     c5 = I.config5()
     A5 = c5["A"]
