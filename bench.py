@@ -132,7 +132,7 @@ def main():
         print(json.dumps({"extra": args.extra, "result": res}), flush=True)
         return
     log("building the n=160000 workload")
-    cfg = I.config2()
+    cfg = I.random_banded_ilu2()
     A, k, restart, rtol = cfg["A"], cfg["k"], cfg["restart"], cfg["rtol"]
     rp = torch.from_numpy(A.rowptr).to(dev)
     ci = torch.from_numpy(A.col).to(dev)
@@ -267,7 +267,7 @@ def extras(T, I, torch, np, dev, ctx, only=None):
     if only not in (None, "batched"):
         return res | reverse_extra(T, I, torch, dev)
     log("batched: 256 x 128^2 ILU(2) in one graph")
-    c4 = I.config4()
+    c4 = I.batched_conv_diff_2d_ilu2()
     A4 = c4["A"]
     rp4 = torch.from_numpy(A4.rowptr).to(dev)
     ci4 = torch.from_numpy(A4.col).to(dev)
@@ -313,7 +313,7 @@ def reverse_extra(T, I, torch, dev):
     reps = 10
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     log("reverse mode: 16 x 32^3 ILU(1)")
-    c5 = I.config5()
+    c5 = I.differentiated_conv_diff_3d_ilu1()
     A5 = c5["A"]
     pat5 = T.symbolic(torch.from_numpy(A5.rowptr).to(dev), torch.from_numpy(A5.col).to(dev), 1)
     av5 = torch.from_numpy(A5.val).to(dev)
@@ -358,7 +358,7 @@ def paper_scale_extra(T, I, torch, dev, ctx):
     median of 3).  The paper's figures for its own matrix (Tables 3 and 4,
     2008-era CPUs) are context, not a baseline."""
     log("paper-scale ILU(1), n = 160,000")
-    c = I.config_paper_k1()
+    c = I.paper_scale_random_ilu1()
     A = c["A"]
     rp = torch.from_numpy(A.rowptr).to(dev)
     ci = torch.from_numpy(A.col).to(dev)
@@ -403,7 +403,7 @@ def stencil27_extra(T, I, torch, dev, ctx):
     out = []
     for m, k in ((50, 0), (50, 1), (50, 2), (50, 3), (90, 1)):
         log(f"27-point stencil {m}^3 ILU({k})")
-        c = I.config_stencil27(m=m, k=k)
+        c = I.stencil27_ilu(m=m, k=k)
         A = c["A"]
         rp = torch.from_numpy(A.rowptr).to(dev)
         ci = torch.from_numpy(A.col).to(dev)

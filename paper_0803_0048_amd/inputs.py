@@ -48,13 +48,14 @@ __all__ = [
     "random_banded",
     "random_pattern",
     "stencil27_3d",
-    "config_stencil27",
-    "config1",
-    "config2",
-    "config3",
-    "config4",
-    "config5",
-    "CONFIGS",
+    "stencil27_ilu",
+    "conv_diff_2d_64x64_ilu1",
+    "random_banded_ilu2",
+    "conv_diff_3d_ilu",
+    "batched_conv_diff_2d_ilu2",
+    "differentiated_conv_diff_3d_ilu1",
+    "random_uniform",
+    "paper_scale_random_ilu1",
 ]
 
 
@@ -205,7 +206,7 @@ def stencil27_3d(m: int, eps: float, bvec) -> CSR:
     return CSR(n, rowptr, col, val, {"kind": "stencil27_3d", "m": m, "h": h})
 
 
-def config_stencil27(m: int = 50, k: int = 1, seed: int = 1006):
+def stencil27_ilu(m: int = 50, k: int = 1, seed: int = 1006):
     """3-D 27-point stencil (next-step workload, Sec. 4.2's 50^3 to 90^3),
     eps = 1, b ~ U[-10, 10]^3 (convection mild enough to keep the diagonal
     dominant), rhs ~ N(0, 1); ILU(k) for k = 0..3."""
@@ -363,11 +364,11 @@ def random_pattern(n: int, density: float, seed: int, *, diag_dominant: bool = T
 
 
 # ----------------------------------------------------------------------------
-# The five named workloads.  Seeds 1001-1005; batched instance i draws from
+# The named workloads.  Seeds 1001-1007; batched instance i draws from
 # SeedSequence(seed).spawn(B)[i].
 # ----------------------------------------------------------------------------
 
-def config1(seed: int = 1001):
+def conv_diff_2d_64x64_ilu1(seed: int = 1001):
     """2-D 5-point, 64 x 64, eps = 1, (bx, by) ~ U[-20, 20]^2; ILU(1)."""
     rng = np.random.default_rng(seed)
     bx, by = rng.uniform(-20.0, 20.0, size=2)
@@ -376,7 +377,7 @@ def config1(seed: int = 1001):
     return {"name": "conv_diff_2d_64x64_ilu1", "A": A, "b": b, "k": 1, "restart": 30, "rtol": 1e-8}
 
 
-def config2(seed: int = 1002, n: int = 160_000):
+def random_banded_ilu2(seed: int = 1002, n: int = 160_000):
     """Random banded n = 160,000, 8 band + 2 anywhere columns; ILU(2), GMRES(30)."""
     A = random_banded(n, seed)
     rng = np.random.default_rng(seed + 7919)
@@ -390,7 +391,7 @@ PAPER_K1_COUNTS = {40_000: (5_120_950, 196_223_519), 80_000: (6_960_983, 195_202
                    160_000: (9_832_794, 198_969_083), 320_000: (14_090_553, 206_489_590)}
 
 
-def config_paper_k1(n: int = 160_000, seed: int = 1007, per_row: float | None = None):
+def paper_scale_random_ilu1(n: int = 160_000, seed: int = 1007, per_row: float | None = None):
     """Paper-scale ILU(1): a uniform random sparse matrix with Table 3's entry
     count for this n (the generator behind the table is not available, so the
     count is matched, not the matrix).  ``per_row`` overrides the entries per
@@ -406,7 +407,7 @@ def config_paper_k1(n: int = 160_000, seed: int = 1007, per_row: float | None = 
             "paper_final_entries": PAPER_K1_COUNTS.get(n, (None, None))[1]}
 
 
-def config3(seed: int = 1003, m: int = 64, k: int = 2):
+def conv_diff_3d_ilu(seed: int = 1003, m: int = 64, k: int = 2):
     """3-D 7-point, 64^3, eps = 1, b ~ U[-200, 200]^3 with max |b_c| > 2/h
     (cell Peclet > 1, not diagonally dominant); ILU(k) for k = 0..3, GMRES(50)."""
     h = 1.0 / (m + 1)
@@ -422,7 +423,7 @@ def config3(seed: int = 1003, m: int = 64, k: int = 2):
     return {"name": f"conv_diff_3d_{m}cubed_ilu{k}", "A": A, "b": b, "k": k, "restart": 50, "rtol": 1e-8}
 
 
-def config4(seed: int = 1004, B: int = 256, m: int = 128):
+def batched_conv_diff_2d_ilu2(seed: int = 1004, B: int = 256, m: int = 128):
     """B instances of a 2-D 5-point 128 x 128 stencil sharing one pattern,
     eps ~ U[0.5, 2], (bx, by) ~ U[-50, 50]^2 per instance; ILU(2)."""
     kids = np.random.SeedSequence(seed).spawn(B)
@@ -438,7 +439,7 @@ def config4(seed: int = 1004, B: int = 256, m: int = 128):
     return {"name": f"batched_conv_diff_2d_{m}x{m}_x{B}_ilu2", "A": A, "b": rhs, "k": 2}
 
 
-def config5(seed: int = 1005, B: int = 16, m: int = 32):
+def differentiated_conv_diff_3d_ilu1(seed: int = 1005, B: int = 16, m: int = 32):
     """B instances of a 3-D 7-point 32^3 stencil, eps ~ U[0.5, 2],
     b ~ U[-50, 50]^3 per instance, rhs and target t ~ N(0, 1); ILU(1)."""
     kids = np.random.SeedSequence(seed).spawn(B)
@@ -455,6 +456,3 @@ def config5(seed: int = 1005, B: int = 16, m: int = 32):
         tgt[:, i] = rng.standard_normal(n)
     A = conv_diff_3d(m, eps, bv)
     return {"name": f"diff_conv_diff_3d_{m}cubed_x{B}_ilu1", "A": A, "b": rhs, "t": tgt, "k": 1}
-
-
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

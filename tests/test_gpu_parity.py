@@ -105,7 +105,7 @@ def test_dot_bits_and_fixed_shape():
 
 
 def test_spmv_bits():
-    A = I.config1()["A"]
+    A = I.conv_diff_2d_64x64_ilu1()["A"]
     x = np.random.default_rng(1).standard_normal(A.n)
     pat = T.symbolic(g(A.rowptr), g(A.col), 0)
     assert_bits_equal(T.spmv(pat, g(A.val), g(x)), O.spmv(A.n, A.rowptr, A.col, A.val, x), "A x")
@@ -186,14 +186,14 @@ def _gmres_parity(pat, f, A, b, restart, maxit, rtol):
 
 
 def test_config1_conv_diff_2d_ilu1():
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     pat, f, ref = _full(c["A"], c["k"], c["b"])
     info = _gmres_parity(pat, (f, ref), c["A"], c["b"], 30, 1000, 1e-8)
     assert info["relres"] <= 1e-8
 
 
 def test_config2_random_banded_ilu2():
-    c = I.config2()
+    c = I.random_banded_ilu2()
     log("  oracle + gpu on n=160000, ILU(2)")
     pat, f, ref = _full(c["A"], c["k"], c["b"])
     log(f"  pattern info {pat.info}")
@@ -203,19 +203,19 @@ def test_config2_random_banded_ilu2():
 
 @pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_config3_conv_diff_3d(k):
-    c = I.config3(k=k)
+    c = I.conv_diff_3d_ilu(k=k)
     _full(c["A"], k, c["b"])
 
 
 def test_config3_gmres_ilu1():
-    c = I.config3(k=1)
+    c = I.conv_diff_3d_ilu(k=1)
     pat, f, ref = _full(c["A"], 1, c["b"])
     _gmres_parity(pat, (f, ref), c["A"], c["b"], 50, 150, 1e-8)
 
 
 def test_repeatable_across_launch_shapes():
     """Same bits for any number of wavefronts (race check by repetition)."""
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     pat = T.symbolic(g(A.rowptr), g(A.col), 2)
     av, bv = g(A.val), g(c["b"])
@@ -241,11 +241,11 @@ def test_repeatable_across_launch_shapes():
     ctx.set_solver(0)
 
 
-@pytest.mark.parametrize("cfg", ["c3k1", "s27k1"])
+@pytest.mark.parametrize("cfg", ["cd3d_k1", "s27_k1"])
 def test_row_groups_agree_full_size(cfg):
     """Rows per ticket and task counters of the row kernels (numeric,
     wavefront-per-row solves, inverses): the oracle's bits for every setting."""
-    c = I.config3(k=1) if cfg == "c3k1" else I.config_stencil27(m=50, k=1)
+    c = I.conv_diff_3d_ilu(k=1) if cfg == "cd3d_k1" else I.stencil27_ilu(m=50, k=1)
     A, b, k = c["A"], c["b"], 1
     rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
     vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
@@ -274,10 +274,10 @@ def test_row_groups_agree_full_size(cfg):
         ctx.set_solver(0)
 
 
-@pytest.mark.parametrize("cfg", ["c2", "c3k1"])
+@pytest.mark.parametrize("cfg", ["banded", "cd3d_k1"])
 def test_solver_shapes_agree_full_size(cfg):
     """Every solve launch shape: same bits as the oracle."""
-    c = I.config2() if cfg == "c2" else I.config3(k=1)
+    c = I.random_banded_ilu2() if cfg == "banded" else I.conv_diff_3d_ilu(k=1)
     A, b = c["A"], c["b"]
     pat = T.symbolic(g(A.rowptr), g(A.col), c["k"])
     f = T.numeric(pat, g(A.val))
@@ -293,8 +293,8 @@ def test_solver_shapes_agree_full_size(cfg):
     ctx.set_solver(0)
 
 
-def test_repeatable_config2():
-    c = I.config2()
+def test_repeatable_random_banded():
+    c = I.random_banded_ilu2()
     A = c["A"]
     pat = T.symbolic(g(A.rowptr), g(A.col), 2)
     av = g(A.val)
@@ -323,7 +323,7 @@ def test_zero_pivot_reported():
 
 
 def test_watchdog_times_out_and_recovers():
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     pat = T.symbolic(g(A.rowptr), g(A.col), 1)
     ctx = T.context(0)
@@ -363,7 +363,7 @@ def test_reserved_nan_input_rejected():
 # batched factorization under one graph
 # ----------------------------------------------------------------------------------
 def test_config4_batched_graph():
-    c = I.config4()
+    c = I.batched_conv_diff_2d_ilu2()
     A, rhs = c["A"], c["b"]
     B = A.batch
     pat = T.symbolic(g(A.rowptr), g(A.col), 2)
@@ -401,7 +401,7 @@ def test_config4_batched_graph():
 
 def test_batched_partial_group():
     """A batch that is not a multiple of 64 instances."""
-    c = I.config4(B=70, m=24)
+    c = I.batched_conv_diff_2d_ilu2(B=70, m=24)
     A, rhs = c["A"], c["b"]
     pat = T.symbolic(g(A.rowptr), g(A.col), 2)
     rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, 2)
@@ -489,7 +489,7 @@ def test_adjoint_batched_bits(case):
 
 
 def test_config5_autograd_against_oracle_and_fd():
-    c = I.config5()
+    c = I.differentiated_conv_diff_3d_ilu1()
     A, rhs, tgt = c["A"], c["b"], c["t"]
     B = A.batch
     pat = T.symbolic(g(A.rowptr), g(A.col), 1)
@@ -571,19 +571,19 @@ def test_inverse_small_sweep():
         _inverse_parity(A, k, rng.standard_normal(n), waves=int(rng.choice([0, 1, 5, 64])))
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c3k1", "c3k2"])
+@pytest.mark.parametrize("cfg", ["cd2d", "cd3d_k1", "cd3d_k2"])
 def test_inverse_stencils(cfg):
-    c = I.config1() if cfg == "c1" else I.config3(k=int(cfg[-1]))
-    _inverse_parity(c["A"], c["k"] if cfg == "c1" else int(cfg[-1]), c["b"])
+    c = I.conv_diff_2d_64x64_ilu1() if cfg == "cd2d" else I.conv_diff_3d_ilu(k=int(cfg[-1]))
+    _inverse_parity(c["A"], c["k"] if cfg == "cd2d" else int(cfg[-1]), c["b"])
 
 
 def test_inverse_config2_full_size():
-    c = I.config2()
+    c = I.random_banded_ilu2()
     _inverse_parity(c["A"], c["k"], c["b"])
 
 
 def test_gmres_inverse_bits():
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     pat, f, G, (rpF, ciF, vF, vG) = _inverse_parity(A, 1, c["b"])
     ref = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vG, c["b"], restart=30, maxit=400, rtol=1e-8,
@@ -597,11 +597,13 @@ def test_gmres_inverse_bits():
 # ----------------------------------------------------------------------------------
 # BiCGSTAB (Sec. 4's Krylov method)
 # ----------------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["c1_ilu", "c1_inverse", "c3k1_ilu", "c2_ilu", "c2_inverse"])
+@pytest.mark.parametrize("case", ["cd2d_ilu", "cd2d_inverse", "cd3dk1_ilu", "banded_ilu", "banded_inverse"])
 def test_bicgstab_bits(case):
     name, prec = case.split("_")
-    c = I.config1() if name == "c1" else (I.config3(k=1) if name == "c3k1" else I.config2())
-    A, k = c["A"], (1 if name != "c2" else c["k"])
+    make = {"cd2d": I.conv_diff_2d_64x64_ilu1, "cd3dk1": lambda: I.conv_diff_3d_ilu(k=1),
+            "banded": I.random_banded_ilu2}
+    c = make[name]()
+    A, k = c["A"], (1 if name != "banded" else c["k"])
     rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
     vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
     pat = T.symbolic(g(A.rowptr), g(A.col), k)
@@ -627,7 +629,7 @@ def test_bicgstab_bits(case):
 # ----------------------------------------------------------------------------------
 @pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_stencil27_small(k):
-    c = I.config_stencil27(m=12, k=k)
+    c = I.stencil27_ilu(m=12, k=k)
     pat, f, ref = _full(c["A"], k, c["b"])
     if k == 1:
         _gmres_parity(pat, (f, ref), c["A"], c["b"], 50, 200, 1e-8)
@@ -637,7 +639,7 @@ def test_stencil27_small(k):
 def test_stencil27_50cubed(k):
     """At the paper's smallest size (50^3 = 125,000 rows): pattern, factor and
     both solves bit for bit."""
-    c = I.config_stencil27(m=50, k=k)
+    c = I.stencil27_ilu(m=50, k=k)
     _full(c["A"], k, c["b"])
 
 
@@ -651,7 +653,7 @@ PAPER_ROW = 9_832_794 / 160_000  # entries per row of A in Table 3's 160K matrix
 def test_paper_scale_rows_small_bits():
     """Rows of the paper's length (~1,000 entries of F, up to ~1,550) on a
     3,000-row matrix: pattern, factor and both solves bit for bit."""
-    c = I.config_paper_k1(n=3000, per_row=PAPER_ROW)
+    c = I.paper_scale_random_ilu1(n=3000, per_row=PAPER_ROW)
     pat, _, _ = _full(c["A"], 1, c["b"])
     assert pat.info["long_rows"] > 0
 
@@ -675,7 +677,7 @@ def test_paper_scale_160k_sampled_rows():
     rows' patterns against the level definition, and their factor rows
     against the oracle's elimination of that row on the GPU's pivot rows
     (a row of F depends only on A's row and its pivots' final U rows)."""
-    c = I.config_paper_k1()
+    c = I.paper_scale_random_ilu1()
     A = c["A"]
     pat = T.symbolic(g(A.rowptr), g(A.col), 1)
     info = pat.info

@@ -180,7 +180,7 @@ def test_numeric_full_fill_is_exact_lu():
 
 def test_numeric_ilu_defining_property():
     """(L~ U~)_ij = a_ij on every position kept in the pattern."""
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     for k in (0, 1, 2):
         rpF, ciF, _, vF, bad = O.ilu(A, k)
@@ -269,7 +269,7 @@ def test_numeric_zero_pivot_reports_smallest_row():
 # --------------------------------------------------------------------------
 
 def test_apply_against_triangular_solves():
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     rpF, ciF, _, vF, _ = O.ilu(A, 2)
     F = sp.csr_matrix((vF, ciF, rpF), shape=(A.n, A.n)).toarray()
@@ -372,7 +372,7 @@ def test_dot_shape_is_fixed():
 
 
 def test_spmv_matches_scipy_and_order():
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     x = np.random.default_rng(0).standard_normal(A.n)
     y = O.spmv(A.n, A.rowptr, A.col, A.val, x)
@@ -398,7 +398,7 @@ def test_gmres_exact_lu_converges_in_one_iteration():
 
 
 def test_gmres_converges_and_residuals_monotone():
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     rpF, ciF, _, vF, _ = O.ilu(A, 1)
     r = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, c["b"], restart=10, rtol=1e-8)
@@ -415,7 +415,7 @@ def test_gmres_first_cycle_is_krylov_minimum():
     """Within the first cycle the implicit residual after j steps is the
     minimum of ||b - A M^-1 v|| over the j-dimensional Krylov space of
     A M^-1 started at b (x0 = 0) -- computed here by a dense least-squares."""
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     rpF, ciF, _, vF, _ = O.ilu(A, 0)
     b = c["b"]
@@ -445,7 +445,7 @@ def test_gmres_first_cycle_is_krylov_minimum():
 
 
 def test_gmres_zero_rhs_and_maxit():
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     rpF, ciF, _, vF, _ = O.ilu(A, 0)
     r = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, np.zeros(A.n), restart=5)
@@ -456,7 +456,7 @@ def test_gmres_zero_rhs_and_maxit():
 
 def test_gmres_iterations_near_scipy():
     sl = pytest.importorskip("scipy.sparse.linalg")
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     rpF, ciF, _, vF, _ = O.ilu(A, 1)
     r = O.gmres(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, c["b"], restart=30, rtol=1e-8)
@@ -678,7 +678,7 @@ def test_inverse_incomplete_defining_property():
     L~), and (U~ G)_it = delta_it: the level-based inverse is exact on its
     own pattern (Eq. 5 restricted to it)."""
     u = 2.0**-53
-    cases = [(I.config1()["A"], k) for k in (0, 1, 2)]
+    cases = [(I.conv_diff_2d_64x64_ilu1()["A"], k) for k in (0, 1, 2)]
     cases += [(I.random_pattern(120, 0.04, seed=90 + s, diag_dominant=True), s % 3) for s in range(3)]
     for A, k in cases:
         rpF, ciF, _, vF, bad = O.ilu(A, k)
@@ -756,7 +756,7 @@ def test_gmres_with_inverse():
     b = np.random.default_rng(1).standard_normal(n)
     r = O.gmres(n, rp, ci, v, rpF, ciF, vG, b, restart=10, maxit=20, rtol=1e-10, inverse=True)
     assert r["iters"] == 1 and r["relres"] <= 1e-10
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     rpF, ciF, _, vF, _ = O.ilu(A, 1)
     vG = O.inverse(A.n, rpF, ciF, vF)
@@ -779,7 +779,7 @@ def test_bicgstab_iterates_match_scipy():
     differs), for both preconditioners."""
     from scipy.sparse.linalg import LinearOperator, bicgstab as sp_bicgstab
 
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     rpF, ciF, _, vF, _ = O.ilu(A, 1)
     vG = O.inverse(A.n, rpF, ciF, vF)
@@ -811,7 +811,7 @@ def test_bicgstab_exact_preconditioner_one_half_step():
 
 
 def test_bicgstab_converges_and_edge_cases():
-    c = I.config1()
+    c = I.conv_diff_2d_64x64_ilu1()
     A = c["A"]
     rpF, ciF, _, vF, _ = O.ilu(A, 1)
     r = O.bicgstab(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, c["b"], maxit=400, rtol=1e-8)
