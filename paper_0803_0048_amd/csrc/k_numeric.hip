@@ -168,11 +168,13 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
             np = uniform(fit > 0 ? fit : 1);
             const int32_t npair = uniform(piv_e[np]);
             const bool big = npair > kPairCap;  // a single pivot with more pairs than fit
+            bool all_final = false;
             {
                 constexpr int kPS = kPairCap / kWave;
                 constexpr int kPv = kPivCap / kWave;
                 const int32_t nst = big ? 0 : npair;
                 int32_t q[kPS], pp[kPS], dh[kPv];
+                bool fin = true;  // every staged value already final
 #pragma unroll
                 for (int u = 0; u < kPS; ++u) {
                     const int32_t e = lane + u * kWave;
@@ -191,7 +193,10 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
                 for (int u = 0; u < kPS; ++u) v[u] = lane + u * kWave < nst ? ld_cached(F + q[u]) : 0ull;
 #pragma unroll
                 for (int u = 0; u < kPv; ++u)
-                    if (lane + u * kWave < np) piv_u[lane + u * kWave] = ud[u];
+                    if (lane + u * kWave < np) {
+                        piv_u[lane + u * kWave] = ud[u];
+                        fin = fin && ud[u] != kPending;
+                    }
 #pragma unroll
                 for (int u = 0; u < kPS; ++u) {
                     const int32_t e = lane + u * kWave;
@@ -199,15 +204,19 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
                         pr_q[e] = q[u];
                         pr_p[e] = (int32_t)(pp[u] - rs);
                         pr_v[e] = v[u];
+                        fin = fin && v[u] != kPending;
                     }
                 }
+                all_final = !big && __all(fin);
             }
             wave_sync();
             for (int32_t i = 0; i < np; ++i) {
                 const int64_t s = s0 + i;
                 uint64_t ub = piv_u[i];
                 const int32_t ea = piv_e[i], eb = piv_e[i + 1];
-                if (!big) {
+                if (all_final) {
+                    // nothing to wait for in this group
+                } else if (!big) {
                     // the pivot and every value it contributes, polled together
                     bool ok = ub != kPending;
                     for (int32_t e = ea + lane; e < eb; e += kWave) ok = ok && pr_v[e] != kPending;
