@@ -337,6 +337,25 @@ def test_watchdog_times_out_and_recovers():
     assert_bits_equal(T.numeric(pat, g(A.val)), vF, "F after recovery")
 
 
+def test_context_settings_reject_out_of_range():
+    """Launch-shape settings outside their documented ranges are refused with
+    E_INVAL and leave the previous setting in force."""
+    ctx = T.context(0)
+    for call, bad in ((ctx.set_group, (-1, 65)), (ctx.set_tickets, (-1, 9)), (ctx.set_solver, (-1, 4)),
+                      (ctx.set_numeric, (-1, 3)), (ctx.set_grid, (-1,))):
+        for v in bad:
+            with pytest.raises(T.TpiluError) as e:
+                call(v)
+            assert e.value.status == T.E_INVAL, (call.__name__, v)
+    c = I.conv_diff_2d_64x64_ilu1()
+    A = c["A"]
+    pat = T.symbolic(g(A.rowptr), g(A.col), c["k"])
+    f = T.numeric(pat, g(A.val))
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, c["k"])
+    vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
+    assert_bits_equal(f, vF, "F after refused settings")
+
+
 def test_invalid_csr_rejected():
     with pytest.raises(T.TpiluError) as e:
         T.symbolic(g(np.array([0, 1, 2], np.int64)), g(np.array([0, 0], np.int32)), 1)  # no diag in row 1
