@@ -108,8 +108,8 @@ TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t waves);
 /* Launch shape of the single-instance triangular solves: 0 = automatic
  * (lane per row when a triangle's rows hold at most 40 entries on average
  * and a dependency level at least max(64, 16 x that average) rows, else a
- * wavefront per row), 1 = a wavefront per row over the whole device,
- * 2 = one workgroup (16 wavefronts on one CU), 3 = a lane per row (64 rows per
+ * wavefront per row), 1 = a wavefront per row (on the whole device or on
+ * one XCD, see tpilu_ctx_set_placement), 2 = one workgroup (16 wavefronts on one CU), 3 = a lane per row (64 rows per
  * wavefront) over the whole device.  The same setting picks the shape of the
  * two products of tpilu_apply_inverse: 1 a wavefront per row, 3 a thread per
  * row, 0 automatic (64 rows per wavefront staged through LDS when the
@@ -130,6 +130,21 @@ TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode);
  * pivot's updates).  Same bits in every mode. */
 enum { TPILU_NUMERIC_AUTO = 0, TPILU_NUMERIC_FLOW = 1, TPILU_NUMERIC_PIVOT = 2 };
 TPILU_API tpilu_status tpilu_ctx_set_numeric(tpilu_ctx ctx, int mode);
+
+/* Placement of the single-instance numeric kernels and of the
+ * wavefront-per-row solves: 0 = automatic (the numeric kernels on the whole
+ * device; a solve on one XCD when its device-wide shape would take at most
+ * 256 wavefronts, i.e. a dependency level holds fewer than 32 rows, or fewer
+ * than 64 short ones, and a row half at most 128 entries on average),
+ * 1 = the whole device, 2 = one XCD.  On one XCD, grid wavefronts are
+ * launched per XCD; the first workgroup to start names its XCD and the
+ * workgroups of the other XCDs exit at once.  Values are then handed from
+ * row to row through that XCD's L2 (ordinary stores, agent-scope loads)
+ * instead of through memory, a round trip of about 0.5 us instead of 0.9 us
+ * on MI355X: deep, narrow dependency graphs gain, work that needs many rows
+ * in flight loses the other XCDs.  Same bits in every placement. */
+enum { TPILU_PLACE_AUTO = 0, TPILU_PLACE_DEVICE = 1, TPILU_PLACE_XCD = 2 };
+TPILU_API tpilu_status tpilu_ctx_set_placement(tpilu_ctx ctx, int where);
 
 /* Rows per ticket of the kernels that give a wavefront one row at a time
  * (numeric factorization, wavefront-per-row solves, incomplete inverses):

@@ -20,7 +20,7 @@ OK, E_INVAL, E_NOMEM, E_ZEROPIVOT, E_DEVICE, E_NOTCONV, E_TIMEOUT = range(7)
 
 EXPORTED = [
     "tpilu_ctx_create", "tpilu_ctx_set_stream", "tpilu_ctx_destroy", "tpilu_status_string",
-    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_numeric", "tpilu_ctx_set_group", "tpilu_ctx_set_tickets", "tpilu_inverse", "tpilu_apply_inverse", "tpilu_gmres_inverse", "tpilu_bicgstab", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
+    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_numeric", "tpilu_ctx_set_placement", "tpilu_ctx_set_group", "tpilu_ctx_set_tickets", "tpilu_inverse", "tpilu_apply_inverse", "tpilu_gmres_inverse", "tpilu_bicgstab", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
     "tpilu_pattern_export", "tpilu_pattern_destroy", "tpilu_numeric", "tpilu_pattern_check",
     "tpilu_apply", "tpilu_gmres", "tpilu_spmv", "tpilu_dot", "tpilu_apply_adjoint",
     "tpilu_numeric_adjoint", "tpilu_batched_graph_create", "tpilu_batched_graph_launch",
@@ -72,6 +72,7 @@ def load_library():
             "tpilu_ctx_set_grid": ([P, i32], st),
             "tpilu_ctx_set_solver": ([P, C.c_int], st),
             "tpilu_ctx_set_numeric": ([P, C.c_int], st),
+            "tpilu_ctx_set_placement": ([P, C.c_int], st),
             "tpilu_ctx_set_group": ([P, C.c_int32], st),
             "tpilu_ctx_set_tickets": ([P, C.c_int32], st),
             "tpilu_ctx_set_trace": ([P, P], st),
@@ -158,6 +159,14 @@ class Context:
         """Kernel of the single-instance numeric factorization (same bits in
         every mode): 0 automatic, 1 dataflow, 2 pivot-serial."""
         self.check(load_library().tpilu_ctx_set_numeric(self.h, mode), "set_numeric")
+
+    PLACE_AUTO, PLACE_DEVICE, PLACE_XCD = 0, 1, 2
+
+    def set_placement(self, where: int = 0):
+        """Where the single-instance numeric kernels and wavefront-per-row
+        solves run (same bits everywhere): 0 automatic, 1 whole device,
+        2 one XCD."""
+        self.check(load_library().tpilu_ctx_set_placement(self.h, where), "set_placement")
 
     def set_group(self, rows: int = 0):
         """Level-order rows per ticket of the wavefront-per-row kernels

@@ -50,7 +50,8 @@ struct Ctl {
     uint32_t status;        // kSt* bits
     uint32_t pad;
     unsigned long long bad_row;  // smallest row with a zero final pivot, or ~0
-    uint32_t pad2[58];
+    uint32_t leader;        // 1 + the XCD a one-XCD kernel runs on, 0 = not chosen yet
+    uint32_t pad2[57];
     uint32_t part[kTicketParts * kTicketStride];  // position counters (next_pos)
 };
 
@@ -240,13 +241,18 @@ __device__ __forceinline__ double bcast_lane(double v, int src) {
 }
 
 // Communication scope of the hand-off protocol: across the whole device
-// (agent-scope loads, bypassing the per-XCD L2s) or inside one workgroup
-// (all waves on one CU, whose caches are coherent for them).
-enum class Scope { Device, Workgroup };
+// (agent-scope stores, written through to memory, and agent-scope loads),
+// inside one XCD (ordinary stores, which stay in the XCD's L2, read back with
+// agent-scope loads, which skip the CU's L1 and take a line the L2 holds
+// dirty; measured on MI355X at about 0.5 us a round trip against about 0.9
+// us device-wide), or inside one workgroup (all waves on one CU, whose caches
+// are coherent for them).  A workgroup-scope load may hit the CU's L1 and then
+// never sees a store from another CU.
+enum class Scope { Device, Xcd, Workgroup };
 
 template <Scope S>
 __device__ __forceinline__ uint64_t ld_poll(const double* p) {
-    if constexpr (S == Scope::Device) return ld_coherent(p);
+    if constexpr (S != Scope::Workgroup) return ld_coherent(p);
     return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -259,6 +265,32 @@ __device__ __forceinline__ void st_final(double* p, double v) {
         __hip_atomic_store(reinterpret_cast<uint64_t*>(p), as_u64(v), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+}
+
+// XCD the calling wavefront runs on (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ uint32_t xcd_id() {
+    return static_cast<uint32_t>(__builtin_amdgcn_s_getreg(20 | (3 << 11))) & 0xFu;
+}
+
+// Membership of a one-XCD launch (single-wavefront workgroups): the first
+// workgroup to get here names its own XCD, and only workgroups on that XCD
+// take part; the others return at once.  Whatever order the hardware deals
+// workgroups to XCDs in, the chosen one holds at least that first workgroup,
+// so the work is always done.  ctl->leader is cleared before every launch.
+__device__ __forceinline__ bool xcd_member(Ctl* ctl) {
+    const uint32_t me = xcd_id() + 1u;
+    uint32_t l = 0u;
+    if (lane_id() == 0) {
+        l = __hip_atomic_load(&ctl->leader, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (l == 0u) {
+            uint32_t expected = 0u;
+            l = __hip_atomic_compare_exchange_strong(&ctl->leader, &expected, me, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    ? me
+                    : expected;
+        }
+    }
+    return __builtin_amdgcn_readfirstlane(l) == me;
 }
 
 // Running subtraction s <- s - f_k * v_k for k = 0 .. cnt-1 in that order,

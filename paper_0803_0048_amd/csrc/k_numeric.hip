@@ -25,6 +25,7 @@ __global__ void k_fill_pending(double* __restrict__ p, int64_t n, Ctl* ctl, int 
     if (blockIdx.x == 0 && threadIdx.x < kTicketParts) ctl->part[threadIdx.x * kTicketStride] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->ticket = 0;
+        ctl->leader = 0;
         if (reset_status) {
             ctl->abort = 0;
             ctl->status = 0;
@@ -108,6 +109,7 @@ __device__ __forceinline__ void wait_pivot(const double* F, int32_t i, int32_t n
 constexpr int kPivCap = 128;   // pivots staged per group
 constexpr int kPairCap = 512;  // update pairs staged per group
 
+template <Scope S>
 __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __restrict__ a_val,
                                                     double* F, Ctl* ctl, uint64_t spin_limit,
                                                     int64_t skip_row) {
@@ -118,12 +120,16 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
     __shared__ int32_t pr_q[kPairCap];
     __shared__ int32_t pr_p[kPairCap];
     __shared__ uint64_t pr_v[kPairCap];
+    if constexpr (S == Scope::Xcd) {
+        if (!xcd_member(ctl)) return;
+    }
+    const uint32_t parts = S == Scope::Xcd ? 1u : (uint32_t)P.parts;
     const int lane = lane_id();
     const int32_t n = P.n;
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, (uint32_t)n, (uint32_t)P.groupL, (uint32_t)P.parts, run, t)) break;
+        if (!next_pos(ctl, (uint32_t)n, (uint32_t)P.groupL, parts, run, t)) break;
         const int32_t j = P.permL ? P.permL[t] : (int32_t)t;
         trace_mark(P.trace, j);
         // The loads of a row are issued level by level of their address
@@ -254,7 +260,7 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
         if (lane == 0 && W[dl] == 0.0) atomicMin(&ctl->bad_row, (unsigned long long)j);
         if ((int64_t)j != skip_row) {
             // U part first: later rows wait on it; the L part is only read by later kernels
-            for (int32_t e = dl + lane; e < len; e += kWave) st_publish(F + rs + e, W[e]);
+            for (int32_t e = dl + lane; e < len; e += kWave) st_final<S>(F + rs + e, W[e]);
             for (int32_t e = lane; e < dl; e += kWave) F[rs + e] = W[e];
         }
         trace_mark(P.trace, (int64_t)n + j);
@@ -289,6 +295,7 @@ size_t flow_lds_bytes(int32_t max_row, int32_t cap) {
            ((size_t)max_row + 1) * 4;
 }
 
+template <Scope S>
 __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __restrict__ a_val, double* F,
                                                      Ctl* ctl, uint64_t spin_limit, int64_t skip_row,
                                                      int32_t max_row, int32_t cap) {
@@ -301,12 +308,16 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
     int32_t* Ss = Uq + max_row;                                      // [cap] pivot entry of update
     int32_t* Sq = Ss + cap;                                          // [cap] F slot of f_ht
     int32_t* Tb = Sq + cap;                                          // [max_row + 1] chunk offsets
+    if constexpr (S == Scope::Xcd) {
+        if (!xcd_member(ctl)) return;
+    }
+    const uint32_t parts = S == Scope::Xcd ? 1u : (uint32_t)P.parts;
     const int lane = lane_id();
     const int32_t n = P.n;
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, (uint32_t)n, (uint32_t)P.groupL, (uint32_t)P.parts, run, t)) break;
+        if (!next_pos(ctl, (uint32_t)n, (uint32_t)P.groupL, parts, run, t)) break;
         const int32_t j = P.permL ? P.permL[t] : (int32_t)t;
         trace_mark(P.trace, j);
         const int64_t rs = P.rpF[j], re = P.rpF[j + 1];
@@ -379,7 +390,7 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
                                 if (ub == kPending) fin = false;
                                 else Lb[p] = as_u64(acc / as_f64(ub));
                             } else {
-                                if (publish) st_publish(F + rs + p, acc);
+                                if (publish) st_final<S>(F + rs + p, acc);
                                 if (p == dl && acc == 0.0) atomicMin(&ctl->bad_row, (unsigned long long)j);
                             }
                             if (fin) {
@@ -449,7 +460,7 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
             }
             // after an abort, release anything that might still wait on this row
             if (stop)
-                for (int32_t q = dl + lane; q < len; q += kWave) st_publish(F + rs + q, as_f64(kQNaN));
+                for (int32_t q = dl + lane; q < len; q += kWave) st_final<S>(F + rs + q, as_f64(kQNaN));
         }
         trace_mark(P.trace, (int64_t)n + j);
         wave_sync();
@@ -676,16 +687,26 @@ int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, in
 
 hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, double* f_val,
                           Ctl* ctl, uint64_t spin_limit, int64_t skip_row, int32_t grid,
-                          int32_t max_row, int32_t max_lrow, bool flow, hipStream_t s) {
+                          int32_t max_row, int32_t max_lrow, bool flow, bool one_xcd, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
+    const dim3 g1(one_xcd ? grid * kXcds : grid);
     if (batch == 1 && flow) {
         const int32_t mr = std::max(max_row, 1), cap = flow_cap(max_lrow);
-        hipLaunchKernelGGL(k_numeric_flow, dim3(grid), dim3(64), flow_lds_bytes(mr, cap), s, P, a_val, f_val,
-                           ctl, spin_limit, skip_row, mr, cap);
+        const size_t lds = flow_lds_bytes(mr, cap);
+        if (one_xcd)
+            hipLaunchKernelGGL(k_numeric_flow<Scope::Xcd>, g1, dim3(64), lds, s, P, a_val, f_val, ctl, spin_limit,
+                               skip_row, mr, cap);
+        else
+            hipLaunchKernelGGL(k_numeric_flow<Scope::Device>, g1, dim3(64), lds, s, P, a_val, f_val, ctl,
+                               spin_limit, skip_row, mr, cap);
     } else if (batch == 1) {
-        size_t lds = (size_t)std::max(max_row, 1) * sizeof(double);
-        hipLaunchKernelGGL(k_numeric_row, dim3(grid), dim3(64), lds, s, P, a_val, f_val, ctl,
-                           spin_limit, skip_row);
+        const size_t lds = (size_t)std::max(max_row, 1) * sizeof(double);
+        if (one_xcd)
+            hipLaunchKernelGGL(k_numeric_row<Scope::Xcd>, g1, dim3(64), lds, s, P, a_val, f_val, ctl, spin_limit,
+                               skip_row);
+        else
+            hipLaunchKernelGGL(k_numeric_row<Scope::Device>, g1, dim3(64), lds, s, P, a_val, f_val, ctl,
+                               spin_limit, skip_row);
     } else {
         size_t lds = (size_t)std::max(max_row, 1) * sizeof(double) * kWave;
         hipLaunchKernelGGL(k_numeric_batch, dim3(grid), dim3(64), lds, s, P, a_val, batch, f_val,

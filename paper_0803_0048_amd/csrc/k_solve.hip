@@ -73,25 +73,37 @@ __device__ __forceinline__ void backward_row(const PatDev& P, const double* __re
 }
 
 // whole device: persistent grid, rows handed out by the task counters
+// S == Scope::Xcd: only the workgroups on one XCD take part, all drawing
+// from one counter (which workgroups those are is known only at run time)
+template <Scope S>
 __global__ __launch_bounds__(64) void k_forward_row(PatDev P, const double* __restrict__ F,
                                                     const double* __restrict__ b, double* x,
                                                     Ctl* ctl, uint64_t spin_limit) {
+    if constexpr (S == Scope::Xcd) {
+        if (!xcd_member(ctl)) return;
+    }
+    const uint32_t parts = S == Scope::Xcd ? 1u : (uint32_t)P.parts;
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, (uint32_t)P.n, (uint32_t)P.groupL, (uint32_t)P.parts, run, t)) break;
-        forward_row<Scope::Device>(P, F, b, x, ctl, spin_limit, P.permL ? P.permL[t] : (int32_t)t);
+        if (!next_pos(ctl, (uint32_t)P.n, (uint32_t)P.groupL, parts, run, t)) break;
+        forward_row<S>(P, F, b, x, ctl, spin_limit, P.permL ? P.permL[t] : (int32_t)t);
     }
 }
 
+template <Scope S>
 __global__ __launch_bounds__(64) void k_backward_row(PatDev P, const double* __restrict__ F,
                                                      const double* __restrict__ x, double* y,
                                                      Ctl* ctl, uint64_t spin_limit) {
+    if constexpr (S == Scope::Xcd) {
+        if (!xcd_member(ctl)) return;
+    }
+    const uint32_t parts = S == Scope::Xcd ? 1u : (uint32_t)P.parts;
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, (uint32_t)P.n, (uint32_t)P.groupU, (uint32_t)P.parts, run, t)) break;
-        backward_row<Scope::Device>(P, F, x, y, ctl, spin_limit, P.permU ? P.permU[t] : P.n - 1 - (int32_t)t);
+        if (!next_pos(ctl, (uint32_t)P.n, (uint32_t)P.groupU, parts, run, t)) break;
+        backward_row<S>(P, F, x, y, ctl, spin_limit, P.permU ? P.permU[t] : P.n - 1 - (int32_t)t);
     }
 }
 
@@ -334,17 +346,23 @@ __global__ __launch_bounds__(64) void k_backward_batch(PatDev P, const double* _
     }
 }
 
-// single instance: grid > 0 wavefront per row, grid == 0 one workgroup,
-// grid < 0 lane per row with -grid wavefronts
+// single instance: grid > 0 wavefront per row (one_xcd: grid wavefronts per
+// XCD launched, those of one XCD working), grid == 0 one workgroup, grid < 0
+// lane per row with -grid wavefronts
 hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, const double* b,
-                          double* x, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s) {
+                          double* x, Ctl* ctl, uint64_t spin_limit, int32_t grid, bool one_xcd,
+                          hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
     if (batch == 1 && grid == 0)
         hipLaunchKernelGGL(k_forward_wg, dim3(1), dim3(1024), 0, s, P, f_val, b, x, ctl, spin_limit);
     else if (batch == 1 && grid < 0)
         hipLaunchKernelGGL(k_solve_lanes<false>, dim3(-grid), dim3(64), 0, s, P, f_val, b, x, ctl, spin_limit);
+    else if (batch == 1 && one_xcd)
+        hipLaunchKernelGGL(k_forward_row<Scope::Xcd>, dim3(grid * kXcds), dim3(64), 0, s, P, f_val, b, x, ctl,
+                           spin_limit);
     else if (batch == 1)
-        hipLaunchKernelGGL(k_forward_row, dim3(grid), dim3(64), 0, s, P, f_val, b, x, ctl, spin_limit);
+        hipLaunchKernelGGL(k_forward_row<Scope::Device>, dim3(grid), dim3(64), 0, s, P, f_val, b, x, ctl,
+                           spin_limit);
     else
         hipLaunchKernelGGL(k_forward_batch, dim3(grid), dim3(64), 0, s, P, f_val, batch, b, x, ctl,
                            spin_limit);
@@ -352,14 +370,19 @@ hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, c
 }
 
 hipError_t launch_backward(const PatDev& P, const double* f_val, int32_t batch, const double* x,
-                           double* y, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s) {
+                           double* y, Ctl* ctl, uint64_t spin_limit, int32_t grid, bool one_xcd,
+                           hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
     if (batch == 1 && grid == 0)
         hipLaunchKernelGGL(k_backward_wg, dim3(1), dim3(1024), 0, s, P, f_val, x, y, ctl, spin_limit);
     else if (batch == 1 && grid < 0)
         hipLaunchKernelGGL(k_solve_lanes<true>, dim3(-grid), dim3(64), 0, s, P, f_val, x, y, ctl, spin_limit);
+    else if (batch == 1 && one_xcd)
+        hipLaunchKernelGGL(k_backward_row<Scope::Xcd>, dim3(grid * kXcds), dim3(64), 0, s, P, f_val, x, y,
+                           ctl, spin_limit);
     else if (batch == 1)
-        hipLaunchKernelGGL(k_backward_row, dim3(grid), dim3(64), 0, s, P, f_val, x, y, ctl, spin_limit);
+        hipLaunchKernelGGL(k_backward_row<Scope::Device>, dim3(grid), dim3(64), 0, s, P, f_val, x, y, ctl,
+                           spin_limit);
     else
         hipLaunchKernelGGL(k_backward_batch, dim3(grid), dim3(64), 0, s, P, f_val, batch, x, y, ctl,
                            spin_limit);

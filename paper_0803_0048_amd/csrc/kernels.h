@@ -119,11 +119,14 @@ struct PatDev {
 // reset_status, the sticky status words)
 hipError_t launch_fill_pending(double* p, int64_t n, Ctl* ctl, bool reset_status, hipStream_t s);
 
+constexpr int32_t kXcds = 8;  // XCDs of an MI355X
+
 // flow: the single-instance dataflow kernel (needs the target-major schedule
-// and numeric_flow_fits); otherwise the pivot-serial one
+// and numeric_flow_fits); otherwise the pivot-serial one.  one_xcd (single
+// instance): grid wavefronts per XCD launched, those of one XCD working.
 hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, double* f_val,
                           Ctl* ctl, uint64_t spin_limit, int64_t skip_row, int32_t grid,
-                          int32_t max_row, int32_t max_lrow, bool flow, hipStream_t s);
+                          int32_t max_row, int32_t max_lrow, bool flow, bool one_xcd, hipStream_t s);
 int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, int num_cu);
 bool numeric_flow_fits(int32_t max_row, int32_t max_lrow, size_t lds_limit);
 // target-major update schedule (mode 0 count per slot, mode 1 fill); LDS of
@@ -134,12 +137,15 @@ hipError_t launch_tsched(int32_t n, const int64_t* rpF, const int32_t* diagF, co
 size_t tsched_lds_bytes(int32_t max_row, int32_t max_lrow);
 
 // ---- triangular solves -------------------------------------------------------------
-// single instance: grid > 0 wavefront per row, 0 one workgroup, < 0 lane per
-// row with -grid wavefronts; batches: lanes = instances with grid wavefronts
+// single instance: grid > 0 wavefront per row (one_xcd: grid wavefronts on
+// one XCD), 0 one workgroup, < 0 lane per row with -grid wavefronts;
+// batches: lanes = instances with grid wavefronts
 hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, const double* b,
-                          double* x, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s);
+                          double* x, Ctl* ctl, uint64_t spin_limit, int32_t grid, bool one_xcd,
+                          hipStream_t s);
 hipError_t launch_backward(const PatDev& P, const double* f_val, int32_t batch, const double* x,
-                           double* y, Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s);
+                           double* y, Ctl* ctl, uint64_t spin_limit, int32_t grid, bool one_xcd,
+                           hipStream_t s);
 
 // ---- Krylov building blocks ---------------------------------------------------
 constexpr int kDotLanes = 16384;  // fixed shape of every inner product

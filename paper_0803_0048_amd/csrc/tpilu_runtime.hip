@@ -29,6 +29,7 @@ struct tpilu_ctx_s {
     int32_t grid_override = 0;
     int solver = 0;  // 0 auto, 1 wavefront per row, 2 one workgroup, 3 lane per row
     int numeric = 0;  // 0 auto, 1 dataflow, 2 pivot-serial
+    int placement = 0;  // row kernels: 0 auto, 1 whole device, 2 one XCD
     int32_t group = 0;  // level-order positions per ticket of the row kernels; 0 auto
     int32_t tickets = 0;  // position counters of the row kernels; 0 auto
     bool timing = false;
@@ -85,6 +86,15 @@ constexpr int32_t kAdjointWaves = 512;
 constexpr int32_t kAdjointBatchWaves = 1024;  // batched reverse elimination (3-D 7-point 32^3 x16: 1.9 ms, 2.2 at 512)
 constexpr int32_t kInverseWaves = 1024;  // incomplete inverses (n=160,000 ILU(2): 7.0 ms, 8.3 at 512)
 constexpr int64_t kNarrowWidth = 32;   // n / depth below this: narrow
+// Wavefront-per-row solves run on one XCD, where the hand-offs stay in that
+// XCD's L2, when the device-wide shape would take at most 256 wavefronts (a
+// dependency level of fewer than 32 rows, or fewer than 64 of short rows)
+// and a row half holds at most this many entries on average.  Measured on
+// MI355X (forward / backward ms, device vs one XCD): random banded n=160,000
+// ILU(2) (13 rows per level, 82 entries per half) 11.8 / 12.6 vs 8.4 / 9.3;
+// 2-D 64 x 64 ILU(1) 0.18 / 0.19 vs 0.14 / 0.16; Table 3 scale ILU(1) (40
+// rows per level, 640 entries per half) 5.2 / 6.0 vs 12.0 / 12.2.
+constexpr int64_t kXcdMaxAvg = 128;
 constexpr int64_t kLevelLaneMax = 14;  // level computation: lane per node below this many dependencies
 constexpr int64_t kLevelWideMax = 60;  // wavefront per node: the wide window below this, else the narrow one
 constexpr int32_t kLevelWavesWide = 768;
@@ -363,22 +373,28 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
                            pat->n < kFlowMaxWidth * std::max<int64_t>(pat->depth_l, 1);
     const bool flow = batch == 1 && pat->flow && (ctx->numeric == 1 || (ctx->numeric == 0 && auto_flow));
     HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, pat->ctl, true, ctx->stream));
+    // one XCD only when asked for: the factorization keeps many rows in flight
+    // and needs the whole device (random banded n=160,000 ILU(2): 8.5 ms on
+    // the device, 26 ms on one XCD); there the grid is that XCD's resident
+    // maximum
+    const bool one_xcd = batch == 1 && ctx->placement == 2;
     const int grid = ctx->grid_override
                          ? ctx->grid_override
-                         : numeric_grid(batch, pat->st.max_row, pat->st.max_lrow, flow, ctx->num_cu);
+                         : std::max(1, numeric_grid(batch, pat->st.max_row, pat->st.max_lrow, flow, ctx->num_cu) /
+                                           (one_xcd ? kXcds : 1));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_NUMERIC);
         HIPCHK(ctx, launch_numeric(pdev(ctx, pat, RowKernel::Numeric, true), a_val, batch, f_val, pat->ctl,
                                    ctx->spin_limit, ctx->skip_row, grid, pat->st.max_row, pat->st.max_lrow, flow,
-                                   ctx->stream));
+                                   one_xcd, ctx->stream));
     }
     return TPILU_OK;
 }
 
 // Launch shape of the single-instance solves, per direction (the grid
 // argument of launch_forward / launch_backward): > 0 wavefront per row with
-// that many wavefronts, 0 one workgroup, < 0 lane per row with -grid
-// wavefronts.  Automatic choice: lane per row when the rows are short and a
+// that many wavefronts (on one XCD when one_xcd), 0 one workgroup, < 0 lane
+// per row with -grid wavefronts.  Automatic choice: lane per row when the rows are short and a
 // dependency level is wide next to the row length (a lane runs a whole row
 // alone, so it needs many rows per level to beat 64 lanes on one row),
 // namely rows per level >= max(64, 16 x average entries per row half); else
@@ -394,8 +410,13 @@ constexpr int64_t kLaneMinWidth = 64;  // rows per dependency level at or above
 constexpr int64_t kLaneWidthPerEntry = 16;  // ... and at or above this many per entry of a row half
 constexpr int32_t kLaneWaves = 128;
 
-int32_t solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool backward) {
-    if (batch > 1) return ctx->grid_override ? ctx->grid_override : kBatchSolveWaves;
+struct SolveShape {
+    int32_t grid;
+    bool one_xcd;
+};
+
+SolveShape solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool backward) {
+    if (batch > 1) return {ctx->grid_override ? ctx->grid_override : kBatchSolveWaves, false};
     const int64_t n = std::max<int64_t>(pat->n, 1);
     const int64_t half = backward ? pat->nnz_f - (int64_t)pat->st.nnz_l - pat->n : (int64_t)pat->st.nnz_l;
     const int64_t depth = std::max<int64_t>(1, backward ? pat->depth_u : pat->depth_l);
@@ -406,28 +427,32 @@ int32_t solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool backwa
                            width * n >= kLaneWidthPerEntry * half;
         mode = lanes ? 3 : 1;
     }
-    if (mode == 2) return 0;
-    if (mode == 3) return -(ctx->grid_override ? ctx->grid_override : kLaneWaves);
-    if (ctx->grid_override) return ctx->grid_override;
+    if (mode == 2) return {0, false};
+    if (mode == 3) return {-(ctx->grid_override ? ctx->grid_override : kLaneWaves), false};
     const int64_t width = n / depth;
-    if (width < kNarrowWidth) return kSolveWavesNarrow;
-    if (width < 64 && half < 64 * n) return kSolveWavesMid;
-    return kSolveWavesWide;
+    const bool few_short = (width < kNarrowWidth && half <= kXcdMaxAvg * n) || (width < 64 && half < 64 * n);
+    const bool one_xcd = ctx->placement == 2 || (ctx->placement == 0 && few_short);
+    if (ctx->grid_override) return {ctx->grid_override, one_xcd};
+    if (width < kNarrowWidth) return {kSolveWavesNarrow, one_xcd};
+    if (width < 64 && half < 64 * n) return {kSolveWavesMid, one_xcd};
+    return {kSolveWavesWide, one_xcd};
 }
 
 tpilu_status enqueue_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val, int32_t batch,
                            const double* b, double* y, double* x, bool reset) {
-    const int32_t gf = solve_shape(ctx, pat, batch, false), gb = solve_shape(ctx, pat, batch, true);
+    const SolveShape gf = solve_shape(ctx, pat, batch, false), gb = solve_shape(ctx, pat, batch, true);
     const PatDev P = pdev(ctx, pat, RowKernel::Solve, true);
     HIPCHK(ctx, launch_fill_pending(x, pat->n * batch, pat->ctl, reset, ctx->stream));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_FORWARD);
-        HIPCHK(ctx, launch_forward(P, f_val, batch, b, x, pat->ctl, ctx->spin_limit, gf, ctx->stream));
+        HIPCHK(ctx, launch_forward(P, f_val, batch, b, x, pat->ctl, ctx->spin_limit, gf.grid, gf.one_xcd,
+                                   ctx->stream));
     }
     HIPCHK(ctx, launch_fill_pending(y, pat->n * batch, pat->ctl, false, ctx->stream));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_BACKWARD);
-        HIPCHK(ctx, launch_backward(P, f_val, batch, x, y, pat->ctl, ctx->spin_limit, gb, ctx->stream));
+        HIPCHK(ctx, launch_backward(P, f_val, batch, x, y, pat->ctl, ctx->spin_limit, gb.grid, gb.one_xcd,
+                                    ctx->stream));
     }
     return TPILU_OK;
 }
@@ -735,6 +760,13 @@ extern "C" TPILU_API tpilu_status tpilu_ctx_set_numeric(tpilu_ctx ctx, int mode)
     if (!ctx) return TPILU_E_INVAL;
     if (mode < 0 || mode > 2) return fail(ctx, TPILU_E_INVAL, "numeric mode must be 0, 1 or 2");
     ctx->numeric = mode;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_placement(tpilu_ctx ctx, int where) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (where < 0 || where > 2) return fail(ctx, TPILU_E_INVAL, "placement must be 0, 1 or 2");
+    ctx->placement = where;
     return TPILU_OK;
 }
 

@@ -27,6 +27,7 @@ def _gpu_guard(request):
     ctx.set_grid(0)
     ctx.set_solver(0)
     ctx.set_numeric(0)
+    ctx.set_placement(0)
     ctx.set_group(0)
     ctx.set_tickets(0)
     ctx.set_watchdog(0, -1)
@@ -222,8 +223,10 @@ def test_repeatable_across_launch_shapes():
     ctx = T.context(0)
     ref_f = T.numeric(pat, av)
     ref_y = T.apply(pat, ref_f, bv)
-    for solver in (ctx.SOLVER_DEVICE, ctx.SOLVER_WORKGROUP, ctx.SOLVER_LANES):
+    for solver, place in ((ctx.SOLVER_DEVICE, ctx.PLACE_DEVICE), (ctx.SOLVER_DEVICE, ctx.PLACE_XCD),
+                          (ctx.SOLVER_WORKGROUP, 0), (ctx.SOLVER_LANES, 0)):
         ctx.set_solver(solver)
+        ctx.set_placement(place)
         for waves, group, tickets in ((1, 1, 8), (2, 3, 8), (7, 0, 3), (64, 64, 1), (1000, 2, 5), (0, 0, 0),
                                       (40000, 5, 8)):
             ctx.set_grid(waves)
@@ -232,13 +235,14 @@ def test_repeatable_across_launch_shapes():
             for _ in range(3):
                 f = T.numeric(pat, av)
                 y = T.apply(pat, f, bv)
-                key = (solver, waves, group, tickets)
+                key = (solver, place, waves, group, tickets)
                 assert torch.equal(f.view(torch.int64), ref_f.view(torch.int64)), key
                 assert torch.equal(y.view(torch.int64), ref_y.view(torch.int64)), key
     ctx.set_grid(0)
     ctx.set_group(0)
     ctx.set_tickets(0)
     ctx.set_solver(0)
+    ctx.set_placement(0)
 
 
 @pytest.mark.parametrize("cfg", ["cd3d_k1", "s27_k1"])
@@ -256,7 +260,8 @@ def test_row_groups_agree_full_size(cfg):
     modes = [ctx.NUMERIC_PIVOT] + ([ctx.NUMERIC_FLOW] if pat.info["flow_ready"] else [])
     try:
         ctx.set_solver(ctx.SOLVER_DEVICE)
-        for group, tickets in ((1, 1), (1, 8), (2, 3), (5, 8), (8, 2), (64, 8)):
+        for group, tickets, place in ((1, 1, 1), (1, 8, 2), (2, 3, 1), (5, 8, 2), (8, 2, 1), (64, 8, 2)):
+            ctx.set_placement(place)
             ctx.set_group(group)
             ctx.set_tickets(tickets)
             for mode in modes:
@@ -272,6 +277,7 @@ def test_row_groups_agree_full_size(cfg):
         ctx.set_tickets(0)
         ctx.set_numeric(0)
         ctx.set_solver(0)
+        ctx.set_placement(0)
 
 
 @pytest.mark.parametrize("cfg", ["banded", "cd3d_k1"])
@@ -285,12 +291,15 @@ def test_solver_shapes_agree_full_size(cfg):
     vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
     x_ref, y_ref = O.apply(A.n, rpF, ciF, vF, b)
     ctx = T.context(0)
-    for solver in (ctx.SOLVER_DEVICE, ctx.SOLVER_WORKGROUP, ctx.SOLVER_LANES):
+    for solver, place in ((ctx.SOLVER_DEVICE, ctx.PLACE_DEVICE), (ctx.SOLVER_DEVICE, ctx.PLACE_XCD),
+                          (ctx.SOLVER_WORKGROUP, 0), (ctx.SOLVER_LANES, 0)):
         ctx.set_solver(solver)
+        ctx.set_placement(place)
         y, x = T.apply(pat, f, g(b), return_x=True)
-        assert_bits_equal(x, x_ref, f"x solver {solver}")
-        assert_bits_equal(y, y_ref, f"y solver {solver}")
+        assert_bits_equal(x, x_ref, f"x solver {solver} placement {place}")
+        assert_bits_equal(y, y_ref, f"y solver {solver} placement {place}")
     ctx.set_solver(0)
+    ctx.set_placement(0)
 
 
 def test_repeatable_random_banded():
@@ -342,7 +351,7 @@ def test_context_settings_reject_out_of_range():
     E_INVAL and leave the previous setting in force."""
     ctx = T.context(0)
     for call, bad in ((ctx.set_group, (-1, 65)), (ctx.set_tickets, (-1, 9)), (ctx.set_solver, (-1, 4)),
-                      (ctx.set_numeric, (-1, 3)), (ctx.set_grid, (-1,))):
+                      (ctx.set_numeric, (-1, 3)), (ctx.set_placement, (-1, 3)), (ctx.set_grid, (-1,))):
         for v in bad:
             with pytest.raises(T.TpiluError) as e:
                 call(v)
