@@ -113,6 +113,7 @@ __global__ __launch_bounds__(64) void k_adj_solve_u(PatDev P, AdjPat T, const do
         // rows j < i of column i, taken in ascending j
         const int64_t a0 = T.tpU[i], a1 = T.tpU[i + 1];
         double s = sanitize_input(ybar[(int64_t)i * B + b], ctl);
+        const double fii = F[(int64_t)P.diagF[i] * B + b];
         for (int64_t c = a0; c < a1; c += kWave) {
             const int32_t cnt = (int32_t)min<int64_t>(kWave, a1 - c);
             double f = 0.0;
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(64) void k_adj_solve_u(PatDev P, AdjPat T, const do
             }
             s = chain_sub<Scope::Device>(s, cnt, f, src, ctl, spin_limit);
         }
-        const double r = s / F[(int64_t)P.diagF[i] * B + b];
+        const double r = s / fii;
         if (lane == 0) st_publish(z + (int64_t)i * B + b, r);
     }
 }
@@ -181,6 +182,7 @@ __global__ __launch_bounds__(64) void k_adj_solve_u_batch(PatDev P, AdjPat T, co
         if (col < B) {
             const int64_t a0 = T.tpU[i], a1 = T.tpU[i + 1];
             double s = sanitize_input(ybar[(int64_t)i * B + col], ctl);
+            const double fii = F[(int64_t)P.diagF[i] * B + col];
             for (int64_t c = a0; c < a1; c += kAdjChunk) {  // rows j < i of column i, ascending
                 double fv[kAdjChunk];
                 uint64_t zv[kAdjChunk];
@@ -202,7 +204,7 @@ __global__ __launch_bounds__(64) void k_adj_solve_u_batch(PatDev P, AdjPat T, co
                 for (int u = 0; u < kAdjChunk; ++u)
                     if (c + u < a1) s = s - fv[u] * as_f64(zv[u]);
             }
-            st_publish(z + (int64_t)i * B + col, s / F[(int64_t)P.diagF[i] * B + col]);
+            st_publish(z + (int64_t)i * B + col, s / fii);
         }
     }
 }
