@@ -131,8 +131,9 @@ TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode);
 enum { TPILU_NUMERIC_AUTO = 0, TPILU_NUMERIC_FLOW = 1, TPILU_NUMERIC_PIVOT = 2 };
 TPILU_API tpilu_status tpilu_ctx_set_numeric(tpilu_ctx ctx, int mode);
 
-/* Placement of the single-instance numeric kernels and of the
- * wavefront-per-row solves: 0 = automatic (the numeric kernels on the whole
+/* Placement of the single-instance numeric kernels, of the
+ * wavefront-per-row solves and of the single-instance transposed solves of
+ * tpilu_apply_adjoint: 0 = automatic (the numeric kernels on the whole
  * device; a solve on one XCD when its device-wide shape would take at most
  * 256 wavefronts, i.e. a dependency level holds fewer than 32 rows, or fewer
  * than 64 short ones, and a row half at most 128 entries on average),

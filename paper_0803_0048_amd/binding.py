@@ -163,9 +163,9 @@ class Context:
     PLACE_AUTO, PLACE_DEVICE, PLACE_XCD = 0, 1, 2
 
     def set_placement(self, where: int = 0):
-        """Where the single-instance numeric kernels and wavefront-per-row
-        solves run (same bits everywhere): 0 automatic, 1 whole device,
-        2 one XCD."""
+        """Where the single-instance numeric kernels, wavefront-per-row
+        solves and single-instance transposed solves run (same bits
+        everywhere): 0 automatic, 1 whole device, 2 one XCD."""
         self.check(load_library().tpilu_ctx_set_placement(self.h, where), "set_placement")
 
     def set_group(self, rows: int = 0):

@@ -96,7 +96,6 @@ __device__ __noinline__ double wait_final_slow(const double* p, Ctl* ctl, uint64
             }
         }
         ++n;
-        __builtin_amdgcn_s_sleep(1);
     }
 }
 

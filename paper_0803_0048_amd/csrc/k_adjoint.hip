@@ -99,21 +99,29 @@ hipError_t launch_sort_columns(int32_t n, const int64_t* tp, int32_t* ts, int32_
 // transposed solves
 // ----------------------------------------------------------------------------------
 // z = U~^-T ybar: i ascending, z_i = (ybar_i - sum_{j<i} f_ji z_j) / f_ii
+// (S == Scope::Xcd: single instance, every wavefront on one XCD, as the
+// forward and backward solves)
+template <Scope S>
 __global__ __launch_bounds__(64) void k_adj_solve_u(PatDev P, AdjPat T, const double* __restrict__ F,
                                                     int32_t B, const double* __restrict__ ybar,
                                                     double* z, Ctl* ctl, uint64_t spin_limit) {
+    if constexpr (S == Scope::Xcd) {
+        if (!xcd_member(ctl)) return;
+    }
+    const uint32_t parts = S == Scope::Xcd ? 1u : (uint32_t)P.parts;
     const int lane = lane_id();
     const uint32_t ntask = (uint32_t)P.n * (uint32_t)B;
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
+        if (!next_pos(ctl, ntask, 1u, parts, run, t)) break;
         const int32_t i = T.permUT[t / (uint32_t)B];
         const int32_t b = (int32_t)(t % (uint32_t)B);
         // rows j < i of column i, taken in ascending j
         const int64_t a0 = T.tpU[i], a1 = T.tpU[i + 1];
         double s = sanitize_input(ybar[(int64_t)i * B + b], ctl);
-        const double fii = F[(int64_t)P.diagF[i] * B + b];
+        double fii = 0.0;  // read before the chain on one XCD, after it device-wide
+        if constexpr (S == Scope::Xcd) fii = F[(int64_t)P.diagF[i] * B + b];
         for (int64_t c = a0; c < a1; c += kWave) {
             const int32_t cnt = (int32_t)min<int64_t>(kWave, a1 - c);
             double f = 0.0;
@@ -122,23 +130,29 @@ __global__ __launch_bounds__(64) void k_adj_solve_u(PatDev P, AdjPat T, const do
                 f = F[(int64_t)T.tsU[c + lane] * B + b];
                 src = z + (int64_t)T.trU[c + lane] * B + b;
             }
-            s = chain_sub<Scope::Device>(s, cnt, f, src, ctl, spin_limit);
+            s = chain_sub<S>(s, cnt, f, src, ctl, spin_limit);
         }
+        if constexpr (S != Scope::Xcd) fii = F[(int64_t)P.diagF[i] * B + b];
         const double r = s / fii;
-        if (lane == 0) st_publish(z + (int64_t)i * B + b, r);
+        if (lane == 0) st_final<S>(z + (int64_t)i * B + b, r);
     }
 }
 
 // w = L~^-T z: i descending, w_i = z_i - sum_{j>i} f_ji w_j, j descending
+template <Scope S>
 __global__ __launch_bounds__(64) void k_adj_solve_l(PatDev P, AdjPat T, const double* __restrict__ F,
                                                     int32_t B, const double* __restrict__ z,
                                                     double* w, Ctl* ctl, uint64_t spin_limit) {
+    if constexpr (S == Scope::Xcd) {
+        if (!xcd_member(ctl)) return;
+    }
+    const uint32_t parts = S == Scope::Xcd ? 1u : (uint32_t)P.parts;
     const int lane = lane_id();
     const uint32_t ntask = (uint32_t)P.n * (uint32_t)B;
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
+        if (!next_pos(ctl, ntask, 1u, parts, run, t)) break;
         const int32_t i = T.permLT[t / (uint32_t)B];
         const int32_t b = (int32_t)(t % (uint32_t)B);
         // rows j > i of column i, taken in descending j
@@ -153,9 +167,9 @@ __global__ __launch_bounds__(64) void k_adj_solve_l(PatDev P, AdjPat T, const do
                 f = F[(int64_t)T.tsL[a] * B + b];
                 src = w + (int64_t)T.trL[a] * B + b;
             }
-            s = chain_sub<Scope::Device>(s, cnt, f, src, ctl, spin_limit);
+            s = chain_sub<S>(s, cnt, f, src, ctl, spin_limit);
         }
-        if (lane == 0) st_publish(w + (int64_t)i * B + b, s);
+        if (lane == 0) st_final<S>(w + (int64_t)i * B + b, s);
     }
 }
 
@@ -250,27 +264,33 @@ __global__ __launch_bounds__(64) void k_adj_solve_l_batch(PatDev P, AdjPat T, co
 
 hipError_t launch_adj_solve_u(const PatDev& P, const AdjPat& T, const double* f_val,
                               int32_t batch, const double* ybar, double* z, Ctl* ctl,
-                              uint64_t spin_limit, int32_t grid, hipStream_t s) {
+                              uint64_t spin_limit, int32_t grid, bool one_xcd, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
     if (batch > 1)
         hipLaunchKernelGGL(k_adj_solve_u_batch, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, ybar, z, ctl,
                            spin_limit);
+    else if (one_xcd)
+        hipLaunchKernelGGL(k_adj_solve_u<Scope::Xcd>, dim3(grid * kXcds), dim3(64), 0, s, P, T, f_val, batch,
+                           ybar, z, ctl, spin_limit);
     else
-        hipLaunchKernelGGL(k_adj_solve_u, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, ybar, z, ctl,
-                           spin_limit);
+        hipLaunchKernelGGL(k_adj_solve_u<Scope::Device>, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, ybar, z,
+                           ctl, spin_limit);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_solve_l(const PatDev& P, const AdjPat& T, const double* f_val,
                               int32_t batch, const double* z, double* w, Ctl* ctl,
-                              uint64_t spin_limit, int32_t grid, hipStream_t s) {
+                              uint64_t spin_limit, int32_t grid, bool one_xcd, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
     if (batch > 1)
         hipLaunchKernelGGL(k_adj_solve_l_batch, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, z, w, ctl,
                            spin_limit);
+    else if (one_xcd)
+        hipLaunchKernelGGL(k_adj_solve_l<Scope::Xcd>, dim3(grid * kXcds), dim3(64), 0, s, P, T, f_val, batch, z,
+                           w, ctl, spin_limit);
     else
-        hipLaunchKernelGGL(k_adj_solve_l, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, z, w, ctl,
-                           spin_limit);
+        hipLaunchKernelGGL(k_adj_solve_l<Scope::Device>, dim3(grid), dim3(64), 0, s, P, T, f_val, batch, z, w,
+                           ctl, spin_limit);
     return hipGetLastError();
 }
 

@@ -98,7 +98,6 @@ __device__ __forceinline__ void wait_pivot(const double* F, int32_t i, int32_t n
             }
         }
         ++polls;
-        __builtin_amdgcn_s_sleep(1);
     }
     wave_sync();
 }
@@ -447,7 +446,6 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
                     }
                 }
                 ++polls;
-                __builtin_amdgcn_s_sleep(1);
             }
             wave_sync();
             p0 = p1;

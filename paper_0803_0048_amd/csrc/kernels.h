@@ -197,12 +197,14 @@ hipError_t launch_transpose_fill(int32_t n, const int64_t* rpF, const int32_t* c
 hipError_t launch_sort_columns(int32_t n, const int64_t* tp, int32_t* ts, int32_t* tr,
                                hipStream_t s);
 
+// one_xcd (single instance): grid wavefronts per XCD launched, those of one
+// XCD working
 hipError_t launch_adj_solve_u(const PatDev& P, const AdjPat& T, const double* f_val,
                               int32_t batch, const double* ybar, double* z, Ctl* ctl,
-                              uint64_t spin_limit, int32_t grid, hipStream_t s);
+                              uint64_t spin_limit, int32_t grid, bool one_xcd, hipStream_t s);
 hipError_t launch_adj_solve_l(const PatDev& P, const AdjPat& T, const double* f_val,
                               int32_t batch, const double* z, double* w, Ctl* ctl,
-                              uint64_t spin_limit, int32_t grid, hipStream_t s);
+                              uint64_t spin_limit, int32_t grid, bool one_xcd, hipStream_t s);
 hipError_t launch_adj_fbar(const PatDev& P, int32_t batch, const double* x, const double* y,
                            const double* z, const double* w, double* fbar, hipStream_t s);
 hipError_t launch_adj_numeric(const PatDev& P, const AdjPat& T, const double* f_val,

@@ -415,6 +415,14 @@ struct SolveShape {
     bool one_xcd;
 };
 
+// placement of a wavefront-per-row sweep over n rows of `depth` dependency
+// levels whose row halves hold `half` entries in all (rule at kXcdMaxAvg)
+bool solve_on_xcd(tpilu_ctx ctx, int64_t n, int64_t half, int64_t depth) {
+    if (ctx->placement != 0) return ctx->placement == 2;
+    const int64_t width = n / std::max<int64_t>(depth, 1);
+    return (width < kNarrowWidth && half <= kXcdMaxAvg * n) || (width < 64 && half < 64 * n);
+}
+
 SolveShape solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool backward) {
     if (batch > 1) return {ctx->grid_override ? ctx->grid_override : kBatchSolveWaves, false};
     const int64_t n = std::max<int64_t>(pat->n, 1);
@@ -430,8 +438,7 @@ SolveShape solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool bac
     if (mode == 2) return {0, false};
     if (mode == 3) return {-(ctx->grid_override ? ctx->grid_override : kLaneWaves), false};
     const int64_t width = n / depth;
-    const bool few_short = (width < kNarrowWidth && half <= kXcdMaxAvg * n) || (width < 64 && half < 64 * n);
-    const bool one_xcd = ctx->placement == 2 || (ctx->placement == 0 && few_short);
+    const bool one_xcd = solve_on_xcd(ctx, n, half, depth);
     if (ctx->grid_override) return {ctx->grid_override, one_xcd};
     if (width < kNarrowWidth) return {kSolveWavesNarrow, one_xcd};
     if (width < 64 && half < 64 * n) return {kSolveWavesMid, one_xcd};
@@ -1499,11 +1506,22 @@ extern "C" TPILU_API tpilu_status tpilu_apply_adjoint(tpilu_ctx ctx, tpilu_patte
     double* z = pat->grow(pat->ws_z, sizeof(double) * (size_t)pat->n * batch);
     if (!z) return fail(ctx, TPILU_E_NOMEM, "adjoint workspace");
     AdjPat T{pat->tpL, pat->tsL, pat->trL, pat->tpU, pat->tsU, pat->trU, pat->permUT, pat->permLT};
-    const int grid = ctx->grid_override ? ctx->grid_override : batch > 1 ? kBatchSolveWaves : kAdjointWaves;
+    // transposed sweeps: the DAGs of U~ and L~ reversed, of the same depths
+    const int64_t n = pat->n, half_u = pat->nnz_f - (int64_t)pat->st.nnz_l - n, half_l = pat->st.nnz_l;
+    const bool xu = batch == 1 && solve_on_xcd(ctx, n, half_u, pat->depth_u);
+    const bool xl = batch == 1 && solve_on_xcd(ctx, n, half_l, pat->depth_l);
+    auto waves = [&](bool x, int64_t depth) {
+        if (ctx->grid_override) return (int)ctx->grid_override;
+        if (batch > 1) return (int)kBatchSolveWaves;
+        if (!x) return (int)kAdjointWaves;
+        return n / std::max<int64_t>(depth, 1) < kNarrowWidth ? (int)kSolveWavesNarrow : (int)kSolveWavesMid;
+    };
     HIPCHK(ctx, launch_fill_pending(z, pat->n * batch, pat->ctl, true, s));
-    HIPCHK(ctx, launch_adj_solve_u(pdev(ctx, pat), T, f_val, batch, ybar, z, pat->ctl, ctx->spin_limit, grid, s));
+    HIPCHK(ctx, launch_adj_solve_u(pdev(ctx, pat), T, f_val, batch, ybar, z, pat->ctl, ctx->spin_limit,
+                                   waves(xu, pat->depth_u), xu, s));
     HIPCHK(ctx, launch_fill_pending(bbar, pat->n * batch, pat->ctl, false, s));
-    HIPCHK(ctx, launch_adj_solve_l(pdev(ctx, pat), T, f_val, batch, z, bbar, pat->ctl, ctx->spin_limit, grid, s));
+    HIPCHK(ctx, launch_adj_solve_l(pdev(ctx, pat), T, f_val, batch, z, bbar, pat->ctl, ctx->spin_limit,
+                                   waves(xl, pat->depth_l), xl, s));
     HIPCHK(ctx, launch_adj_fbar(pdev(ctx, pat), batch, x, y, z, bbar, fbar, s));
     return TPILU_OK;
 }

@@ -464,11 +464,41 @@ def test_adjoint_small_bits():
         pat = T.symbolic(g(A.rowptr), g(A.col), k)
         f = T.numeric(pat, g(A.val))
         y, x = T.apply(pat, f, g(b), return_x=True)
-        bbar, fbar = T.apply_adjoint(pat, f, x, y, 2.0 * (y - g(t)))
-        assert_bits_equal(bbar, bbar_r, "bbar")
-        assert_bits_equal(fbar, Fbar_r, "Fbar")
+        ctx = T.context(0)
+        try:
+            for place in (ctx.PLACE_AUTO, ctx.PLACE_DEVICE, ctx.PLACE_XCD):
+                ctx.set_placement(place)
+                bbar, fbar = T.apply_adjoint(pat, f, x, y, 2.0 * (y - g(t)))
+                assert_bits_equal(bbar, bbar_r, f"bbar placement {place}")
+                assert_bits_equal(fbar, Fbar_r, f"Fbar placement {place}")
+        finally:
+            ctx.set_placement(0)
         abar, _ = T.numeric_adjoint(pat, f, fbar)
         assert_bits_equal(abar, abar_r, "abar")
+
+
+def test_adjoint_random_banded_bits():
+    """Transposed solves of one instance at full size (narrow graph: one XCD
+    by default) against the sequential adjoint, on both placements."""
+    c = I.random_banded_ilu2()
+    A, b = c["A"], c["b"]
+    t = np.random.default_rng(21).standard_normal(A.n)
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, c["k"])
+    vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
+    x_r, y_r = O.apply(A.n, rpF, ciF, vF, b)
+    bbar_r, Fbar_r = O.apply_adjoint(A.n, rpF, ciF, vF, x_r, y_r, 2.0 * (y_r - t))
+    pat = T.symbolic(g(A.rowptr), g(A.col), c["k"])
+    f = T.numeric(pat, g(A.val))
+    y, x = T.apply(pat, f, g(b), return_x=True)
+    ctx = T.context(0)
+    try:
+        for place in (ctx.PLACE_AUTO, ctx.PLACE_DEVICE, ctx.PLACE_XCD):
+            ctx.set_placement(place)
+            bbar, fbar = T.apply_adjoint(pat, f, x, y, 2.0 * (y - g(t)))
+            assert_bits_equal(bbar, bbar_r, f"bbar placement {place}")
+            assert_bits_equal(fbar, Fbar_r, f"Fbar placement {place}")
+    finally:
+        ctx.set_placement(0)
 
 
 def _arrow(n, seed):
