@@ -294,15 +294,20 @@ size_t flow_lds_bytes(int32_t max_row, int32_t cap) {
            ((size_t)max_row + 1) * 4;
 }
 
+typedef __attribute__((address_space(3))) uint64_t LdsU64;
+
 template <Scope S>
 __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __restrict__ a_val, double* F,
                                                      Ctl* ctl, uint64_t spin_limit, int64_t skip_row,
                                                      int32_t max_row, int32_t cap) {
     extern __shared__ uint64_t lds_u64[];
     double* Wv = reinterpret_cast<double*>(lds_u64);                  // [max_row] initial values
-    volatile uint64_t* Lb = lds_u64 + max_row;                       // [max_row] l of L entries
-    volatile uint64_t* Ud = lds_u64 + 2 * (size_t)max_row;           // [max_row] pivot diagonals
-    volatile uint64_t* Sv = lds_u64 + 3 * (size_t)max_row;           // [cap] staged f_ht
+    // arrays that lanes update for one another inside the loops below:
+    // volatile, so every read goes to LDS, and typed as LDS so that the reads
+    // are LDS instructions rather than generic (flat) loads
+    volatile LdsU64* Lb = (volatile LdsU64*)(lds_u64 + max_row);              // [max_row] l of L entries
+    volatile LdsU64* Ud = (volatile LdsU64*)(lds_u64 + 2 * (size_t)max_row);  // [max_row] pivot diagonals
+    volatile LdsU64* Sv = (volatile LdsU64*)(lds_u64 + 3 * (size_t)max_row);  // [cap] staged f_ht
     int32_t* Uq = reinterpret_cast<int32_t*>(lds_u64 + 3 * (size_t)max_row + cap);  // [max_row]
     int32_t* Ss = Uq + max_row;                                      // [cap] pivot entry of update
     int32_t* Sq = Ss + cap;                                          // [cap] F slot of f_ht
