@@ -76,9 +76,9 @@ constexpr int32_t kSolveWavesWide = 1024;
 // kFlowMinL entries, an entry receives fewer than kFlowMaxChain updates on
 // average and a dependency level holds fewer than kFlowMaxWidth rows.  On
 // narrow graphs the dataflow kernel's short hand-off wins (random banded
-// n=160,000: ILU(1) 1.4 vs 4.8 ms, ILU(2) 8.5 vs 21 ms); on wide ones the
+// n=160,000: ILU(1) 0.72 vs 5.2 ms, ILU(2) 6.0 vs 22.9 ms); on wide ones the
 // pivot-serial kernel's cheaper rows do (27-point 30^3 ILU(1), 71 rows per
-// level: 1.4 vs 2.1 ms; 7-point 64^3 ILU(2): 3.0 vs 4.3 ms).
+// level: 1.28 vs 1.47 ms; 7-point 64^3 ILU(2): 2.19 vs 2.72 ms).
 constexpr int64_t kFlowMinL = 4;
 constexpr int64_t kFlowMaxChain = 12;
 constexpr int64_t kFlowMaxWidth = 64;
@@ -158,8 +158,8 @@ struct DeviceGuard {
 // serialised), which on wide levels caps how fast rows can be handed out;
 // grouping divides that traffic but runs a group's rows back to back.  The
 // numeric kernels overlap a row's work with its wait on earlier levels, so
-// there a group costs a whole row time per level (c2: 8.5 -> 147 ms at 2
-// rows): always 1.  Solves and inverses gain on wide levels (7-point 64^3,
+// there a group costs a whole row time per level (random banded n=160,000
+// ILU(2): 8.5 -> 147 ms at 2 rows): always 1.  Solves and inverses gain on wide levels (7-point 64^3,
 // ILU(1), 692 rows per level: wavefront-per-row forward 5.5 -> 3.3 ms at 3
 // rows, inverse 6.6 -> 4.0 ms at 2 rows) and lose on narrow ones.
 enum class RowKernel { Numeric, Solve, Inverse };
@@ -366,17 +366,16 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
     // long update chains per entry (a lane walks its entry's chain alone) are
     // faster pivot by pivot with the lanes over that pivot's updates.
     // Measured: random banded n=160,000 ILU(2) (1.7 updates per entry)
-    // 8.3 ms dataflow vs 25 ms pivot-serial; 27-point 50^3 ILU(2) and ILU(3)
-    // (16.5 and 26 per entry) 21 and 41 ms dataflow vs 12 and 21 ms.
+    // 6.0 ms dataflow vs 22.9 ms pivot-serial; 27-point 50^3 ILU(2) and ILU(3)
+    // (16.5 and 26 per entry) 20.8 and 38.7 ms dataflow vs 4.7 and 8.6 ms.
     const bool auto_flow = (int64_t)pat->st.nnz_l >= kFlowMinL * pat->n &&
                            pat->n_updates < kFlowMaxChain * pat->nnz_f &&
                            pat->n < kFlowMaxWidth * std::max<int64_t>(pat->depth_l, 1);
     const bool flow = batch == 1 && pat->flow && (ctx->numeric == 1 || (ctx->numeric == 0 && auto_flow));
     HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, pat->ctl, true, ctx->stream));
     // one XCD only when asked for: the factorization keeps many rows in flight
-    // and needs the whole device (random banded n=160,000 ILU(2): 8.5 ms on
-    // the device, 26 ms on one XCD); there the grid is that XCD's resident
-    // maximum
+    // and needs the whole device (random banded n=160,000 ILU(2) ran 3x
+    // slower on one XCD); there the grid is that XCD's resident maximum
     const bool one_xcd = batch == 1 && ctx->placement == 2;
     const int grid = ctx->grid_override
                          ? ctx->grid_override
