@@ -54,14 +54,25 @@ int orc_validate(int64_t n, const int64_t *rp, const int32_t *ci)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Phase I: symbolic factorization, Algorithm 1 (Sec. 2.2).                  */
+/* Phase I: the level-k pattern of F (Def. 2.3; Sec. 2.2 computes it as     */
+/* Phase I of ILU(k)).                                                       */
 /*                                                                           */
-/* For each row j in ascending order: admit A's entries with level 0, then   */
-/* repeatedly take the smallest not yet processed column i < j of row j      */
-/* (entries inserted while the row is being merged included), and for each   */
-/* entry t > i of the already final row i compute the weight                 */
-/* level(j,i) + level(i,t) + 1; an existing entry keeps the minimum, a new   */
-/* one is inserted when its weight does not exceed k.                        */
+/* Def. 2.3 gives every position (j,t) a level: 0 where A stores an entry    */
+/* (every stored entry, explicit zeros included), otherwise the minimum over */
+/* h < min(j,t) of level(j,h) + level(h,t) + 1.  The pattern is the set of   */
+/* positions whose level is at most k.                                       */
+/*                                                                           */
+/* This routine evaluates that recurrence directly.  Rows go in ascending    */
+/* order: the terms of row j only use positions (j,h) with h < j and rows h  */
+/* < j, which are complete by then.  Inside row j the positions are found in */
+/* rounds of increasing level value L = 0, 1, ..., k: round 0 takes A's      */
+/* row; round L takes every position not found yet for which some h of row j */
+/* with h < j and level a < L has (h,t), t > h, at level L-1-a.  A position  */
+/* found in round L has no term below L (a smaller term would have been seen */
+/* in an earlier round, whose parts were all known by then), so L is its     */
+/* level.  Pruning: a term is larger than each of its two parts, so a        */
+/* position of level <= k only ever takes its minimum over parts of level    */
+/* <= k; rows h are therefore kept only up to level k.                       */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int64_t n, nnz;
@@ -80,44 +91,40 @@ void orc_pattern_free(orc_pattern *p)
     p->lev = NULL;
 }
 
-/* binary min-heap of column indices */
-static void heap_push(int32_t *h, int64_t *sz, int32_t v)
-{
-    int64_t i = (*sz)++;
-    h[i] = v;
-    while (i > 0) {
-        int64_t par = (i - 1) / 2;
-        if (h[par] <= h[i]) break;
-        int32_t t = h[par];
-        h[par] = h[i];
-        h[i] = t;
-        i = par;
-    }
-}
-
-static int32_t heap_pop(int32_t *h, int64_t *sz)
-{
-    int32_t top = h[0];
-    int64_t s = --(*sz);
-    h[0] = h[s];
-    int64_t i = 0;
-    for (;;) {
-        int64_t l = 2 * i + 1, r = l + 1, m = i;
-        if (l < s && h[l] < h[m]) m = l;
-        if (r < s && h[r] < h[m]) m = r;
-        if (m == i) break;
-        int32_t t = h[m];
-        h[m] = h[i];
-        h[i] = t;
-        i = m;
-    }
-    return top;
-}
-
 static int cmp_i32(const void *a, const void *b)
 {
     int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
     return (x > y) - (x < y);
+}
+
+/* (level, column) pairs of a row's strict upper part, ordered by level and
+ * then column, so that the positions of one level are one contiguous run */
+typedef struct {
+    int32_t lev, col;
+} lev_col;
+
+static int cmp_lev_col(const void *a, const void *b)
+{
+    const lev_col *x = (const lev_col *)a, *y = (const lev_col *)b;
+    if (x->lev != y->lev) return (x->lev > y->lev) - (x->lev < y->lev);
+    return (x->col > y->col) - (x->col < y->col);
+}
+
+/* grow two parallel int32 arrays of capacity *cap to hold `need` entries;
+ * returns 0 when out of memory (both arrays stay valid and owned) */
+static int grow_pair(int32_t **a, int32_t **b, int64_t *cap, int64_t need)
+{
+    if (need <= *cap) return 1;
+    int64_t c = *cap;
+    while (c < need) c *= 2;
+    int32_t *a2 = (int32_t *)realloc(*a, (size_t)c * sizeof(int32_t));
+    if (!a2) return 0;
+    *a = a2;
+    int32_t *b2 = (int32_t *)realloc(*b, (size_t)c * sizeof(int32_t));
+    if (!b2) return 0;
+    *b = b2;
+    *cap = c;
+    return 1;
 }
 
 int orc_symbolic(int64_t n, const int64_t *rp, const int32_t *ci, int32_t k, orc_pattern *out)
@@ -127,72 +134,108 @@ int orc_symbolic(int64_t n, const int64_t *rp, const int32_t *ci, int32_t k, orc
     int st = orc_validate(n, rp, ci);
     if (st) return st;
 
-    int64_t cap = rp[n] > 16 ? rp[n] : 16;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    int64_t cap = rp[n] > 16 ? rp[n] : 16, ucap = cap;
     int64_t *rowptr = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
     int32_t *col = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
     int32_t *lev = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
-    int32_t *lev_of = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t)); /* -1: absent */
-    int32_t *list = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-    int32_t *heap = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-    if (!rowptr || !col || !lev || !lev_of || !list || !heap) {
-        free(rowptr); free(col); free(lev); free(lev_of); free(list); free(heap);
-        return ORC_ENOMEM;
-    }
-    for (int64_t t = 0; t < n; ++t) lev_of[t] = -1;
+    /* strict upper part of every finished row, by level then column */
+    int64_t *uptr = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int32_t *ucol = (int32_t *)malloc((size_t)ucap * sizeof(int32_t));
+    int32_t *ulev = (int32_t *)malloc((size_t)ucap * sizeof(int32_t));
+    int32_t *lev_of = (int32_t *)malloc(nn * sizeof(int32_t)); /* level of (j,t) in row j, -1 if absent */
+    int32_t *found = (int32_t *)malloc(nn * sizeof(int32_t));  /* columns of row j, in order found */
+    int32_t *lower = (int32_t *)malloc(nn * sizeof(int32_t));  /* its columns h < j, in order found */
+    lev_col *upper = (lev_col *)malloc(nn * sizeof(lev_col));
+    int ok = rowptr && col && lev && uptr && ucol && ulev && lev_of && found && lower && upper;
+    if (ok)
+        for (int64_t t = 0; t < n; ++t) lev_of[t] = -1;
 
-    int64_t nnz = 0;
-    rowptr[0] = 0;
-    for (int64_t j = 0; j < n; ++j) {
-        int64_t len = 0, hs = 0;
-        /* initialization: admit the entries of A with level 0 */
+    int64_t nnz = 0, unnz = 0;
+    int64_t max_up = -1; /* highest level in the strict upper part of any finished row */
+    if (ok) {
+        rowptr[0] = 0;
+        uptr[0] = 0;
+    }
+    for (int64_t j = 0; ok && j < n; ++j) {
+        int64_t nf = 0, nl = 0, max_low = -1;
+        /* level 0: the entries A stores in row j */
         for (int64_t p = rp[j]; p < rp[j + 1]; ++p) {
             int32_t t = ci[p];
             lev_of[t] = 0;
-            list[len++] = t;
-            if (t < j) heap_push(heap, &hs, t);
+            found[nf++] = t;
+            if (t < j) {
+                lower[nl++] = t;
+                max_low = 0;
+            }
         }
-        /* row-merge update pass */
-        while (hs > 0) {
-            int32_t i = heap_pop(heap, &hs);
-            int64_t lji = lev_of[i];
-            for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-                int32_t t = col[q];
-                if (t <= i) continue;
-                int64_t w = lji + (int64_t)lev[q] + 1;
-                if (lev_of[t] >= 0) {
-                    if (w < lev_of[t]) lev_of[t] = (int32_t)w;
-                } else if (w <= k) {
-                    lev_of[t] = (int32_t)w;
-                    list[len++] = t;
-                    if (t < j) heap_push(heap, &hs, t);
+        /* levels 1, 2, ...: a round can only produce levels up to
+         * max_low + max_up + 1, and never more than k */
+        for (int64_t L = 1; L <= (int64_t)k && L <= max_low + max_up + 1; ++L) {
+            const int64_t nl_start = nl; /* positions found in this round have level L */
+            for (int64_t a_i = 0; a_i < nl_start; ++a_i) {
+                const int32_t h = lower[a_i];
+                const int64_t a = lev_of[h];
+                if (a > L - 1) continue;
+                const int64_t b = L - 1 - a;
+                /* the run of row h's strict upper part at level b */
+                int64_t lo = uptr[h], hi = uptr[h + 1];
+                while (lo < hi) {
+                    int64_t mid = lo + (hi - lo) / 2;
+                    if (ulev[mid] < b) lo = mid + 1;
+                    else hi = mid;
+                }
+                for (int64_t q = lo; q < uptr[h + 1] && ulev[q] == b; ++q) {
+                    const int32_t t = ucol[q];
+                    if (lev_of[t] >= 0) continue; /* already at a level <= L */
+                    lev_of[t] = (int32_t)L;
+                    found[nf++] = t;
+                    if (t < j) {
+                        lower[nl++] = t;
+                        max_low = L;
+                    }
                 }
             }
         }
-        qsort(list, (size_t)len, sizeof(int32_t), cmp_i32);
-        if (nnz + len > cap) {
-            while (nnz + len > cap) cap *= 2;
-            int32_t *c2 = (int32_t *)realloc(col, (size_t)cap * sizeof(int32_t));
-            if (!c2) { free(col); col = NULL; }
-            else col = c2;
-            int32_t *l2 = col ? (int32_t *)realloc(lev, (size_t)cap * sizeof(int32_t)) : NULL;
-            if (!l2) { free(lev); lev = NULL; }
-            else lev = l2;
-            if (!col || !lev) {
-                free(rowptr); free(col); free(lev); free(lev_of); free(list); free(heap);
-                return ORC_ENOMEM;
+        qsort(found, (size_t)nf, sizeof(int32_t), cmp_i32);
+        int64_t nu = 0;
+        for (int64_t a = 0; a < nf; ++a)
+            if (found[a] > j) {
+                upper[nu].lev = lev_of[found[a]];
+                upper[nu].col = found[a];
+                ++nu;
             }
+        qsort(upper, (size_t)nu, sizeof(lev_col), cmp_lev_col);
+        if (!grow_pair(&col, &lev, &cap, nnz + nf) || !grow_pair(&ucol, &ulev, &ucap, unnz + nu)) ok = 0;
+        if (!ok) break;
+        for (int64_t a = 0; a < nf; ++a) {
+            col[nnz + a] = found[a];
+            lev[nnz + a] = lev_of[found[a]];
+            lev_of[found[a]] = -1;
         }
-        for (int64_t a = 0; a < len; ++a) {
-            col[nnz + a] = list[a];
-            lev[nnz + a] = lev_of[list[a]];
-            lev_of[list[a]] = -1;
+        for (int64_t a = 0; a < nu; ++a) {
+            ucol[unnz + a] = upper[a].col;
+            ulev[unnz + a] = upper[a].lev;
+            if (upper[a].lev > max_up) max_up = upper[a].lev;
         }
-        nnz += len;
+        nnz += nf;
+        unnz += nu;
         rowptr[j + 1] = nnz;
+        uptr[j + 1] = unnz;
     }
+    free(uptr);
+    free(ucol);
+    free(ulev);
     free(lev_of);
-    free(list);
-    free(heap);
+    free(found);
+    free(lower);
+    free(upper);
+    if (!ok) {
+        free(rowptr);
+        free(col);
+        free(lev);
+        return ORC_ENOMEM;
+    }
     out->n = n;
     out->nnz = nnz;
     out->rowptr = rowptr;
