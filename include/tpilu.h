@@ -259,8 +259,11 @@ TPILU_API tpilu_status tpilu_pattern_check(tpilu_ctx ctx, tpilu_pattern pat, int
  *   forward  (Eq. 3b): x_i = b_i - sum_{h<i} f_ih x_h, subtractions in
  *                      ascending h;
  *   backward:          y_i = (x_i - sum_{j>i} f_ij y_j) / f_ii, subtractions
- *                      from right to left (j descending, the order Sec. 3.5
- *                      gives for the U~ stage), then the division.
+ *                      from right to left (j descending), then the
+ *                      division.  The paper leaves this order open; right
+ *                      to left is fixed here because the value that arrives
+ *                      last (that of the nearest row) is then the last term
+ *                      of the chain.
  * f_val, b, y: [n * batch] / [nnz_f * batch] device arrays; x_out (nullable,
  * n * batch) receives the intermediate x.  b and y may not alias.
  * ------------------------------------------------------------------------- */
@@ -353,6 +356,38 @@ TPILU_API tpilu_status tpilu_spmv(tpilu_ctx ctx, tpilu_pattern pat, const double
 TPILU_API tpilu_status tpilu_dot(tpilu_ctx ctx, int64_t n, const double *x, const double *y,
                                  double *result);
 
+/* Measurements of the dependency critical path (no numeric result).
+ *
+ * tpilu_numeric_critical_path runs the dataflow elimination kernel in a mode
+ * that carries, instead of values, the number of row-to-row hand-offs on the
+ * longest chain of dependencies ending in each entry of F (an update of
+ * f_jt needs f_ht, and l_jh needs f_hh, from row h: one hand-off each; work
+ * inside a row costs none), and writes the largest count into *hops (host).
+ * This many hand-offs must happen one after another in any parallel
+ * factorization that keeps the bits of Eq. 2.  TPILU_E_INVAL when the
+ * pattern's rows do not fit the dataflow kernel.  Waits for the stream.
+ *
+ * tpilu_handoff_probe has two wavefronts pass a value back and forth
+ * `rounds` times (1 .. 2^24) through device memory with the publish and poll
+ * operations of the persistent kernels, on one XCD (same_xcd != 0: plain
+ * stores kept in that XCD's L2) or on two different XCDs (stores written
+ * through), and writes the mean round trip in nanoseconds into
+ * *ns_round_trip (host); one hand-off is half of it.  Waits for the stream;
+ * TPILU_E_TIMEOUT if no partner wavefront appeared within the watchdog. */
+TPILU_API tpilu_status tpilu_numeric_critical_path(tpilu_ctx ctx, tpilu_pattern pat, int32_t *hops);
+TPILU_API tpilu_status tpilu_handoff_probe(tpilu_ctx ctx, int32_t same_xcd, int32_t rounds,
+                                           double *ns_round_trip);
+
+/* Givens rotations of `count` pairs (a_i, b_i), with the device code of the
+ * rotation step of tpilu_gmres: rho_i = sqrt(a_i * a_i + b_i * b_i) (each
+ * product and the sum rounded on their own, no hypot), c_i = a_i / rho_i,
+ * s_i = b_i / rho_i, every operation correctly rounded binary64.  All five
+ * arrays device, [count], no aliasing of inputs with outputs.  Exposed so
+ * that the square root and the divisions of the GMRES step can be checked
+ * bit for bit on many operands. */
+TPILU_API tpilu_status tpilu_givens(tpilu_ctx ctx, int64_t count, const double *a, const double *b,
+                                    double *rho, double *c, double *s);
+
 /* ---------------------------------------------------------------------------
  * Reverse mode of y = U~^-1 L~^-1 b (given x = L~^-1 b and y from the forward
  * pass, and ybar = dLoss/dy):
@@ -385,15 +420,26 @@ TPILU_API tpilu_status tpilu_numeric_adjoint(tpilu_ctx ctx, tpilu_pattern pat, c
  * stream, tpilu_numeric(a_val -> f_val) followed by tpilu_apply(f_val, b ->
  * y) for all `batch` instances, and instantiates the graph.  The device
  * arrays passed here are baked into the graph: each launch recomputes f_val
- * and y from the CURRENT contents of a_val and b.  Launch with
- * tpilu_batched_graph_launch on any stream of the ctx's device; status
- * (zero pivot, watchdog) is read with tpilu_pattern_check.
+ * and y from the CURRENT contents of a_val and b.  The graph owns its
+ * intermediate vector (n * batch doubles) and its control block, allocated
+ * here and freed by tpilu_batched_graph_destroy, so later calls on the same
+ * pattern never touch them; it reads the pattern's arrays, so the pattern
+ * must outlive the graph.  Launch with tpilu_batched_graph_launch on any
+ * stream of the ctx's device; two launches of one graph must not overlap
+ * (they share its vector and control block).  b and y may not alias.
+ *
+ * tpilu_batched_graph_check waits for `hip_stream` (a hipStream_t as void*,
+ * NULL = the null stream) and reports the status of the graph's last launch
+ * on it: TPILU_E_ZEROPIVOT with *bad_row (host, nullable) = the smallest row
+ * with a +-0 final pivot over all instances (else -1), TPILU_E_TIMEOUT after a
+ * watchdog timeout, TPILU_E_INVAL for the reserved NaN in an input.
  * ------------------------------------------------------------------------- */
 TPILU_API tpilu_status tpilu_batched_graph_create(tpilu_ctx ctx, tpilu_pattern pat,
                                                   const double *a_val, int32_t batch,
                                                   double *f_val, const double *b, double *y,
                                                   tpilu_graph *out);
 TPILU_API tpilu_status tpilu_batched_graph_launch(tpilu_graph g, void *hip_stream);
+TPILU_API tpilu_status tpilu_batched_graph_check(tpilu_graph g, void *hip_stream, int64_t *bad_row);
 TPILU_API void tpilu_batched_graph_destroy(tpilu_graph g);
 
 #ifdef __cplusplus

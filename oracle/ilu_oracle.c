@@ -351,10 +351,13 @@ int orc_numeric_rows(int64_t n, const int64_t *rpA, const int32_t *ciA, const do
 
 /* ------------------------------------------------------------------------ */
 /* Applying M^-1 = U~^-1 L~^-1 (Eq. 1): forward substitution (Eq. 3b) with   */
-/* a running subtraction in ascending column order; then the U~ stage from   */
-/* the last row to the first and from right to left within a row (the order */
-/* Sec. 3.5 gives for the U~ stage): running subtraction in descending      */
-/* column order, then the division by the pivot.                            */
+/* a running subtraction in ascending column order; then the backward        */
+/* substitution from the last row to the first, each row a running           */
+/* subtraction in descending column order (right to left) followed by the   */
+/* division by the pivot.  The paper does not fix the order inside the      */
+/* backward substitution; right to left is the reading taken (the nearest   */
+/* row's value, the last one to be known in a parallel sweep, is then the   */
+/* last term).                                                              */
 /* ------------------------------------------------------------------------ */
 int orc_apply(int64_t n, const int64_t *rpF, const int32_t *ciF, const double *vF,
               const double *p, double *x, double *y)

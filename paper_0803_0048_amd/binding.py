@@ -24,7 +24,8 @@ EXPORTED = [
     "tpilu_pattern_export", "tpilu_pattern_destroy", "tpilu_numeric", "tpilu_pattern_check",
     "tpilu_apply", "tpilu_gmres", "tpilu_spmv", "tpilu_dot", "tpilu_apply_adjoint",
     "tpilu_numeric_adjoint", "tpilu_batched_graph_create", "tpilu_batched_graph_launch",
-    "tpilu_batched_graph_destroy",
+    "tpilu_batched_graph_check", "tpilu_batched_graph_destroy", "tpilu_givens",
+    "tpilu_numeric_critical_path", "tpilu_handoff_probe",
 ]
 
 
@@ -92,10 +93,14 @@ def load_library():
             "tpilu_apply_inverse": ([P, P, P, i32, P, P, P], st),
             "tpilu_spmv": ([P, P, P, P, P], st),
             "tpilu_dot": ([P, i64, P, P, C.POINTER(dbl)], st),
+            "tpilu_givens": ([P, i64, P, P, P, P, P], st),
+            "tpilu_numeric_critical_path": ([P, P, C.POINTER(i32)], st),
+            "tpilu_handoff_probe": ([P, i32, i32, C.POINTER(dbl)], st),
             "tpilu_apply_adjoint": ([P, P, P, i32, P, P, P, P, P], st),
             "tpilu_numeric_adjoint": ([P, P, P, i32, P, P], st),
             "tpilu_batched_graph_create": ([P, P, P, i32, P, P, P, C.POINTER(P)], st),
             "tpilu_batched_graph_launch": ([P, P], st),
+            "tpilu_batched_graph_check": ([P, P, C.POINTER(i64)], st),
             "tpilu_batched_graph_destroy": ([P], None),
         }
         for name, (args, res) in sig.items():
@@ -221,6 +226,16 @@ def _need(t, dtype, name, device):
     return t
 
 
+def _need_size(t, dtype, name, device, lead, batch=1):
+    """_need plus the shape the kernels will index: [lead] for one instance,
+    [lead, batch] for a batch (entry-major, instance-minor)."""
+    _need(t, dtype, name, device)
+    want = (lead,) if batch == 1 and t.dim() == 1 else (lead, batch)
+    if tuple(t.shape) != want:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {want}")
+    return t
+
+
 # ----------------------------------------------------------------------------------
 # pattern (Phase I)
 # ----------------------------------------------------------------------------------
@@ -292,7 +307,12 @@ def numeric(pat: Pattern, a_val: torch.Tensor, out: torch.Tensor | None = None, 
     _need(a_val, torch.float64, "a_val", pat.device)
     B = _batch_of(a_val, pat.nnz_a, "a_val")
     shape = (pat.nnz_f,) if a_val.dim() == 1 else (pat.nnz_f, B)
-    f = torch.empty(shape, dtype=torch.float64, device=pat.device) if out is None else _need(out, torch.float64, "out", pat.device)
+    if out is None:
+        f = torch.empty(shape, dtype=torch.float64, device=pat.device)
+    else:
+        f = _need(out, torch.float64, "out", pat.device)
+        if tuple(f.shape) != shape:
+            raise ValueError(f"out has shape {tuple(f.shape)}, expected {shape}")
     ctx = context(pat.device)
     bad = C.c_int64(-1)
     st = load_library().tpilu_numeric(ctx.h, pat.h, _ptr(a_val), B, _ptr(f), C.byref(bad) if check else None)
@@ -315,9 +335,11 @@ def apply(pat: Pattern, f_val: torch.Tensor, b: torch.Tensor, out: torch.Tensor 
     _need(f_val, torch.float64, "f_val", pat.device)
     _need(b, torch.float64, "b", pat.device)
     B = _batch_of(b, pat.n, "b")
-    if _batch_of(f_val, pat.nnz_f, "f_val") != B:
+    if _batch_of(f_val, pat.nnz_f, "f_val") != B or f_val.dim() != b.dim():
         raise ValueError("f_val and b batch sizes differ")
-    y = torch.empty_like(b) if out is None else _need(out, torch.float64, "out", pat.device)
+    y = torch.empty_like(b) if out is None else _need_size(out, torch.float64, "out", pat.device, pat.n, B)
+    if out is not None and (out.dim() != b.dim() or out.data_ptr() == b.data_ptr()):
+        raise ValueError("out must be shaped like b and must not be b")
     x = torch.empty_like(b) if return_x else None
     ctx = context(pat.device)
     st = load_library().tpilu_apply(ctx.h, pat.h, _ptr(f_val), B, _ptr(b), _ptr(y), _ptr(x))
@@ -330,7 +352,9 @@ def inverse(pat: Pattern, f_val: torch.Tensor, out: torch.Tensor | None = None) 
     _need(f_val, torch.float64, "f_val", pat.device)
     if _batch_of(f_val, pat.nnz_f, "f_val") != 1:
         raise ValueError("incomplete inverses: one instance only")
-    g = torch.empty_like(f_val) if out is None else _need(out, torch.float64, "out", pat.device)
+    g = torch.empty_like(f_val) if out is None else _need_size(out, torch.float64, "out", pat.device, pat.nnz_f)
+    if g.data_ptr() == f_val.data_ptr():
+        raise ValueError("out must not be f_val")
     ctx = context(pat.device)
     ctx.check(load_library().tpilu_inverse(ctx.h, pat.h, _ptr(f_val), 1, _ptr(g)), "inverse")
     return g
@@ -341,9 +365,11 @@ def apply_inverse(pat: Pattern, g_val: torch.Tensor, b: torch.Tensor, out: torch
     """y = U~~^-1 L~~^-1 b with the incomplete inverses (two products, Eq. 3a)."""
     _need(g_val, torch.float64, "g_val", pat.device)
     _need(b, torch.float64, "b", pat.device)
-    if _batch_of(b, pat.n, "b") != 1:
+    if _batch_of(b, pat.n, "b") != 1 or _batch_of(g_val, pat.nnz_f, "g_val") != 1:
         raise ValueError("incomplete inverses: one instance only")
-    y = torch.empty_like(b) if out is None else _need(out, torch.float64, "out", pat.device)
+    y = torch.empty_like(b) if out is None else _need_size(out, torch.float64, "out", pat.device, pat.n)
+    if y.data_ptr() == b.data_ptr():
+        raise ValueError("out must not be b")
     x = torch.empty_like(b) if return_x else None
     ctx = context(pat.device)
     st = load_library().tpilu_apply_inverse(ctx.h, pat.h, _ptr(g_val), 1, _ptr(b), _ptr(y), _ptr(x))
@@ -352,8 +378,8 @@ def apply_inverse(pat: Pattern, g_val: torch.Tensor, b: torch.Tensor, out: torch
 
 
 def spmv(pat: Pattern, a_val: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
-    _need(a_val, torch.float64, "a_val", pat.device)
-    _need(x, torch.float64, "x", pat.device)
+    _need_size(a_val, torch.float64, "a_val", pat.device, pat.nnz_a)
+    _need_size(x, torch.float64, "x", pat.device, pat.n)
     y = torch.empty(pat.n, dtype=torch.float64, device=pat.device)
     ctx = context(pat.device)
     ctx.check(load_library().tpilu_spmv(ctx.h, pat.h, _ptr(a_val), _ptr(x), _ptr(y)), "spmv")
@@ -364,10 +390,45 @@ def dot(x: torch.Tensor, y: torch.Tensor) -> float:
     """Fixed-shape inner product (16384 strided partial sums, then a pairwise tree)."""
     _need(x, torch.float64, "x", None)
     _need(y, torch.float64, "y", x.device)
+    if y.numel() != x.numel():
+        raise ValueError(f"x has {x.numel()} entries, y {y.numel()}")
     ctx = context(x.device)
     r = C.c_double(0.0)
     ctx.check(load_library().tpilu_dot(ctx.h, x.numel(), _ptr(x), _ptr(y), C.byref(r)), "dot")
     return r.value
+
+
+def givens(a: torch.Tensor, b: torch.Tensor):
+    """(rho, c, s) of the rotation of every pair (a_i, b_i), computed by the
+    device code of the GMRES rotation step."""
+    _need(a, torch.float64, "a", None)
+    _need(b, torch.float64, "b", a.device)
+    if a.shape != b.shape:
+        raise ValueError("a and b differ in shape")
+    rho, c, s = torch.empty_like(a), torch.empty_like(a), torch.empty_like(a)
+    ctx = context(a.device)
+    ctx.check(load_library().tpilu_givens(ctx.h, a.numel(), _ptr(a), _ptr(b), _ptr(rho), _ptr(c), _ptr(s)),
+              "givens")
+    return rho, c, s
+
+
+def numeric_critical_path(pat: Pattern) -> int:
+    """Row-to-row hand-offs on the longest dependency chain of the numeric
+    factorization (the dataflow kernel run in hop-count mode)."""
+    ctx = context(pat.device)
+    h = C.c_int32(0)
+    ctx.check(load_library().tpilu_numeric_critical_path(ctx.h, pat.h, C.byref(h)), "numeric_critical_path")
+    return h.value
+
+
+def handoff_probe(same_xcd: bool, rounds: int = 2000, device=None) -> float:
+    """Mean round trip (ns) of a value passed between two wavefronts through
+    device memory, on one XCD or across two."""
+    ctx = context(device)
+    ns = C.c_double(0.0)
+    ctx.check(load_library().tpilu_handoff_probe(ctx.h, 1 if same_xcd else 0, rounds, C.byref(ns)),
+              "handoff_probe")
+    return ns.value
 
 
 def gmres(pat: Pattern, a_val: torch.Tensor, f_val: torch.Tensor, b: torch.Tensor, x0: torch.Tensor | None = None,
@@ -376,10 +437,10 @@ def gmres(pat: Pattern, a_val: torch.Tensor, f_val: torch.Tensor, b: torch.Tenso
     """Right-preconditioned restarted GMRES.  Returns (x, info).  inverse=True:
     f_val holds the incomplete inverses (from inverse()) and M^-1 is applied by
     two products."""
-    _need(a_val, torch.float64, "a_val", pat.device)
-    _need(f_val, torch.float64, "f_val", pat.device)
-    _need(b, torch.float64, "b", pat.device)
-    x = torch.zeros_like(b) if x0 is None else _need(x0, torch.float64, "x0", pat.device).clone()
+    _need_size(a_val, torch.float64, "a_val", pat.device, pat.nnz_a)
+    _need_size(f_val, torch.float64, "f_val", pat.device, pat.nnz_f)
+    _need_size(b, torch.float64, "b", pat.device, pat.n)
+    x = torch.zeros_like(b) if x0 is None else _need_size(x0, torch.float64, "x0", pat.device, pat.n).clone()
     if maxit is None:
         maxit = min(10 * pat.n, 100000)
     hist = (C.c_double * max(maxit, 1))()
@@ -401,10 +462,10 @@ def bicgstab(pat: Pattern, a_val: torch.Tensor, m_val: torch.Tensor, b: torch.Te
     """Right-preconditioned BiCGSTAB (Sec. 4's solver).  m_val: the factor, or
     the incomplete inverses with inverse=True.  maxit / iters count half steps.
     Returns (x, info)."""
-    _need(a_val, torch.float64, "a_val", pat.device)
-    _need(m_val, torch.float64, "m_val", pat.device)
-    _need(b, torch.float64, "b", pat.device)
-    x = torch.zeros_like(b) if x0 is None else _need(x0, torch.float64, "x0", pat.device).clone()
+    _need_size(a_val, torch.float64, "a_val", pat.device, pat.nnz_a)
+    _need_size(m_val, torch.float64, "m_val", pat.device, pat.nnz_f)
+    _need_size(b, torch.float64, "b", pat.device, pat.n)
+    x = torch.zeros_like(b) if x0 is None else _need_size(x0, torch.float64, "x0", pat.device, pat.n).clone()
     if maxit is None:
         maxit = min(10 * pat.n, 100000)
     hist = (C.c_double * max(maxit, 1))()
@@ -424,6 +485,10 @@ def apply_adjoint(pat: Pattern, f_val, x, y, ybar):
     for t, nm in ((f_val, "f_val"), (x, "x"), (y, "y"), (ybar, "ybar")):
         _need(t, torch.float64, nm, pat.device)
     B = _batch_of(ybar, pat.n, "ybar")
+    _need_size(f_val, torch.float64, "f_val", pat.device, pat.nnz_f, B)
+    for t, nm in ((x, "x"), (y, "y")):
+        if tuple(t.shape) != tuple(ybar.shape):
+            raise ValueError(f"{nm} has shape {tuple(t.shape)}, expected {tuple(ybar.shape)}")
     bbar = torch.empty_like(ybar)
     fbar = torch.empty_like(f_val)
     ctx = context(pat.device)
@@ -437,6 +502,8 @@ def numeric_adjoint(pat: Pattern, f_val, fbar):
     """Reverse sweep of the elimination.  Returns (abar, fbar after the sweep)."""
     _need(f_val, torch.float64, "f_val", pat.device)
     B = _batch_of(f_val, pat.nnz_f, "f_val")
+    if tuple(fbar.shape) != tuple(f_val.shape):
+        raise ValueError(f"fbar has shape {tuple(fbar.shape)}, expected {tuple(f_val.shape)}")
     fb = _need(fbar, torch.float64, "fbar", pat.device).clone()
     shape = (pat.nnz_a,) if f_val.dim() == 1 else (pat.nnz_a, B)
     abar = torch.empty(shape, dtype=torch.float64, device=pat.device)
@@ -459,10 +526,16 @@ class BatchedGraph:
         B = _batch_of(a_val, pat.nnz_a, "a_val")
         if _batch_of(b, pat.n, "b") != B:
             raise ValueError("a_val and b batch sizes differ")
+        if a_val.dim() != b.dim():
+            raise ValueError("a_val and b must both be 1-D or both 2-D")
         self.pat, self.a_val, self.b = pat, a_val, b
         self.f_val = torch.empty((pat.nnz_f, B) if a_val.dim() == 2 else (pat.nnz_f,), dtype=torch.float64,
                                  device=pat.device) if f_val is None else f_val
         self.y = torch.empty_like(b) if y is None else y
+        _need_size(self.f_val, torch.float64, "f_val", pat.device, pat.nnz_f, B)
+        _need_size(self.y, torch.float64, "y", pat.device, pat.n, B)
+        if self.f_val.dim() != a_val.dim() or self.y.dim() != b.dim() or self.y.data_ptr() == b.data_ptr():
+            raise ValueError("f_val and y must be shaped like the factor and b, and y must not be b")
         ctx = context(pat.device)
         h = C.c_void_p()
         st = load_library().tpilu_batched_graph_create(ctx.h, pat.h, _ptr(a_val), B, _ptr(self.f_val), _ptr(b),
@@ -475,6 +548,18 @@ class BatchedGraph:
         st = load_library().tpilu_batched_graph_launch(self.h, C.c_void_p(s))
         if st != OK:
             raise TpiluError(st, "batched_graph_launch failed")
+
+    def check(self) -> int:
+        """Wait for the current stream and report the status of the last
+        launch on it; returns bad_row or -1, raises on a zero pivot or timeout."""
+        s = torch.cuda.current_stream(self.pat.device).cuda_stream
+        bad = C.c_int64(-1)
+        st = load_library().tpilu_batched_graph_check(self.h, C.c_void_p(s), C.byref(bad))
+        if st == E_ZEROPIVOT:
+            raise ZeroPivotError(st, f"batched graph: zero pivot in row {bad.value}", bad.value)
+        if st != OK:
+            raise TpiluError(st, "batched graph: device status", bad.value)
+        return bad.value
 
     def __del__(self):
         h = getattr(self, "h", None)

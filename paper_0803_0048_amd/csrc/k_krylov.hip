@@ -163,6 +163,38 @@ hipError_t launch_gm_start(int64_t n, const double* partial, double* beta_slot, 
     return hipGetLastError();
 }
 
+// The rotation that zeroes b against a: rho = sqrt(a*a + b*b) (each product
+// and the sum rounded on its own, no hypot), c = a / rho, s = b / rho, all
+// correctly rounded binary64 operations.
+struct Rotation {
+    double rho, c, s;
+};
+__device__ __forceinline__ Rotation givens_rotation(double a, double b) {
+    Rotation r;
+    r.rho = __builtin_sqrt(a * a + b * b);
+    r.c = a / r.rho;
+    r.s = b / r.rho;
+    return r;
+}
+
+__global__ void k_givens_batch(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                               double* rho, double* c, double* s) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const Rotation r = givens_rotation(a[i], b[i]);
+        rho[i] = r.rho;
+        c[i] = r.c;
+        s[i] = r.s;
+    }
+}
+
+hipError_t launch_givens_batch(int64_t n, const double* a, const double* b, double* rho, double* c, double* s,
+                               hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_givens_batch, dim3(blocks), dim3(256), 0, st, n, a, b, rho, c, s);
+    return hipGetLastError();
+}
+
 // Givens: apply rotations 0..j-1 to column j of H, form rotation j with
 // rho = sqrt(a*a + b*b) (no hypot), update g, count the iteration and decide
 // whether the cycle stops (|g_{j+1}| <= tol, maxit reached, or breakdown).
@@ -177,11 +209,10 @@ __global__ void k_gm_givens(double* H, double* cs, double* sn, double* g, int32_
         H[(i + 1) * m + j] = cs[i] * c - sn[i] * a;
         H[i * m + j] = tau;
     }
-    const double a = H[j * m + j], c = H[(j + 1) * m + j];
-    const double rho = __builtin_sqrt(a * a + c * c);
-    cs[j] = a / rho;
-    sn[j] = c / rho;
-    H[j * m + j] = rho;
+    const Rotation rot = givens_rotation(H[j * m + j], H[(j + 1) * m + j]);
+    cs[j] = rot.c;
+    sn[j] = rot.s;
+    H[j * m + j] = rot.rho;
     H[(j + 1) * m + j] = 0.0;
     g[j + 1] = -sn[j] * g[j];
     g[j] = cs[j] * g[j];

@@ -296,7 +296,13 @@ size_t flow_lds_bytes(int32_t max_row, int32_t cap) {
 
 typedef __attribute__((address_space(3))) uint64_t LdsU64;
 
-template <Scope S>
+// kHops: instead of values, every entry carries the number of hand-offs
+// between rows on the longest chain of dependencies that ends in it (its
+// final value needs pivot-row values; the same kernel, the same waits, with
+// the update acc - l * v replaced by max(acc, l, v + 1) and the division by
+// max(acc, u + 1)).  The largest count over F is the elimination's critical
+// path measured in row-to-row hand-offs.
+template <Scope S, bool kHops = false>
 __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __restrict__ a_val, double* F,
                                                      Ctl* ctl, uint64_t spin_limit, int64_t skip_row,
                                                      int32_t max_row, int32_t cap) {
@@ -336,8 +342,9 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
             Lb[e] = kPending;
         }
         wave_sync();
-        for (int64_t q = P.rpA[j] + lane; q < P.rpA[j + 1]; q += kWave)
-            Wv[P.a2f[q] - rs] = sanitize_input(a_val[q], ctl);
+        if constexpr (!kHops)
+            for (int64_t q = P.rpA[j] + lane; q < P.rpA[j + 1]; q += kWave)
+                Wv[P.a2f[q] - rs] = sanitize_input(a_val[q], ctl);
         const int64_t row0 = P.tptr[rs];
         const bool whole = P.tptr[re] - row0 <= cap;
         bool stop = false;
@@ -383,7 +390,10 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
                             const uint64_t lb = Lb[Ss[e]];
                             const uint64_t vb = Sv[e];
                             if (lb == kPending || vb == kPending) break;
-                            acc = acc - as_f64(lb) * as_f64(vb);
+                            if constexpr (kHops)
+                                acc = fmax(acc, fmax(as_f64(lb), as_f64(vb) + 1.0));
+                            else
+                                acc = acc - as_f64(lb) * as_f64(vb);
                             ++e;
                             prog = true;
                         }
@@ -392,10 +402,12 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
                             if (p < dl) {
                                 const uint64_t ub = Ud[p];
                                 if (ub == kPending) fin = false;
+                                else if constexpr (kHops) Lb[p] = as_u64(fmax(acc, as_f64(ub) + 1.0));
                                 else Lb[p] = as_u64(acc / as_f64(ub));
                             } else {
                                 if (publish) st_final<S>(F + rs + p, acc);
-                                if (p == dl && acc == 0.0) atomicMin(&ctl->bad_row, (unsigned long long)j);
+                                if (!kHops && p == dl && acc == 0.0)
+                                    atomicMin(&ctl->bad_row, (unsigned long long)j);
                             }
                             if (fin) {
                                 prog = true;
@@ -667,6 +679,30 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
 }
 
 int32_t flow_cap(int32_t max_lrow) { return std::max(kFlowCap, max_lrow); }
+
+hipError_t launch_numeric_hops(const PatDev& P, double* f_hops, Ctl* ctl, uint64_t spin_limit, int32_t grid,
+                               int32_t max_row, int32_t max_lrow, hipStream_t s) {
+    if (P.n <= 0) return hipSuccess;
+    const int32_t mr = std::max(max_row, 1), cap = flow_cap(max_lrow);
+    hipLaunchKernelGGL((k_numeric_flow<Scope::Device, true>), dim3(grid), dim3(64), flow_lds_bytes(mr, cap), s, P,
+                       nullptr, f_hops, ctl, spin_limit, (int64_t)-1, mr, cap);
+    return hipGetLastError();
+}
+
+// largest value of v[0..n) (non-negative whole numbers) into *out (pre-set to 0)
+__global__ void k_max_count(const double* __restrict__ v, int64_t n, int32_t* out) {
+    int32_t m = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, (int32_t)v[i]);
+    for (int o = kWave / 2; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+    if (lane_id() == 0) atomicMax(out, m);
+}
+
+hipError_t launch_max_count(const double* v, int64_t n, int32_t* out, hipStream_t s) {
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_max_count, dim3(blocks), dim3(256), 0, s, v, n, out);
+    return hipGetLastError();
+}
 
 bool numeric_flow_fits(int32_t max_row, int32_t max_lrow, size_t lds_limit) {
     return flow_lds_bytes(std::max(max_row, 1), flow_cap(max_lrow)) <= lds_limit;

@@ -2,8 +2,10 @@
 //
 // forward  (Eq. 3b): x_i = b_i - f_ih1 x_h1 - f_ih2 x_h2 - ...   h ascending
 // backward:          y_i = (x_i - f_ijm y_jm - ... - f_ij1 y_j1) / f_ii,
-//                    j descending (right to left, the order Sec. 3.5 gives
-//                    for the U~ stage)
+//                    j descending (right to left).  The paper leaves the
+//                    order of the backward substitution open; right to left
+//                    makes the value that arrives last (the nearest row's)
+//                    the last term of the chain.
 //
 // Both are dependency-driven: rows go in ascending order for the forward
 // sweep and descending for the backward one.  For one instance a wavefront

@@ -128,6 +128,12 @@ hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, d
                           Ctl* ctl, uint64_t spin_limit, int64_t skip_row, int32_t grid,
                           int32_t max_row, int32_t max_lrow, bool flow, bool one_xcd, hipStream_t s);
 int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, int num_cu);
+// the dataflow kernel in hop-count mode: f_hops (pre-filled with kPending)
+// receives, per entry, the row-to-row hand-offs on the longest dependency
+// chain ending in it (strict lower slots: when l is ready)
+hipError_t launch_numeric_hops(const PatDev& P, double* f_hops, Ctl* ctl, uint64_t spin_limit, int32_t grid,
+                               int32_t max_row, int32_t max_lrow, hipStream_t s);
+hipError_t launch_max_count(const double* v, int64_t n, int32_t* out, hipStream_t s);
 bool numeric_flow_fits(int32_t max_row, int32_t max_lrow, size_t lds_limit);
 // target-major update schedule (mode 0 count per slot, mode 1 fill); LDS of
 // tsched_lds_bytes per wavefront
@@ -168,6 +174,10 @@ hipError_t launch_gm_start(int64_t n, const double* partial, double* beta_slot, 
 hipError_t launch_gm_givens(double* H, double* cs, double* sn, double* g, int32_t m, int32_t j,
                             double tol, int32_t* iters, int32_t maxit, double* hist,
                             int32_t* stop, hipStream_t s);
+// rho, c, s of the rotation of every pair (a_i, b_i), with the same device
+// code as the GMRES step
+hipError_t launch_givens_batch(int64_t n, const double* a, const double* b, double* rho, double* c, double* s,
+                               hipStream_t st);
 hipError_t launch_gm_backsub(const double* H, const double* g, double* yv, int32_t m, int32_t jj,
                              hipStream_t s);
 hipError_t launch_gm_combine(int64_t n, const double* V, const double* yv, int32_t jj, double* u,
@@ -246,5 +256,13 @@ hipError_t launch_inverse(const PatDev& P, const InvSched& S, const double* f_va
 enum { kProdWaveRows = 0, kProdThreadRows = 1, kProdTile = 2 };
 hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const double* b, double* x, double* y,
                                 int shape, hipStream_t s);
+
+// ---- hand-off probe -------------------------------------------------------------------
+size_t probe_buf_bytes();
+// two wavefronts (on one XCD, or on two different XCDs) pass a counter back
+// and forth `rounds` times through global memory; buf (probe_buf_bytes(),
+// zeroed) receives the wall-clock ticks and a status word
+hipError_t launch_handoff(void* buf, int32_t rounds, bool same_xcd, uint64_t spin_limit, hipStream_t s);
+void probe_read(const void* host_copy, unsigned long long* ticks, uint32_t* status);
 
 }  // namespace tpilu

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -262,10 +263,24 @@ PatDev pdev(tpilu_ctx ctx, tpilu_pattern pat, RowKernel kind = RowKernel::Numeri
     return pat->dev(trace ? ctx->trace : nullptr, kind, ctx->group, ctx->tickets);
 }
 
+// A captured batch: its graph, and the intermediate vector and control block
+// the captured kernels use, owned by the graph so that no later call on the
+// pattern (which may regrow or reuse the pattern's own workspace and control
+// block) can touch them.  The pattern's read-only arrays are used too: the
+// pattern must outlive the graph.
 struct tpilu_graph_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int device = 0;
+    Alloc al;
+    double* x = nullptr;
+    Ctl* ctl = nullptr;
+    ~tpilu_graph_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        al.put(x);
+        al.put(ctl);
+    }
 };
 
 namespace {
@@ -323,8 +338,8 @@ struct TimedLaunch {
     tpilu_ctx ctx;
     int kind;
     hipEvent_t a = nullptr, b = nullptr;
-    TimedLaunch(tpilu_ctx c, int k) : ctx(c), kind(k) {
-        if (!ctx->timing) return;
+    TimedLaunch(tpilu_ctx c, int k, bool allowed = true) : ctx(c), kind(k) {
+        if (!ctx->timing || !allowed) return;
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
         if (hipEventCreate(&a) != hipSuccess) { a = nullptr; return; }
@@ -353,7 +368,7 @@ size_t batch_numeric_lds(int32_t max_row) {
 }
 
 tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val, int32_t batch,
-                             double* f_val) {
+                             double* f_val, Ctl* ctl) {
     if (batch > 1 && batch_numeric_lds(pat->st.max_row) > kBatchLdsLimit)
         return fail(ctx, TPILU_E_INVAL,
                     "batched factorization supports rows of at most 80 entries");
@@ -372,7 +387,6 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
                            pat->n_updates < kFlowMaxChain * pat->nnz_f &&
                            pat->n < kFlowMaxWidth * std::max<int64_t>(pat->depth_l, 1);
     const bool flow = batch == 1 && pat->flow && (ctx->numeric == 1 || (ctx->numeric == 0 && auto_flow));
-    HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, pat->ctl, true, ctx->stream));
     // one XCD only when asked for: the factorization keeps many rows in flight
     // and needs the whole device (random banded n=160,000 ILU(2) ran 3x
     // slower on one XCD); there the grid is that XCD's resident maximum
@@ -382,8 +396,11 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
                          : std::max(1, numeric_grid(batch, pat->st.max_row, pat->st.max_lrow, flow, ctx->num_cu) /
                                            (one_xcd ? kXcds : 1));
     {
+        // the timed region holds the pending-marker fill of F too: the
+        // elimination cannot run without it
         TimedLaunch tl(ctx, TPILU_KERNEL_NUMERIC);
-        HIPCHK(ctx, launch_numeric(pdev(ctx, pat, RowKernel::Numeric, true), a_val, batch, f_val, pat->ctl,
+        HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, ctl, true, ctx->stream));
+        HIPCHK(ctx, launch_numeric(pdev(ctx, pat, RowKernel::Numeric, true), a_val, batch, f_val, ctl,
                                    ctx->spin_limit, ctx->skip_row, grid, pat->st.max_row, pat->st.max_lrow, flow,
                                    one_xcd, ctx->stream));
     }
@@ -445,19 +462,19 @@ SolveShape solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool bac
 }
 
 tpilu_status enqueue_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val, int32_t batch,
-                           const double* b, double* y, double* x, bool reset) {
+                           const double* b, double* y, double* x, bool reset, Ctl* ctl, bool timed = true) {
     const SolveShape gf = solve_shape(ctx, pat, batch, false), gb = solve_shape(ctx, pat, batch, true);
     const PatDev P = pdev(ctx, pat, RowKernel::Solve, true);
-    HIPCHK(ctx, launch_fill_pending(x, pat->n * batch, pat->ctl, reset, ctx->stream));
+    HIPCHK(ctx, launch_fill_pending(x, pat->n * batch, ctl, reset, ctx->stream));
     {
-        TimedLaunch tl(ctx, TPILU_KERNEL_FORWARD);
-        HIPCHK(ctx, launch_forward(P, f_val, batch, b, x, pat->ctl, ctx->spin_limit, gf.grid, gf.one_xcd,
+        TimedLaunch tl(ctx, TPILU_KERNEL_FORWARD, timed);
+        HIPCHK(ctx, launch_forward(P, f_val, batch, b, x, ctl, ctx->spin_limit, gf.grid, gf.one_xcd,
                                    ctx->stream));
     }
-    HIPCHK(ctx, launch_fill_pending(y, pat->n * batch, pat->ctl, false, ctx->stream));
+    HIPCHK(ctx, launch_fill_pending(y, pat->n * batch, ctl, false, ctx->stream));
     {
-        TimedLaunch tl(ctx, TPILU_KERNEL_BACKWARD);
-        HIPCHK(ctx, launch_backward(P, f_val, batch, x, y, pat->ctl, ctx->spin_limit, gb.grid, gb.one_xcd,
+        TimedLaunch tl(ctx, TPILU_KERNEL_BACKWARD, timed);
+        HIPCHK(ctx, launch_backward(P, f_val, batch, x, y, ctl, ctx->spin_limit, gb.grid, gb.one_xcd,
                                     ctx->stream));
     }
     return TPILU_OK;
@@ -1108,7 +1125,7 @@ extern "C" TPILU_API tpilu_status tpilu_numeric(tpilu_ctx ctx, tpilu_pattern pat
     if (!a_val || !f_val) return fail(ctx, TPILU_E_INVAL, "null array");
     DeviceGuard dg(ctx->device);
     trace("numeric", pat->n, batch);
-    st = enqueue_numeric(ctx, pat, a_val, batch, f_val);
+    st = enqueue_numeric(ctx, pat, a_val, batch, f_val, pat->ctl);
     if (st) return st;
     if (bad_row) return read_ctl(ctx, pat, bad_row, false);
     return TPILU_OK;
@@ -1135,7 +1152,7 @@ extern "C" TPILU_API tpilu_status tpilu_apply(tpilu_ctx ctx, tpilu_pattern pat, 
         if (!x) return fail(ctx, TPILU_E_NOMEM, "apply workspace");
     }
     trace("apply", pat->n, batch);
-    return enqueue_apply(ctx, pat, f_val, batch, b, y, x, true);
+    return enqueue_apply(ctx, pat, f_val, batch, b, y, x, true, pat->ctl);
 }
 
 extern "C" TPILU_API tpilu_status tpilu_inverse(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val,
@@ -1207,6 +1224,67 @@ extern "C" TPILU_API tpilu_status tpilu_dot(tpilu_ctx ctx, int64_t n, const doub
     return TPILU_OK;
 }
 
+extern "C" TPILU_API tpilu_status tpilu_numeric_critical_path(tpilu_ctx ctx, tpilu_pattern pat, int32_t* hops) {
+    tpilu_status st = check_common(ctx, pat, 1);
+    if (st) return st;
+    if (!hops) return fail(ctx, TPILU_E_INVAL, "null output");
+    *hops = 0;
+    if (pat->n == 0) return TPILU_OK;
+    if (!pat->flow)
+        return fail(ctx, TPILU_E_INVAL, "critical path: the rows of this pattern do not fit the dataflow kernel");
+    DeviceGuard dg(ctx->device);
+    TmpBufs T{pat->al, {}};
+    double* h = (double*)T.get(sizeof(double) * (size_t)pat->nnz_f);
+    int32_t* mx = (int32_t*)T.get(64);
+    if (!h || !mx) return fail(ctx, TPILU_E_NOMEM, "critical path workspace");
+    hipStream_t s = ctx->stream;
+    const int grid = ctx->grid_override ? ctx->grid_override
+                                        : numeric_grid(1, pat->st.max_row, pat->st.max_lrow, true, ctx->num_cu);
+    HIPCHK(ctx, launch_fill_pending(h, pat->nnz_f, pat->ctl, true, s));
+    HIPCHK(ctx, launch_numeric_hops(pdev(ctx, pat), h, pat->ctl, ctx->spin_limit, grid, pat->st.max_row,
+                                    pat->st.max_lrow, s));
+    HIPCHK(ctx, launch_fill_i32(mx, 1, 0, s));
+    HIPCHK(ctx, launch_max_count(h, pat->nnz_f, mx, s));
+    HIPCHK(ctx, hipMemcpyAsync(hops, mx, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    return read_ctl(ctx, pat, nullptr, false);
+}
+
+extern "C" TPILU_API tpilu_status tpilu_handoff_probe(tpilu_ctx ctx, int32_t same_xcd, int32_t rounds,
+                                                      double* ns_round_trip) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (!ns_round_trip || rounds < 1 || rounds > (1 << 24)) return fail(ctx, TPILU_E_INVAL, "bad argument");
+    *ns_round_trip = 0.0;
+    DeviceGuard dg(ctx->device);
+    Alloc al = ctx_alloc(ctx);
+    const size_t bytes = probe_buf_bytes();
+    void* buf = al.get(bytes);
+    if (!buf) return fail(ctx, TPILU_E_NOMEM, "probe buffer");
+    std::vector<unsigned char> host(bytes, 0);
+    hipStream_t s = ctx->stream;
+    hipError_t e = hipMemcpyAsync(buf, host.data(), bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_handoff(buf, rounds, same_xcd != 0, ctx->spin_limit, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), buf, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    al.put(buf);
+    if (e != hipSuccess) return fail(ctx, TPILU_E_DEVICE, std::string("handoff probe: ") + hipGetErrorString(e));
+    unsigned long long ticks = 0;
+    uint32_t status = 0;
+    probe_read(host.data(), &ticks, &status);
+    if (status) return fail(ctx, TPILU_E_TIMEOUT, "handoff probe: a wait ran out (no partner on the XCD?)");
+    *ns_round_trip = (double)ticks * 1000.0 / (double)ctx->ticks_per_us / (double)rounds;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_givens(tpilu_ctx ctx, int64_t count, const double* a, const double* b,
+                                               double* rho, double* c, double* s) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (count < 0 || (count > 0 && (!a || !b || !rho || !c || !s)))
+        return fail(ctx, TPILU_E_INVAL, "bad argument");
+    DeviceGuard dg(ctx->device);
+    HIPCHK(ctx, launch_givens_batch(count, a, b, rho, c, s, ctx->stream));
+    return TPILU_OK;
+}
+
 // =====================================================================================
 // GMRES
 // =====================================================================================
@@ -1220,7 +1298,7 @@ namespace {
 // z = M^-1 v: the two substitutions with F, or the two products with G
 tpilu_status enqueue_precond(tpilu_ctx ctx, tpilu_pattern pat, const double* m_val, bool inverse,
                              const double* v, double* z, double* t, bool reset) {
-    if (!inverse) return enqueue_apply(ctx, pat, m_val, 1, v, z, t, reset);
+    if (!inverse) return enqueue_apply(ctx, pat, m_val, 1, v, z, t, reset, pat->ctl);
     if (reset) HIPCHK(ctx, launch_fill_pending(nullptr, 0, pat->ctl, true, ctx->stream));
     HIPCHK(ctx, launch_apply_inverse(pdev(ctx, pat), m_val, v, t, z, inverse_product_shape(ctx, pat),
                                      ctx->stream));
@@ -1315,10 +1393,19 @@ tpilu_status gmres_impl(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val, c
                                              V + (size_t)(j + 1) * nn, s));
             HIPCHK(ctx, launch_gm_givens(H, cs, sn, g, m, j, tol, iflags, maxit, dhist, iflags + 1, s));
             int32_t hf[2] = {0, 0};
+            uint32_t cst = 0;
             HIPCHK(ctx, hipMemcpyAsync(hf, iflags, sizeof(hf), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipMemcpyAsync(&cst, &pat->ctl->status, sizeof(cst), hipMemcpyDeviceToHost, s));
             HIPCHK(ctx, hipStreamSynchronize(s));
             it_host = hf[0];
             jj = j + 1;
+            // a preconditioner wait that ran out leaves NaN iterates behind,
+            // which no stopping test catches: end the solve at once
+            if (cst & kStTimeout) {
+                *iters = it_host;
+                *relres = NAN;
+                return read_ctl(ctx, pat, nullptr, false);
+            }
             if (hf[1]) break;
         }
         HIPCHK(ctx, launch_gm_backsub(H, g, yv, m, jj, s));
@@ -1438,8 +1525,15 @@ extern "C" TPILU_API tpilu_status tpilu_bicgstab(tpilu_ctx ctx, tpilu_pattern pa
             double snorm = 0.0, rv = 0.0;
             st = nrm(sv, &snorm);
             if (st) return st;
+            uint32_t cst = 0;
             HIPCHK(ctx, hipMemcpyAsync(&rv, sc + kBiRv, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipMemcpyAsync(&cst, &pat->ctl->status, sizeof(cst), hipMemcpyDeviceToHost, s));
             HIPCHK(ctx, hipStreamSynchronize(s));
+            if (cst & kStTimeout) {  // NaN iterates from here on: stop (see GMRES)
+                *iters = it;
+                *relres = NAN;
+                return read_ctl(ctx, pat, nullptr, false);
+            }
             if (rv == 0.0) { breakdown = true; break; }
             if (hist) hist[it] = snorm;
             ++it;
@@ -1466,7 +1560,13 @@ extern "C" TPILU_API tpilu_status tpilu_bicgstab(tpilu_ctx ctx, tpilu_pattern pa
             double so[2] = {0, 0};  // tt, omega
             HIPCHK(ctx, hipMemcpyAsync(&so[0], sc + kBiTt, sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(ctx, hipMemcpyAsync(&so[1], sc + kBiOmega, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipMemcpyAsync(&cst, &pat->ctl->status, sizeof(cst), hipMemcpyDeviceToHost, s));
             HIPCHK(ctx, hipStreamSynchronize(s));
+            if (cst & kStTimeout) {
+                *iters = it;
+                *relres = NAN;
+                return read_ctl(ctx, pat, nullptr, false);
+            }
             if (so[0] == 0.0) { breakdown = true; break; }
             if (hist) hist[it] = rnorm;
             ++it;
@@ -1563,43 +1663,62 @@ extern "C" TPILU_API tpilu_status tpilu_batched_graph_create(tpilu_ctx ctx, tpil
     if (!out) return fail(ctx, TPILU_E_INVAL, "null output");
     *out = nullptr;
     if (!a_val || !f_val || !b || !y) return fail(ctx, TPILU_E_INVAL, "null array");
+    if (b == y) return fail(ctx, TPILU_E_INVAL, "b and y alias");
     if (pat->n == 0) return fail(ctx, TPILU_E_INVAL, "empty pattern");
     DeviceGuard dg(ctx->device);
-    double* x = pat->grow(pat->ws_x, sizeof(double) * (size_t)pat->n * batch);
-    if (!x) return fail(ctx, TPILU_E_NOMEM, "graph workspace");
+    tpilu_graph g = new (std::nothrow) tpilu_graph_s;
+    if (!g) return fail(ctx, TPILU_E_NOMEM, "graph handle");
+    g->device = ctx->device;
+    g->al = ctx_alloc(ctx);
+    g->x = (double*)g->al.get(sizeof(double) * (size_t)pat->n * batch);
+    g->ctl = (Ctl*)g->al.get(sizeof(Ctl));
+    if (!g->x || !g->ctl) {
+        delete g;
+        return fail(ctx, TPILU_E_NOMEM, "graph workspace");
+    }
+    {
+        Ctl z{};
+        z.bad_row = ~0ull;
+        hipError_t e = hipMemcpy(g->ctl, &z, sizeof(Ctl), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            delete g;
+            return fail(ctx, TPILU_E_DEVICE, std::string("graph control block: ") + hipGetErrorString(e));
+        }
+    }
     hipStream_t cap = nullptr;
-    HIPCHK(ctx, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    {
+        hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete g;
+            return fail(ctx, TPILU_E_DEVICE, std::string("capture stream: ") + hipGetErrorString(e));
+        }
+    }
     hipStream_t saved = ctx->stream;
     ctx->stream = cap;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        st = enqueue_numeric(ctx, pat, a_val, batch, f_val);
-        if (st == TPILU_OK) st = enqueue_apply(ctx, pat, f_val, batch, b, y, x, false);
+        st = enqueue_numeric(ctx, pat, a_val, batch, f_val, g->ctl);
+        if (st == TPILU_OK) st = enqueue_apply(ctx, pat, f_val, batch, b, y, g->x, false, g->ctl);
         e = hipStreamEndCapture(cap, &graph);
     }
     ctx->stream = saved;
     (void)hipStreamDestroy(cap);
+    g->graph = graph;
     if (st) {
-        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
         return st;
     }
-    if (e != hipSuccess) return fail(ctx, TPILU_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
+        delete g;
+        return fail(ctx, TPILU_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        g->exec = nullptr;
+        delete g;
         return fail(ctx, TPILU_E_DEVICE, std::string("instantiate: ") + hipGetErrorString(e));
     }
-    tpilu_graph g = new (std::nothrow) tpilu_graph_s;
-    if (!g) {
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        return fail(ctx, TPILU_E_NOMEM, "graph handle");
-    }
-    g->graph = graph;
-    g->exec = exec;
-    g->device = ctx->device;
     *out = g;
     return TPILU_OK;
 }
@@ -1611,10 +1730,23 @@ extern "C" TPILU_API tpilu_status tpilu_batched_graph_launch(tpilu_graph g, void
     return TPILU_OK;
 }
 
+extern "C" TPILU_API tpilu_status tpilu_batched_graph_check(tpilu_graph g, void* hip_stream, int64_t* bad_row) {
+    if (!g) return TPILU_E_INVAL;
+    DeviceGuard dg(g->device);
+    if (hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)) != hipSuccess) return TPILU_E_DEVICE;
+    Ctl h{};
+    if (hipMemcpy(&h, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost) != hipSuccess) return TPILU_E_DEVICE;
+    // the status words are reset by the graph's first kernel on every launch
+    const int64_t bad = h.bad_row == ~0ull ? -1 : (int64_t)h.bad_row;
+    if (bad_row) *bad_row = bad;
+    if (h.status & kStTimeout) return TPILU_E_TIMEOUT;
+    if (h.status & kStReservedNaN) return TPILU_E_INVAL;
+    if (bad >= 0) return TPILU_E_ZEROPIVOT;
+    return TPILU_OK;
+}
+
 extern "C" TPILU_API void tpilu_batched_graph_destroy(tpilu_graph g) {
     if (!g) return;
     DeviceGuard dg(g->device);
-    if (g->exec) (void)hipGraphExecDestroy(g->exec);
-    if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
 }

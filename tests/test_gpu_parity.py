@@ -92,6 +92,41 @@ def test_division_and_update_rounding_bits():
     assert_bits_equal(fh[3][fin], u11[fin], "d - l b")
 
 
+def test_givens_sqrt_and_division_bits():
+    """The rotation step of GMRES, rho = sqrt(a*a + b*b), c = a / rho,
+    s = b / rho, on 2^20 operand pairs spread over the whole binary64 range
+    (subnormal to overflowing squares, zeros, infinities, NaNs), against IEEE
+    host arithmetic (numpy's sqrt and division are correctly rounded)."""
+    rng = np.random.default_rng(7)
+    B = 1 << 20
+    a = rng.standard_normal(B) * np.exp2(rng.integers(-1074, 1024, B).astype(np.float64))
+    b = rng.standard_normal(B) * np.exp2(rng.integers(-1074, 1024, B).astype(np.float64))
+    # a quarter with the two magnitudes close (cancellation-free but sqrt of a
+    # sum of comparable squares), a quarter of raw random bit patterns
+    q = B // 4
+    b[:q] = a[:q] * rng.uniform(0.5, 2.0, q)
+    a[q:2 * q] = rng.integers(0, 1 << 63, q, dtype=np.uint64).view(np.float64) * rng.choice([-1, 1], q)
+    b[q:2 * q] = rng.integers(0, 1 << 63, q, dtype=np.uint64).view(np.float64)
+    sp = np.array([0.0, -0.0, 5e-324, -5e-324, 2.2250738585072014e-308, 1.4916681462400413e-154,
+                   1.3407807929942596e154, 1.7976931348623157e308, np.inf, -np.inf, np.nan, 1.0, 3.0])
+    k = sp.size
+    a[2 * q:2 * q + k * k] = np.repeat(sp, k)
+    b[2 * q:2 * q + k * k] = np.tile(sp, k)
+    rho, c, s = T.givens(g(a), g(b))
+    with np.errstate(all="ignore"):
+        rho_r = np.sqrt(a * a + b * b)
+        c_r = a / rho_r
+        s_r = b / rho_r
+    assert_bits_equal(rho, rho_r, "rho = sqrt(a*a + b*b)")
+    assert_bits_equal(c, c_r, "c = a / rho")
+    assert_bits_equal(s, s_r, "s = b / rho")
+    # and the norms of the solvers: sqrt of a fixed-shape inner product
+    for n in (1, 2, 16385):
+        x = rng.standard_normal(n) * 10.0 ** rng.uniform(-150, 150)
+        got = T.dot(g(x), g(x))
+        assert bits(np.array([np.sqrt(got)]))[0] == bits(np.array([np.sqrt(O.dot(x, x))]))[0]
+
+
 def test_dot_bits_and_fixed_shape():
     rng = np.random.default_rng(2)
     for n in (0, 1, 63, 16384, 16385, 100_003, 1_000_000):
@@ -208,10 +243,21 @@ def test_config3_conv_diff_3d(k):
     _full(c["A"], k, c["b"])
 
 
-def test_config3_gmres_ilu1():
-    c = I.conv_diff_3d_ilu(k=1)
-    pat, f, ref = _full(c["A"], 1, c["b"])
-    _gmres_parity(pat, (f, ref), c["A"], c["b"], 50, 150, 1e-8)
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_config3_gmres_and_bicgstab(k):
+    """Sec. 4.2's 3-D convection-dominated problem at 64^3: GMRES(50) and
+    BiCGSTAB (the paper's solver) with ILU(k), iterates bit for bit."""
+    c = I.conv_diff_3d_ilu(k=k)
+    A, b = c["A"], c["b"]
+    pat, f, ref = _full(A, k, b)
+    info = _gmres_parity(pat, (f, ref), A, b, 50, 3000, 1e-8)
+    assert info["relres"] <= 1e-8
+    rpF, ciF, vF = ref
+    r = O.bicgstab(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, b, maxit=3000, rtol=1e-8)
+    x, binfo = T.bicgstab(pat, g(A.val), f, g(b), maxit=3000, rtol=1e-8)
+    assert binfo["iters"] == r["iters"] and binfo["status"] == r["status"] == 0, (binfo["iters"], r["iters"])
+    assert_bits_equal(np.array(binfo["hist"]), r["hist"], "BiCGSTAB residual history")
+    assert_bits_equal(x, r["x"], "BiCGSTAB x")
 
 
 def test_repeatable_across_launch_shapes():
@@ -424,7 +470,39 @@ def test_config4_batched_graph():
     f2 = T.numeric(pat, av)
     assert torch.equal(graph.f_val.view(torch.int64), f2.view(torch.int64))
     assert not torch.equal(f2.view(torch.int64), f_eager.view(torch.int64))
+    assert graph.check() == -1
     assert T.check(pat) == -1
+
+
+def test_graph_owns_its_workspace():
+    """A graph captured at 16 instances keeps working after eager calls on the
+    same pattern regrow the pattern's own workspace (64 instances) and reuse
+    its control block: the graph has its own intermediate vector and control
+    block.  Every instance is compared with the oracle."""
+    c = I.batched_conv_diff_2d_ilu2(B=64, m=24)
+    A, rhs = c["A"], c["b"]
+    pat = T.symbolic(g(A.rowptr), g(A.col), 2)
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, 2)
+    a16 = g(np.ascontiguousarray(A.val[:, :16]))
+    b16 = g(np.ascontiguousarray(rhs[:, :16]))
+    graph = T.BatchedGraph(pat, a16, b16)
+    graph.launch()
+    assert graph.check() == -1
+    # eager work at a larger batch on the same pattern (regrows its workspace)
+    f64 = T.numeric(pat, g(A.val))
+    y64 = T.apply(pat, f64, g(rhs))
+    graph.launch()
+    y64b = T.apply(pat, f64, g(rhs))  # eager work queued behind the launch
+    assert graph.check() == -1
+    f = graph.f_val.cpu().numpy()
+    y = graph.y.cpu().numpy()
+    for inst in range(16):
+        vF, _ = O.numeric(A.n, A.rowptr, A.col, A.val[:, inst].copy(), rpF, ciF)
+        _, yr = O.apply(A.n, rpF, ciF, vF, rhs[:, inst])
+        assert_bits_equal(f[:, inst], vF, f"graph F {inst}")
+        assert_bits_equal(y[:, inst], yr, f"graph y {inst}")
+    assert torch.equal(y64.view(torch.int64), y64b.view(torch.int64))
+    assert_bits_equal(y64[:, :16], y, "eager vs graph")
 
 
 def test_batched_partial_group():
@@ -558,7 +636,7 @@ def test_config5_autograd_against_oracle_and_fd():
     loss.backward()
     ga, gb = av.grad.cpu().numpy(), bv.grad.cpu().numpy()
     rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, 1)
-    for inst in (0, 7, 15):
+    for inst in range(B):
         abar_r, bbar_r, _ = _oracle_grads(A, rpF, ciF, A.val[:, inst].copy(), rhs[:, inst], tgt[:, inst])
         assert_bits_equal(ga[:, inst], abar_r, f"d/dA instance {inst}")
         assert_bits_equal(gb[:, inst], bbar_r, f"d/db instance {inst}")
@@ -701,6 +779,14 @@ def test_stencil27_50cubed(k):
     _full(c["A"], k, c["b"])
 
 
+def test_stencil27_90cubed_ilu1():
+    """The largest 27-point size the benchmark runs (90^3 = 729,000 rows,
+    4.4 x 10^7 entries of F, lane-per-row solves): pattern, factor and both
+    solves bit for bit."""
+    c = I.stencil27_ilu(m=90, k=1)
+    _full(c["A"], 1, c["b"])
+
+
 # ----------------------------------------------------------------------------------
 # Paper-scale ILU(1) (Table 3's general sparse matrices, about 1,250 entries per row
 # of F): long rows through the larger symbolic maps and the pivot-serial kernel
@@ -716,43 +802,28 @@ def test_paper_scale_rows_small_bits():
     assert pat.info["long_rows"] > 0
 
 
-def _k1_row_pattern(A, j):
-    """Level <= 1 pattern of row j from the definition of the levels: an entry
-    has level 1 exactly when it is reached through a pivot h < j of level 0
-    with a level-0 entry (h, t), t > h; stored entries have level 0."""
-    a = A.col[A.rowptr[j]:A.rowptr[j + 1]].astype(np.int64)
-    lev = {int(t): 0 for t in a}
-    for h in a[a < j]:
-        ah = A.col[A.rowptr[h]:A.rowptr[h + 1]].astype(np.int64)
-        for t in ah[ah > h]:
-            lev.setdefault(int(t), 1)
-    cols = np.array(sorted(lev), dtype=np.int64)
-    return cols, np.array([lev[int(t)] for t in cols], dtype=np.uint8)
+def test_paper_scale_160k_all_rows():
+    """Table 3's 160K size at full scale (about 2 x 10^8 entries of F): every
+    row's pattern, levels and factor values and both solves, against the
+    digests the oracle wrote (tests/golden/paper_scale_ilu1_digests.py), per
+    block of 1,000 rows."""
+    from tests.golden.paper_scale_ilu1_digests import block_digests, read_digests
 
-
-def test_paper_scale_160k_sampled_rows():
-    """Table 3's 160K size at full scale (~2 x 10^8 entries of F): sampled
-    rows' patterns against the level definition, and their factor rows
-    against the oracle's elimination of that row on the GPU's pivot rows
-    (a row of F depends only on A's row and its pivots' final U rows)."""
+    meta, want = read_digests()
     c = I.paper_scale_random_ilu1()
     A = c["A"]
+    assert int(meta["n"]) == A.n and int(meta["nnz_a"]) == A.nnz
     pat = T.symbolic(g(A.rowptr), g(A.col), 1)
     info = pat.info
     log(f"[gpu] paper-scale 160K: nnz_f {info['nnz_f']} long rows {info['long_rows']} "
         f"overflow {info['overflow_rows']} depth {info['depth_l']}")
+    assert info["nnz_f"] == int(meta["nnz_f"])
     f = T.numeric(pat, g(A.val))
+    y, x = T.apply(pat, f, g(c["b"]), return_x=True)
     ex = pat.export()
-    rpF = ex["rowptr"].cpu().numpy()
-    ciF = ex["col"].cpu().numpy()
-    lvF = ex["level"].cpu().numpy()
-    vF = f.cpu().numpy()
-    rng = np.random.default_rng(160)
-    rows = np.unique(np.concatenate([[0, 1, A.n // 2, A.n - 1], rng.integers(0, A.n, 60)]))
-    for j in rows:
-        cols, lev = _k1_row_pattern(A, j)
-        assert np.array_equal(ciF[rpF[j]:rpF[j + 1]], cols), f"pattern of row {j}"
-        assert np.array_equal(lvF[rpF[j]:rpF[j + 1]], lev), f"levels of row {j}"
-    ref = O.numeric_rows(A.n, A.rowptr, A.col, A.val, rpF, ciF, vF, rows)
-    for j, r in zip(rows, ref):
-        assert np.array_equal(vF[rpF[j]:rpF[j + 1]].view(np.int64), r.view(np.int64)), f"factor row {j}"
+    got = block_digests(ex["rowptr"].cpu().numpy(), ex["col"].cpu().numpy(), ex["level"].cpu().numpy(),
+                        f.cpu().numpy(), x.cpu().numpy(), y.cpu().numpy())
+    assert len(got) == len(want)
+    what = ("pattern", "factor", "x", "y")
+    bad = [(w[0], what[q]) for w, h in zip(want, got) for q in range(4) if w[2 + q] != h[2 + q]]
+    assert not bad, f"{len(bad)} mismatching (first row of block, part): {bad[:10]}"
