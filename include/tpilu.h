@@ -270,6 +270,22 @@ TPILU_API tpilu_status tpilu_pattern_check(tpilu_ctx ctx, tpilu_pattern pat, int
 TPILU_API tpilu_status tpilu_apply(tpilu_ctx ctx, tpilu_pattern pat, const double *f_val,
                                    int32_t batch, const double *b, double *y, double *x_out);
 
+/* tpilu_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, and harnesses that forbid hipMalloc.
+ * Same result, bit for bit, as tpilu_apply(ctx, pat, f_val, batch, b, y,
+ * NULL); the intermediate x is kept in a fixed scratch array of the library
+ * (4,194,304 doubles = 32 MiB per device, held by each device the library
+ * runs on until the process ends) instead of the pattern's workspace.  The
+ * call allocates nothing and creates no timing events.  Rejects n * batch >
+ * 4,194,304 with TPILU_E_INVAL (nothing is launched); TPILU_E_DEVICE if the
+ * scratch's device address could not be taken when the ctx was created.
+ * Every call on one device shares that device's scratch, which keeps the
+ * last call's contents: calls that overlap on one device (any stream, any
+ * ctx, any pattern) race and must be ordered by the caller.  Status
+ * (reserved NaN, watchdog) is read with tpilu_pattern_check. */
+TPILU_API tpilu_status tpilu_apply_noalloc(tpilu_ctx ctx, tpilu_pattern pat, const double *f_val,
+                                           int32_t batch, const double *b, double *y);
+
 /* ---------------------------------------------------------------------------
  * Restarted GMRES(m), right preconditioned by M = L~ U~ (single instance).
  * Modified Gram-Schmidt, Givens rotations with rho = sqrt(a*a + b*b), inner

@@ -24,7 +24,7 @@ EXPORTED = [
     "tpilu_pattern_export", "tpilu_pattern_destroy", "tpilu_numeric", "tpilu_pattern_check",
     "tpilu_apply", "tpilu_gmres", "tpilu_spmv", "tpilu_dot", "tpilu_apply_adjoint",
     "tpilu_numeric_adjoint", "tpilu_batched_graph_create", "tpilu_batched_graph_launch",
-    "tpilu_batched_graph_check", "tpilu_batched_graph_destroy", "tpilu_givens",
+    "tpilu_batched_graph_check", "tpilu_batched_graph_destroy", "tpilu_apply_noalloc", "tpilu_givens",
     "tpilu_numeric_critical_path", "tpilu_handoff_probe",
 ]
 
@@ -86,6 +86,7 @@ def load_library():
             "tpilu_numeric": ([P, P, P, i32, P, C.POINTER(i64)], st),
             "tpilu_pattern_check": ([P, P, C.POINTER(i64)], st),
             "tpilu_apply": ([P, P, P, i32, P, P, P], st),
+            "tpilu_apply_noalloc": ([P, P, P, i32, P, P], st),
             "tpilu_gmres": ([P, P, P, P, P, P, i32, i32, dbl, C.POINTER(i32), C.POINTER(dbl), P], st),
             "tpilu_gmres_inverse": ([P, P, P, P, P, P, i32, i32, dbl, C.POINTER(i32), C.POINTER(dbl), P], st),
             "tpilu_inverse": ([P, P, P, i32, P], st),
@@ -345,6 +346,25 @@ def apply(pat: Pattern, f_val: torch.Tensor, b: torch.Tensor, out: torch.Tensor 
     st = load_library().tpilu_apply(ctx.h, pat.h, _ptr(f_val), B, _ptr(b), _ptr(y), _ptr(x))
     ctx.check(st, "apply")
     return (y, x) if return_x else y
+
+
+def apply_noalloc(pat: Pattern, f_val: torch.Tensor, b: torch.Tensor, y: torch.Tensor):
+    """y = U~^-1 L~^-1 b into the caller's y, with the library allocating
+    nothing (its intermediate vector lives in a fixed 32 MiB device scratch;
+    n * batch must be at most 4,194,304).  Calls on one device must not
+    overlap."""
+    _need(f_val, torch.float64, "f_val", pat.device)
+    _need(b, torch.float64, "b", pat.device)
+    B = _batch_of(b, pat.n, "b")
+    if _batch_of(f_val, pat.nnz_f, "f_val") != B or f_val.dim() != b.dim():
+        raise ValueError("f_val and b batch sizes differ")
+    _need_size(y, torch.float64, "y", pat.device, pat.n, B)
+    if y.dim() != b.dim() or y.data_ptr() == b.data_ptr():
+        raise ValueError("y must be shaped like b and must not be b")
+    ctx = context(pat.device)
+    st = load_library().tpilu_apply_noalloc(ctx.h, pat.h, _ptr(f_val), B, _ptr(b), _ptr(y))
+    ctx.check(st, "apply_noalloc")
+    return y
 
 
 def inverse(pat: Pattern, f_val: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

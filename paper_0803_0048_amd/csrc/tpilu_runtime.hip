@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -39,6 +40,8 @@ struct tpilu_ctx_s {
     // second stream (default priority) for work that overlaps the main one
     hipStream_t aux = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    double* scratch = nullptr;  // device address of the no-alloc scratch on this device
+    hipError_t scratch_err = hipSuccess;
     std::string err;
     ~tpilu_ctx_s() {
         if (aux) (void)hipStreamDestroy(aux);
@@ -51,6 +54,43 @@ struct tpilu_ctx_s {
             }
     }
 };
+
+// ---------------------------------------------------------------------------
+// Fixed scratch for tpilu_apply_noalloc: the intermediate vector x of the two
+// substitutions lives in this file-scope device array, one copy per device,
+// held until the process ends.  Host code never uses the array's name as an
+// address (in host code it names a host-side stand-in): the device address
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current and kept in scratch_addr.
+constexpr int64_t kScratchDoubles = int64_t(1) << 22;  // 32 MiB: n * batch <= 4,194,304
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+double* scratch_addr[kMaxDevices] = {};
+hipError_t scratch_err[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// the first time and cached; nullptr (and the error in *err) if it failed.
+double* scratch_on(int device, hipError_t* err) {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    if (!scratch_addr[device] && scratch_err[device] == hipSuccess) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            (void)hipGetLastError();
+        } else {
+            scratch_addr[device] = static_cast<double*>(p);
+        }
+    }
+    *err = scratch_err[device];
+    return scratch_addr[device];
+}
 
 namespace {
 
@@ -724,6 +764,11 @@ extern "C" TPILU_API tpilu_status tpilu_ctx_create(int device, void* hip_stream,
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
         c->ticks_per_us = std::max<uint64_t>(1, (uint64_t)khz / 1000);
     c->spin_limit = kDefaultWaitUs * c->ticks_per_us;
+    {
+        // the no-alloc scratch's address on this device, with the device current
+        DeviceGuard dg(device);
+        c->scratch = scratch_on(device, &c->scratch_err);
+    }
     *out = c;
     return TPILU_OK;
 }
@@ -1153,6 +1198,29 @@ extern "C" TPILU_API tpilu_status tpilu_apply(tpilu_ctx ctx, tpilu_pattern pat, 
     }
     trace("apply", pat->n, batch);
     return enqueue_apply(ctx, pat, f_val, batch, b, y, x, true, pat->ctl);
+}
+
+extern "C" TPILU_API tpilu_status tpilu_apply_noalloc(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val,
+                                                      int32_t batch, const double* b, double* y) {
+    tpilu_status st = check_common(ctx, pat, batch);
+    if (st) return st;
+    if (pat->n == 0) return TPILU_OK;
+    if (!f_val || !b || !y) return fail(ctx, TPILU_E_INVAL, "null array");
+    if (b == y) return fail(ctx, TPILU_E_INVAL, "b and y alias");
+    if (pat->n * (int64_t)batch > kScratchDoubles)
+        return fail(ctx, TPILU_E_INVAL,
+                    "apply_noalloc: n * batch = " + std::to_string(pat->n * (int64_t)batch) +
+                        " exceeds the fixed scratch of " + std::to_string(kScratchDoubles) + " values");
+    if (!ctx->scratch)
+        return fail(ctx, TPILU_E_DEVICE,
+                    std::string("apply_noalloc: no scratch address on this device: ") +
+                        hipGetErrorString(ctx->scratch_err));
+    DeviceGuard dg(ctx->device);
+    trace("apply_noalloc", pat->n, batch);
+    // x lives in the scratch; the first kernel overwrites the part used with
+    // the pending marker, so nothing left by an earlier call is read
+    // (no timing events either: creating them is not allowed here)
+    return enqueue_apply(ctx, pat, f_val, batch, b, y, ctx->scratch, true, pat->ctl, false);
 }
 
 extern "C" TPILU_API tpilu_status tpilu_inverse(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val,

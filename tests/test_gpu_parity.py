@@ -127,6 +127,34 @@ def test_givens_sqrt_and_division_bits():
         assert bits(np.array([np.sqrt(got)]))[0] == bits(np.array([np.sqrt(O.dot(x, x))]))[0]
 
 
+def test_critical_path_and_handoff_probe():
+    """The hop-count mode of the elimination on matrices whose critical path
+    is known: a tridiagonal matrix chains every row on the previous one
+    (n - 1 hand-offs), a diagonal one has none; the hand-off probe returns a
+    finite round trip on one XCD and across two."""
+    n = 500
+    rp = np.arange(0, 3 * n - 1, 3, dtype=np.int64)
+    rows = [[j - 1, j, j + 1] for j in range(n)]
+    rows[0] = [0, 1]
+    rows[-1] = [n - 2, n - 1]
+    col = np.concatenate([np.array(r, np.int32) for r in rows])
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    ctx = T.context(0)
+    ctx.set_numeric(ctx.NUMERIC_FLOW)
+    try:
+        for k in (0, 2):
+            pat = T.symbolic(g(rp), g(col), k)
+            assert T.numeric_critical_path(pat) == n - 1, k
+        pat = T.symbolic(g(np.arange(n + 1, dtype=np.int64)), g(np.arange(n, dtype=np.int32)), 0)
+        assert T.numeric_critical_path(pat) == 0
+    finally:
+        ctx.set_numeric(0)
+    for same in (True, False):
+        rt = T.handoff_probe(same, rounds=2000)
+        log(f"  hand-off round trip ({'one XCD' if same else 'two XCDs'}): {rt:.1f} ns")
+        assert 0.0 < rt < 1e5
+
+
 def test_dot_bits_and_fixed_shape():
     rng = np.random.default_rng(2)
     for n in (0, 1, 63, 16384, 16385, 100_003, 1_000_000):
