@@ -446,10 +446,12 @@ def latency_floors(T, ctx, pat, pinfo, avg, n):
     res = {"handoff_round_trip_ns": {"two_xcds": rt_dev, "one_xcd": rt_xcd},
            "hop_ns": {"two_xcds": hop_dev, "one_xcd": hop_xcd}}
     try:
-        hops = T.numeric_critical_path(pat)
+        hops = int(round(T.numeric_critical_path(pat, 1.0, 0.0)))
+        steps = int(round(T.numeric_critical_path(pat, 0.0, 1.0)))
     except T.TpiluError:
-        hops = None
+        hops = steps = None
     if hops is not None:
+        res["numeric_longest_l_chain"] = steps
         fl = hops * hop_dev * 1e-6
         res["numeric"] = {"critical_path_hops": hops, "floor_ms": fl, "achieved_ms": avg["numeric"],
                           "achieved_over_floor": avg["numeric"] / fl if fl > 0 else None,

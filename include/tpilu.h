@@ -375,13 +375,17 @@ TPILU_API tpilu_status tpilu_dot(tpilu_ctx ctx, int64_t n, const double *x, cons
 /* Measurements of the dependency critical path (no numeric result).
  *
  * tpilu_numeric_critical_path runs the dataflow elimination kernel in a mode
- * that carries, instead of values, the number of row-to-row hand-offs on the
- * longest chain of dependencies ending in each entry of F (an update of
- * f_jt needs f_ht, and l_jh needs f_hh, from row h: one hand-off each; work
- * inside a row costs none), and writes the largest count into *hops (host).
- * This many hand-offs must happen one after another in any parallel
- * factorization that keeps the bits of Eq. 2.  TPILU_E_INVAL when the
- * pattern's rows do not fit the dataflow kernel.  Waits for the stream.
+ * that carries, instead of values, the length of the longest chain of
+ * dependencies ending in each entry of F, and writes the largest length over
+ * F into *length (host).  On a chain, every hand-off between rows (an update
+ * of f_jt needs f_ht, and l_jh needs f_hh, from row h) weighs w_hop, and
+ * every l of a row (a division whose result entries of the same row wait
+ * for) weighs w_step; other work inside a row weighs nothing.  With w_hop = 1
+ * and w_step = 0 the length is the number of row-to-row hand-offs that must
+ * happen one after another in any parallel factorization that keeps the
+ * bits of Eq. 2; with both set to measured times it models a latency floor.
+ * Weights must be finite and >= 0.  TPILU_E_INVAL when the pattern's rows do
+ * not fit the dataflow kernel.  Waits for the stream.
  *
  * tpilu_handoff_probe has two wavefronts pass a value back and forth
  * `rounds` times (1 .. 2^24) through device memory with the publish and poll
@@ -390,7 +394,8 @@ TPILU_API tpilu_status tpilu_dot(tpilu_ctx ctx, int64_t n, const double *x, cons
  * through), and writes the mean round trip in nanoseconds into
  * *ns_round_trip (host); one hand-off is half of it.  Waits for the stream;
  * TPILU_E_TIMEOUT if no partner wavefront appeared within the watchdog. */
-TPILU_API tpilu_status tpilu_numeric_critical_path(tpilu_ctx ctx, tpilu_pattern pat, int32_t *hops);
+TPILU_API tpilu_status tpilu_numeric_critical_path(tpilu_ctx ctx, tpilu_pattern pat, double w_hop,
+                                                   double w_step, double *length);
 TPILU_API tpilu_status tpilu_handoff_probe(tpilu_ctx ctx, int32_t same_xcd, int32_t rounds,
                                            double *ns_round_trip);
 

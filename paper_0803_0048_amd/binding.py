@@ -95,7 +95,7 @@ def load_library():
             "tpilu_spmv": ([P, P, P, P, P], st),
             "tpilu_dot": ([P, i64, P, P, C.POINTER(dbl)], st),
             "tpilu_givens": ([P, i64, P, P, P, P, P], st),
-            "tpilu_numeric_critical_path": ([P, P, C.POINTER(i32)], st),
+            "tpilu_numeric_critical_path": ([P, P, dbl, dbl, C.POINTER(dbl)], st),
             "tpilu_handoff_probe": ([P, i32, i32, C.POINTER(dbl)], st),
             "tpilu_apply_adjoint": ([P, P, P, i32, P, P, P, P, P], st),
             "tpilu_numeric_adjoint": ([P, P, P, i32, P, P], st),
@@ -432,12 +432,14 @@ def givens(a: torch.Tensor, b: torch.Tensor):
     return rho, c, s
 
 
-def numeric_critical_path(pat: Pattern) -> int:
-    """Row-to-row hand-offs on the longest dependency chain of the numeric
-    factorization (the dataflow kernel run in hop-count mode)."""
+def numeric_critical_path(pat: Pattern, w_hop: float = 1.0, w_step: float = 0.0) -> float:
+    """Longest dependency chain of the numeric factorization, a row-to-row
+    hand-off weighing w_hop and an l of a row weighing w_step (the dataflow
+    kernel run in critical-path mode); the defaults count hand-offs."""
     ctx = context(pat.device)
-    h = C.c_int32(0)
-    ctx.check(load_library().tpilu_numeric_critical_path(ctx.h, pat.h, C.byref(h)), "numeric_critical_path")
+    h = C.c_double(0.0)
+    ctx.check(load_library().tpilu_numeric_critical_path(ctx.h, pat.h, float(w_hop), float(w_step), C.byref(h)),
+              "numeric_critical_path")
     return h.value
 
 

@@ -296,16 +296,18 @@ size_t flow_lds_bytes(int32_t max_row, int32_t cap) {
 
 typedef __attribute__((address_space(3))) uint64_t LdsU64;
 
-// kHops: instead of values, every entry carries the number of hand-offs
-// between rows on the longest chain of dependencies that ends in it (its
-// final value needs pivot-row values; the same kernel, the same waits, with
-// the update acc - l * v replaced by max(acc, l, v + 1) and the division by
-// max(acc, u + 1)).  The largest count over F is the elimination's critical
-// path measured in row-to-row hand-offs.
+// kHops: instead of values, every entry carries the length of the longest
+// chain of dependencies that ends in it, a hand-off between rows (a pivot-row
+// value used by row j) weighing w_hop and an l of row j (a division whose
+// result other entries of the row wait for) weighing w_step: the same kernel
+// and the same waits, with the update acc - l * v replaced by
+// max(acc, l, v + w_hop) and the division by max(acc, u + w_hop) + w_step.
+// The largest value over F is the elimination's critical path.
 template <Scope S, bool kHops = false>
 __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __restrict__ a_val, double* F,
                                                      Ctl* ctl, uint64_t spin_limit, int64_t skip_row,
-                                                     int32_t max_row, int32_t cap) {
+                                                     int32_t max_row, int32_t cap, double w_hop = 1.0,
+                                                     double w_step = 0.0) {
     extern __shared__ uint64_t lds_u64[];
     double* Wv = reinterpret_cast<double*>(lds_u64);                  // [max_row] initial values
     // arrays that lanes update for one another inside the loops below:
@@ -391,7 +393,7 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
                             const uint64_t vb = Sv[e];
                             if (lb == kPending || vb == kPending) break;
                             if constexpr (kHops)
-                                acc = fmax(acc, fmax(as_f64(lb), as_f64(vb) + 1.0));
+                                acc = fmax(acc, fmax(as_f64(lb), as_f64(vb) + w_hop));
                             else
                                 acc = acc - as_f64(lb) * as_f64(vb);
                             ++e;
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
                             if (p < dl) {
                                 const uint64_t ub = Ud[p];
                                 if (ub == kPending) fin = false;
-                                else if constexpr (kHops) Lb[p] = as_u64(fmax(acc, as_f64(ub) + 1.0));
+                                else if constexpr (kHops) Lb[p] = as_u64(fmax(acc, as_f64(ub) + w_hop) + w_step);
                                 else Lb[p] = as_u64(acc / as_f64(ub));
                             } else {
                                 if (publish) st_final<S>(F + rs + p, acc);
@@ -681,26 +683,27 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
 int32_t flow_cap(int32_t max_lrow) { return std::max(kFlowCap, max_lrow); }
 
 hipError_t launch_numeric_hops(const PatDev& P, double* f_hops, Ctl* ctl, uint64_t spin_limit, int32_t grid,
-                               int32_t max_row, int32_t max_lrow, hipStream_t s) {
+                               int32_t max_row, int32_t max_lrow, double w_hop, double w_step, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
     const int32_t mr = std::max(max_row, 1), cap = flow_cap(max_lrow);
     hipLaunchKernelGGL((k_numeric_flow<Scope::Device, true>), dim3(grid), dim3(64), flow_lds_bytes(mr, cap), s, P,
-                       nullptr, f_hops, ctl, spin_limit, (int64_t)-1, mr, cap);
+                       nullptr, f_hops, ctl, spin_limit, (int64_t)-1, mr, cap, w_hop, w_step);
     return hipGetLastError();
 }
 
-// largest value of v[0..n) (non-negative whole numbers) into *out (pre-set to 0)
-__global__ void k_max_count(const double* __restrict__ v, int64_t n, int32_t* out) {
-    int32_t m = 0;
+// largest value of v[0..n) (non-negative, not NaN) into *out (pre-set to
+// 0): non-negative doubles order like their bit patterns
+__global__ void k_max_nonneg(const double* __restrict__ v, int64_t n, unsigned long long* out) {
+    unsigned long long m = 0ull;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        m = max(m, (int32_t)v[i]);
-    for (int o = kWave / 2; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+        m = max(m, (unsigned long long)as_u64(v[i]));
+    for (int o = kWave / 2; o > 0; o >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, o));
     if (lane_id() == 0) atomicMax(out, m);
 }
 
-hipError_t launch_max_count(const double* v, int64_t n, int32_t* out, hipStream_t s) {
+hipError_t launch_max_nonneg(const double* v, int64_t n, unsigned long long* out, hipStream_t s) {
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
-    hipLaunchKernelGGL(k_max_count, dim3(blocks), dim3(256), 0, s, v, n, out);
+    hipLaunchKernelGGL(k_max_nonneg, dim3(blocks), dim3(256), 0, s, v, n, out);
     return hipGetLastError();
 }
 

@@ -128,12 +128,13 @@ hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, d
                           Ctl* ctl, uint64_t spin_limit, int64_t skip_row, int32_t grid,
                           int32_t max_row, int32_t max_lrow, bool flow, bool one_xcd, hipStream_t s);
 int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, int num_cu);
-// the dataflow kernel in hop-count mode: f_hops (pre-filled with kPending)
-// receives, per entry, the row-to-row hand-offs on the longest dependency
-// chain ending in it (strict lower slots: when l is ready)
-hipError_t launch_numeric_hops(const PatDev& P, double* f_hops, Ctl* ctl, uint64_t spin_limit, int32_t grid,
-                               int32_t max_row, int32_t max_lrow, hipStream_t s);
-hipError_t launch_max_count(const double* v, int64_t n, int32_t* out, hipStream_t s);
+// the dataflow kernel in critical-path mode: f_len (pre-filled with
+// kPending) receives, per entry, the length of the longest dependency chain
+// ending in it, a row-to-row hand-off weighing w_hop and an l of a row
+// (strict lower slots: when that l is ready) w_step
+hipError_t launch_numeric_hops(const PatDev& P, double* f_len, Ctl* ctl, uint64_t spin_limit, int32_t grid,
+                               int32_t max_row, int32_t max_lrow, double w_hop, double w_step, hipStream_t s);
+hipError_t launch_max_nonneg(const double* v, int64_t n, unsigned long long* out, hipStream_t s);
 bool numeric_flow_fits(int32_t max_row, int32_t max_lrow, size_t lds_limit);
 // target-major update schedule (mode 0 count per slot, mode 1 fill); LDS of
 // tsched_lds_bytes per wavefront

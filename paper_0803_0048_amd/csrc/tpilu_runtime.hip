@@ -1292,29 +1292,37 @@ extern "C" TPILU_API tpilu_status tpilu_dot(tpilu_ctx ctx, int64_t n, const doub
     return TPILU_OK;
 }
 
-extern "C" TPILU_API tpilu_status tpilu_numeric_critical_path(tpilu_ctx ctx, tpilu_pattern pat, int32_t* hops) {
+extern "C" TPILU_API tpilu_status tpilu_numeric_critical_path(tpilu_ctx ctx, tpilu_pattern pat, double w_hop,
+                                                              double w_step, double* length) {
     tpilu_status st = check_common(ctx, pat, 1);
     if (st) return st;
-    if (!hops) return fail(ctx, TPILU_E_INVAL, "null output");
-    *hops = 0;
+    if (!length) return fail(ctx, TPILU_E_INVAL, "null output");
+    *length = 0.0;
+    if (!(w_hop >= 0.0) || !(w_step >= 0.0) || w_hop > 1e12 || w_step > 1e12)
+        return fail(ctx, TPILU_E_INVAL, "weights must be finite and >= 0");
     if (pat->n == 0) return TPILU_OK;
     if (!pat->flow)
         return fail(ctx, TPILU_E_INVAL, "critical path: the rows of this pattern do not fit the dataflow kernel");
     DeviceGuard dg(ctx->device);
     TmpBufs T{pat->al, {}};
     double* h = (double*)T.get(sizeof(double) * (size_t)pat->nnz_f);
-    int32_t* mx = (int32_t*)T.get(64);
+    unsigned long long* mx = (unsigned long long*)T.get(64);
     if (!h || !mx) return fail(ctx, TPILU_E_NOMEM, "critical path workspace");
     hipStream_t s = ctx->stream;
     const int grid = ctx->grid_override ? ctx->grid_override
                                         : numeric_grid(1, pat->st.max_row, pat->st.max_lrow, true, ctx->num_cu);
     HIPCHK(ctx, launch_fill_pending(h, pat->nnz_f, pat->ctl, true, s));
     HIPCHK(ctx, launch_numeric_hops(pdev(ctx, pat), h, pat->ctl, ctx->spin_limit, grid, pat->st.max_row,
-                                    pat->st.max_lrow, s));
-    HIPCHK(ctx, launch_fill_i32(mx, 1, 0, s));
-    HIPCHK(ctx, launch_max_count(h, pat->nnz_f, mx, s));
-    HIPCHK(ctx, hipMemcpyAsync(hops, mx, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    return read_ctl(ctx, pat, nullptr, false);
+                                    pat->st.max_lrow, w_hop, w_step, s));
+    HIPCHK(ctx, launch_fill_i32((int32_t*)mx, 2, 0, s));
+    HIPCHK(ctx, launch_max_nonneg(h, pat->nnz_f, mx, s));
+    unsigned long long bits = 0ull;
+    HIPCHK(ctx, hipMemcpyAsync(&bits, mx, sizeof(bits), hipMemcpyDeviceToHost, s));
+    st = read_ctl(ctx, pat, nullptr, false);
+    double v = 0.0;
+    std::memcpy(&v, &bits, sizeof(v));
+    *length = v;
+    return st;
 }
 
 extern "C" TPILU_API tpilu_status tpilu_handoff_probe(tpilu_ctx ctx, int32_t same_xcd, int32_t rounds,

@@ -145,6 +145,9 @@ def test_critical_path_and_handoff_probe():
         for k in (0, 2):
             pat = T.symbolic(g(rp), g(col), k)
             assert T.numeric_critical_path(pat) == n - 1, k
+            # one l per row on the chain: l_{j,j-1} waits for u_{j-1,j-1}
+            assert T.numeric_critical_path(pat, 0.0, 1.0) == n - 1, k
+            assert T.numeric_critical_path(pat, 2.0, 0.5) == 2.5 * (n - 1), k
         pat = T.symbolic(g(np.arange(n + 1, dtype=np.int64)), g(np.arange(n, dtype=np.int32)), 0)
         assert T.numeric_critical_path(pat) == 0
     finally:
