@@ -137,7 +137,9 @@ TPILU_API tpilu_status tpilu_ctx_set_numeric(tpilu_ctx ctx, int mode);
  * device; a solve on one XCD when its device-wide shape would take at most
  * 256 wavefronts, i.e. a dependency level holds fewer than 32 rows, or fewer
  * than 64 short ones, and a row half at most 128 entries on average),
- * 1 = the whole device, 2 = one XCD.  On one XCD, grid wavefronts are
+ * 1 = the whole device, 2 = one XCD (then also the dependency-level
+ * computation of tpilu_symbolic, one XCD per dependency graph, when its
+ * nodes have long dependency lists).  On one XCD, grid wavefronts are
  * launched per XCD; the first workgroup to start names its XCD and the
  * workgroups of the other XCDs exit at once.  Values are then handed from
  * row to row through that XCD's L2 (ordinary stores, agent-scope loads)

@@ -249,12 +249,14 @@ __global__ __launch_bounds__(64) void k_apply_inverse_wave(PatDev P, const doubl
 // entries of 64 / kTile rows), then every lane walks its own row there: the
 // in-order sum of a row is one lane's chain, so the wavefront's 64 chains run
 // side by side instead of one at a time.
-constexpr int kTile = 16;
-constexpr int kTileStride = kTile + 1;  // odd stride: lanes reading their rows hit distinct banks
-
-template <bool kUpper>
+// kTile entries per row per staging round: 8 for short rows (a round of 16
+// mostly stages nothing; 7-point 64^3 ILU(1), about 6 entries per half:
+// 0.021 ms with 8, 0.042 with 16, both products), else 16 (27-point 50^3
+// ILU(3), about 82 per half: 0.134 ms with 16, 0.149 with 8, 0.228 with 32).
+template <bool kUpper, int kTile>
 __global__ __launch_bounds__(64) void k_apply_inverse_tile(PatDev P, const double* __restrict__ G,
                                                       const double* __restrict__ in, double* __restrict__ out) {
+    constexpr int kTileStride = kTile + 1;  // odd stride: lanes reading their rows hit distinct banks
     __shared__ double tv[kWave * kTileStride];
     __shared__ int32_t tc[kWave * kTileStride];
     const int lane = lane_id();
@@ -326,10 +328,15 @@ hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const doub
         const int grid = (P.n + 255) / 256;
         hipLaunchKernelGGL(k_apply_inverse_rows<false>, dim3(grid), dim3(256), 0, s, P, g_val, b, x);
         hipLaunchKernelGGL(k_apply_inverse_rows<true>, dim3(grid), dim3(256), 0, s, P, g_val, x, y);
-    } else if (shape == kProdTile) {
+    } else if (shape == kProdTile || shape == kProdTileShort) {
         const int grid = std::min((P.n + kWave - 1) / kWave, 65536);
-        hipLaunchKernelGGL(k_apply_inverse_tile<false>, dim3(grid), dim3(64), 0, s, P, g_val, b, x);
-        hipLaunchKernelGGL(k_apply_inverse_tile<true>, dim3(grid), dim3(64), 0, s, P, g_val, x, y);
+        if (shape == kProdTileShort) {
+            hipLaunchKernelGGL((k_apply_inverse_tile<false, 8>), dim3(grid), dim3(64), 0, s, P, g_val, b, x);
+            hipLaunchKernelGGL((k_apply_inverse_tile<true, 8>), dim3(grid), dim3(64), 0, s, P, g_val, x, y);
+        } else {
+            hipLaunchKernelGGL((k_apply_inverse_tile<false, 16>), dim3(grid), dim3(64), 0, s, P, g_val, b, x);
+            hipLaunchKernelGGL((k_apply_inverse_tile<true, 16>), dim3(grid), dim3(64), 0, s, P, g_val, x, y);
+        }
     } else {
         const int grid = std::min(P.n, 65536);
         hipLaunchKernelGGL(k_apply_inverse_wave<false>, dim3(grid), dim3(64), 0, s, P, g_val, b, x);

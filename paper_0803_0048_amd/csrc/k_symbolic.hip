@@ -466,10 +466,19 @@ hipError_t launch_a2f(int32_t n, const int64_t* rpA, const int32_t* ciA, const i
 // for every t > h stored in both rows, in ascending t.  Phase II replays them
 // (f_jt <- f_jt - f_jh * f_ht); their number is the number of updates.
 // One wavefront per row j; row j's columns are staged in LDS and every
-// candidate t of the pivot row is binary-searched there.
+// candidate t of the pivot row is binary-searched there, inside one bucket of
+// a directory over [c_min, c_max].  A column's bucket is (t - c_min) * mul >>
+// 24 with mul = floor(kSchedDir * 2^24 / range), computed once per row (the
+// same monotone map builds the directory and finds the bucket, so no
+// candidate is missed); a 64-bit division per candidate cost more than the
+// search itself.
 // ------------------------------------------------------------------------------------
 constexpr int kSchedDir = 256;   // buckets of the column directory of row j
 constexpr int kSchedUnroll = 8;  // 64-column chunks of a pivot row loaded per round
+
+__device__ __forceinline__ int32_t sched_bucket(int64_t off, uint64_t mul) {
+    return static_cast<int32_t>((static_cast<uint64_t>(off) * mul) >> 24);
+}
 
 __global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restrict__ rpF,
                                               const int32_t* __restrict__ ciF,
@@ -496,12 +505,15 @@ __global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restri
         wave_sync();
         const int32_t cmin = colsj[0];
         const int64_t range = (int64_t)colsj[len - 1] - cmin + 1;
+        // off < range < 2^31 and mul <= 2^32: the product fits in 64 bits,
+        // and the bucket of any off < range is below kSchedDir
+        const uint64_t mul = ((uint64_t)kSchedDir << 24) / (uint64_t)range;
         for (int32_t b = lane; b <= kSchedDir; b += kWave) {
             // first position whose bucket is >= b
             int32_t lo = 0, hi = len;
             while (lo < hi) {
                 const int32_t mid = (lo + hi) >> 1;
-                const int64_t bm = ((int64_t)colsj[mid] - cmin) * kSchedDir / range;
+                const int64_t bm = sched_bucket((int64_t)colsj[mid] - cmin, mul);
                 if (bm < b) lo = mid + 1;
                 else hi = mid;
             }
@@ -539,7 +551,7 @@ __global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restri
                         const int64_t off = (int64_t)tv[u] - cmin;
                         if (q < he && off >= 0 && off < range) {
                             const int32_t t = tv[u];
-                            const int32_t b = static_cast<int32_t>(off * kSchedDir / range);
+                            const int32_t b = sched_bucket(off, mul);
                             int32_t lo = max(lo0, dir[b]), hi = dir[b + 1] - 1;
                             while (lo <= hi) {
                                 const int32_t mid = (lo + hi) >> 1;
@@ -701,6 +713,10 @@ __device__ __forceinline__ bool level_watchdog(uint32_t& polls, uint64_t& t0, Ct
 // round re-polls all of a chunk's unknown dependencies at once.
 constexpr int kLevelPer = 4;  // dependencies per lane and chunk
 
+// S == Scope::Xcd: every wavefront of the job runs on one XCD and the levels
+// are stored with workgroup scope (they stay in that XCD's L2, where the
+// agent-scope polls of the job's other wavefronts find them)
+template <Scope S>
 __device__ __forceinline__ void level_row(const DepGraph& G, int32_t* depth, Ctl* ctl, uint64_t limit, int32_t i) {
     const int lane = lane_id();
     int64_t a, b;
@@ -743,17 +759,29 @@ __device__ __forceinline__ void level_row(const DepGraph& G, int32_t* depth, Ctl
         }
     }
     for (int off = 32; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off));
-    if (lane == 0) __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) {
+        if constexpr (S == Scope::Xcd)
+            __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
+// S == Scope::Xcd: each job elects its own XCD through its control block (the
+// first of its workgroups to start names it); the job's workgroups elsewhere
+// leave at once
+template <Scope S>
 __global__ __launch_bounds__(64) void k_depth(int32_t n, LevelJob j0, LevelJob j1, int32_t njobs, Ctl* ctl,
                                               uint64_t spin_limit) {
     const LevelJob J = (njobs > 1 && (blockIdx.x & 1)) ? j1 : j0;
+    if constexpr (S == Scope::Xcd) {
+        if (!xcd_member(J.tctl)) return;
+    }
     for (;;) {
         const uint32_t t = wave_ticket(J.tctl);
         if (t >= (uint32_t)n) break;
         const int32_t i = J.desc ? n - 1 - (int32_t)t : (int32_t)t;
-        level_row(J.G, J.depth, ctl, spin_limit, i);
+        level_row<S>(J.G, J.depth, ctl, spin_limit, i);
     }
 }
 
@@ -838,14 +866,18 @@ hipError_t launch_level_order(int32_t n, const int32_t* depth, int32_t max_depth
 }
 
 hipError_t launch_depth(int32_t n, const LevelJob& j0, const LevelJob* j1, Ctl* ctl, uint64_t spin_limit,
-                        int32_t grid, hipStream_t s) {
+                        int32_t grid, bool one_xcd, hipStream_t s) {
     if (n <= 0 || grid == 0) return hipSuccess;
     const int32_t njobs = j1 ? 2 : 1;
     const LevelJob b = j1 ? *j1 : j0;
     if (grid < 0)
         hipLaunchKernelGGL(k_depth_lanes, dim3(-grid * njobs), dim3(64), 0, s, n, j0, b, njobs, ctl, spin_limit);
+    else if (one_xcd)
+        hipLaunchKernelGGL(k_depth<Scope::Xcd>, dim3(grid * njobs * kXcds), dim3(64), 0, s, n, j0, b, njobs, ctl,
+                           spin_limit);
     else
-        hipLaunchKernelGGL(k_depth, dim3(grid * njobs), dim3(64), 0, s, n, j0, b, njobs, ctl, spin_limit);
+        hipLaunchKernelGGL(k_depth<Scope::Device>, dim3(grid * njobs), dim3(64), 0, s, n, j0, b, njobs, ctl,
+                           spin_limit);
     return hipGetLastError();
 }
 

@@ -81,9 +81,10 @@ struct LevelJob {
 // level of every node (1 + max level of its dependencies) for one job, or two
 // independent jobs in one launch (alternate wavefronts; j1 may be null).
 // grid > 0: wavefront per node, grid < 0: lane per node; |grid| wavefronts
-// per job.  Abort and watchdog state live in ctl.
+// per job (one_xcd, wavefront per node: grid wavefronts per XCD launched,
+// those of one XCD per job working).  Abort and watchdog state live in ctl.
 hipError_t launch_depth(int32_t n, const LevelJob& j0, const LevelJob* j1, Ctl* ctl, uint64_t spin_limit,
-                        int32_t grid, hipStream_t s);
+                        int32_t grid, bool one_xcd, hipStream_t s);
 // perm = nodes sorted by level (counting sort); hist needs 2 * max_depth ints
 hipError_t launch_level_order(int32_t n, const int32_t* depth, int32_t max_depth, int32_t* hist,
                               int64_t* off, int64_t* scan_tmp, int32_t* perm, hipStream_t s);
@@ -254,7 +255,8 @@ hipError_t launch_inverse(const PatDev& P, const InvSched& S, const double* f_va
                           Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s);
 // x = L~~^-1 b, y = U~~^-1 x; thread_rows: one thread per row, else a wavefront
 // shapes of the two products of the incomplete inverses
-enum { kProdWaveRows = 0, kProdThreadRows = 1, kProdTile = 2 };
+// (kProdTile stages 16 entries per row and round, kProdTileShort 8)
+enum { kProdWaveRows = 0, kProdThreadRows = 1, kProdTile = 2, kProdTileShort = 3 };
 hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const double* b, double* x, double* y,
                                 int shape, hipStream_t s);
 

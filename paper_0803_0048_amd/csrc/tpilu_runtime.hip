@@ -578,7 +578,13 @@ tpilu_status enqueue_levels(tpilu_ctx ctx, tpilu_pattern pat, const LevelSpec* j
     }
     HIPCHK(ctx, launch_fill_pending(nullptr, 0, pat->ctl, true, s));
     HIPCHK(ctx, launch_fill_pending(nullptr, 0, ctl2, false, s));
-    HIPCHK(ctx, launch_depth(n, jb[0], njobs > 1 ? &jb[1] : nullptr, pat->ctl, ctx->spin_limit, grid, s));
+    // one XCD per DAG only when the placement setting asks for it: on its own
+    // the level kernel gains there (random banded n=160,000 ILU(2): 14.9 ->
+    // 9.6 ms), but it runs beside the update schedule, whose launches on the
+    // same XCDs then slow down (6.2 -> 11 ms), and Phase I as a whole gains
+    // nothing (27.2 vs 30.1 ms; 27-point 50^3 ILU(3) 50.1 vs 53.0 ms)
+    const bool lv_xcd = grid > 0 && ctx->placement == 2;
+    HIPCHK(ctx, launch_depth(n, jb[0], njobs > 1 ? &jb[1] : nullptr, pat->ctl, ctx->spin_limit, grid, lv_xcd, s));
     HIPCHK(ctx, launch_fill_i32(dmax, 32, 0, s));
     for (int q = 0; q < njobs; ++q) {
         HIPCHK(ctx, launch_max_i32(js[q].depth, n, dmax + 16 * q, s));
@@ -620,12 +626,14 @@ tpilu_status compute_levels(tpilu_ctx ctx, tpilu_pattern pat, const LevelSpec* j
 // 419): 0.29 ms by wavefront, 0.35 tiled; paper-scale ILU(1), 1,276 per row:
 // 1.9 ms by wavefront, 2.8 tiled.
 constexpr int64_t kInvTileMaxAvg = 512;
+constexpr int64_t kInvShortAvg = 24;  // entries per row of F at or below: 8-entry tiles
 int inverse_product_shape(tpilu_ctx ctx, tpilu_pattern pat) {
     if (ctx->solver == 1) return kProdWaveRows;
     if (ctx->solver == 3) return kProdThreadRows;
     const int64_t n = std::max<int64_t>(pat->n, 1);
     const bool even = 2 * (int64_t)pat->st.max_row * n <= 3 * pat->nnz_f;
-    return even && pat->nnz_f <= kInvTileMaxAvg * n ? kProdTile : kProdWaveRows;
+    if (!even || pat->nnz_f > kInvTileMaxAvg * n) return kProdWaveRows;
+    return pat->nnz_f <= kInvShortAvg * n ? kProdTileShort : kProdTile;
 }
 
 tpilu_status build_inverse_sched(tpilu_ctx ctx, tpilu_pattern pat) {

@@ -291,6 +291,23 @@ def test_config3_gmres_and_bicgstab(k):
     assert_bits_equal(x, r["x"], "BiCGSTAB x")
 
 
+def test_levels_on_one_xcd():
+    """The dependency levels computed on one XCD per graph (placement 2)
+    give the same pattern, schedules and factor bits as device-wide."""
+    c = I.random_banded_ilu2(n=20_000)
+    A = c["A"]
+    ctx = T.context(0)
+    ref = T.numeric(T.symbolic(g(A.rowptr), g(A.col), 2), g(A.val))
+    ctx.set_placement(ctx.PLACE_XCD)
+    try:
+        pat = T.symbolic(g(A.rowptr), g(A.col), 2)
+    finally:
+        ctx.set_placement(0)
+    rpF, ciF, lvF = O.symbolic(A.n, A.rowptr, A.col, 2)
+    check_pattern(pat, rpF, ciF, lvF, A)
+    assert_bits_equal(T.numeric(pat, g(A.val)), ref, "F with levels from one XCD")
+
+
 def test_repeatable_across_launch_shapes():
     """Same bits for any number of wavefronts (race check by repetition)."""
     c = I.conv_diff_2d_64x64_ilu1()
