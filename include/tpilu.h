@@ -109,8 +109,10 @@ TPILU_API tpilu_status tpilu_ctx_set_grid(tpilu_ctx ctx, int32_t waves);
  * (lane per row when a triangle's rows hold at most 40 entries on average
  * and a dependency level at least max(64, 16 x that average) rows, else a
  * wavefront per row), 1 = a wavefront per row (on the whole device or on
- * one XCD, see tpilu_ctx_set_placement), 2 = one workgroup (16 wavefronts on one CU), 3 = a lane per row (64 rows per
- * wavefront) over the whole device.  The same setting picks the shape of the
+ * one XCD, see tpilu_ctx_set_placement), 2 = one workgroup on one CU (a lane
+ * per row, rows handed over through an LDS ring; measured far slower than
+ * mode 1 on every workload tried, kept as the alternative shape), 3 = a lane
+ * per row (64 rows per wavefront) over the whole device.  The same setting picks the shape of the
  * two products of tpilu_apply_inverse: 1 a wavefront per row, 3 a thread per
  * row, 0 automatic (64 rows per wavefront staged through LDS when the
  * longest row of F is at most 1.5 x the average and the average at most 512

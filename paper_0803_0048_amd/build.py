@@ -23,7 +23,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpilu.so")
-SOURCES = ["k_symbolic.hip", "k_numeric.hip", "k_solve.hip", "k_krylov.hip", "k_adjoint.hip",
+SOURCES = ["k_symbolic.hip", "k_numeric.hip", "k_solve.hip", "k_solve_cu.hip", "k_krylov.hip", "k_adjoint.hip",
            "k_inverse.hip", "k_probe.hip", "tpilu_runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

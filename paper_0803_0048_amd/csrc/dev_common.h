@@ -173,6 +173,11 @@ __device__ __forceinline__ void trace_mark(unsigned long long* trace, int64_t sl
     if (trace && lane_id() == 0) trace[slot] = wall_clock64();
 }
 
+// per-lane form of trace_mark (the lane's own row)
+__device__ __forceinline__ void trace_mark_lane(unsigned long long* trace, int64_t slot, bool on) {
+    if (trace && on) trace[slot] = wall_clock64();
+}
+
 // Value that is the same in every lane, made visibly uniform (SGPR) for the
 // compiler.  Only call with all lanes active.
 __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }

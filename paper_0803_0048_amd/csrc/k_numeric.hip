@@ -425,16 +425,26 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
                 // one round trip for every lane's pending inputs
                 bool got = false;
                 if (have) {
+                    // the indices first (LDS, all together), then every load:
+                    // no LDS round trip between two loads of one round
                     bool need[kFlowLook];
+                    int32_t qi[kFlowLook];
                     uint64_t v[kFlowLook];
 #pragma unroll
                     for (int u = 0; u < kFlowLook; ++u) {
                         const int32_t x = e + u;
-                        need[u] = x < ee && Sv[x] == kPending;
-                        v[u] = need[u] ? ld_coherent(F + Sq[x]) : kPending;
+                        const bool in = x < ee;
+                        const int32_t xi = in ? x : 0;  // a staged index either way; unused when !in
+                        const uint64_t sv = Sv[xi];
+                        qi[u] = Sq[xi];
+                        need[u] = in && sv == kPending;
                     }
-                    const bool needu = p < dl && Ud[p] == kPending;
-                    const uint64_t vu = needu ? ld_coherent(F + Uq[p]) : kPending;
+                    const bool inl = p < dl;
+                    const int32_t uq = Uq[inl ? p : 0];
+                    const bool needu = inl && Ud[inl ? p : 0] == kPending;
+#pragma unroll
+                    for (int u = 0; u < kFlowLook; ++u) v[u] = need[u] ? ld_coherent(F + qi[u]) : kPending;
+                    const uint64_t vu = needu ? ld_coherent(F + uq) : kPending;
 #pragma unroll
                     for (int u = 0; u < kFlowLook; ++u)
                         if (need[u] && v[u] != kPending) { Sv[e + u] = v[u]; got = true; }

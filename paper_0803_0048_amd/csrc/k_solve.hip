@@ -14,9 +14,9 @@
 // advancing as the needed values arrive, which keeps every bit of the
 // sequential result.  With these orders the value that arrives last (the
 // nearest row) is the last term of the chain.  Two launch shapes give the
-// same bits: a persistent grid over the whole device (rows handed out by
-// atomic task counters) and a single workgroup whose 16 wavefronts share one
-// CU; for wide levels of short rows also a lane per row.
+// same bits: a persistent grid over the whole device or one XCD (rows handed
+// out by atomic task counters), and for wide levels of short rows a lane per
+// row (the one-CU shape for deep, narrow graphs is in k_solve_cu.hip).
 // For batches the lanes are instances and each lane runs its own chain.
 // x and y start as kPending and each slot is written once.
 #include "kernels.h"
@@ -113,29 +113,6 @@ __global__ __launch_bounds__(64) void k_backward_row(PatDev P, const double* __r
         if (!next_pos(ctl, (uint32_t)P.n, (uint32_t)P.groupU, parts, run, t)) break;
         backward_row<S>(P, F, x, y, ctl, spin_limit, P.permU ? P.permU[t] : P.n - 1 - (int32_t)t);
     }
-}
-
-// one workgroup (one CU, 16 wavefronts): for dependency graphs that are deep
-// and narrow, the hand-off through the CU's own caches is several times
-// cheaper than a round trip across XCDs.  Rows are dealt round-robin; all
-// wavefronts are resident, so the smallest unfinished row is always being
-// worked on and the sweep cannot deadlock.
-__global__ __launch_bounds__(1024) void k_forward_wg(PatDev P, const double* __restrict__ F,
-                                                     const double* __restrict__ b, double* x,
-                                                     Ctl* ctl, uint64_t spin_limit) {
-    const int32_t wave = uniform((int32_t)(threadIdx.x >> 6));
-    const int32_t nw = (int32_t)(blockDim.x >> 6);
-    for (int32_t r = wave; r < P.n; r += nw)
-        forward_row<Scope::Workgroup>(P, F, b, x, ctl, spin_limit, P.permL ? P.permL[r] : r);
-}
-
-__global__ __launch_bounds__(1024) void k_backward_wg(PatDev P, const double* __restrict__ F,
-                                                      const double* __restrict__ x, double* y,
-                                                      Ctl* ctl, uint64_t spin_limit) {
-    const int32_t wave = uniform((int32_t)(threadIdx.x >> 6));
-    const int32_t nw = (int32_t)(blockDim.x >> 6);
-    for (int32_t r = wave; r < P.n; r += nw)
-        backward_row<Scope::Workgroup>(P, F, x, y, ctl, spin_limit, P.permU ? P.permU[r] : P.n - 1 - r);
 }
 
 // lane per row, for wide dependency graphs of short rows (many rows per level,
@@ -357,15 +334,13 @@ __global__ __launch_bounds__(64) void k_backward_batch(PatDev P, const double* _
 }
 
 // single instance: grid > 0 wavefront per row (one_xcd: grid wavefronts per
-// XCD launched, those of one XCD working), grid == 0 one workgroup, grid < 0
-// lane per row with -grid wavefronts
+// XCD launched, those of one XCD working), grid < 0 lane per row with -grid
+// wavefronts (the one-workgroup shape is launch_solve_cu)
 hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, const double* b,
                           double* x, Ctl* ctl, uint64_t spin_limit, int32_t grid, bool one_xcd,
                           hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    if (batch == 1 && grid == 0)
-        hipLaunchKernelGGL(k_forward_wg, dim3(1), dim3(1024), 0, s, P, f_val, b, x, ctl, spin_limit);
-    else if (batch == 1 && grid < 0)
+    if (batch == 1 && grid < 0)
         hipLaunchKernelGGL(k_solve_lanes<false>, dim3(-grid), dim3(64), 0, s, P, f_val, b, x, ctl, spin_limit);
     else if (batch == 1 && one_xcd)
         hipLaunchKernelGGL(k_forward_row<Scope::Xcd>, dim3(grid * kXcds), dim3(64), 0, s, P, f_val, b, x, ctl,
@@ -383,9 +358,7 @@ hipError_t launch_backward(const PatDev& P, const double* f_val, int32_t batch, 
                            double* y, Ctl* ctl, uint64_t spin_limit, int32_t grid, bool one_xcd,
                            hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
-    if (batch == 1 && grid == 0)
-        hipLaunchKernelGGL(k_backward_wg, dim3(1), dim3(1024), 0, s, P, f_val, x, y, ctl, spin_limit);
-    else if (batch == 1 && grid < 0)
+    if (batch == 1 && grid < 0)
         hipLaunchKernelGGL(k_solve_lanes<true>, dim3(-grid), dim3(64), 0, s, P, f_val, x, y, ctl, spin_limit);
     else if (batch == 1 && one_xcd)
         hipLaunchKernelGGL(k_backward_row<Scope::Xcd>, dim3(grid * kXcds), dim3(64), 0, s, P, f_val, x, y,

@@ -146,14 +146,25 @@ size_t tsched_lds_bytes(int32_t max_row, int32_t max_lrow);
 
 // ---- triangular solves -------------------------------------------------------------
 // single instance: grid > 0 wavefront per row (one_xcd: grid wavefronts on
-// one XCD), 0 one workgroup, < 0 lane per row with -grid wavefronts;
-// batches: lanes = instances with grid wavefronts
+// one XCD), < 0 lane per row with -grid wavefronts (the one-CU shape is
+// launch_solve_cu); batches: lanes = instances with grid wavefronts
 hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, const double* b,
                           double* x, Ctl* ctl, uint64_t spin_limit, int32_t grid, bool one_xcd,
                           hipStream_t s);
 hipError_t launch_backward(const PatDev& P, const double* f_val, int32_t batch, const double* x,
                            double* y, Ctl* ctl, uint64_t spin_limit, int32_t grid, bool one_xcd,
                            hipStream_t s);
+
+// ---- the solves on one CU (lane per row, hand-off through an LDS ring) ----------
+// Pq[slot] = level-order position of the row named by the slot's column
+// (forward order for strict lower slots, backward order for upper ones)
+hipError_t launch_dep_positions(int32_t n, const int64_t* rpF, const int32_t* ciF, const int32_t* diagF,
+                                const int32_t* permL, const int32_t* permU, int32_t* iposL, int32_t* iposU,
+                                int32_t* Pq, hipStream_t s);
+// forward (x = L~^-1 b: in = b, out = x) or backward (y = U~^-1 x: in = x,
+// out = y), single instance, one workgroup; out needs no pending fill
+hipError_t launch_solve_cu(const PatDev& P, const int32_t* Pq, const double* f_val, const double* in, double* out,
+                           bool backward, Ctl* ctl, uint64_t spin_limit, hipStream_t s);
 
 // ---- Krylov building blocks ---------------------------------------------------
 constexpr int kDotLanes = 16384;  // fixed shape of every inner product

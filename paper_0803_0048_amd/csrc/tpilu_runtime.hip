@@ -258,6 +258,11 @@ struct tpilu_pattern_s {
     int64_t* iptr = nullptr;
     int32_t *is_s = nullptr, *is_q = nullptr;
     int64_t n_inv_updates = 0;
+    // per F slot, the level-order position of the row its column names (the
+    // one-CU solves); built with the pattern when those are the automatic
+    // choice, else on first use
+    int32_t* dep_pos = nullptr;
+    bool solve_cu = false;  // the automatic solve shape is the one-CU one
     // target-major update schedule (only when the dataflow numeric kernel fits)
     bool flow = false;
     int64_t* tptr = nullptr;
@@ -467,7 +472,7 @@ constexpr int64_t kLaneWidthPerEntry = 16;  // ... and at or above this many per
 constexpr int32_t kLaneWaves = 128;
 
 struct SolveShape {
-    int32_t grid;
+    int32_t grid;  // 0: one CU (launch_solve_cu)
     bool one_xcd;
 };
 
@@ -503,22 +508,37 @@ SolveShape solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool bac
 
 tpilu_status enqueue_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val, int32_t batch,
                            const double* b, double* y, double* x, bool reset, Ctl* ctl, bool timed = true) {
-    const SolveShape gf = solve_shape(ctx, pat, batch, false), gb = solve_shape(ctx, pat, batch, true);
+    SolveShape gf = solve_shape(ctx, pat, batch, false), gb = solve_shape(ctx, pat, batch, true);
+    // the one-CU shape needs the dependency positions; without them (never
+    // built, and this call may not allocate) the wavefront-per-row shape runs
+    if (!pat->dep_pos) {
+        if (gf.grid == 0) gf = {kSolveWavesNarrow, true};
+        if (gb.grid == 0) gb = {kSolveWavesNarrow, true};
+    }
     const PatDev P = pdev(ctx, pat, RowKernel::Solve, true);
-    HIPCHK(ctx, launch_fill_pending(x, pat->n * batch, ctl, reset, ctx->stream));
+    // the one-CU kernel hands values over through LDS and needs no pending
+    // marks in the output; the control block is reset all the same
+    HIPCHK(ctx, launch_fill_pending(x, gf.grid == 0 ? 0 : pat->n * batch, ctl, reset, ctx->stream));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_FORWARD, timed);
-        HIPCHK(ctx, launch_forward(P, f_val, batch, b, x, ctl, ctx->spin_limit, gf.grid, gf.one_xcd,
-                                   ctx->stream));
+        if (gf.grid == 0)
+            HIPCHK(ctx, launch_solve_cu(P, pat->dep_pos, f_val, b, x, false, ctl, ctx->spin_limit, ctx->stream));
+        else
+            HIPCHK(ctx, launch_forward(P, f_val, batch, b, x, ctl, ctx->spin_limit, gf.grid, gf.one_xcd,
+                                       ctx->stream));
     }
-    HIPCHK(ctx, launch_fill_pending(y, pat->n * batch, ctl, false, ctx->stream));
+    HIPCHK(ctx, launch_fill_pending(y, gb.grid == 0 ? 0 : pat->n * batch, ctl, false, ctx->stream));
     {
         TimedLaunch tl(ctx, TPILU_KERNEL_BACKWARD, timed);
-        HIPCHK(ctx, launch_backward(P, f_val, batch, x, y, ctl, ctx->spin_limit, gb.grid, gb.one_xcd,
-                                    ctx->stream));
+        if (gb.grid == 0)
+            HIPCHK(ctx, launch_solve_cu(P, pat->dep_pos, f_val, x, y, true, ctl, ctx->spin_limit, ctx->stream));
+        else
+            HIPCHK(ctx, launch_backward(P, f_val, batch, x, y, ctl, ctx->spin_limit, gb.grid, gb.one_xcd,
+                                        ctx->stream));
     }
     return TPILU_OK;
 }
+
 
 // temporaries released when the enclosing call returns
 struct TmpBufs {
@@ -531,6 +551,23 @@ struct TmpBufs {
     }
     ~TmpBufs() { for (void* p : v) al.put(p); }
 };
+
+// Per F slot, the level-order position of the row its column names, for the
+// one-CU solves.
+tpilu_status build_dep_positions(tpilu_ctx ctx, tpilu_pattern pat) {
+    if (pat->dep_pos || pat->n == 0) return TPILU_OK;
+    const int32_t n = (int32_t)pat->n;
+    TmpBufs T{pat->al, {}};
+    int32_t* ipl = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);
+    int32_t* ipu = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);
+    int32_t* pq = (int32_t*)pat->take(sizeof(int32_t) * (size_t)pat->nnz_f);
+    if (!ipl || !ipu || !pq) return fail(ctx, TPILU_E_NOMEM, "dependency positions");
+    HIPCHK(ctx, launch_dep_positions(n, pat->rpF, pat->ciF, pat->diagF, pat->permL, pat->permU, ipl, ipu, pq,
+                                     ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    pat->dep_pos = pq;
+    return TPILU_OK;
+}
 
 // Levels of one or two dependency DAGs (computed in one launch, so their
 // chains overlap) and their nodes sorted by level (the ticket order of the
@@ -1205,6 +1242,10 @@ extern "C" TPILU_API tpilu_status tpilu_apply(tpilu_ctx ctx, tpilu_pattern pat, 
         if (!x) return fail(ctx, TPILU_E_NOMEM, "apply workspace");
     }
     trace("apply", pat->n, batch);
+    if (batch == 1 && ctx->solver == 2) {
+        st = build_dep_positions(ctx, pat);
+        if (st) return st;
+    }
     return enqueue_apply(ctx, pat, f_val, batch, b, y, x, true, pat->ctl);
 }
 
