@@ -568,7 +568,10 @@ def batched_extra(T, I, torch, np, dev, ctx, oracle=True):
            "numeric_roofline": roof(mb["numeric"], statistics.median(num), "numeric (batched)"),
            "forward_roofline": roof(mb["forward"], statistics.median(fw), "forward (batched)"),
            "backward_roofline": roof(mb["backward"], statistics.median(bw), "backward (batched)"),
+           "graph_kernels": "fill F, fill x, factorization with the forward substitution fused in, fill y, "
+                            "backward substitution",
            "depth_l": info["depth_l"]}
+    res["long_rows"] = batched_long_rows(T, I, torch, np, dev, oracle=oracle)
     if oracle:
         import oracle as O
 
@@ -588,6 +591,48 @@ def batched_extra(T, I, torch, np, dev, ctx, oracle=True):
         ok = all(bits_equal(np, fh[:, i], outs[i][0]) and bits_equal(np, yh[:, i], outs[i][1]) for i in range(B))
         res["oracle"] = {"ms": oms, "cores": oracle_threads(), "what": "256 x (numeric + apply), one instance "
                          "per thread at a time, each sequential"}
+        res["bitwise_match_all_instances"] = ok
+    return res
+
+
+def batched_long_rows(T, I, torch, np, dev, oracle=True):
+    """70 x 27-point 20^3 ILU(2) (rows of up to 115 entries: the working rows
+    live in global memory) in one graph; roofline from the batched
+    algorithmic bytes; every instance against the oracle."""
+    log("batched: 70 x 27-point 20^3 ILU(2) in one graph (long rows)")
+    c = I.batched_stencil27_ilu(B=70, k=2)
+    A = c["A"]
+    pat = T.symbolic(torch.from_numpy(A.rowptr).to(dev), torch.from_numpy(A.col).to(dev), 2)
+    av = torch.from_numpy(A.val).to(dev)
+    bv = torch.from_numpy(c["b"]).to(dev)
+    graph = T.BatchedGraph(pat, av, bv)
+    graph.launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        graph.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    gms = e0.elapsed_time(e1) / reps
+    graph.check()
+    info = pat.info
+    B = A.batch
+    mb = model_bytes(info["n"], info["nnz_a"], info["nnz_f"], info["nnz_l"], B=B)
+    res = {"instances": B, "n": A.n, "nnz_f": info["nnz_f"], "max_row": info["max_row"], "graph_ms": gms,
+           "roofline": roof(mb["numeric"] + mb["apply"], gms, "graph: numeric + apply, 70 instances"),
+           "depth_l": info["depth_l"]}
+    if oracle:
+        import oracle as O
+
+        rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, 2)
+        fh, yh = graph.f_val.cpu().numpy(), graph.y.cpu().numpy()
+        ok = True
+        for i in range(B):
+            vF, _ = O.numeric(A.n, A.rowptr, A.col, np.ascontiguousarray(A.val[:, i]), rpF, ciF)
+            _, y = O.apply(A.n, rpF, ciF, vF, np.ascontiguousarray(c["b"][:, i]))
+            ok = ok and bits_equal(np, fh[:, i], vF) and bits_equal(np, yh[:, i], y)
         res["bitwise_match_all_instances"] = ok
     return res
 

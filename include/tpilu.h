@@ -249,6 +249,10 @@ TPILU_API void tpilu_pattern_destroy(tpilu_pattern pat);
  * the smallest row whose final pivot is +-0, or -1 (for batches: smallest
  * over all instances).  With bad_row == NULL the call does not wait and the
  * status of the device work is read later with tpilu_pattern_check.
+ * Batches (batch > 1) whose longest row of F has more than 80 entries keep
+ * each in-flight row in a global-memory workspace that the pattern owns and
+ * reuses (up to 1 GiB; fewer wavefronts when a row is very long), else in
+ * LDS; TPILU_E_NOMEM if it cannot be allocated.  Same bits either way.
  * ------------------------------------------------------------------------- */
 TPILU_API tpilu_status tpilu_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double *a_val,
                                      int32_t batch, double *f_val, int64_t *bad_row);
@@ -446,7 +450,8 @@ TPILU_API tpilu_status tpilu_numeric_adjoint(tpilu_ctx ctx, tpilu_pattern pat, c
  * y) for all `batch` instances, and instantiates the graph.  The device
  * arrays passed here are baked into the graph: each launch recomputes f_val
  * and y from the CURRENT contents of a_val and b.  The graph owns its
- * intermediate vector (n * batch doubles) and its control block, allocated
+ * intermediate vector (n * batch doubles), its control block and, for rows
+ * of more than 80 entries, its working rows (see tpilu_numeric), allocated
  * here and freed by tpilu_batched_graph_destroy, so later calls on the same
  * pattern never touch them; it reads the pattern's arrays, so the pattern
  * must outlive the graph.  Launch with tpilu_batched_graph_launch on any

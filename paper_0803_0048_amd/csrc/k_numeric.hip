@@ -503,11 +503,43 @@ constexpr int kBPivCap = 8;
 constexpr int kBPairCap = 32;
 constexpr int kBAChunk = 8;  // A entries loaded per round trip
 constexpr int kBLook = 8;    // pending pair values re-read per polling round
+constexpr int kBWChunk = 8;  // values loaded per round trip (global working rows, publish, fused forward)
 
+// kGW: the working row lives in global memory (a slice of wrow per
+// wavefront, wstride doubles each, same [len][64] layout) instead of LDS, for
+// rows too long for LDS.  A lane reads back only what it wrote itself, so
+// plain loads and stores in program order are enough.  The update loop then
+// reads a pivot's targets a chunk at a time before writing any (one pivot's
+// targets are distinct slots), so it pays one latency per chunk rather than
+// one per update.  (In LDS the same chunking measured slower.)
+//
+// xout non-null: the forward substitution (Eq. 3b) is fused in.  Once a row
+// has stored its factor, its lane computes x_j = b_j - sum of l_jh x_h over
+// the row's L slots in ascending order (the forward kernel's order, so the
+// same bits), from the l values still in the working row and the x_h that
+// the rows of its pivots published when they finished.  Those rows finished
+// before this one, so the extra wait is short and off the chain the factor's
+// dependents wait on (the row's U part is published first).
+template <bool kGW, Scope S>
 __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __restrict__ a_val,
                                                       int32_t B, double* F, Ctl* ctl,
-                                                      uint64_t spin_limit, int64_t skip_row) {
-    extern __shared__ double W[];  // [len][64]
+                                                      uint64_t spin_limit, int64_t skip_row,
+                                                      double* __restrict__ wrow, int64_t wstride,
+                                                      const double* __restrict__ bvec, double* xout) {
+    extern __shared__ double Wl[];  // [len][64]
+    if constexpr (S == Scope::Xcd) {
+        if (!xcd_member(ctl)) return;
+    }
+    const uint32_t parts = S == Scope::Xcd ? 1u : (uint32_t)P.parts;
+    // working-row slice: the block index, or on one XCD (where the members'
+    // block indices follow the hardware's dealing) a number drawn from
+    // ctl->ticket; members beyond the slices leave (the others do the work)
+    uint32_t slot = blockIdx.x;
+    if constexpr (kGW && S == Scope::Xcd) {
+        slot = wave_ticket(ctl);
+        if (slot >= gridDim.x / kXcds) return;
+    }
+    double* const W = kGW ? wrow + (int64_t)slot * wstride : Wl;
     __shared__ int32_t piv_e[kBPivCap + 1];
     __shared__ int32_t piv_dh[kBPivCap];
     __shared__ int32_t pr_q[kBPairCap];
@@ -521,7 +553,7 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
+        if (!next_pos(ctl, ntask, 1u, parts, run, t)) break;
         const int32_t jr = (int32_t)(t / (uint32_t)G);
         const int32_t j = P.permL ? P.permL[jr] : jr;
         const int32_t g = (int32_t)(t % (uint32_t)G);
@@ -602,24 +634,51 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
                 // kBLook of its pending pairs together (one round trip), so a
                 // pivot row that has just been published costs one latency,
                 // not one per value.
+                // State of pivot i, carried across polling rounds: its pair
+                // range [ea, eb), whether its diagonal is final (ur) and the
+                // first pair not yet final (ep).  A round advances ep over the
+                // values it brought, in registers, without rescanning LDS.
                 int32_t i = 0;
                 uint32_t polls = 0;
                 uint64_t t0 = 0;
+                int32_t ea = piv_e[0], eb = piv_e[1];
+                bool ur = vu[lane] != kPending;
+                int32_t ep = ea;
+                while (ep < eb && vv[ep * kWave + lane] != kPending) ++ep;
                 while (i < np) {
-                    const int32_t ea = piv_e[i], eb = piv_e[i + 1];
-                    const bool ur = vu[i * kWave + lane] != kPending;
-                    int32_t ep = ea;
-                    while (ep < eb && vv[ep * kWave + lane] != kPending) ++ep;
                     if (ur && ep == eb) {
                         const int64_t sl = s0 + i - rs;
                         const double l = W[sl * kWave + lane] / as_f64(vu[i * kWave + lane]);
                         W[sl * kWave + lane] = l;
-                        for (int32_t e = ea; e < eb; ++e) {
-                            const int32_t p = pr_p[e];
-                            W[p * kWave + lane] = W[p * kWave + lane] - l * as_f64(vv[e * kWave + lane]);
+                        if (kGW) {
+                            for (int32_t c = ea; c < eb; c += kBWChunk) {
+                                double w[kBWChunk];
+                                int32_t pc[kBWChunk];
+#pragma unroll
+                                for (int u = 0; u < kBWChunk; ++u) {
+                                    pc[u] = pr_p[std::min(c + u, eb - 1)];
+                                    w[u] = W[pc[u] * kWave + lane];
+                                }
+#pragma unroll
+                                for (int u = 0; u < kBWChunk; ++u)
+                                    if (c + u < eb)
+                                        W[pc[u] * kWave + lane] = w[u] - l * as_f64(vv[(c + u) * kWave + lane]);
+                            }
+                        } else {
+                            for (int32_t e = ea; e < eb; ++e) {
+                                const int32_t p = pr_p[e];
+                                W[p * kWave + lane] = W[p * kWave + lane] - l * as_f64(vv[e * kWave + lane]);
+                            }
                         }
                         ++i;
                         polls = 0;
+                        if (i < np) {
+                            ea = eb;
+                            eb = piv_e[i + 1];
+                            ur = vu[i * kWave + lane] != kPending;
+                            ep = ea;
+                            while (ep < eb && vv[ep * kWave + lane] != kPending) ++ep;
+                        }
                         continue;
                     }
                     const double* du = F + (int64_t)piv_dh[i] * B + col;
@@ -631,10 +690,20 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
                         // entries past the pivot's pairs read the diagonal's line again
                         nv[k] = ld_coherent(e < eb ? F + (int64_t)pr_q[e] * B + col : du);
                     }
-                    if (!ur && nu != kPending) vu[i * kWave + lane] = nu;
+                    if (!ur && nu != kPending) {
+                        vu[i * kWave + lane] = nu;
+                        ur = true;
+                    }
+                    int32_t adv = 0;
 #pragma unroll
-                    for (int k = 0; k < kBLook; ++k)
-                        if (ep + k < eb && nv[k] != kPending) vv[(ep + k) * kWave + lane] = nv[k];
+                    for (int k = 0; k < kBLook; ++k) {
+                        const bool fin = ep + k < eb && nv[k] != kPending;
+                        if (fin) vv[(ep + k) * kWave + lane] = nv[k];
+                        if (fin && adv == k) adv = k + 1;
+                    }
+                    ep += adv;
+                    if (adv == kBLook)
+                        while (ep < eb && vv[ep * kWave + lane] != kPending) ++ep;
                     if ((polls & 31u) == 31u) {
                         bool stop = (polls & 255u) == 255u && ld_u32_coherent(&ctl->abort) != 0u;
                         const uint64_t now = wall_clock64();
@@ -650,6 +719,8 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
                             if (vu[i * kWave + lane] == kPending) vu[i * kWave + lane] = kQNaN;
                             for (int32_t e = ea; e < eb; ++e)
                                 if (vv[e * kWave + lane] == kPending) vv[e * kWave + lane] = kQNaN;
+                            ur = true;
+                            ep = eb;
                         }
                     }
                     ++polls;
@@ -683,8 +754,52 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
         const int32_t dl = (int32_t)(dj - rs);
         if (act && W[dl * kWave + lane] == 0.0) atomicMin(&ctl->bad_row, (unsigned long long)j);
         if (act && (int64_t)j != skip_row) {
-            for (int32_t e = dl; e < len; ++e) st_publish(F + (rs + e) * B + col, W[e * kWave + lane]);
-            for (int32_t e = 0; e < dl; ++e) F[(rs + e) * B + col] = W[e * kWave + lane];
+            if (kGW) {
+                // U part first (the rows waiting on it), then L, a chunk of
+                // loads per round trip
+                for (int32_t c = dl; c < len + dl; c += kBWChunk) {
+                    double w[kBWChunk];
+                    int32_t ec[kBWChunk];
+#pragma unroll
+                    for (int u = 0; u < kBWChunk; ++u) {
+                        const int32_t e = std::min(c + u, len + dl - 1);
+                        ec[u] = e < len ? e : e - len;
+                        w[u] = W[ec[u] * kWave + lane];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBWChunk; ++u) {
+                        if (c + u >= len + dl) continue;
+                        if (c + u < len) st_final<S>(F + (rs + ec[u]) * B + col, w[u]);
+                        else F[(rs + ec[u]) * B + col] = w[u];
+                    }
+                }
+            } else {
+                for (int32_t e = dl; e < len; ++e) st_final<S>(F + (rs + e) * B + col, W[e * kWave + lane]);
+                for (int32_t e = 0; e < dl; ++e) F[(rs + e) * B + col] = W[e * kWave + lane];
+            }
+        }
+        if (xout && act) {
+            double sx = sanitize_input(bvec[(int64_t)j * B + col], ctl);
+            for (int32_t c = 0; c < dl; c += kBWChunk) {
+                double fv[kBWChunk];
+                uint64_t xv[kBWChunk];
+                int32_t hh[kBWChunk];
+#pragma unroll
+                for (int u = 0; u < kBWChunk; ++u) {
+                    const int32_t e = std::min(c + u, dl - 1);
+                    hh[u] = P.ciF[rs + e];
+                    fv[u] = W[e * kWave + lane];
+                    xv[u] = ld_cached(xout + (int64_t)hh[u] * B + col);
+                }
+#pragma unroll
+                for (int u = 0; u < kBWChunk; ++u)
+                    if (c + u >= dl) xv[u] = 0ull;
+                settle(xout, hh, xv, B, col, ctl, spin_limit);
+#pragma unroll
+                for (int u = 0; u < kBWChunk; ++u)
+                    if (c + u < dl) sx = sx - fv[u] * as_f64(xv[u]);
+            }
+            if ((int64_t)j != skip_row) st_final<S>(xout + (int64_t)j * B + col, sx);
         }
         wave_sync();
     }
@@ -721,7 +836,7 @@ bool numeric_flow_fits(int32_t max_row, int32_t max_lrow, size_t lds_limit) {
     return flow_lds_bytes(std::max(max_row, 1), flow_cap(max_lrow)) <= lds_limit;
 }
 
-int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, int num_cu) {
+int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, int num_cu, bool global_row) {
     // LDS per wavefront bounds how many rows are in flight; aim for the
     // resident maximum so every ready row has a wavefront
     size_t lds;
@@ -730,8 +845,8 @@ int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, in
     else if (batch == 1)
         lds = (size_t)max_row * 8 + (kPivCap + 1) * 4 + kPivCap * 12 + kPairCap * 16;
     else
-        lds = (size_t)max_row * 8 * kWave + (kBPivCap + 1) * 4 + kBPivCap * 4 + kBPairCap * 8 +
-              (kBPivCap + kBPairCap) * 8 * kWave;
+        lds = (global_row ? 0 : (size_t)max_row * 8 * kWave) + (kBPivCap + 1) * 4 + kBPivCap * 4 +
+              kBPairCap * 8 + (kBPivCap + kBPairCap) * 8 * kWave;
     size_t per_cu = std::max<size_t>(1, (160 * 1024) / std::max<size_t>(lds, 1));
     per_cu = std::min<size_t>(per_cu, 32);
     return (int)(per_cu * (size_t)num_cu);
@@ -739,7 +854,8 @@ int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, in
 
 hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, double* f_val,
                           Ctl* ctl, uint64_t spin_limit, int64_t skip_row, int32_t grid,
-                          int32_t max_row, int32_t max_lrow, bool flow, bool one_xcd, hipStream_t s) {
+                          int32_t max_row, int32_t max_lrow, bool flow, bool one_xcd, double* wrow,
+                          const double* bvec, double* xout, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
     const dim3 g1(one_xcd ? grid * kXcds : grid);
     if (batch == 1 && flow) {
@@ -760,9 +876,23 @@ hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, d
             hipLaunchKernelGGL(k_numeric_row<Scope::Device>, g1, dim3(64), lds, s, P, a_val, f_val, ctl,
                                spin_limit, skip_row);
     } else {
-        size_t lds = (size_t)std::max(max_row, 1) * sizeof(double) * kWave;
-        hipLaunchKernelGGL(k_numeric_batch, dim3(grid), dim3(64), lds, s, P, a_val, batch, f_val,
-                           ctl, spin_limit, skip_row);
+        const int64_t ws = (int64_t)std::max(max_row, 1) * kWave;
+        if (wrow) {
+            if (one_xcd)
+                hipLaunchKernelGGL((k_numeric_batch<true, Scope::Xcd>), g1, dim3(64), 0, s, P, a_val, batch,
+                                   f_val, ctl, spin_limit, skip_row, wrow, ws, bvec, xout);
+            else
+                hipLaunchKernelGGL((k_numeric_batch<true, Scope::Device>), g1, dim3(64), 0, s, P, a_val, batch,
+                                   f_val, ctl, spin_limit, skip_row, wrow, ws, bvec, xout);
+        } else {
+            const size_t lds = (size_t)ws * sizeof(double);
+            if (one_xcd)
+                hipLaunchKernelGGL((k_numeric_batch<false, Scope::Xcd>), g1, dim3(64), lds, s, P, a_val, batch,
+                                   f_val, ctl, spin_limit, skip_row, nullptr, (int64_t)0, bvec, xout);
+            else
+                hipLaunchKernelGGL((k_numeric_batch<false, Scope::Device>), g1, dim3(64), lds, s, P, a_val,
+                                   batch, f_val, ctl, spin_limit, skip_row, nullptr, (int64_t)0, bvec, xout);
+        }
     }
     return hipGetLastError();
 }

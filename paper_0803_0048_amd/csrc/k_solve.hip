@@ -248,9 +248,14 @@ __global__ __launch_bounds__(64) void k_solve_lanes(PatDev P, const double* __re
 // waited on
 constexpr int kSolveChunk = 8;
 
+template <Scope S>
 __global__ __launch_bounds__(64) void k_forward_batch(PatDev P, const double* __restrict__ F,
                                                       int32_t B, const double* __restrict__ b,
                                                       double* x, Ctl* ctl, uint64_t spin_limit) {
+    if constexpr (S == Scope::Xcd) {
+        if (!xcd_member(ctl)) return;
+    }
+    const uint32_t parts = S == Scope::Xcd ? 1u : (uint32_t)P.parts;
     const int lane = lane_id();
     const int32_t n = P.n;
     const int32_t G = (B + kWave - 1) / kWave;
@@ -258,7 +263,7 @@ __global__ __launch_bounds__(64) void k_forward_batch(PatDev P, const double* __
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
+        if (!next_pos(ctl, ntask, 1u, parts, run, t)) break;
         const int32_t ir = (int32_t)(t / (uint32_t)G);
         const int32_t i = P.permL ? P.permL[ir] : ir;
         const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
@@ -285,14 +290,19 @@ __global__ __launch_bounds__(64) void k_forward_batch(PatDev P, const double* __
                 for (int u = 0; u < kSolveChunk; ++u)
                     if (c + u < dj) s = s - fv[u] * as_f64(xv[u]);
             }
-            st_publish(x + (int64_t)i * B + col, s);
+            st_final<S>(x + (int64_t)i * B + col, s);
         }
     }
 }
 
+template <Scope S>
 __global__ __launch_bounds__(64) void k_backward_batch(PatDev P, const double* __restrict__ F,
                                                        int32_t B, const double* __restrict__ x,
                                                        double* y, Ctl* ctl, uint64_t spin_limit) {
+    if constexpr (S == Scope::Xcd) {
+        if (!xcd_member(ctl)) return;
+    }
+    const uint32_t parts = S == Scope::Xcd ? 1u : (uint32_t)P.parts;
     const int lane = lane_id();
     const int32_t n = P.n;
     const int32_t G = (B + kWave - 1) / kWave;
@@ -300,7 +310,7 @@ __global__ __launch_bounds__(64) void k_backward_batch(PatDev P, const double* _
     PosRun run;
     for (;;) {
         uint32_t t;
-        if (!next_pos(ctl, ntask, 1u, (uint32_t)P.parts, run, t)) break;
+        if (!next_pos(ctl, ntask, 1u, parts, run, t)) break;
         const int32_t ir = (int32_t)(t / (uint32_t)G);
         const int32_t i = P.permU ? P.permU[ir] : n - 1 - ir;
         const int32_t col = (int32_t)(t % (uint32_t)G) * kWave + lane;
@@ -328,7 +338,7 @@ __global__ __launch_bounds__(64) void k_backward_batch(PatDev P, const double* _
                 for (int u = 0; u < kSolveChunk; ++u)
                     if (c - u > dj) s = s - fv[u] * as_f64(yv[u]);
             }
-            st_publish(y + (int64_t)i * B + col, s / fii);
+            st_final<S>(y + (int64_t)i * B + col, s / fii);
         }
     }
 }
@@ -348,9 +358,10 @@ hipError_t launch_forward(const PatDev& P, const double* f_val, int32_t batch, c
     else if (batch == 1)
         hipLaunchKernelGGL(k_forward_row<Scope::Device>, dim3(grid), dim3(64), 0, s, P, f_val, b, x, ctl,
                            spin_limit);
+    else if (one_xcd)
+        hipLaunchKernelGGL(k_forward_batch<Scope::Xcd>, dim3(grid * kXcds), dim3(64), 0, s, P, f_val, batch, b, x, ctl, spin_limit);
     else
-        hipLaunchKernelGGL(k_forward_batch, dim3(grid), dim3(64), 0, s, P, f_val, batch, b, x, ctl,
-                           spin_limit);
+        hipLaunchKernelGGL(k_forward_batch<Scope::Device>, dim3(grid), dim3(64), 0, s, P, f_val, batch, b, x, ctl, spin_limit);
     return hipGetLastError();
 }
 
@@ -366,9 +377,10 @@ hipError_t launch_backward(const PatDev& P, const double* f_val, int32_t batch, 
     else if (batch == 1)
         hipLaunchKernelGGL(k_backward_row<Scope::Device>, dim3(grid), dim3(64), 0, s, P, f_val, x, y, ctl,
                            spin_limit);
+    else if (one_xcd)
+        hipLaunchKernelGGL(k_backward_batch<Scope::Xcd>, dim3(grid * kXcds), dim3(64), 0, s, P, f_val, batch, x, y, ctl, spin_limit);
     else
-        hipLaunchKernelGGL(k_backward_batch, dim3(grid), dim3(64), 0, s, P, f_val, batch, x, y, ctl,
-                           spin_limit);
+        hipLaunchKernelGGL(k_backward_batch<Scope::Device>, dim3(grid), dim3(64), 0, s, P, f_val, batch, x, y, ctl, spin_limit);
     return hipGetLastError();
 }
 

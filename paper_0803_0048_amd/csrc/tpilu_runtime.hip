@@ -221,6 +221,7 @@ int32_t row_group(RowKernel kind, int64_t n, int64_t depth) {
 // x16: 0.59 ms, 0.70 at 512); the numeric kernel improves up to the
 // resident maximum.
 constexpr int32_t kBatchSolveWaves = 1024;
+constexpr int32_t kBatchSolveWavesXcd = 256;  // on one XCD (32 CUs)
 
 
 struct tpilu_pattern_s {
@@ -268,7 +269,7 @@ struct tpilu_pattern_s {
     int64_t* tptr = nullptr;
     int32_t *tsl = nullptr, *tq = nullptr;
     // growable workspaces
-    DBuf ws_x, ws_z, ws_fin, ws_lbar, ws_gm, ws_bi;
+    DBuf ws_x, ws_z, ws_fin, ws_lbar, ws_gm, ws_bi, ws_wrow;
 
     void* take(size_t bytes) {
         void* p = al.get(bytes);
@@ -301,6 +302,7 @@ struct tpilu_pattern_s {
     ~tpilu_pattern_s() {
         for (auto& b : owned) al.put(b.p);
         al.put(ws_x.p); al.put(ws_z.p); al.put(ws_fin.p); al.put(ws_lbar.p); al.put(ws_gm.p); al.put(ws_bi.p);
+        al.put(ws_wrow.p);
     }
 };
 
@@ -320,11 +322,13 @@ struct tpilu_graph_s {
     Alloc al;
     double* x = nullptr;
     Ctl* ctl = nullptr;
+    double* wrow = nullptr;  // global working rows of a batch with long rows
     ~tpilu_graph_s() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         al.put(x);
         al.put(ctl);
+        al.put(wrow);
     }
 };
 
@@ -412,11 +416,47 @@ size_t batch_numeric_lds(int32_t max_row) {
     return (size_t)std::max(max_row, 1) * 8 * 64 + 24 * 1024;
 }
 
+// The batched kernel keeps a row of 64 instances in LDS (512 bytes per
+// entry) up to 80 entries (64 KB with its staging); longer rows go to global
+// memory: a slice of grid x max_row x 64 doubles.  The grid is the kernel's
+// resident maximum, cut so that the slices stay within kBatchRowBytes.
+// Measured on MI355X, rows in up to 160 KB of LDS (two wavefronts per CU)
+// were slower than in global memory (seven per CU): 27-point 20^3 ILU(2),
+// 70 instances, 24.8 vs 22.1 ms; ILU(3), 5 instances, 46.6 vs 44.2 ms;
+// 27-point 30^3 ILU(2), 256 instances, 142 vs 107 ms.
+constexpr size_t kBatchRowBytes = size_t(1) << 30;
+bool batch_global_row(tpilu_ctx, tpilu_pattern pat, int32_t batch) {
+    return batch > 1 && batch_numeric_lds(pat->st.max_row) > kBatchLdsLimit;
+}
+// the batched kernels on one XCD (explicit placement only)
+bool batch_one_xcd(tpilu_ctx ctx, int32_t batch) { return batch > 1 && ctx->placement == 2; }
+// working wavefronts of a batched factorization (on one XCD: of that XCD)
+int batch_numeric_grid(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch) {
+    const bool gr = batch_global_row(ctx, pat, batch);
+    int grid = ctx->grid_override ? ctx->grid_override
+                                  : std::max(1, numeric_grid(batch, pat->st.max_row, pat->st.max_lrow, false,
+                                                             ctx->num_cu, gr) /
+                                                    (batch_one_xcd(ctx, batch) ? kXcds : 1));
+    if (gr && !ctx->grid_override) {
+        const size_t per = (size_t)std::max(pat->st.max_row, 1) * 64 * sizeof(double);
+        grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)grid, kBatchRowBytes / per));
+    }
+    return grid;
+}
+// bytes of the global working rows a batched factorization needs (0: none)
+size_t numeric_wrow_bytes(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch) {
+    if (!batch_global_row(ctx, pat, batch)) return 0;
+    return (size_t)batch_numeric_grid(ctx, pat, batch) * (size_t)std::max(pat->st.max_row, 1) * 64 *
+           sizeof(double);
+}
+
+// wrow: numeric_wrow_bytes(ctx, pat, batch) bytes of device memory, or null
+// when that is 0.  b, x (batches only, both or neither): the forward
+// substitution x = L~^-1 b fused into the factorization.
 tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_val, int32_t batch,
-                             double* f_val, Ctl* ctl) {
-    if (batch > 1 && batch_numeric_lds(pat->st.max_row) > kBatchLdsLimit)
-        return fail(ctx, TPILU_E_INVAL,
-                    "batched factorization supports rows of at most 80 entries");
+                             double* f_val, Ctl* ctl, double* wrow, const double* b = nullptr,
+                             double* x = nullptr) {
+    if ((x || b) && (batch < 2 || !x || !b)) return fail(ctx, TPILU_E_INVAL, "fused forward: batches only");
     if (batch == 1 && (size_t)pat->st.max_row * 8 + 12 * 1024 > kBatchLdsLimit)
         return fail(ctx, TPILU_E_INVAL, "numeric factorization supports rows of at most 6600 entries");
     if (batch == 1 && ctx->numeric == 1 && !pat->flow)
@@ -435,19 +475,23 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
     // one XCD only when asked for: the factorization keeps many rows in flight
     // and needs the whole device (random banded n=160,000 ILU(2) ran 3x
     // slower on one XCD); there the grid is that XCD's resident maximum
-    const bool one_xcd = batch == 1 && ctx->placement == 2;
-    const int grid = ctx->grid_override
+    const bool one_xcd = ctx->placement == 2;
+    const int grid = batch > 1 ? batch_numeric_grid(ctx, pat, batch)
+                     : ctx->grid_override
                          ? ctx->grid_override
                          : std::max(1, numeric_grid(batch, pat->st.max_row, pat->st.max_lrow, flow, ctx->num_cu) /
                                            (one_xcd ? kXcds : 1));
+    if (batch_global_row(ctx, pat, batch) && !wrow) return fail(ctx, TPILU_E_NOMEM, "batched working rows");
     {
         // the timed region holds the pending-marker fill of F too: the
         // elimination cannot run without it
         TimedLaunch tl(ctx, TPILU_KERNEL_NUMERIC);
         HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, ctl, true, ctx->stream));
+        if (x) HIPCHK(ctx, launch_fill_pending(x, pat->n * batch, ctl, false, ctx->stream));
         HIPCHK(ctx, launch_numeric(pdev(ctx, pat, RowKernel::Numeric, true), a_val, batch, f_val, ctl,
                                    ctx->spin_limit, ctx->skip_row, grid, pat->st.max_row, pat->st.max_lrow, flow,
-                                   one_xcd, ctx->stream));
+                                   one_xcd, batch_global_row(ctx, pat, batch) ? wrow : nullptr, b, x,
+                                   ctx->stream));
     }
     return TPILU_OK;
 }
@@ -485,7 +529,10 @@ bool solve_on_xcd(tpilu_ctx ctx, int64_t n, int64_t half, int64_t depth) {
 }
 
 SolveShape solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool backward) {
-    if (batch > 1) return {ctx->grid_override ? ctx->grid_override : kBatchSolveWaves, false};
+    if (batch > 1) {
+        const bool x = batch_one_xcd(ctx, batch);
+        return {ctx->grid_override ? ctx->grid_override : x ? kBatchSolveWavesXcd : kBatchSolveWaves, x};
+    }
     const int64_t n = std::max<int64_t>(pat->n, 1);
     const int64_t half = backward ? pat->nnz_f - (int64_t)pat->st.nnz_l - pat->n : (int64_t)pat->st.nnz_l;
     const int64_t depth = std::max<int64_t>(1, backward ? pat->depth_u : pat->depth_l);
@@ -506,8 +553,11 @@ SolveShape solve_shape(tpilu_ctx ctx, tpilu_pattern pat, int32_t batch, bool bac
     return {kSolveWavesWide, one_xcd};
 }
 
+// forward = false: x already holds L~^-1 b (the batched factorization with
+// the forward substitution fused in); only the backward sweep runs
 tpilu_status enqueue_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val, int32_t batch,
-                           const double* b, double* y, double* x, bool reset, Ctl* ctl, bool timed = true) {
+                           const double* b, double* y, double* x, bool reset, Ctl* ctl, bool timed = true,
+                           bool forward = true) {
     SolveShape gf = solve_shape(ctx, pat, batch, false), gb = solve_shape(ctx, pat, batch, true);
     // the one-CU shape needs the dependency positions; without them (never
     // built, and this call may not allocate) the wavefront-per-row shape runs
@@ -518,8 +568,8 @@ tpilu_status enqueue_apply(tpilu_ctx ctx, tpilu_pattern pat, const double* f_val
     const PatDev P = pdev(ctx, pat, RowKernel::Solve, true);
     // the one-CU kernel hands values over through LDS and needs no pending
     // marks in the output; the control block is reset all the same
-    HIPCHK(ctx, launch_fill_pending(x, gf.grid == 0 ? 0 : pat->n * batch, ctl, reset, ctx->stream));
-    {
+    if (forward) {
+        HIPCHK(ctx, launch_fill_pending(x, gf.grid == 0 ? 0 : pat->n * batch, ctl, reset, ctx->stream));
         TimedLaunch tl(ctx, TPILU_KERNEL_FORWARD, timed);
         if (gf.grid == 0)
             HIPCHK(ctx, launch_solve_cu(P, pat->dep_pos, f_val, b, x, false, ctl, ctx->spin_limit, ctx->stream));
@@ -1215,7 +1265,12 @@ extern "C" TPILU_API tpilu_status tpilu_numeric(tpilu_ctx ctx, tpilu_pattern pat
     if (!a_val || !f_val) return fail(ctx, TPILU_E_INVAL, "null array");
     DeviceGuard dg(ctx->device);
     trace("numeric", pat->n, batch);
-    st = enqueue_numeric(ctx, pat, a_val, batch, f_val, pat->ctl);
+    double* wrow = nullptr;
+    if (const size_t wb = numeric_wrow_bytes(ctx, pat, batch)) {
+        wrow = pat->grow(pat->ws_wrow, wb);
+        if (!wrow) return fail(ctx, TPILU_E_NOMEM, "batched working rows");
+    }
+    st = enqueue_numeric(ctx, pat, a_val, batch, f_val, pat->ctl, wrow);
     if (st) return st;
     if (bad_row) return read_ctl(ctx, pat, bad_row, false);
     return TPILU_OK;
@@ -1797,7 +1852,9 @@ extern "C" TPILU_API tpilu_status tpilu_batched_graph_create(tpilu_ctx ctx, tpil
     g->al = ctx_alloc(ctx);
     g->x = (double*)g->al.get(sizeof(double) * (size_t)pat->n * batch);
     g->ctl = (Ctl*)g->al.get(sizeof(Ctl));
-    if (!g->x || !g->ctl) {
+    const size_t wb = numeric_wrow_bytes(ctx, pat, batch);
+    if (wb) g->wrow = (double*)g->al.get(wb);
+    if (!g->x || !g->ctl || (wb && !g->wrow)) {
         delete g;
         return fail(ctx, TPILU_E_NOMEM, "graph workspace");
     }
@@ -1823,8 +1880,11 @@ extern "C" TPILU_API tpilu_status tpilu_batched_graph_create(tpilu_ctx ctx, tpil
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        st = enqueue_numeric(ctx, pat, a_val, batch, f_val, g->ctl);
-        if (st == TPILU_OK) st = enqueue_apply(ctx, pat, f_val, batch, b, y, g->x, false, g->ctl);
+        // batches: the forward substitution runs inside the factorization
+        const bool fused = batch > 1;
+        st = enqueue_numeric(ctx, pat, a_val, batch, f_val, g->ctl, g->wrow, fused ? b : nullptr,
+                             fused ? g->x : nullptr);
+        if (st == TPILU_OK) st = enqueue_apply(ctx, pat, f_val, batch, b, y, g->x, false, g->ctl, true, !fused);
         e = hipStreamEndCapture(cap, &graph);
     }
     ctx->stream = saved;

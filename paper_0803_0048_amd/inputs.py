@@ -53,6 +53,7 @@ __all__ = [
     "random_banded_ilu2",
     "conv_diff_3d_ilu",
     "batched_conv_diff_2d_ilu2",
+    "batched_stencil27_ilu",
     "differentiated_conv_diff_3d_ilu1",
     "random_uniform",
     "paper_scale_random_ilu1",
@@ -437,6 +438,28 @@ def batched_conv_diff_2d_ilu2(seed: int = 1004, B: int = 256, m: int = 128):
         rhs[:, i] = rng.standard_normal(m * m)
     A = conv_diff_2d(m, eps, bxy[:, 0], bxy[:, 1])
     return {"name": f"batched_conv_diff_2d_{m}x{m}_x{B}_ilu2", "A": A, "b": rhs, "k": 2}
+
+
+def batched_stencil27_ilu(seed: int = 1008, B: int = 70, m: int = 20, k: int = 2):
+    """B instances of the 27-point stencil on an m^3 grid sharing one pattern,
+    eps ~ U[0.5, 2], b ~ U[-10, 10]^3 per instance, rhs ~ N(0, 1).  At
+    ILU(2) and ILU(3) its rows reach 115 and 183 entries: the batched
+    factorization's long-row case."""
+    kids = np.random.SeedSequence(seed).spawn(B)
+    base = None
+    vals = []
+    rhs = np.empty((m**3, B))
+    for i, ss in enumerate(kids):
+        rng = np.random.default_rng(ss)
+        eps = rng.uniform(0.5, 2.0)
+        bvec = rng.uniform(-10.0, 10.0, size=3)
+        rhs[:, i] = rng.standard_normal(m**3)
+        Ai = stencil27_3d(m, eps, bvec)
+        base = base or Ai
+        vals.append(Ai.val)
+    A = CSR(base.n, base.rowptr, base.col, np.ascontiguousarray(np.stack(vals, axis=1)),
+            {"kind": "stencil27_3d", "m": m, "h": base.meta["h"]})
+    return {"name": f"batched_stencil27_3d_{m}cubed_x{B}_ilu{k}", "A": A, "b": rhs, "k": k}
 
 
 def differentiated_conv_diff_3d_ilu1(seed: int = 1005, B: int = 16, m: int = 32):

@@ -2,7 +2,8 @@
 through the C ABI, against the oracle where it defines the result:
 GMRES and BiCGSTAB stopped by maxit (E_NOTCONV with the partial iterate),
 a zero right-hand side, BiCGSTAB breakdowns (an inner product exactly zero),
-and E_NOMEM from a failing allocator callback."""
+E_NOMEM from a failing allocator callback, and the watchdog inside a
+batched graph."""
 from __future__ import annotations
 
 import ctypes as C
@@ -199,3 +200,33 @@ def test_enomem_from_allocator_callback():
     finally:
         torch.cuda.synchronize()
         lib.tpilu_ctx_destroy(h)
+
+
+def test_batched_graph_watchdog_and_recovery():
+    """A batched graph whose factorization never publishes one row (the
+    library's test hook, forced from the host) ends with E_TIMEOUT: the rows
+    waiting on it, the fused forward substitution and the backward sweep all
+    give up at the watchdog and the kernels drain.  A graph captured after the
+    hook is cleared gives the eager bits again."""
+    c = I.batched_conv_diff_2d_ilu2(B=70, m=24)
+    A, rhs = c["A"], c["b"]
+    pat = T.symbolic(g(A.rowptr), g(A.col), 2)
+    av, bv = g(A.val), g(rhs)
+    ctx = T.context(0)
+    ctx.set_watchdog(timeout_us=20000, skip_publish_row=100)
+    try:
+        graph = T.BatchedGraph(pat, av, bv)
+        graph.launch()
+        with pytest.raises(T.TpiluError) as e:
+            graph.check()
+        assert e.value.status == T.E_TIMEOUT
+    finally:
+        ctx.set_watchdog(0, -1)
+    del graph
+    f = T.numeric(pat, av)
+    y = T.apply(pat, f, bv)
+    graph = T.BatchedGraph(pat, av, bv)
+    graph.launch()
+    assert graph.check() == -1
+    assert torch.equal(graph.f_val.view(torch.int64), f.view(torch.int64))
+    assert torch.equal(graph.y.view(torch.int64), y.view(torch.int64))

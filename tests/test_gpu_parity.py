@@ -553,6 +553,88 @@ def test_graph_owns_its_workspace():
     assert_bits_equal(y64[:, :16], y, "eager vs graph")
 
 
+@pytest.mark.parametrize("k,B", [(2, 70), (3, 5)])
+def test_batched_long_rows(k, B):
+    """Batches whose rows are longer than the batched kernel's LDS working row
+    (27-point 20^3: 115 entries at ILU(2), 183 at ILU(3)) run with the
+    working rows in global memory: every instance's F and y equal the
+    oracle's, eagerly and under a captured graph (which owns its own working
+    rows), and an instance run alone agrees."""
+    c = I.batched_stencil27_ilu(B=B, k=k)
+    A, rhs = c["A"], c["b"]
+    log(f"{c['name']}")
+    pat = T.symbolic(g(A.rowptr), g(A.col), k)
+    rpF, ciF, lvF = O.symbolic(A.n, A.rowptr, A.col, k)
+    check_pattern(pat, rpF, ciF, lvF, A)
+    assert pat.info["max_row"] > 80
+    av, bv = g(A.val), g(rhs)
+    f = T.numeric(pat, av)
+    y = T.apply(pat, f, bv)
+    assert T.check(pat) == -1
+    graph = T.BatchedGraph(pat, av, bv)
+    graph.launch()
+    assert graph.check() == -1
+    fh, yh = f.cpu().numpy(), y.cpu().numpy()
+    for inst in range(B):
+        vF, bad = O.numeric(A.n, A.rowptr, A.col, A.val[:, inst].copy(), rpF, ciF)
+        assert bad == -1
+        _, yr = O.apply(A.n, rpF, ciF, vF, rhs[:, inst])
+        assert_bits_equal(fh[:, inst], vF, f"F instance {inst}")
+        assert_bits_equal(yh[:, inst], yr, f"y instance {inst}")
+    assert torch.equal(graph.f_val.view(torch.int64), f.view(torch.int64))
+    assert torch.equal(graph.y.view(torch.int64), y.view(torch.int64))
+    fs = T.numeric(pat, g(A.val[:, B - 1].copy()))
+    assert_bits_equal(fs, fh[:, B - 1], "single vs batched")
+
+
+def _dominant_batch(A, B, rng):
+    vals = rng.uniform(-1, 1, (A.nnz, B))
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    rowsum = np.zeros((A.n, B))
+    np.add.at(rowsum, rows, np.abs(vals))
+    diag = A.col == rows
+    vals[diag] = 1.1 * rowsum[rows[diag]] + 1.0
+    return vals
+
+
+@pytest.mark.parametrize("case", ["arrow", "full_lu"])
+def test_batched_global_rows(case):
+    """Rows too long for an LDS working row (over 80 entries for 64 instances)
+    are factored with the working rows in global memory: an arrow matrix
+    (600-entry last row, 599 pivots with 2 pairs each, B=70: two instance
+    groups, the second partial) and the complete LU of a random pattern
+    (k = n: rows of up to 381 entries whose pivots have hundreds of pairs, more than the
+    pair lists hold).  Every instance's F equals the oracle's, eagerly and
+    under a graph."""
+    rng = np.random.default_rng(21)
+    if case == "arrow":
+        A, B, k = _arrow(600, 5), 70, 2
+    else:
+        A, B, k = I.random_pattern(400, 0.05, seed=31), 3, 400
+    vals = _dominant_batch(A, B, rng)
+    rhs = rng.standard_normal((A.n, B))
+    rpF, ciF, lvF = O.symbolic(A.n, A.rowptr, A.col, k)
+    pat = T.symbolic(g(A.rowptr), g(A.col), k)
+    check_pattern(pat, rpF, ciF, lvF, A)
+    assert pat.info["max_row"] > 80
+    av, bv = g(vals), g(rhs)
+    f = T.numeric(pat, av)
+    y = T.apply(pat, f, bv)
+    assert T.check(pat) == -1
+    graph = T.BatchedGraph(pat, av, bv)
+    graph.launch()
+    assert graph.check() == -1
+    fh, yh = f.cpu().numpy(), y.cpu().numpy()
+    for inst in range(B):
+        vF, bad = O.numeric(A.n, A.rowptr, A.col, vals[:, inst].copy(), rpF, ciF)
+        assert bad == -1
+        _, yr = O.apply(A.n, rpF, ciF, vF, rhs[:, inst])
+        assert_bits_equal(fh[:, inst], vF, f"F instance {inst}")
+        assert_bits_equal(yh[:, inst], yr, f"y instance {inst}")
+    assert torch.equal(graph.f_val.view(torch.int64), f.view(torch.int64))
+    assert torch.equal(graph.y.view(torch.int64), y.view(torch.int64))
+
+
 def test_batched_partial_group():
     """A batch that is not a multiple of 64 instances."""
     c = I.batched_conv_diff_2d_ilu2(B=70, m=24)
@@ -660,8 +742,10 @@ def test_adjoint_batched_bits(case):
     rhs, tgt = rng.standard_normal((A.n, B)), rng.standard_normal((A.n, B))
     rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
     pat = T.symbolic(g(A.rowptr), g(A.col), k)
-    # factors instance by instance (the batched factorization caps row length)
-    f = torch.stack([T.numeric(pat, g(vals[:, i].copy())) for i in range(B)], dim=1).contiguous()
+    f = T.numeric(pat, g(vals))
+    # the batched factors equal the single-instance ones
+    for i in range(B):
+        assert_bits_equal(f[:, i].contiguous(), T.numeric(pat, g(vals[:, i].copy())), f"instance {i}")
     y, x = T.apply(pat, f, g(rhs), return_x=True)
     bbar, fbar = T.apply_adjoint(pat, f, x, y, 2.0 * (y - g(tgt)))
     abar, _ = T.numeric_adjoint(pat, f, fbar.clone())
