@@ -14,7 +14,9 @@ import threading
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtpilu.so")
+# TPILU_LIBRARY=jitter selects the race check build (libtpilu_jitter.so, same
+# kernels with random pauses at every hand-off), which only a test uses
+LIB_PATH = os.path.join(HERE, "libtpilu_jitter.so" if os.environ.get("TPILU_LIBRARY") == "jitter" else "libtpilu.so")
 
 OK, E_INVAL, E_NOMEM, E_ZEROPIVOT, E_DEVICE, E_NOTCONV, E_TIMEOUT = range(7)
 

@@ -1,4 +1,7 @@
-"""Build the gfx950 HIP library ``libtpilu.so`` in-tree.
+"""Build the gfx950 HIP library ``libtpilu.so`` in-tree, and next to it
+``libtpilu_jitter.so``: the same sources with ``-DTPILU_JITTER``, which adds a
+pseudo-random pause before every publishing store and after every coherent
+load (the race check build; only a test loads it, never the product path).
 
 Every HIP unit is compiled with ``-ffp-contract=off``: hipcc contracts a*b-c
 into an FMA by default, which would change the bits of every update.
@@ -23,6 +26,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpilu.so")
+JITTER_LIB = os.path.join(HERE, "libtpilu_jitter.so")
 SOURCES = ["k_symbolic.hip", "k_numeric.hip", "k_solve.hip", "k_solve_cu.hip", "k_krylov.hip", "k_adjoint.hip",
            "k_inverse.hip", "k_probe.hip", "tpilu_runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -34,9 +38,9 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, build_dir: str) -> str:
+def _compile(src: str, build_dir: str, defines=()) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *defines, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -48,19 +52,27 @@ def _compile(src: str, build_dir: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    build_dir = os.path.join(HERE, "_build")
+def _build_one(lib: str, build_dir: str, defines=(), verbose: bool = False) -> str:
     os.makedirs(build_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, build_dir, defines), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
+        print("built", lib)
+    return lib
+
+
+def build(verbose: bool = False, jitter: bool = True) -> str:
+    """Build libtpilu.so and (jitter=True) libtpilu_jitter.so; returns the
+    product library's path."""
+    _build_one(LIB, os.path.join(HERE, "_build"), (), verbose)
+    if jitter:
+        _build_one(JITTER_LIB, os.path.join(HERE, "_build_jitter"), ("-DTPILU_JITTER",), verbose)
     return LIB
 
 

@@ -55,18 +55,39 @@ struct Ctl {
     uint32_t part[kTicketParts * kTicketStride];  // position counters (next_pos)
 };
 
+// Race check build (compiled with -DTPILU_JITTER, never the product): a
+// pseudo-random pause of 0 to 31 x 64 cycles, the same for the whole
+// wavefront, before every publishing store and after every coherent load, so
+// that hand-offs happen in orders and at times the normal timing never
+// produces.  The results must keep their bits.
+#ifdef TPILU_JITTER
+__device__ __forceinline__ void jitter(uint32_t salt) {
+    uint32_t h = (uint32_t)wall_clock64() * 0x9E3779B9u ^ (blockIdx.x + 0x7F4A7C15u) * 0x85EBCA6Bu ^ salt;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    const uint32_t r = __builtin_amdgcn_readfirstlane(h) & 31u;
+    for (uint32_t k = 0; k < r; ++k) __builtin_amdgcn_s_sleep(1);
+}
+#else
+__device__ __forceinline__ void jitter(uint32_t) {}
+#endif
+
 __device__ __forceinline__ uint64_t as_u64(double d) { return __builtin_bit_cast(uint64_t, d); }
 __device__ __forceinline__ double as_f64(uint64_t u) { return __builtin_bit_cast(double, u); }
 
 __device__ __forceinline__ uint64_t ld_coherent(const double* p) {
-    return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t v = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    jitter((uint32_t)v);
+    return v;
 }
 __device__ __forceinline__ uint64_t ld_cached(const double* p) {
     return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 __device__ __forceinline__ void st_publish(double* p, double v) {
+    jitter((uint32_t)(uintptr_t)p);
     __hip_atomic_store(reinterpret_cast<uint64_t*>(p), as_u64(v), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -257,8 +278,10 @@ enum class Scope { Device, Xcd, Workgroup };
 template <Scope S>
 __device__ __forceinline__ uint64_t ld_poll(const double* p) {
     if constexpr (S != Scope::Workgroup) return ld_coherent(p);
-    return __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint64_t v = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    jitter((uint32_t)v);
+    return v;
 }
 
 template <Scope S>
@@ -266,6 +289,7 @@ __device__ __forceinline__ void st_final(double* p, double v) {
     if constexpr (S == Scope::Device) {
         st_publish(p, v);
     } else {
+        jitter((uint32_t)(uintptr_t)p);
         __hip_atomic_store(reinterpret_cast<uint64_t*>(p), as_u64(v), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
     }

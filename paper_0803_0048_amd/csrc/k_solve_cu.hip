@@ -122,6 +122,7 @@ __global__ __launch_bounds__(1024) void k_solve_cu(PatDev P, const int32_t* __re
                     double x;
                     if (t1 == q && t2 == q) {
                         x = v;
+                        jitter((uint32_t)q);
                     } else if (t1 > q) {  // reused by a later position: q is in global memory
                         const int32_t row = perm ? perm[q] : (kBackward ? n - 1 - q : q);
                         x = as_f64(ld_coherent(out + row));
@@ -136,6 +137,7 @@ __global__ __launch_bounds__(1024) void k_solve_cu(PatDev P, const int32_t* __re
                     const double r = kBackward ? acc / fii : acc;
                     res = r;
                     const int32_t slot = p & (kRing - 1);
+                    jitter((uint32_t)p);
                     rt[slot] = -2;  // being written
                     rv[slot] = r;
                     rt[slot] = p;

@@ -688,7 +688,9 @@ __device__ __forceinline__ void dep_range(const DepGraph& G, int32_t i, int64_t&
 }
 
 __device__ __forceinline__ int32_t ld_level(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    jitter((uint32_t)v);
+    return v;
 }
 
 // watchdog over polling rounds without progress; true = give up
@@ -760,6 +762,7 @@ __device__ __forceinline__ void level_row(const DepGraph& G, int32_t* depth, Ctl
     }
     for (int off = 32; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off));
     if (lane == 0) {
+        jitter((uint32_t)i);
         if constexpr (S == Scope::Xcd)
             __hip_atomic_store(depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else
@@ -821,6 +824,7 @@ __global__ __launch_bounds__(64) void k_depth_lanes(int32_t n, LevelJob j0, Leve
                     prog = true;
                 }
                 if (q >= b) {
+                    jitter((uint32_t)i);
                     __hip_atomic_store(J.depth + i, best + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     done = true;
                 }

@@ -50,6 +50,23 @@ def test_library_exports_every_declared_symbol(lib):
         getattr(lib, n)
 
 
+def test_jitter_build_exports_the_same_symbols(lib):
+    """The race check build is the same library with pauses compiled in: same
+    entry points, and the product path does not load it."""
+    from paper_0803_0048_amd import binding, build
+
+    jit = build.JITTER_LIB
+    if not os.path.exists(jit):
+        pytest.skip("jitter build not present")
+    outs = []
+    for path in (binding.LIB_PATH, jit):
+        out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True, check=True).stdout
+        outs.append(set(re.findall(r"\bT\s+(tpilu_\w+)", out)))
+    assert outs[0] == outs[1]
+    assert os.path.basename(binding.LIB_PATH) == "libtpilu.so"
+    assert "libtpilu_jitter.so" not in open("/proc/self/maps").read()
+
+
 def test_library_binds_to_torch_hip_runtime(lib):
     import torch
 
