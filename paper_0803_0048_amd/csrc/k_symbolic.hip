@@ -96,6 +96,27 @@ __device__ __forceinline__ bool map_min(int32_t* keys, int32_t* vals, uint32_t m
     return false;
 }
 
+// map_min on the endpoint map of an LDS tier: an insert that finds no slot
+// within kProbeMax probes fails, which the row then reports as overflowing
+// (and the next tier builds it).  A linear-probing table near full makes
+// every probe sequence long; giving up early keeps a row that will not fit
+// from paying for a full table.
+constexpr uint32_t kProbeMax = 64;
+__device__ __forceinline__ bool map_min_bounded(int32_t* keys, int32_t* vals, uint32_t mask, int32_t key,
+                                                int32_t val, uint32_t max_probe) {
+    uint32_t h = hslot(key, mask);
+    const uint32_t lim = min(max_probe, mask + 1u);
+    for (uint32_t probe = 0; probe < lim; ++probe) {
+        int32_t old = atomicCAS(&keys[h], kEmpty, key);
+        if (old == kEmpty || old == key) {
+            atomicMin(&vals[h], val);
+            return true;
+        }
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
 __device__ __forceinline__ int32_t map_get(const int32_t* keys, const int32_t* vals, uint32_t mask,
                                            int32_t key) {
     uint32_t h = hslot(key, mask);
@@ -116,7 +137,86 @@ struct SymWs {
     int32_t *ok, *ol;  // compacted row (column, level)
     int32_t* ctr;      // [0],[1] frontier sizes, [2] overflow, [3] output size
     uint32_t emask, fmask, fcap;
+    uint32_t eprobe;   // most probes of an endpoint insert before the row counts as overflowing
+    uint32_t* bm;      // LDS tiers: the space of ok, reused as a bitmap of bm_bits columns
+    uint32_t bm_bits;  //   (0: the global tier, which sorts its compacted row instead)
 };
+
+constexpr int32_t kSymSortMax = 512;  // longest row the sorting network orders
+
+// exclusive prefix sum over the wavefront's lanes
+__device__ __forceinline__ int32_t wave_excl_sum(int32_t v, int32_t& total) {
+    const int lane = lane_id();
+    int32_t x = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    total = __shfl(x, kWave - 1);
+    return x - v;
+}
+
+// Write row i of F (column, level) in ascending column order straight from
+// the endpoint map: the map's columns are marked in a bitmap over a window
+// of bm_bits columns, each lane takes a block of the window's words, a
+// prefix over the lanes' bit counts gives every block its first output
+// position, and the lane emits its block's columns in order, looking each
+// level up in the map.  Windows follow each other from the row's smallest
+// column to its largest.  O(row + column range / 32), against the
+// O(row log^2 row) of a sorting network.
+__device__ __forceinline__ void sym_emit_sorted(int32_t i, const int64_t* __restrict__ rpF, int32_t* __restrict__ ciF,
+                                uint8_t* __restrict__ lvF, int32_t* __restrict__ diagF, const SymWs& W) {
+    const int lane = lane_id();
+    int32_t cmin = kBig, cmax = -1;
+    for (uint32_t sl = lane; sl <= W.emask; sl += kWave) {
+        const int32_t c = W.ek[sl];
+        if (c != kEmpty) {
+            cmin = min(cmin, c);
+            cmax = max(cmax, c);
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        cmin = min(cmin, __shfl_xor(cmin, off));
+        cmax = max(cmax, __shfl_xor(cmax, off));
+    }
+    const int64_t base = rpF[i];
+    int64_t out = base;
+    for (int64_t w0 = cmin; w0 <= cmax; w0 += W.bm_bits) {
+        const int32_t span = (int32_t)min<int64_t>(W.bm_bits, (int64_t)cmax - w0 + 1);
+        const int32_t nw = (span + 31) >> 5;
+        for (int32_t x = lane; x < nw; x += kWave) W.bm[x] = 0u;
+        wave_sync();
+        for (uint32_t sl = lane; sl <= W.emask; sl += kWave) {
+            const int32_t c = W.ek[sl];
+            if (c != kEmpty && c >= w0 && c < w0 + span) {
+                const int32_t o = (int32_t)(c - w0);
+                atomicOr(&W.bm[o >> 5], 1u << (o & 31));
+            }
+        }
+        wave_sync();
+        const int32_t per = (nw + kWave - 1) / kWave;
+        const int32_t wb = min(lane * per, nw), we = min(wb + per, nw);
+        int32_t mine = 0;
+        for (int32_t x = wb; x < we; ++x) mine += __popc(W.bm[x]);
+        int32_t total = 0;
+        int64_t r = out + wave_excl_sum(mine, total);
+        for (int32_t x = wb; x < we; ++x) {
+            uint32_t bits = W.bm[x];
+            while (bits) {
+                const int32_t b = __builtin_ctz(bits);
+                bits &= bits - 1u;
+                const int32_t c = (int32_t)(w0 + x * 32 + b);
+                const int32_t lev = map_get(W.ek, W.ev, W.emask, c);
+                ciF[r] = c;
+                lvF[r] = static_cast<uint8_t>(min(lev, 255));
+                if (c == i) diagF[i] = static_cast<int32_t>(r);
+                ++r;
+            }
+        }
+        out += total;
+        wave_sync();
+    }
+}
 
 __device__ __forceinline__ void sym_row(int32_t i, const int64_t* __restrict__ rpA,
                                         const int32_t* __restrict__ ciA, int32_t k, int mode,
@@ -133,7 +233,7 @@ __device__ __forceinline__ void sym_row(int32_t i, const int64_t* __restrict__ r
     const int64_t a0 = rpA[i], a1 = rpA[i + 1];
     for (int64_t p = a0 + lane; p < a1; p += kWave) {
         int32_t c = ciA[p];
-        bool ok = map_min(W.ek, W.ev, W.emask, c, 0);
+        bool ok = map_min_bounded(W.ek, W.ev, W.emask, c, 0, W.eprobe);
         if (c < i) {
             int32_t slot = atomicAdd(&W.ctr[0], 1);
             if (slot < (int32_t)W.fcap) { W.fv[0][slot] = c; W.fm[0][slot] = c; }
@@ -149,16 +249,22 @@ __device__ __forceinline__ void sym_row(int32_t i, const int64_t* __restrict__ r
         if (nf == 0 || uniform(W.ctr[2])) break;
         // endpoints reachable from this frontier in one more edge
         for (int32_t f = lane; f < nf; f += kWave) {
-            int32_t v = W.fv[cur][f], M = W.fm[cur][f];
+            if (W.ctr[2]) break;  // overflowing: the next tier builds this row
+            int32_t v = (cur ? W.fv[1] : W.fv[0])[f], M = (cur ? W.fm[1] : W.fm[0])[f];
             for (int64_t p = rpA[v]; p < rpA[v + 1]; ++p) {
                 int32_t j = ciA[p];
-                if (j > M && !map_min(W.ek, W.ev, W.emask, j, d)) W.ctr[2] = 1;
+                if (j > M && !map_min_bounded(W.ek, W.ev, W.emask, j, d, W.eprobe)) {
+                    W.ctr[2] = 1;
+                    break;
+                }
             }
         }
         if (d == k) break;
+        wave_sync();
+        if (uniform(W.ctr[2])) break;
         // next frontier
         for (int32_t f = lane; f < nf; f += kWave) {
-            int32_t v = W.fv[cur][f], M = W.fm[cur][f];
+            int32_t v = (cur ? W.fv[1] : W.fv[0])[f], M = (cur ? W.fm[1] : W.fm[0])[f];
             for (int64_t p = rpA[v]; p < rpA[v + 1]; ++p) {
                 int32_t w = ciA[p];
                 if (w < i && !map_min(W.ck, W.cv, W.fmask, w, max(M, w))) W.ctr[2] = 1;
@@ -176,7 +282,7 @@ __device__ __forceinline__ void sym_row(int32_t i, const int64_t* __restrict__ r
             if (c < map_get(W.bk, W.bv, W.fmask, w)) {
                 bool ok = map_min(W.bk, W.bv, W.fmask, w, c);
                 int32_t slot = atomicAdd(&W.ctr[nxt], 1);
-                if (slot < (int32_t)W.fcap) { W.fv[nxt][slot] = w; W.fm[nxt][slot] = c; }
+                if (slot < (int32_t)W.fcap) { (nxt ? W.fv[1] : W.fv[0])[slot] = w; (nxt ? W.fm[1] : W.fm[0])[slot] = c; }
                 else ok = false;
                 if (!ok) W.ctr[2] = 1;
             }
@@ -188,6 +294,21 @@ __device__ __forceinline__ void sym_row(int32_t i, const int64_t* __restrict__ r
     if (uniform(W.ctr[2])) {
         if (mode == 0 && lane == 0) cnt[i] = -1;
         return;
+    }
+    if (W.bm_bits) {
+        int32_t mine = 0;
+        for (uint32_t sl = lane; sl <= W.emask; sl += kWave) mine += W.ek[sl] != kEmpty;
+        for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+        if (mode == 0) {
+            if (lane == 0) cnt[i] = mine;
+            return;
+        }
+        // long rows: through the bitmap; short ones: the sorting network
+        // below costs less than a pass over the column range
+        if (mine > kSymSortMax) {
+            sym_emit_sorted(i, rpF, ciF, lvF, diagF, W);
+            return;
+        }
     }
     // compact the row
     for (uint32_t s = lane; s <= W.emask; s += kWave) {
@@ -259,6 +380,9 @@ __global__ __launch_bounds__(64) void k_sym_rows_lds(int32_t n, const int64_t* _
     W.fv[0] = f0v; W.fm[0] = f0m; W.fv[1] = f1v; W.fm[1] = f1m;
     W.ok = ok; W.ol = ol; W.ctr = ctr;
     W.emask = kEnd - 1; W.fmask = kSymFrontCap - 1; W.fcap = kSymFrontCap;
+    W.eprobe = kProbeMax;
+    W.bm = reinterpret_cast<uint32_t*>(ok);
+    W.bm_bits = (uint32_t)kEnd * 32u;
     for (int32_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
         int32_t i = row_list ? row_list[r] : r;
         if (mode == 1 && tier_of && tier_of[i] != tier) continue;  // built by another tier
@@ -294,6 +418,9 @@ __global__ __launch_bounds__(64) void k_sym_rows_global(int32_t n, const int64_t
     W.fv[0] = fl; W.fm[0] = fl + n; W.fv[1] = fl + 2 * (size_t)n; W.fm[1] = fl + 3 * (size_t)n;
     W.ctr = fl + 4 * (size_t)n;
     W.emask = gcap - 1; W.fmask = gcap - 1; W.fcap = (uint32_t)n;
+    W.eprobe = gcap;  // sized for any row (gcap >= 2n + 2): never gives up
+    W.bm = nullptr;
+    W.bm_bits = 0;
     for (int32_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
         int32_t i = row_list ? row_list[r] : r;
         if (mode == 1 && tier_of && tier_of[i] != 2) continue;
@@ -320,6 +447,59 @@ hipError_t launch_sym_rows(int tier, int32_t n, const int64_t* rpA, const int32_
     }
     return hipGetLastError();
 }
+
+// Routing of rows to the tiers before the count pass.  ub_i = |row i of A| +
+// sum over stored a_ih, h < i, of the entries of row h right of h: every
+// position of level <= 1 of row i is one of those terms (Def. 2.3 with one
+// interior vertex), so for k = 1 it bounds the row's length, counting
+// duplicates.  Rows whose bound passes `limit` go straight to the larger
+// maps of tier 1: built in tier 0 they would only fill its map and be given
+// up.  The routing only changes where a row is built, never what it holds
+// (a row tier 1 cannot hold still goes on to the global tier).
+__global__ void k_row_upper(int32_t n, const int64_t* __restrict__ rpA, const int32_t* __restrict__ ciA,
+                            int32_t* __restrict__ nup) {
+    const int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n) return;
+    int64_t lo = rpA[h], hi = rpA[h + 1];
+    const int64_t end = hi;
+    while (lo < hi) {  // first entry right of the diagonal
+        const int64_t mid = (lo + hi) >> 1;
+        if (ciA[mid] <= h) lo = mid + 1;
+        else hi = mid;
+    }
+    nup[h] = (int32_t)(end - lo);
+}
+
+__global__ void k_route_rows(int32_t n, const int64_t* __restrict__ rpA, const int32_t* __restrict__ ciA,
+                             const int32_t* __restrict__ nup, int64_t limit, int32_t* __restrict__ list0,
+                             int32_t* __restrict__ list1, int32_t* __restrict__ counts, uint8_t* __restrict__ tier_of) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t a0 = rpA[i], a1 = rpA[i + 1];
+    int64_t ub = a1 - a0;
+    for (int64_t p = a0; p < a1 && ub <= limit; ++p) {
+        const int32_t h = ciA[p];
+        if (h >= i) break;
+        ub += nup[h];
+    }
+    if (ub > limit) {
+        list1[atomicAdd(&counts[1], 1)] = i;
+        tier_of[i] = 1;
+    } else {
+        list0[atomicAdd(&counts[0], 1)] = i;
+    }
+}
+
+hipError_t launch_route_rows(int32_t n, const int64_t* rpA, const int32_t* ciA, int32_t* nup, int64_t limit,
+                             int32_t* list0, int32_t* list1, int32_t* counts, uint8_t* tier_of, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_upper, dim3((n + 255) / 256), dim3(256), 0, s, n, rpA, ciA, nup);
+    hipLaunchKernelGGL(k_route_rows, dim3((n + 255) / 256), dim3(256), 0, s, n, rpA, ciA, nup, limit, list0, list1,
+                       counts, tier_of);
+    return hipGetLastError();
+}
+
+int64_t sym_route_limit() { return (int64_t)(kSymEndCap - kSymEndCap / 8) * 5 / 4; }
 
 __global__ void k_collect_overflow(int32_t n_rows, const int32_t* __restrict__ list,
                                    const int32_t* __restrict__ cnt, int32_t* row_list, int32_t* n_over,
@@ -473,39 +653,85 @@ hipError_t launch_a2f(int32_t n, const int64_t* rpA, const int32_t* ciA, const i
 // candidate is missed); a 64-bit division per candidate cost more than the
 // search itself.
 // ------------------------------------------------------------------------------------
-constexpr int kSchedDir = 256;   // buckets of the column directory of row j
+constexpr int kSchedDir = 1024;  // buckets of the column directory of row j
 constexpr int kSchedUnroll = 8;  // 64-column chunks of a pivot row loaded per round
 
 __device__ __forceinline__ int32_t sched_bucket(int64_t off, uint64_t mul) {
     return static_cast<int32_t>((static_cast<uint64_t>(off) * mul) >> 24);
 }
 
+// Modes: 0 counts the pairs of every pivot slot (scount) and records its
+// pivot's diagonal slot (lsd); 1 writes them at sptr (the scan of the
+// counts); 2 does both in one pass: the counts as mode 0, and the pairs, in
+// order, to a pool.  A wavefront takes the pool a chunk of pool.chunk pairs
+// at a time (one atomic per chunk) and writes each round's pairs straight
+// into its chunk; a run of one row's pairs inside one chunk is a segment
+// (row, index of its first pair within the row, pool position, count),
+// closed when the row ends or the chunk is full.  k_sched_copy then moves
+// each segment to sptr[first slot of its row] + that index.  If the pool or
+// the segment list is too small, mode 2 raises *overflow and stops storing
+// (the counts stay exact): the caller then runs mode 1.  Mode 3 only adds
+// the sampled rows' pair count into sample[0] and their candidate count into
+// sample[2] (rows j with j % stride == 0), to size the pool and to decide
+// whether one pass pays.
+// DirT: uint16_t when every row has fewer than 65536 entries (half the LDS
+// of int32_t, which keeps more wavefronts resident: random n=160,000 ILU(1),
+// rows of ~1,250 entries, 400 -> 332 ms with 1,024 buckets; 256 buckets of
+// int32_t took 400 ms, 1,024 of int32_t 398 ms, 4,096 of uint16_t 412 ms).
+// split > 1 (mode 3): each sampled row is shared by `split` wavefronts, each
+// taking every split-th block of 64 pivots, so the few sampled rows still
+// fill the device.
+template <typename DirT>
 __global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restrict__ rpF,
                                               const int32_t* __restrict__ ciF,
                                               const int32_t* __restrict__ diagF, int mode,
                                               int32_t* __restrict__ scount, int32_t* __restrict__ lsd,
                                               const int64_t* __restrict__ sptr,
-                                              int32_t* __restrict__ sq, int32_t* __restrict__ sp) {
+                                              int32_t* __restrict__ sq, int32_t* __restrict__ sp,
+                                              SchedPool pool, int32_t max_row, int32_t stride,
+                                              int32_t split) {
     extern __shared__ int32_t colsj[];
     // Row j's sorted columns get a directory: bucket b of [c_min, c_max]
     // holds the columns at positions dir[b] .. dir[b+1]-1, so a candidate t
     // is searched among a handful of columns instead of the whole row.
-    __shared__ int32_t dir[kSchedDir + 1];
+    __shared__ DirT dir[kSchedDir + 1];
     // the pivots of the row, 64 at a time: diagonal slot and row end of each
     __shared__ int32_t pdh[kWave], phe[kWave];
     __shared__ int64_t pout[kWave];
     const int lane = lane_id();
-    for (int32_t j = blockIdx.x; j < n; j += gridDim.x) {
+    const bool counts = mode == 0 || mode == 2;
+    int64_t cbase = -1;          // mode 2: pool position of the wavefront's chunk (-2: pool exhausted)
+    int32_t used = 0, seg0 = 0;  // pairs used in the chunk; start of the open segment
+    const int64_t nsampled = ((int64_t)n + stride - 1) / stride;
+    for (int64_t task = blockIdx.x; task < nsampled * split; task += gridDim.x) {
+        const int32_t j = (int32_t)((task / split) * stride);
+        const int32_t part = (int32_t)(task % split);
         const int64_t rs = rpF[j], re = rpF[j + 1];
         const int32_t len = static_cast<int32_t>(re - rs);
         const int64_t dj = diagF[j];
+        // mode 2: the open segment is [seg0, used) of the current chunk
+        int64_t row_done = 0;  // pairs of this row in closed segments
+        auto close_seg = [&]() {
+            if (cbase >= 0 && used > seg0) {
+                unsigned long long g = 0;
+                if (lane == 0) g = atomicAdd(pool.ctr + 1, 1ull);
+                g = __shfl(g, 0);
+                if (g < (unsigned long long)pool.seg_cap) {
+                    if (lane == 0) pool.seg[g] = make_longlong4(j, row_done, cbase + seg0, used - seg0);
+                } else if (lane == 0) {
+                    atomicOr(pool.overflow, 1u);
+                }
+                row_done += used - seg0;
+            }
+            seg0 = used;
+        };
         for (int32_t e = lane; e < len; e += kWave) colsj[e] = ciF[rs + e];
-        if (mode == 0)
+        if (counts)
             for (int64_t s = dj + lane; s < re; s += kWave) scount[s] = 0;
         wave_sync();
         const int32_t cmin = colsj[0];
         const int64_t range = (int64_t)colsj[len - 1] - cmin + 1;
-        // off < range < 2^31 and mul <= 2^32: the product fits in 64 bits,
+        // off < range < 2^31 and mul <= 2^34: the product fits in 64 bits,
         // and the bucket of any off < range is below kSchedDir
         const uint64_t mul = ((uint64_t)kSchedDir << 24) / (uint64_t)range;
         for (int32_t b = lane; b <= kSchedDir; b += kWave) {
@@ -517,10 +743,10 @@ __global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restri
                 if (bm < b) lo = mid + 1;
                 else hi = mid;
             }
-            dir[b] = lo;
+            dir[b] = (DirT)lo;
         }
         wave_sync();
-        for (int64_t s0 = rs; s0 < dj; s0 += kWave) {
+        for (int64_t s0 = rs + (int64_t)part * kWave; s0 < dj; s0 += (int64_t)kWave * split) {
             const int32_t np = static_cast<int32_t>(min<int64_t>(kWave, dj - s0));
             if (lane < np) {
                 const int32_t h = ciF[s0 + lane];
@@ -528,7 +754,7 @@ __global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restri
                 pdh[lane] = dh;
                 phe[lane] = static_cast<int32_t>(rpF[h + 1]);
                 pout[lane] = mode == 1 ? sptr[s0 + lane] : 0;
-                if (mode == 0) lsd[s0 + lane] = dh;
+                if (counts) lsd[s0 + lane] = dh;
             }
             wave_sync();
             for (int32_t p = 0; p < np; ++p) {
@@ -552,7 +778,7 @@ __global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restri
                         if (q < he && off >= 0 && off < range) {
                             const int32_t t = tv[u];
                             const int32_t b = sched_bucket(off, mul);
-                            int32_t lo = max(lo0, dir[b]), hi = dir[b + 1] - 1;
+                            int32_t lo = max(lo0, (int32_t)dir[b]), hi = (int32_t)dir[b + 1] - 1;
                             while (lo <= hi) {
                                 const int32_t mid = (lo + hi) >> 1;
                                 const int32_t c = colsj[mid];
@@ -567,25 +793,88 @@ __global__ __launch_bounds__(64) void k_sched(int32_t n, const int64_t* __restri
                             sq[out + found + rank] = static_cast<int32_t>(q);
                             sp[out + found + rank] = static_cast<int32_t>(rs + pos);
                         }
+                        if (mode == 2 && m && cbase != -2) {
+                            const int32_t c = __popcll(m);
+                            if (cbase < 0 || used + c > pool.chunk) {
+                                close_seg();
+                                unsigned long long at = 0;
+                                if (lane == 0) at = atomicAdd(pool.ctr, (unsigned long long)pool.chunk);
+                                at = __shfl(at, 0);
+                                if (at + (unsigned long long)pool.chunk > (unsigned long long)pool.cap) {
+                                    if (lane == 0) atomicOr(pool.overflow, 1u);
+                                    cbase = -2;
+                                } else {
+                                    cbase = (int64_t)at;
+                                }
+                                used = 0;
+                                seg0 = 0;
+                            }
+                            if (cbase >= 0) {
+                                if (pos >= 0) {
+                                    const int32_t rank = __popcll(m & ((1ull << lane) - 1ull));
+                                    pool.q[cbase + used + rank] = static_cast<int32_t>(q);
+                                    pool.p[cbase + used + rank] = static_cast<int32_t>(rs + pos);
+                                }
+                                used += c;
+                            }
+                        }
                         found += __popcll(m);
                     }
                 }
-                if (mode == 0 && lane == 0) scount[s] = found;
+                if (counts && lane == 0) scount[s] = found;
+                if (mode == 3 && lane == 0) {
+                    if (found) atomicAdd(pool.sample, (unsigned long long)found);
+                    if (he > dh + 1) atomicAdd(pool.sample + 2, (unsigned long long)(he - dh - 1));
+                }
             }
             wave_sync();
         }
+        if (mode == 2) close_seg();
         wave_sync();
     }
 }
 
+// mode 2's segments to their places: one wavefront per segment
+__global__ __launch_bounds__(64) void k_sched_copy(SchedPool pool, int64_t nseg, const int64_t* __restrict__ rpF,
+                                                   const int64_t* __restrict__ sptr, int32_t* __restrict__ sq,
+                                                   int32_t* __restrict__ sp) {
+    const int lane = lane_id();
+    for (int64_t g = blockIdx.x; g < nseg; g += gridDim.x) {
+        const longlong4 d = pool.seg[g];
+        const int64_t dst = sptr[rpF[d.x]] + d.y;
+        for (int64_t e = lane; e < d.w; e += kWave) {
+            sq[dst + e] = pool.q[d.z + e];
+            sp[dst + e] = pool.p[d.z + e];
+        }
+    }
+}
+
+hipError_t launch_sched_copy(const SchedPool& pool, int64_t nseg, const int64_t* rpF, const int64_t* sptr,
+                             int32_t* sq, int32_t* sp, hipStream_t s) {
+    if (nseg <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(nseg, 65536);
+    hipLaunchKernelGGL(k_sched_copy, dim3(grid), dim3(64), 0, s, pool, nseg, rpF, sptr, sq, sp);
+    return hipGetLastError();
+}
+
 hipError_t launch_sched(int32_t n, const int64_t* rpF, const int32_t* ciF, const int32_t* diagF,
                         int mode, int32_t* scount, int32_t* lsd, const int64_t* sptr,
-                        int32_t* sq, int32_t* sp, int32_t max_row, hipStream_t s) {
-    size_t lds = (size_t)max(max_row, 1) * sizeof(int32_t);
-    int grid = min(n, 65536);
+                        int32_t* sq, int32_t* sp, int32_t max_row, hipStream_t s, const SchedPool* pool,
+                        int32_t stride) {
+    const int32_t mr = max(max_row, 1);
+    size_t lds = (size_t)mr * sizeof(int32_t);
+    stride = max(stride, 1);
+    const int32_t split = mode == 3 ? kSchedSampleSplit : 1;
+    const int64_t tasks = ((int64_t)n + stride - 1) / stride * split;
+    int grid = (int)std::min<int64_t>(tasks, 65536);
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sched, dim3(grid), dim3(64), lds, s, n, rpF, ciF, diagF, mode, scount,
-                       lsd, sptr, sq, sp);
+    const SchedPool none{};
+    if (mr < 65536)
+        hipLaunchKernelGGL(k_sched<uint16_t>, dim3(grid), dim3(64), lds, s, n, rpF, ciF, diagF, mode, scount,
+                           lsd, sptr, sq, sp, pool ? *pool : none, mr, stride, split);
+    else
+        hipLaunchKernelGGL(k_sched<int32_t>, dim3(grid), dim3(64), lds, s, n, rpF, ciF, diagF, mode, scount,
+                           lsd, sptr, sq, sp, pool ? *pool : none, mr, stride, split);
     return hipGetLastError();
 }
 

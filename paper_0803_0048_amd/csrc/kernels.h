@@ -34,6 +34,11 @@ hipError_t launch_sym_rows(int tier, int32_t n, const int64_t* rpA, const int32_
 __host__ __device__ size_t sym_global_scratch_ints(int32_t n, uint32_t gcap);  // per block
 
 // rows (of `list`, or 0..n_rows-1) with cnt < 0 -> row_list, *n_over; tier_of[row] = tier
+// rows whose one-step bound passes `limit` into list1 (and tier_of 1),
+// the others into list0; counts[0], counts[1] are their running sizes (pre-set)
+hipError_t launch_route_rows(int32_t n, const int64_t* rpA, const int32_t* ciA, int32_t* nup, int64_t limit,
+                             int32_t* list0, int32_t* list1, int32_t* counts, uint8_t* tier_of, hipStream_t s);
+int64_t sym_route_limit();
 hipError_t launch_collect_overflow(int32_t n_rows, const int32_t* list, const int32_t* cnt, int32_t* row_list,
                                    int32_t* n_over, uint8_t* tier_of, int tier, hipStream_t s);
 
@@ -46,9 +51,30 @@ hipError_t launch_a2f(int32_t n, const int64_t* rpA, const int32_t* ciA, const i
 
 // update schedule: mode 0 counts matches per L slot (and writes lsd = diag
 // slot of the pivot), mode 1 writes the (q, p) pairs
+// the pool of the one-pass schedule (k_sched mode 2) and the sample counter
+// of mode 3; seg entries are (row, index of the first pair within the row,
+// pool position, count); ctr[0] = pairs taken (whole chunks), ctr[1] =
+// segments taken
+struct SchedPool {
+    int32_t* q = nullptr;
+    int32_t* p = nullptr;
+    int64_t cap = 0;
+    int32_t chunk = 0;  // pairs a wavefront takes at a time
+    longlong4* seg = nullptr;
+    int64_t seg_cap = 0;
+    unsigned long long* ctr = nullptr;
+    uint32_t* overflow = nullptr;
+    unsigned long long* sample = nullptr;
+};
 hipError_t launch_sched(int32_t n, const int64_t* rpF, const int32_t* ciF, const int32_t* diagF,
                         int mode, int32_t* scount, int32_t* lsd, const int64_t* sptr,
-                        int32_t* sq, int32_t* sp, int32_t max_row, hipStream_t s);
+                        int32_t* sq, int32_t* sp, int32_t max_row, hipStream_t s,
+                        const SchedPool* pool = nullptr, int32_t stride = 1);
+constexpr int32_t kSchedSampleStride = 241;  // rows sampled (j % 241 == 0) to size the pool
+constexpr int32_t kSchedSampleSplit = 16;   // wavefronts sharing one sampled row
+constexpr int64_t kSchedOnePassRatio = 8;   // candidates per pair above which the one-pass schedule runs
+hipError_t launch_sched_copy(const SchedPool& pool, int64_t nseg, const int64_t* rpF, const int64_t* sptr,
+                             int32_t* sq, int32_t* sp, hipStream_t s);
 
 struct PatStats {
     unsigned long long nnz_l;

@@ -1046,20 +1046,34 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
     // ---- a2: level-of-fill pattern, count pass
     TmpBufs T{P->al, {}};
     int32_t* cnt = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);
-    int32_t* over_list = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);  // rows past tier 0
+    int32_t* list0 = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);      // rows tier 0 builds first
+    int32_t* over_list = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);  // rows for tier 1
     int32_t* over2_list = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);  // rows past tier 1
     int32_t* over_n = (int32_t*)T.get(64);
     uint8_t* tier_of = (uint8_t*)T.get((size_t)n + 4);
     int64_t* scan_tmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(n));
-    if (!cnt || !over_list || !over2_list || !over_n || !tier_of || !scan_tmp)
+    if (!cnt || !list0 || !over_list || !over2_list || !over_n || !tier_of || !scan_tmp)
         return bail(fail(ctx, TPILU_E_NOMEM, "symbolic scratch"));
     HIPCHK(ctx, launch_fill_i32((int32_t*)tier_of, (n + 4) / 4, 0, s));
+    HIPCHK(ctx, launch_fill_i32(over_n, 4, 0, s));
     const int sym_grid = std::min<int64_t>(n, (int64_t)ctx->num_cu * 4);
-    trace("symbolic: count pass", n, k);
-    HIPCHK(ctx, launch_sym_rows(0, ni, P->rpA, P->ciA, k, nullptr, ni, 0, cnt, nullptr, nullptr,
-                                nullptr, nullptr, nullptr, nullptr, 0, sym_grid, s));
-    HIPCHK(ctx, launch_fill_i32(over_n, 2, 0, s));
-    HIPCHK(ctx, launch_collect_overflow(ni, nullptr, cnt, over_list, over_n, tier_of, 1, s));
+    // rows whose one-step bound already passes tier 0's capacity start in
+    // tier 1 (over_list[0, n_pred)); the rest (list0) start in tier 0
+    int32_t n0 = ni;
+    if (k >= 1) {
+        HIPCHK(ctx, launch_route_rows(ni, P->rpA, P->ciA, cnt, sym_route_limit(), list0, over_list, over_n + 2,
+                                      tier_of, s));
+        int32_t rc[2] = {0, 0};
+        HIPCHK(ctx, hipMemcpyAsync(rc, over_n + 2, sizeof(rc), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        n0 = rc[0];
+        HIPCHK(ctx, hipMemcpyAsync(over_n, over_n + 3, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    const int32_t* l0 = k >= 1 ? list0 : nullptr;
+    trace("symbolic: count pass, rows starting in tier 0", n, n0);
+    HIPCHK(ctx, launch_sym_rows(0, ni, P->rpA, P->ciA, k, l0, n0, 0, cnt, nullptr, nullptr,
+                                nullptr, nullptr, nullptr, nullptr, 0, std::min(std::max(n0, 1), sym_grid), s));
+    HIPCHK(ctx, launch_collect_overflow(n0, l0, cnt, over_list, over_n, tier_of, 1, s));
     int32_t n_over = 0, n_over2 = 0;
     HIPCHK(ctx, hipMemcpyAsync(&n_over, over_n, sizeof(n_over), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
@@ -1103,8 +1117,8 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
     if (!P->ciF || !P->lvF || !P->diagF || !P->a2f || !P->lsd || !P->sptr)
         return bail(fail(ctx, TPILU_E_NOMEM, "pattern arrays"));
     // fill pass
-    HIPCHK(ctx, launch_sym_rows(0, ni, P->rpA, P->ciA, k, nullptr, ni, 1, cnt, P->rpF, P->ciF, P->lvF,
-                                P->diagF, tier_of, nullptr, 0, sym_grid, s));
+    HIPCHK(ctx, launch_sym_rows(0, ni, P->rpA, P->ciA, k, l0, n0, 1, cnt, P->rpF, P->ciF, P->lvF,
+                                P->diagF, tier_of, nullptr, 0, std::min(std::max(n0, 1), sym_grid), s));
     if (n_over > 0)
         HIPCHK(ctx, launch_sym_rows(1, ni, P->rpA, P->ciA, k, over_list, n_over, 1, cnt, P->rpF, P->ciF,
                                     P->lvF, P->diagF, tier_of, nullptr, 0, std::min(n_over, sym_grid), s));
@@ -1149,24 +1163,78 @@ extern "C" TPILU_API tpilu_status tpilu_symbolic(tpilu_ctx ctx, int64_t n, int64
         tpilu_status ls = enqueue_levels(ctx, P, ljobs, 2, ctx->aux, T, &ldmax);
         if (ls != TPILU_OK) return bail(ls);
     }
-    // ---- update schedule for Phase II
-    trace("symbolic: schedule count", P->st.max_row, P->st.max_lrow);
+    // ---- update schedule for Phase II: one search pass that counts and
+    // stages the pairs in a pool (sized from a sample of the rows), a scan,
+    // and a copy into place; the two-pass form (count, then search again and
+    // write) when the pool cannot be had or turns out too small
+    trace("symbolic: schedule", P->st.max_row, P->st.max_lrow);
     int32_t* scount = (int32_t*)T.get(sizeof(int32_t) * (size_t)nnzf);
     int64_t* scan2 = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(nnzf));
-    if (!scount || !scan2) return bail(fail(ctx, TPILU_E_NOMEM, "schedule scratch"));
-    HIPCHK(ctx, launch_sched(ni, P->rpF, P->ciF, P->diagF, 0, scount, P->lsd, nullptr, nullptr, nullptr,
-                             P->st.max_row, s));
+    unsigned long long* sctr = (unsigned long long*)T.get(64);
+    if (!scount || !scan2 || !sctr) return bail(fail(ctx, TPILU_E_NOMEM, "schedule scratch"));
+    HIPCHK(ctx, launch_fill_i32((int32_t*)sctr, 16, 0, s));
+    SchedPool pool{};
+    pool.ctr = sctr;
+    pool.sample = sctr + 2;  // [0] pairs, [2] candidates
+    pool.overflow = (uint32_t*)(sctr + 3);
+    HIPCHK(ctx, launch_sched(ni, P->rpF, P->ciF, P->diagF, 3, nullptr, nullptr, nullptr, nullptr, nullptr,
+                             P->st.max_row, s, &pool, kSchedSampleStride));
+    unsigned long long sample[3] = {0, 0, 0};  // pairs, (unused), candidates of the sampled rows
+    HIPCHK(ctx, hipMemcpyAsync(sample, pool.sample, sizeof(sample), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    // One pass saves a second search (about one probe per candidate) and
+    // costs a copy of the pairs and the sample; taken when candidates
+    // outnumber pairs kSchedOnePassRatio to 1 (measured on MI355X: random
+    // n=160,000 ILU(1), 55 candidates per pair, 697 -> 434 ms; 27-point 50^3
+    // ILU(3), few candidates per pair, 53 ms with two passes, 57 with one)
+    {
+        const int64_t est = (int64_t)sample[0] * kSchedSampleStride;
+        const bool worth = (int64_t)sample[2] > kSchedOnePassRatio * (int64_t)sample[0];
+        // chunks of about a quarter of a wavefront's expected share (64 to
+        // 4096 pairs): few atomics, and little left unused in the chunks
+        // the wavefronts hold when they finish
+        const int64_t waves = std::min<int64_t>(n, 65536);
+        pool.chunk = (int32_t)std::min<int64_t>(4096, std::max<int64_t>(64, (est / waves / 4 + 63) / 64 * 64));
+        pool.cap = est + est / 2 + waves * pool.chunk + (1 << 20);
+        pool.seg_cap = pool.cap / pool.chunk + n + 1;
+        size_t free_b = 0, total_b = 0;
+        const bool fits = worth && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+                          (size_t)pool.cap * 8 + (size_t)pool.seg_cap * 32 <= free_b / 3;
+        if (fits) {
+            pool.q = (int32_t*)T.get(sizeof(int32_t) * (size_t)pool.cap);
+            pool.p = (int32_t*)T.get(sizeof(int32_t) * (size_t)pool.cap);
+            pool.seg = (longlong4*)T.get(sizeof(longlong4) * (size_t)pool.seg_cap);
+        }
+        if (!pool.q || !pool.p || !pool.seg) {
+            pool.cap = 0;
+            pool.seg_cap = 0;
+        }
+    }
+    const bool one_pass = pool.cap > 0;
+    trace("symbolic: schedule pool (pairs), one pass", pool.cap, one_pass);
+    if (one_pass)
+        HIPCHK(ctx, launch_sched(ni, P->rpF, P->ciF, P->diagF, 2, scount, P->lsd, nullptr, nullptr, nullptr,
+                                 P->st.max_row, s, &pool));
+    else
+        HIPCHK(ctx, launch_sched(ni, P->rpF, P->ciF, P->diagF, 0, scount, P->lsd, nullptr, nullptr, nullptr,
+                                 P->st.max_row, s));
     HIPCHK(ctx, launch_scan(scount, nnzf, P->sptr, scan2, s));
     int64_t nupd = 0;
+    unsigned long long pc[4] = {0, 0, 0, 0};
     HIPCHK(ctx, hipMemcpyAsync(&nupd, P->sptr + nnzf, sizeof(nupd), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(pc, sctr, sizeof(pc), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     P->n_updates = nupd;
-    trace("symbolic: schedule fill, updates", nupd);
+    const bool pooled = one_pass && (pc[3] & 0xffffffffull) == 0;
+    trace("symbolic: schedule updates, taken from the pool", nupd, pooled);
     P->sq = (int32_t*)P->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nupd, 1));
     P->sp = (int32_t*)P->take(sizeof(int32_t) * (size_t)std::max<int64_t>(nupd, 1));
     if (!P->sq || !P->sp) return bail(fail(ctx, TPILU_E_NOMEM, "schedule"));
-    HIPCHK(ctx, launch_sched(ni, P->rpF, P->ciF, P->diagF, 1, nullptr, nullptr, P->sptr, P->sq, P->sp,
-                             P->st.max_row, s));
+    if (pooled)
+        HIPCHK(ctx, launch_sched_copy(pool, (int64_t)pc[1], P->rpF, P->sptr, P->sq, P->sp, s));
+    else
+        HIPCHK(ctx, launch_sched(ni, P->rpF, P->ciF, P->diagF, 1, nullptr, nullptr, P->sptr, P->sq, P->sp,
+                                 P->st.max_row, s));
     // ---- the same schedule by target, for the dataflow numeric kernel
     if (numeric_flow_fits(P->st.max_row, P->st.max_lrow, kBatchLdsLimit) &&
         tsched_lds_bytes(P->st.max_row, P->st.max_lrow) <= kBatchLdsLimit) {
