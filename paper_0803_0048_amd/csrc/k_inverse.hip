@@ -253,16 +253,19 @@ __global__ __launch_bounds__(64) void k_apply_inverse_wave(PatDev P, const doubl
 // mostly stages nothing; 7-point 64^3 ILU(1), about 6 entries per half:
 // 0.021 ms with 8, 0.042 with 16, both products), else 16 (27-point 50^3
 // ILU(3), about 82 per half: 0.134 ms with 16, 0.149 with 8, 0.228 with 32).
+// rows (nullable): the order rows are taken in, 64 to a wavefront; sorted by
+// the length of the half they sum, so the rows of one wavefront are about
+// equally long and its lanes finish together
 template <bool kUpper, int kTile>
 __global__ __launch_bounds__(64) void k_apply_inverse_tile(PatDev P, const double* __restrict__ G,
-                                                      const double* __restrict__ in, double* __restrict__ out) {
+                                                      const double* __restrict__ in, double* __restrict__ out,
+                                                      const int32_t* __restrict__ rows) {
     constexpr int kTileStride = kTile + 1;  // odd stride: lanes reading their rows hit distinct banks
-    __shared__ double tv[kWave * kTileStride];
-    __shared__ int32_t tc[kWave * kTileStride];
+    __shared__ double tv[kWave * kTileStride];  // the staged products g_ij * in_j
     const int lane = lane_id();
     for (int64_t r0 = (int64_t)blockIdx.x * kWave; r0 < P.n; r0 += (int64_t)gridDim.x * kWave) {
-        const int64_t i = r0 + lane;
-        const bool has = i < P.n;
+        const bool has = r0 + lane < P.n;
+        const int64_t i = !has ? 0 : rows ? (int64_t)rows[r0 + lane] : r0 + lane;
         int64_t a = 0, b = 0;
         if (has) {
             const int64_t dj = P.diagF[i];
@@ -273,28 +276,39 @@ __global__ __launch_bounds__(64) void k_apply_inverse_tile(PatDev P, const doubl
         for (int off = 32; off > 0; off >>= 1) maxlen = max(maxlen, (int64_t)__shfl_xor(maxlen, off));
         double s = 0.0;
         for (int64_t k0 = 0; k0 < maxlen; k0 += kTile) {
-            // stage entries k0 .. k0+kTile-1 of every row: instruction u loads
-            // rows u*(64/kTile) .. +(64/kTile)-1, kTile entries each
+            // stage the products of entries k0 .. k0+kTile-1 of every row:
+            // instruction u takes rows u*(64/kTile) .. +(64/kTile)-1, kTile
+            // consecutive entries each, so both the entries and the gathered
+            // in_j of one row (sorted columns, often close together) come in
+            // whole lines; each lane then adds its own row's products in order
+            // in three phases (column and value loads of every u, then the
+            // gathers, then the products), so a round costs two memory
+            // latencies; entries past a row's end load a clamped, in-bounds
+            // slot and are not stored
+            int32_t cu[kTile];
+            double gu[kTile];
+            uint32_t on = 0u;
+            const int kk = lane % kTile;  // entry of the row's slice
 #pragma unroll
             for (int u = 0; u < kTile; ++u) {
                 const int rr = u * (kWave / kTile) + lane / kTile;  // row of the tile
-                const int kk = lane % kTile;                        // entry of that row's slice
                 const int64_t ar = __shfl(a, rr), br = __shfl(b, rr);
                 const int64_t e = ar + k0 + kk;
-                if (e < br) {
-                    tv[rr * kTileStride + kk] = G[e];
-                    tc[rr * kTileStride + kk] = P.ciF[e];
-                }
+                if (e < br) on |= 1u << u;
+                const int64_t ec = e < br ? e : (br > ar ? br - 1 : 0);
+                cu[u] = P.ciF[ec];
+                gu[u] = G[ec];
             }
+#pragma unroll
+            for (int u = 0; u < kTile; ++u) gu[u] = gu[u] * in[cu[u]];
+#pragma unroll
+            for (int u = 0; u < kTile; ++u)
+                if (on & (1u << u)) tv[(u * (kWave / kTile) + lane / kTile) * kTileStride + kk] = gu[u];
             wave_sync();
             const int32_t cnt = (int32_t)max<int64_t>(0, min<int64_t>(kTile, len - k0));
-            double prod[kTile];
 #pragma unroll
             for (int kk = 0; kk < kTile; ++kk)
-                prod[kk] = kk < cnt ? tv[lane * kTileStride + kk] * in[tc[lane * kTileStride + kk]] : 0.0;
-#pragma unroll
-            for (int kk = 0; kk < kTile; ++kk)
-                if (kk < cnt) s = s + prod[kk];
+                if (kk < cnt) s = s + tv[lane * kTileStride + kk];
             wave_sync();
         }
         if (has) {
@@ -321,8 +335,26 @@ __global__ __launch_bounds__(256) void k_apply_inverse_rows(PatDev P, const doub
     out[i] = s;
 }
 
+// Keys the tiled products sort their rows by (launch_level_order takes keys
+// from 1): 1 + the length of the strict lower half (lenL) or of the upper
+// half with the diagonal (lenU), each at most the longest row
+__global__ void k_half_lengths(int32_t n, const int64_t* __restrict__ rpF, const int32_t* __restrict__ diagF,
+                               int32_t* __restrict__ lenL, int32_t* __restrict__ lenU) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    lenL[i] = 1 + (int32_t)(diagF[i] - rpF[i]);
+    lenU[i] = 1 + (int32_t)(rpF[i + 1] - diagF[i]);
+}
+
+hipError_t launch_half_lengths(int32_t n, const int64_t* rpF, const int32_t* diagF, int32_t* lenL, int32_t* lenU,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_half_lengths, dim3((n + 255) / 256), dim3(256), 0, s, n, rpF, diagF, lenL, lenU);
+    return hipGetLastError();
+}
+
 hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const double* b, double* x, double* y,
-                                int shape, hipStream_t s) {
+                                int shape, const int32_t* rowsL, const int32_t* rowsU, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
     if (shape == kProdThreadRows) {
         const int grid = (P.n + 255) / 256;
@@ -331,11 +363,13 @@ hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const doub
     } else if (shape == kProdTile || shape == kProdTileShort) {
         const int grid = std::min((P.n + kWave - 1) / kWave, 65536);
         if (shape == kProdTileShort) {
-            hipLaunchKernelGGL((k_apply_inverse_tile<false, 8>), dim3(grid), dim3(64), 0, s, P, g_val, b, x);
-            hipLaunchKernelGGL((k_apply_inverse_tile<true, 8>), dim3(grid), dim3(64), 0, s, P, g_val, x, y);
+            hipLaunchKernelGGL((k_apply_inverse_tile<false, 8>), dim3(grid), dim3(64), 0, s, P, g_val, b, x, rowsL);
+            hipLaunchKernelGGL((k_apply_inverse_tile<true, 8>), dim3(grid), dim3(64), 0, s, P, g_val, x, y, rowsU);
         } else {
-            hipLaunchKernelGGL((k_apply_inverse_tile<false, 16>), dim3(grid), dim3(64), 0, s, P, g_val, b, x);
-            hipLaunchKernelGGL((k_apply_inverse_tile<true, 16>), dim3(grid), dim3(64), 0, s, P, g_val, x, y);
+            hipLaunchKernelGGL((k_apply_inverse_tile<false, 16>), dim3(grid), dim3(64), 0, s, P, g_val, b, x,
+                               rowsL);
+            hipLaunchKernelGGL((k_apply_inverse_tile<true, 16>), dim3(grid), dim3(64), 0, s, P, g_val, x, y,
+                               rowsU);
         }
     } else {
         const int grid = std::min(P.n, 65536);

@@ -111,7 +111,8 @@ struct LevelJob {
 // those of one XCD per job working).  Abort and watchdog state live in ctl.
 hipError_t launch_depth(int32_t n, const LevelJob& j0, const LevelJob* j1, Ctl* ctl, uint64_t spin_limit,
                         int32_t grid, bool one_xcd, hipStream_t s);
-// perm = nodes sorted by level (counting sort); hist needs 2 * max_depth ints
+// perm = nodes sorted by level (counting sort); levels are 1 .. max_depth
+// (depth[i] >= 1); hist needs 2 * max_depth ints
 hipError_t launch_level_order(int32_t n, const int32_t* depth, int32_t max_depth, int32_t* hist,
                               int64_t* off, int64_t* scan_tmp, int32_t* perm, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
@@ -299,8 +300,11 @@ hipError_t launch_inverse(const PatDev& P, const InvSched& S, const double* f_va
 // shapes of the two products of the incomplete inverses
 // (kProdTile stages 16 entries per row and round, kProdTileShort 8)
 enum { kProdWaveRows = 0, kProdThreadRows = 1, kProdTile = 2, kProdTileShort = 3 };
+// rowsL / rowsU (nullable): the tiled products' row orders (by half length)
 hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const double* b, double* x, double* y,
-                                int shape, hipStream_t s);
+                                int shape, const int32_t* rowsL, const int32_t* rowsU, hipStream_t s);
+hipError_t launch_half_lengths(int32_t n, const int64_t* rpF, const int32_t* diagF, int32_t* lenL, int32_t* lenU,
+                               hipStream_t s);
 
 // ---- hand-off probe -------------------------------------------------------------------
 size_t probe_buf_bytes();
