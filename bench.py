@@ -244,6 +244,9 @@ def main():
     ap.add_argument("--numeric-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--step-only", action="store_true",
+                    help="only the timed step and the numeric / apply timings (for profiling one workload): "
+                         "no latency floors, no other workloads, no extras")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--extra", choices=["batched", "reverse", "stencil27", "paper_scale", "conv_diff_3d",
@@ -365,7 +368,7 @@ def main():
 
     # latency floors: dependency critical path x measured hand-off time
     log("latency floors: hand-off probes and the elimination's critical path")
-    floors = latency_floors(T, ctx, pat, pinfo, avg, n)
+    floors = None if args.step_only else latency_floors(T, ctx, pat, pinfo, avg, n)
 
     out = {
         "metric": METRIC,
@@ -402,12 +405,13 @@ def main():
 
     # the other single-matrix workloads, every phase, GPU next to the oracle
     out["workloads"] = {}
-    for name, c in (("conv_diff_2d_64x64_ilu1", I.conv_diff_2d_64x64_ilu1()),
-                    *((f"conv_diff_3d_64cubed_ilu{kk}", I.conv_diff_3d_ilu(k=kk)) for kk in (0, 1, 2, 3))):
+    for name, c in () if args.step_only else (
+            ("conv_diff_2d_64x64_ilu1", I.conv_diff_2d_64x64_ilu1()),
+            *((f"conv_diff_3d_64cubed_ilu{kk}", I.conv_diff_3d_ilu(k=kk)) for kk in (0, 1, 2, 3))):
         log(f"workload {name}")
         out["workloads"][name] = single_workload(T, I, torch, np, ctx, c, oracle=not args.no_cpu_baseline)
 
-    if not args.no_extras:
+    if not args.no_extras and not args.step_only:
         out["extras"] = {}
         out["extras"]["batched"] = batched_extra(T, I, torch, np, dev, ctx, oracle=not args.no_cpu_baseline)
         out["extras"]["reverse_mode"] = reverse_extra(T, I, torch, np, dev, oracle=not args.no_cpu_baseline)
