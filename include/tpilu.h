@@ -139,15 +139,22 @@ TPILU_API tpilu_status tpilu_ctx_set_numeric(tpilu_ctx ctx, int mode);
  * device; a solve on one XCD when its device-wide shape would take at most
  * 256 wavefronts, i.e. a dependency level holds fewer than 32 rows, or fewer
  * than 64 short ones, and a row half at most 128 entries on average),
- * 1 = the whole device, 2 = one XCD (then also the dependency-level
- * computation of tpilu_symbolic, one XCD per dependency graph, when its
- * nodes have long dependency lists).  On one XCD, grid wavefronts are
+ * 1 = the whole device, 2 = one XCD (then also the batched factorization
+ * and solves, and the dependency-level computation of tpilu_symbolic, one XCD
+ * per dependency graph, when its nodes have long dependency lists).  On one
+ * XCD, grid wavefronts are
  * launched per XCD; the first workgroup to start names its XCD and the
  * workgroups of the other XCDs exit at once.  Values are then handed from
  * row to row through that XCD's L2 (ordinary stores, agent-scope loads)
  * instead of through memory, a round trip of about 0.5 us instead of 0.9 us
  * on MI355X: deep, narrow dependency graphs gain, work that needs many rows
- * in flight loses the other XCDs.  Same bits in every placement. */
+ * in flight loses the other XCDs.  Same bits in every placement.
+ * Assumption: that a workgroup-scope store by one CU is seen by an
+ * agent-scope load from another CU of the same XCD rests on the hardware
+ * (the CU's vector L1 writes through to the XCD's L2, which serves the
+ * agent-scope load), not on a promise of the scoped memory model; it is
+ * tested bit for bit in every placement (and under the race check build),
+ * and placement 1 never relies on it. */
 enum { TPILU_PLACE_AUTO = 0, TPILU_PLACE_DEVICE = 1, TPILU_PLACE_XCD = 2 };
 TPILU_API tpilu_status tpilu_ctx_set_placement(tpilu_ctx ctx, int where);
 
@@ -223,7 +230,7 @@ typedef struct {
     int32_t depth_u;     /* rows on the longest dependency chain of U~ (backward order) */
     int32_t overflow_rows; /* rows the symbolic pass had to redo in global memory */
     int32_t flow_ready;  /* 1 if the dataflow numeric kernel can run on this pattern */
-    int32_t long_rows;   /* rows the symbolic pass redid with its larger LDS maps */
+    int32_t long_rows;   /* rows the symbolic pass built with its larger LDS maps */
 } tpilu_pattern_info_t;
 
 TPILU_API tpilu_status tpilu_pattern_info(tpilu_pattern pat, tpilu_pattern_info_t *info /* host */);
