@@ -54,8 +54,8 @@ COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "random_banded_n160000_ilu2_hbm
 
 
 def library_source_digest():
-    """sha256 over the library's HIP sources and its header: what the HBM
-    counters in the committed summary were taken on."""
+    """sha256 over the library's HIP sources (kernels and runtime): what the
+    HBM counters in the committed summary were taken on."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_0803_0048_amd", "csrc")
@@ -63,8 +63,6 @@ def library_source_digest():
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode())
             h.update(fh.read())
-    with open(os.path.join(ROOT, "include", "tpilu.h"), "rb") as fh:
-        h.update(fh.read())
     return h.hexdigest()
 
 
