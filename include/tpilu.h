@@ -133,6 +133,17 @@ TPILU_API tpilu_status tpilu_ctx_set_solver(tpilu_ctx ctx, int mode);
 enum { TPILU_NUMERIC_AUTO = 0, TPILU_NUMERIC_FLOW = 1, TPILU_NUMERIC_PIVOT = 2 };
 TPILU_API tpilu_status tpilu_ctx_set_numeric(tpilu_ctx ctx, int mode);
 
+/* Rounding of the update of Eq. 6b (f_jt <- f_jt - l_jh u_ht) in the numeric
+ * factorization (tpilu_numeric and the batched graphs created afterwards):
+ * 0 (default) rounds the product and the difference on their own, 1 rounds
+ * the exact f_jt - l_jh u_ht once (a fused multiply-add).  Both are fixed
+ * by IEEE-754 binary64 alone, so either mode gives the same bits in every
+ * kernel, launch shape and placement, and matches a sequential CPU
+ * elimination computed the same way; the two modes differ from each other in
+ * the last bits.  The divisions, the substitutions, the incomplete inverses
+ * and the reverse mode are not affected.  TPILU_E_INVAL for other values. */
+TPILU_API tpilu_status tpilu_ctx_set_fused(tpilu_ctx ctx, int on);
+
 /* Placement of the single-instance numeric kernels, of the
  * wavefront-per-row solves and of the single-instance transposed solves of
  * tpilu_apply_adjoint: 0 = automatic (the numeric kernels on the whole

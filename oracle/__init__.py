@@ -54,6 +54,7 @@ def lib():
         L.orc_symbolic.argtypes = [i64, P, P, i32, C.POINTER(_Pattern)]
         L.orc_pattern_free.argtypes = [C.POINTER(_Pattern)]
         L.orc_numeric.argtypes = [i64, P, P, P, P, P, P, C.POINTER(i64)]
+        L.orc_numeric_fused.argtypes = [i64, P, P, P, P, P, P, C.POINTER(i64)]
         L.orc_numeric_rows.argtypes = [i64, P, P, P, P, P, P, i64, P, P]
         L.orc_apply.argtypes = [i64, P, P, P, P, P, P]
         L.orc_spmv.argtypes = [i64, P, P, P, P, P]
@@ -116,13 +117,16 @@ def symbolic(n, rowptr, col, k):
     return rpF, ciF, lvF
 
 
-def numeric(n, rowptr, col, val, rowptrF, colF):
-    """Row-wise IKJ elimination on the pattern.  Returns (F values, bad_row)."""
+def numeric(n, rowptr, col, val, rowptrF, colF, fused=False):
+    """Row-wise IKJ elimination on the pattern.  Returns (F values, bad_row).
+    ``fused``: every update f - l * u rounded once (fused multiply-add)
+    instead of product and difference rounded on their own."""
     rp, ci, v = _c(rowptr, np.int64), _c(col, np.int32), _c(val, np.float64)
     rpF, ciF = _c(rowptrF, np.int64), _c(colF, np.int32)
     vF = np.empty(ciF.shape[0], dtype=np.float64)
     bad = C.c_int64(-1)
-    st = lib().orc_numeric(n, _p(rp), _p(ci), _p(v), _p(rpF), _p(ciF), _p(vF), C.byref(bad))
+    fn = lib().orc_numeric_fused if fused else lib().orc_numeric
+    st = fn(n, _p(rp), _p(ci), _p(v), _p(rpF), _p(ciF), _p(vF), C.byref(bad))
     if st not in (OK, EZEROPIVOT):
         raise OracleError(st, "numeric")
     return vF, int(bad.value)

@@ -265,6 +265,9 @@ static int find_diag(int64_t n, const int64_t *rpF, const int32_t *ciF, int64_t 
 /* A zero pivot does not stop the elimination (IEEE division yields +-inf or */
 /* NaN); *bad_row receives the smallest row whose final pivot f_jj is +-0,   */
 /* or -1.                                                                    */
+/* The update is rounded in one of two ways: product and difference each     */
+/* rounded (orc_numeric), or the exact f_jt - f_jh * f_ht rounded once, a    */
+/* fused multiply-add (orc_numeric_fused).                                   */
 /* ------------------------------------------------------------------------ */
 /* Row j of the factor (Eq. 2 restricted to the pattern, IKJ order): A's row
  * scattered into F's pattern, then for every pivot h < j of the row in
@@ -274,7 +277,7 @@ static int find_diag(int64_t n, const int64_t *rpF, const int32_t *ciF, int64_t 
  * own slots.  slot_of must be all -1 on entry and is left so. */
 static int eliminate_row(int64_t j, const int64_t *rpA, const int32_t *ciA, const double *vA,
                          const int64_t *rpF, const int32_t *ciF, const int64_t *diag,
-                         int64_t *slot_of, const double *vpiv, double *row)
+                         int64_t *slot_of, const double *vpiv, double *row, int fused)
 {
     const int64_t r0 = rpF[j];
     int st = ORC_OK;
@@ -294,7 +297,7 @@ static int eliminate_row(int64_t j, const int64_t *rpA, const int32_t *ciA, cons
             double l = row[s - r0];
             for (int64_t q = diag[h] + 1; q < rpF[h + 1]; ++q) {
                 int64_t p = slot_of[ciF[q]];
-                if (p >= 0) row[p] = row[p] - l * vpiv[q];
+                if (p >= 0) row[p] = fused ? fma(-l, vpiv[q], row[p]) : row[p] - l * vpiv[q];
             }
         }
     }
@@ -302,8 +305,8 @@ static int eliminate_row(int64_t j, const int64_t *rpA, const int32_t *ciA, cons
     return st;
 }
 
-int orc_numeric(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
-                const int64_t *rpF, const int32_t *ciF, double *vF, int64_t *bad_row)
+static int numeric_impl(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
+                        const int64_t *rpF, const int32_t *ciF, double *vF, int64_t *bad_row, int fused)
 {
     *bad_row = -1;
     int64_t *slot_of = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
@@ -315,7 +318,7 @@ int orc_numeric(int64_t n, const int64_t *rpA, const int32_t *ciA, const double 
 
     for (int64_t j = 0; j < n; ++j) {
         /* rows are produced in order, so every pivot row is final in vF */
-        st = eliminate_row(j, rpA, ciA, vA, rpF, ciF, diag, slot_of, vF, vF + rpF[j]);
+        st = eliminate_row(j, rpA, ciA, vA, rpF, ciF, diag, slot_of, vF, vF + rpF[j], fused);
         if (st) break;
         if (vF[diag[j]] == 0.0 && *bad_row < 0) *bad_row = j;
     }
@@ -323,6 +326,18 @@ int orc_numeric(int64_t n, const int64_t *rpA, const int32_t *ciA, const double 
     free(diag);
     if (st) return st;
     return *bad_row >= 0 ? ORC_EZEROPIVOT : ORC_OK;
+}
+
+int orc_numeric(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
+                const int64_t *rpF, const int32_t *ciF, double *vF, int64_t *bad_row)
+{
+    return numeric_impl(n, rpA, ciA, vA, rpF, ciF, vF, bad_row, 0);
+}
+
+int orc_numeric_fused(int64_t n, const int64_t *rpA, const int32_t *ciA, const double *vA,
+                      const int64_t *rpF, const int32_t *ciF, double *vF, int64_t *bad_row)
+{
+    return numeric_impl(n, rpA, ciA, vA, rpF, ciF, vF, bad_row, 1);
 }
 
 /* The listed rows alone, each eliminated against the pivot rows given in
@@ -341,7 +356,7 @@ int orc_numeric_rows(int64_t n, const int64_t *rpA, const int32_t *ciA, const do
     for (int64_t r = 0; r < nrows && st == ORC_OK; ++r) {
         const int64_t j = rows[r];
         if (j < 0 || j >= n) { st = ORC_EINVAL; break; }
-        st = eliminate_row(j, rpA, ciA, vA, rpF, ciF, diag, slot_of, vF, out + o);
+        st = eliminate_row(j, rpA, ciA, vA, rpF, ciF, diag, slot_of, vF, out + o, 0);
         o += rpF[j + 1] - rpF[j];
     }
     free(slot_of);

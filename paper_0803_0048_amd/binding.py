@@ -22,7 +22,7 @@ OK, E_INVAL, E_NOMEM, E_ZEROPIVOT, E_DEVICE, E_NOTCONV, E_TIMEOUT = range(7)
 
 EXPORTED = [
     "tpilu_ctx_create", "tpilu_ctx_set_stream", "tpilu_ctx_destroy", "tpilu_status_string",
-    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_numeric", "tpilu_ctx_set_placement", "tpilu_ctx_set_group", "tpilu_ctx_set_tickets", "tpilu_inverse", "tpilu_apply_inverse", "tpilu_gmres_inverse", "tpilu_bicgstab", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
+    "tpilu_last_error", "tpilu_ctx_set_watchdog", "tpilu_ctx_set_grid", "tpilu_ctx_set_solver", "tpilu_ctx_set_numeric", "tpilu_ctx_set_fused", "tpilu_ctx_set_placement", "tpilu_ctx_set_group", "tpilu_ctx_set_tickets", "tpilu_inverse", "tpilu_apply_inverse", "tpilu_gmres_inverse", "tpilu_bicgstab", "tpilu_ctx_set_trace", "tpilu_ctx_set_timing", "tpilu_ctx_read_timing", "tpilu_symbolic", "tpilu_pattern_info",
     "tpilu_pattern_export", "tpilu_pattern_destroy", "tpilu_numeric", "tpilu_pattern_check",
     "tpilu_apply", "tpilu_gmres", "tpilu_spmv", "tpilu_dot", "tpilu_apply_adjoint",
     "tpilu_numeric_adjoint", "tpilu_batched_graph_create", "tpilu_batched_graph_launch",
@@ -75,6 +75,7 @@ def load_library():
             "tpilu_ctx_set_grid": ([P, i32], st),
             "tpilu_ctx_set_solver": ([P, C.c_int], st),
             "tpilu_ctx_set_numeric": ([P, C.c_int], st),
+            "tpilu_ctx_set_fused": ([P, C.c_int], st),
             "tpilu_ctx_set_placement": ([P, C.c_int], st),
             "tpilu_ctx_set_group": ([P, C.c_int32], st),
             "tpilu_ctx_set_tickets": ([P, C.c_int32], st),
@@ -167,6 +168,12 @@ class Context:
         """Kernel of the single-instance numeric factorization (same bits in
         every mode): 0 automatic, 1 dataflow, 2 pivot-serial."""
         self.check(load_library().tpilu_ctx_set_numeric(self.h, mode), "set_numeric")
+
+    def set_fused(self, on: bool = False):
+        """Update of the numeric factorization (Eq. 6b): False rounds the
+        product and the difference on their own, True rounds the exact
+        f - l * u once (fused multiply-add)."""
+        self.check(load_library().tpilu_ctx_set_fused(self.h, int(bool(on))), "set_fused")
 
     PLACE_AUTO, PLACE_DEVICE, PLACE_XCD = 0, 1, 2
 

@@ -73,6 +73,16 @@ __device__ __forceinline__ void jitter(uint32_t salt) {
 __device__ __forceinline__ void jitter(uint32_t) {}
 #endif
 
+// The update of Eq. 6b, f - l * u: by default the product and the difference
+// are rounded on their own; with kFused as one fused multiply-add (a single
+// rounding of the exact f - l * u).  Negating l is exact, so both forms
+// are fixed by IEEE-754 alone.
+template <bool kFused>
+__device__ __forceinline__ double ikj_update(double f, double l, double u) {
+    if constexpr (kFused) return __builtin_fma(-l, u, f);
+    else return f - l * u;
+}
+
 __device__ __forceinline__ uint64_t as_u64(double d) { return __builtin_bit_cast(uint64_t, d); }
 __device__ __forceinline__ double as_f64(uint64_t u) { return __builtin_bit_cast(double, u); }
 

@@ -108,7 +108,7 @@ __device__ __forceinline__ void wait_pivot(const double* F, int32_t i, int32_t n
 constexpr int kPivCap = 128;   // pivots staged per group
 constexpr int kPairCap = 512;  // update pairs staged per group
 
-template <Scope S>
+template <Scope S, bool kFused = false>
 __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __restrict__ a_val,
                                                     double* F, Ctl* ctl, uint64_t spin_limit,
                                                     int64_t skip_row) {
@@ -240,14 +240,14 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
                         const uint64_t vb = pr_v[e];
                         const double v = as_f64(vb == kPending ? kQNaN : vb);  // pending only after a timeout
                         const int32_t p = pr_p[e];
-                        W[p] = W[p] - l * v;
+                        W[p] = ikj_update<kFused>(W[p], l, v);
                     }
                 } else {
                     for (int64_t e = e0 + lane; e < e0 + npair; e += kWave) {
                         const int32_t q = P.sq[e];
                         const int32_t p = (int32_t)(P.sp[e] - rs);
                         const double v = wait_final(F + q, ctl, spin_limit);
-                        W[p] = W[p] - l * v;
+                        W[p] = ikj_update<kFused>(W[p], l, v);
                     }
                 }
                 wave_sync();
@@ -303,7 +303,7 @@ typedef __attribute__((address_space(3))) uint64_t LdsU64;
 // and the same waits, with the update acc - l * v replaced by
 // max(acc, l, v + w_hop) and the division by max(acc, u + w_hop) + w_step.
 // The largest value over F is the elimination's critical path.
-template <Scope S, bool kHops = false>
+template <Scope S, bool kHops = false, bool kFused = false>
 __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __restrict__ a_val, double* F,
                                                      Ctl* ctl, uint64_t spin_limit, int64_t skip_row,
                                                      int32_t max_row, int32_t cap, double w_hop = 1.0,
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
                             if constexpr (kHops)
                                 acc = fmax(acc, fmax(as_f64(lb), as_f64(vb) + w_hop));
                             else
-                                acc = acc - as_f64(lb) * as_f64(vb);
+                                acc = ikj_update<kFused>(acc, as_f64(lb), as_f64(vb));
                             ++e;
                             prog = true;
                         }
@@ -520,7 +520,7 @@ constexpr int kBWChunk = 8;  // values loaded per round trip (global working row
 // the rows of its pivots published when they finished.  Those rows finished
 // before this one, so the extra wait is short and off the chain the factor's
 // dependents wait on (the row's U part is published first).
-template <bool kGW, Scope S>
+template <bool kGW, Scope S, bool kFused = false>
 __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __restrict__ a_val,
                                                       int32_t B, double* F, Ctl* ctl,
                                                       uint64_t spin_limit, int64_t skip_row,
@@ -662,12 +662,14 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
 #pragma unroll
                                 for (int u = 0; u < kBWChunk; ++u)
                                     if (c + u < eb)
-                                        W[pc[u] * kWave + lane] = w[u] - l * as_f64(vv[(c + u) * kWave + lane]);
+                                        W[pc[u] * kWave + lane] =
+                                            ikj_update<kFused>(w[u], l, as_f64(vv[(c + u) * kWave + lane]));
                             }
                         } else {
                             for (int32_t e = ea; e < eb; ++e) {
                                 const int32_t p = pr_p[e];
-                                W[p * kWave + lane] = W[p * kWave + lane] - l * as_f64(vv[e * kWave + lane]);
+                                W[p * kWave + lane] =
+                                    ikj_update<kFused>(W[p * kWave + lane], l, as_f64(vv[e * kWave + lane]));
                             }
                         }
                         ++i;
@@ -737,14 +739,14 @@ __global__ __launch_bounds__(64) void k_numeric_batch(PatDev P, const double* __
                             const double v = wait_final(F + (int64_t)pr_q[e] * B + col,
                                                         vv[e * kWave + lane], ctl, spin_limit);
                             const int32_t p = pr_p[e];
-                            W[p * kWave + lane] = W[p * kWave + lane] - l * v;
+                            W[p * kWave + lane] = ikj_update<kFused>(W[p * kWave + lane], l, v);
                         }
                     } else {
                         for (int64_t e = e0; e < e0 + npair; ++e) {
                             const int32_t q = P.sq[e];
                             const int64_t p = P.sp[e] - rs;
                             const double v = wait_final(F + (int64_t)q * B + col, ctl, spin_limit);
-                            W[p * kWave + lane] = W[p * kWave + lane] - l * v;
+                            W[p * kWave + lane] = ikj_update<kFused>(W[p * kWave + lane], l, v);
                         }
                     }
                 }
@@ -852,7 +854,8 @@ int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, in
     return (int)(per_cu * (size_t)num_cu);
 }
 
-hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, double* f_val,
+template <bool kFused>
+hipError_t launch_numeric_t(const PatDev& P, const double* a_val, int32_t batch, double* f_val,
                           Ctl* ctl, uint64_t spin_limit, int64_t skip_row, int32_t grid,
                           int32_t max_row, int32_t max_lrow, bool flow, bool one_xcd, double* wrow,
                           const double* bvec, double* xout, hipStream_t s) {
@@ -862,39 +865,49 @@ hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, d
         const int32_t mr = std::max(max_row, 1), cap = flow_cap(max_lrow);
         const size_t lds = flow_lds_bytes(mr, cap);
         if (one_xcd)
-            hipLaunchKernelGGL(k_numeric_flow<Scope::Xcd>, g1, dim3(64), lds, s, P, a_val, f_val, ctl, spin_limit,
+            hipLaunchKernelGGL((k_numeric_flow<Scope::Xcd, false, kFused>), g1, dim3(64), lds, s, P, a_val, f_val, ctl, spin_limit,
                                skip_row, mr, cap);
         else
-            hipLaunchKernelGGL(k_numeric_flow<Scope::Device>, g1, dim3(64), lds, s, P, a_val, f_val, ctl,
+            hipLaunchKernelGGL((k_numeric_flow<Scope::Device, false, kFused>), g1, dim3(64), lds, s, P, a_val, f_val, ctl,
                                spin_limit, skip_row, mr, cap);
     } else if (batch == 1) {
         const size_t lds = (size_t)std::max(max_row, 1) * sizeof(double);
         if (one_xcd)
-            hipLaunchKernelGGL(k_numeric_row<Scope::Xcd>, g1, dim3(64), lds, s, P, a_val, f_val, ctl, spin_limit,
+            hipLaunchKernelGGL((k_numeric_row<Scope::Xcd, kFused>), g1, dim3(64), lds, s, P, a_val, f_val, ctl, spin_limit,
                                skip_row);
         else
-            hipLaunchKernelGGL(k_numeric_row<Scope::Device>, g1, dim3(64), lds, s, P, a_val, f_val, ctl,
+            hipLaunchKernelGGL((k_numeric_row<Scope::Device, kFused>), g1, dim3(64), lds, s, P, a_val, f_val, ctl,
                                spin_limit, skip_row);
     } else {
         const int64_t ws = (int64_t)std::max(max_row, 1) * kWave;
         if (wrow) {
             if (one_xcd)
-                hipLaunchKernelGGL((k_numeric_batch<true, Scope::Xcd>), g1, dim3(64), 0, s, P, a_val, batch,
+                hipLaunchKernelGGL((k_numeric_batch<true, Scope::Xcd, kFused>), g1, dim3(64), 0, s, P, a_val, batch,
                                    f_val, ctl, spin_limit, skip_row, wrow, ws, bvec, xout);
             else
-                hipLaunchKernelGGL((k_numeric_batch<true, Scope::Device>), g1, dim3(64), 0, s, P, a_val, batch,
+                hipLaunchKernelGGL((k_numeric_batch<true, Scope::Device, kFused>), g1, dim3(64), 0, s, P, a_val, batch,
                                    f_val, ctl, spin_limit, skip_row, wrow, ws, bvec, xout);
         } else {
             const size_t lds = (size_t)ws * sizeof(double);
             if (one_xcd)
-                hipLaunchKernelGGL((k_numeric_batch<false, Scope::Xcd>), g1, dim3(64), lds, s, P, a_val, batch,
+                hipLaunchKernelGGL((k_numeric_batch<false, Scope::Xcd, kFused>), g1, dim3(64), lds, s, P, a_val, batch,
                                    f_val, ctl, spin_limit, skip_row, nullptr, (int64_t)0, bvec, xout);
             else
-                hipLaunchKernelGGL((k_numeric_batch<false, Scope::Device>), g1, dim3(64), lds, s, P, a_val,
+                hipLaunchKernelGGL((k_numeric_batch<false, Scope::Device, kFused>), g1, dim3(64), lds, s, P, a_val,
                                    batch, f_val, ctl, spin_limit, skip_row, nullptr, (int64_t)0, bvec, xout);
         }
     }
     return hipGetLastError();
+}
+
+hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, double* f_val,
+                          Ctl* ctl, uint64_t spin_limit, int64_t skip_row, int32_t grid,
+                          int32_t max_row, int32_t max_lrow, bool flow, bool one_xcd, double* wrow,
+                          const double* bvec, double* xout, bool fused, hipStream_t s) {
+    return fused ? launch_numeric_t<true>(P, a_val, batch, f_val, ctl, spin_limit, skip_row, grid, max_row, max_lrow,
+                                          flow, one_xcd, wrow, bvec, xout, s)
+                 : launch_numeric_t<false>(P, a_val, batch, f_val, ctl, spin_limit, skip_row, grid, max_row,
+                                           max_lrow, flow, one_xcd, wrow, bvec, xout, s);
 }
 
 }  // namespace tpilu

@@ -155,11 +155,11 @@ constexpr int32_t kXcds = 8;  // XCDs of an MI355X
 // wrow (batches only): non-null puts every wavefront's working row in global
 // memory, grid x max_row x 64 doubles, instead of LDS.  xout (batches only):
 // non-null fuses the forward substitution x = L~^-1 bvec in (xout pre-filled
-// with kPending).
+// with kPending).  fused: every update of Eq. 6b as one fused multiply-add.
 hipError_t launch_numeric(const PatDev& P, const double* a_val, int32_t batch, double* f_val,
                           Ctl* ctl, uint64_t spin_limit, int64_t skip_row, int32_t grid,
                           int32_t max_row, int32_t max_lrow, bool flow, bool one_xcd, double* wrow,
-                          const double* bvec, double* xout, hipStream_t s);
+                          const double* bvec, double* xout, bool fused, hipStream_t s);
 int numeric_grid(int32_t batch, int32_t max_row, int32_t max_lrow, bool flow, int num_cu, bool global_row = false);
 // the dataflow kernel in critical-path mode: f_len (pre-filled with
 // kPending) receives, per entry, the length of the longest dependency chain

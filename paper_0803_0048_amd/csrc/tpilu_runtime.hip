@@ -31,6 +31,7 @@ struct tpilu_ctx_s {
     int32_t grid_override = 0;
     int solver = 0;  // 0 auto, 1 wavefront per row, 2 one workgroup, 3 lane per row
     int numeric = 0;  // 0 auto, 1 dataflow, 2 pivot-serial
+    bool fused = false;  // numeric updates as one fused multiply-add
     int placement = 0;  // row kernels: 0 auto, 1 whole device, 2 one XCD
     int32_t group = 0;  // level-order positions per ticket of the row kernels; 0 auto
     int32_t tickets = 0;  // position counters of the row kernels; 0 auto
@@ -495,7 +496,7 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
         HIPCHK(ctx, launch_numeric(pdev(ctx, pat, RowKernel::Numeric, true), a_val, batch, f_val, ctl,
                                    ctx->spin_limit, ctx->skip_row, grid, pat->st.max_row, pat->st.max_lrow, flow,
                                    one_xcd, batch_global_row(ctx, pat, batch) ? wrow : nullptr, b, x,
-                                   ctx->stream));
+                                   ctx->fused, ctx->stream));
     }
     return TPILU_OK;
 }
@@ -964,6 +965,13 @@ extern "C" TPILU_API tpilu_status tpilu_ctx_set_numeric(tpilu_ctx ctx, int mode)
     if (!ctx) return TPILU_E_INVAL;
     if (mode < 0 || mode > 2) return fail(ctx, TPILU_E_INVAL, "numeric mode must be 0, 1 or 2");
     ctx->numeric = mode;
+    return TPILU_OK;
+}
+
+extern "C" TPILU_API tpilu_status tpilu_ctx_set_fused(tpilu_ctx ctx, int on) {
+    if (!ctx) return TPILU_E_INVAL;
+    if (on < 0 || on > 1) return fail(ctx, TPILU_E_INVAL, "fused must be 0 or 1");
+    ctx->fused = on == 1;
     return TPILU_OK;
 }
 

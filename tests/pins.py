@@ -21,6 +21,8 @@ from __future__ import annotations
 
 from collections import deque
 
+from fractions import Fraction
+
 import numpy as np
 
 INF = 1 << 40
@@ -107,6 +109,33 @@ def dense_masked_lu(Ad: np.ndarray, mask: np.ndarray) -> np.ndarray:
         blk = F[np.ix_(rows, cols)]
         F[np.ix_(rows, cols)] = np.where(sub, upd, blk)
     return np.where(mask, F, 0.0)
+
+
+def fused_update(f: float, l: float, u: float) -> float:
+    """f - l * u rounded once to the nearest double (ties to even), from exact
+    rational arithmetic: what a fused multiply-add must return.  An exact
+    zero takes the sign IEEE-754 gives the float expression, which is then
+    exact as well."""
+    ex = Fraction(f) - Fraction(l) * Fraction(u)
+    if ex == 0:
+        return f - l * u
+    return ex.numerator / ex.denominator  # int / int is correctly rounded
+
+
+def dense_masked_lu_fused(Ad: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """The elimination of dense_masked_lu (KIJ on the mask), every update
+    f_ij - l_ih f_hj rounded once (fused_update); divisions as usual."""
+    n = Ad.shape[0]
+    F = [[float(Ad[i, j]) if mask[i, j] else 0.0 for j in range(n)] for i in range(n)]
+    for h in range(n):
+        for i in range(h + 1, n):
+            if not mask[i, h]:
+                continue
+            F[i][h] = F[i][h] / F[h][h]
+            for j in range(h + 1, n):
+                if mask[h, j] and mask[i, j]:
+                    F[i][j] = fused_update(F[i][j], F[i][h], F[h][j])
+    return np.where(mask, np.array(F, dtype=np.float64).reshape(n, n), 0.0)
 
 
 def to_dense_vals(n, rowptr, col, val):

@@ -27,6 +27,7 @@ def _gpu_guard(request):
     ctx.set_grid(0)
     ctx.set_solver(0)
     ctx.set_numeric(0)
+    ctx.set_fused(False)
     ctx.set_placement(0)
     ctx.set_group(0)
     ctx.set_tickets(0)
@@ -633,6 +634,79 @@ def test_batched_global_rows(case):
         assert_bits_equal(yh[:, inst], yr, f"y instance {inst}")
     assert torch.equal(graph.f_val.view(torch.int64), f.view(torch.int64))
     assert torch.equal(graph.y.view(torch.int64), y.view(torch.int64))
+
+
+@pytest.mark.parametrize("case", ["conv_diff_2d_ilu1", "banded_n6000_ilu2", "banded_n160000_ilu2"])
+def test_fused_update_single(case):
+    """The fused update (one rounding of f - l u in Eq. 6b): both
+    single-instance kernels, on the whole device and on one XCD, against the
+    oracle's fused elimination; the default mode is unchanged afterwards and
+    differs from the fused one."""
+    A, k = {"conv_diff_2d_ilu1": lambda: (I.conv_diff_2d_64x64_ilu1()["A"], 1),
+            "banded_n6000_ilu2": lambda: (I.random_banded_ilu2(n=6000)["A"], 2),
+            "banded_n160000_ilu2": lambda: (I.random_banded_ilu2()["A"], 2)}[case]()
+    ctx = T.context(0)
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
+    vF, bad = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF, fused=True)
+    v0, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF)
+    assert bad == -1
+    pat = T.symbolic(g(A.rowptr), g(A.col), k)
+    modes = [ctx.NUMERIC_PIVOT] + ([ctx.NUMERIC_FLOW] if pat.info["flow_ready"] else [])
+    try:
+        ctx.set_fused(True)
+        for place in (ctx.PLACE_DEVICE, ctx.PLACE_XCD):
+            ctx.set_placement(place)
+            for mode in modes:
+                ctx.set_numeric(mode)
+                assert_bits_equal(T.numeric(pat, g(A.val), check=False), vF, f"fused F kernel {mode} place {place}")
+                assert T.check(pat) == -1
+    finally:
+        ctx.set_fused(False)
+        ctx.set_numeric(0)
+        ctx.set_placement(0)
+    assert_bits_equal(T.numeric(pat, g(A.val), check=False), v0, "default F after the fused runs")
+    assert not np.array_equal(bits(vF), bits(v0))
+
+
+@pytest.mark.parametrize("case", ["lds_rows", "global_rows"])
+def test_fused_update_batched(case):
+    """The fused update in the batched kernels (working rows in LDS and in
+    global memory), eagerly and in a graph created in fused mode (which
+    keeps it for its launches): every instance against the oracle."""
+    rng = np.random.default_rng(44)
+    if case == "lds_rows":
+        c = I.batched_conv_diff_2d_ilu2(B=70, m=24)
+        A, k, vals, rhs = c["A"], 2, c["A"].val, c["b"]
+        B = A.batch
+    else:
+        A, B, k = _arrow(600, 5), 66, 2
+        vals = _dominant_batch(A, B, rng)
+        rhs = rng.standard_normal((A.n, B))
+    rpF, ciF, _ = O.symbolic(A.n, A.rowptr, A.col, k)
+    pat = T.symbolic(g(A.rowptr), g(A.col), k)
+    av, bv = g(vals), g(rhs)
+    ctx = T.context(0)
+    try:
+        ctx.set_fused(True)
+        f = T.numeric(pat, av)
+        y = T.apply(pat, f, bv)
+        graph = T.BatchedGraph(pat, av, bv)
+    finally:
+        ctx.set_fused(False)
+    graph.launch()
+    torch.cuda.synchronize()
+    assert graph.check() == -1
+    fh, yh = f.cpu().numpy(), y.cpu().numpy()
+    for inst in range(B):
+        vF, bad = O.numeric(A.n, A.rowptr, A.col, np.ascontiguousarray(vals[:, inst]), rpF, ciF, fused=True)
+        assert bad == -1
+        _, yr = O.apply(A.n, rpF, ciF, vF, np.ascontiguousarray(rhs[:, inst]))
+        assert_bits_equal(fh[:, inst], vF, f"fused F instance {inst}")
+        assert_bits_equal(yh[:, inst], yr, f"fused y instance {inst}")
+    assert torch.equal(graph.f_val.view(torch.int64), f.view(torch.int64))
+    assert torch.equal(graph.y.view(torch.int64), y.view(torch.int64))
+    f0 = T.numeric(pat, av)
+    assert not torch.equal(f0.view(torch.int64), f.view(torch.int64))
 
 
 def test_batched_partial_group():

@@ -165,6 +165,31 @@ def test_numeric_bitwise_equals_dense_masked_elimination(seed):
         assert bad == -1 or vF[rpF[bad]:rpF[bad + 1]][ciF[rpF[bad]:rpF[bad + 1]] == bad][0] == 0.0
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_numeric_fused_bitwise_equals_single_rounding(seed):
+    """Fused mode: every update of Eq. 6b is the exact f - l u rounded once.
+    Against a dense KIJ elimination whose updates are computed in exact
+    rational arithmetic and rounded once (pins.fused_update); the two modes
+    must also differ somewhere, or the mode is not applied."""
+    rng = np.random.default_rng(960 + seed)
+    differ = False
+    for _ in range(12):
+        n = int(rng.integers(2, 26))
+        A = I.random_pattern(n, float(rng.choice([0.1, 0.2, 0.3])), seed=int(rng.integers(1 << 30)),
+                             diag_dominant=bool(rng.integers(2)))
+        k = int(rng.choice([0, 1, 2, n]))
+        M = P.dense_pattern(n, A.rowptr, A.col)
+        mask = P.levels_dp(M) <= k
+        rpF, ciF, _ = P.csr_from_dense_mask(mask)
+        vF, _ = O.numeric(n, A.rowptr, A.col, A.val, rpF, ciF, fused=True)
+        D = P.dense_masked_lu_fused(A.to_dense(), mask)
+        rows = np.repeat(np.arange(n), np.diff(rpF))
+        assert np.array_equal(P.bits(vF), P.bits(D[rows, ciF])), (n, k)
+        v0, _ = O.numeric(n, A.rowptr, A.col, A.val, rpF, ciF)
+        differ = differ or not np.array_equal(P.bits(v0), P.bits(vF))
+    assert differ
+
+
 def test_numeric_full_fill_is_exact_lu():
     """k = infinity: L~ U~ is the LU factorization of A (no pivoting), so the
     two triangular solves solve A y = b to rounding."""
