@@ -253,19 +253,19 @@ __global__ __launch_bounds__(64) void k_apply_inverse_wave(PatDev P, const doubl
 // mostly stages nothing; 7-point 64^3 ILU(1), about 6 entries per half:
 // 0.021 ms with 8, 0.042 with 16, both products), else 16 (27-point 50^3
 // ILU(3), about 82 per half: 0.134 ms with 16, 0.149 with 8, 0.228 with 32).
-// rows (nullable): the order rows are taken in, 64 to a wavefront; sorted by
-// the length of the half they sum, so the rows of one wavefront are about
-// equally long and its lanes finish together
+// Rows in their natural order, 64 consecutive ones to a wavefront: their
+// entries and the in_j they gather lie close together.  (Sorting the rows by
+// length so that a wavefront's lanes finish together measured slower on every
+// pattern tried, even and uneven alike.)
 template <bool kUpper, int kTile>
 __global__ __launch_bounds__(64) void k_apply_inverse_tile(PatDev P, const double* __restrict__ G,
-                                                      const double* __restrict__ in, double* __restrict__ out,
-                                                      const int32_t* __restrict__ rows) {
+                                                      const double* __restrict__ in, double* __restrict__ out) {
     constexpr int kTileStride = kTile + 1;  // odd stride: lanes reading their rows hit distinct banks
     __shared__ double tv[kWave * kTileStride];  // the staged products g_ij * in_j
     const int lane = lane_id();
     for (int64_t r0 = (int64_t)blockIdx.x * kWave; r0 < P.n; r0 += (int64_t)gridDim.x * kWave) {
         const bool has = r0 + lane < P.n;
-        const int64_t i = !has ? 0 : rows ? (int64_t)rows[r0 + lane] : r0 + lane;
+        const int64_t i = has ? r0 + lane : 0;
         int64_t a = 0, b = 0;
         if (has) {
             const int64_t dj = P.diagF[i];
@@ -335,26 +335,8 @@ __global__ __launch_bounds__(256) void k_apply_inverse_rows(PatDev P, const doub
     out[i] = s;
 }
 
-// Keys the tiled products sort their rows by (launch_level_order takes keys
-// from 1): 1 + the length of the strict lower half (lenL) or of the upper
-// half with the diagonal (lenU), each at most the longest row
-__global__ void k_half_lengths(int32_t n, const int64_t* __restrict__ rpF, const int32_t* __restrict__ diagF,
-                               int32_t* __restrict__ lenL, int32_t* __restrict__ lenU) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    lenL[i] = 1 + (int32_t)(diagF[i] - rpF[i]);
-    lenU[i] = 1 + (int32_t)(rpF[i + 1] - diagF[i]);
-}
-
-hipError_t launch_half_lengths(int32_t n, const int64_t* rpF, const int32_t* diagF, int32_t* lenL, int32_t* lenU,
-                               hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_half_lengths, dim3((n + 255) / 256), dim3(256), 0, s, n, rpF, diagF, lenL, lenU);
-    return hipGetLastError();
-}
-
 hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const double* b, double* x, double* y,
-                                int shape, const int32_t* rowsL, const int32_t* rowsU, hipStream_t s) {
+                                int shape, hipStream_t s) {
     if (P.n <= 0) return hipSuccess;
     if (shape == kProdThreadRows) {
         const int grid = (P.n + 255) / 256;
@@ -363,13 +345,11 @@ hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const doub
     } else if (shape == kProdTile || shape == kProdTileShort) {
         const int grid = std::min((P.n + kWave - 1) / kWave, 65536);
         if (shape == kProdTileShort) {
-            hipLaunchKernelGGL((k_apply_inverse_tile<false, 8>), dim3(grid), dim3(64), 0, s, P, g_val, b, x, rowsL);
-            hipLaunchKernelGGL((k_apply_inverse_tile<true, 8>), dim3(grid), dim3(64), 0, s, P, g_val, x, y, rowsU);
+            hipLaunchKernelGGL((k_apply_inverse_tile<false, 8>), dim3(grid), dim3(64), 0, s, P, g_val, b, x);
+            hipLaunchKernelGGL((k_apply_inverse_tile<true, 8>), dim3(grid), dim3(64), 0, s, P, g_val, x, y);
         } else {
-            hipLaunchKernelGGL((k_apply_inverse_tile<false, 16>), dim3(grid), dim3(64), 0, s, P, g_val, b, x,
-                               rowsL);
-            hipLaunchKernelGGL((k_apply_inverse_tile<true, 16>), dim3(grid), dim3(64), 0, s, P, g_val, x, y,
-                               rowsU);
+            hipLaunchKernelGGL((k_apply_inverse_tile<false, 16>), dim3(grid), dim3(64), 0, s, P, g_val, b, x);
+            hipLaunchKernelGGL((k_apply_inverse_tile<true, 16>), dim3(grid), dim3(64), 0, s, P, g_val, x, y);
         }
     } else {
         const int grid = std::min(P.n, 65536);

@@ -300,11 +300,8 @@ hipError_t launch_inverse(const PatDev& P, const InvSched& S, const double* f_va
 // shapes of the two products of the incomplete inverses
 // (kProdTile stages 16 entries per row and round, kProdTileShort 8)
 enum { kProdWaveRows = 0, kProdThreadRows = 1, kProdTile = 2, kProdTileShort = 3 };
-// rowsL / rowsU (nullable): the tiled products' row orders (by half length)
 hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const double* b, double* x, double* y,
-                                int shape, const int32_t* rowsL, const int32_t* rowsU, hipStream_t s);
-hipError_t launch_half_lengths(int32_t n, const int64_t* rpF, const int32_t* diagF, int32_t* lenL, int32_t* lenU,
-                               hipStream_t s);
+                                int shape, hipStream_t s);
 
 // ---- hand-off probe -------------------------------------------------------------------
 size_t probe_buf_bytes();

@@ -264,10 +264,6 @@ struct tpilu_pattern_s {
     // one-CU solves); built with the pattern when those are the automatic
     // choice, else on first use
     int32_t* dep_pos = nullptr;
-    // rows sorted by the length of their strict lower half (inv_rowsL) and
-    // of their upper half (inv_rowsU): the row orders of the tiled products
-    // with the incomplete inverses (built on first use)
-    int32_t *inv_rowsL = nullptr, *inv_rowsU = nullptr;
     bool solve_cu = false;  // the automatic solve shape is the one-CU one
     // target-major update schedule (only when the dataflow numeric kernel fits)
     bool flow = false;
@@ -607,41 +603,6 @@ struct TmpBufs {
     ~TmpBufs() { for (void* p : v) al.put(p); }
 };
 
-// Row orders of the tiled products: for patterns of uneven rows (longest
-// over 1.5 x the average), rows by half length (counting sort), so that the
-// 64 rows of a wavefront are about equally long; even patterns keep the
-// natural order, whose neighbouring rows gather neighbouring entries.
-// Measured on MI355X, both products: random banded n=160,000 ILU(2)
-// (longest row 419, average 164) 0.26 ms sorted, 0.35 sorted only inside
-// blocks of 4,096 rows, 0.29 by wavefront per row; 7-point 64^3 ILU(1)
-// 0.029 ms in natural order, 0.046 sorted.  Without the orders (no memory)
-// the products take the rows in natural order.
-bool inv_rows_even(tpilu_pattern pat) {
-    return 2 * (int64_t)pat->st.max_row * std::max<int64_t>(pat->n, 1) <= 3 * pat->nnz_f;
-}
-tpilu_status build_inv_rows(tpilu_ctx ctx, tpilu_pattern pat) {
-    if (pat->inv_rowsL || pat->n == 0 || inv_rows_even(pat)) return TPILU_OK;
-    const int32_t n = (int32_t)pat->n;
-    const int32_t keys = pat->st.max_row + 1;
-    TmpBufs T{pat->al, {}};
-    int32_t* lenL = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);
-    int32_t* lenU = (int32_t*)T.get(sizeof(int32_t) * (size_t)n);
-    int32_t* hist = (int32_t*)T.get(sizeof(int32_t) * 2 * (size_t)keys);
-    int64_t* off = (int64_t*)T.get(sizeof(int64_t) * ((size_t)keys + 1));
-    int64_t* stmp = (int64_t*)T.get(sizeof(int64_t) * scan_tmp_elems(keys));
-    int32_t* rl = (int32_t*)pat->take(sizeof(int32_t) * (size_t)n);
-    int32_t* ru = (int32_t*)pat->take(sizeof(int32_t) * (size_t)n);
-    if (!lenL || !lenU || !hist || !off || !stmp || !rl || !ru) return TPILU_OK;
-    hipStream_t s = ctx->stream;
-    HIPCHK(ctx, launch_half_lengths(n, pat->rpF, pat->diagF, lenL, lenU, s));
-    HIPCHK(ctx, launch_level_order(n, lenL, keys, hist, off, stmp, rl, s));
-    HIPCHK(ctx, launch_level_order(n, lenU, keys, hist, off, stmp, ru, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    pat->inv_rowsL = rl;
-    pat->inv_rowsU = ru;
-    return TPILU_OK;
-}
-
 // Per F slot, the level-order position of the row its column names, for the
 // one-CU solves.
 tpilu_status build_dep_positions(tpilu_ctx ctx, tpilu_pattern pat) {
@@ -758,10 +719,7 @@ int inverse_product_shape(tpilu_ctx ctx, tpilu_pattern pat) {
     if (ctx->solver == 1) return kProdWaveRows;
     if (ctx->solver == 3) return kProdThreadRows;
     const int64_t n = std::max<int64_t>(pat->n, 1);
-    // rows sorted by length make every tile even; without that order, only
-    // a pattern of even rows takes tiles
-    const bool even = pat->inv_rowsL || inv_rows_even(pat);
-    if (!even || pat->nnz_f > kInvTileMaxAvg * n) return kProdWaveRows;
+    if (pat->nnz_f > kInvTileMaxAvg * n) return kProdWaveRows;
     return pat->nnz_f <= kInvShortAvg * n ? kProdTileShort : kProdTile;
 }
 
@@ -1481,10 +1439,8 @@ extern "C" TPILU_API tpilu_status tpilu_apply_inverse(tpilu_ctx ctx, tpilu_patte
         x = pat->grow(pat->ws_x, sizeof(double) * (size_t)pat->n);
         if (!x) return fail(ctx, TPILU_E_NOMEM, "apply workspace");
     }
-    st = build_inv_rows(ctx, pat);
-    if (st) return st;
     HIPCHK(ctx, launch_apply_inverse(pdev(ctx, pat), g_val, b, x, y, inverse_product_shape(ctx, pat),
-                                     pat->inv_rowsL, pat->inv_rowsU, ctx->stream));
+                                     ctx->stream));
     return TPILU_OK;
 }
 
@@ -1600,7 +1556,7 @@ tpilu_status enqueue_precond(tpilu_ctx ctx, tpilu_pattern pat, const double* m_v
     if (!inverse) return enqueue_apply(ctx, pat, m_val, 1, v, z, t, reset, pat->ctl);
     if (reset) HIPCHK(ctx, launch_fill_pending(nullptr, 0, pat->ctl, true, ctx->stream));
     HIPCHK(ctx, launch_apply_inverse(pdev(ctx, pat), m_val, v, t, z, inverse_product_shape(ctx, pat),
-                                     pat->inv_rowsL, pat->inv_rowsU, ctx->stream));
+                                     ctx->stream));
     return TPILU_OK;
 }
 
@@ -1740,11 +1696,6 @@ extern "C" TPILU_API tpilu_status tpilu_gmres_inverse(tpilu_ctx ctx, tpilu_patte
                                                       const double* g_val, const double* b, double* x,
                                                       int32_t restart, int32_t maxit, double rtol,
                                                       int32_t* iters, double* relres, double* hist) {
-    if (ctx && pat && pat->n > 0) {
-        DeviceGuard dg(ctx->device);
-        const tpilu_status st = build_inv_rows(ctx, pat);
-        if (st) return st;
-    }
     return gmres_impl(ctx, pat, a_val, g_val, true, b, x, restart, maxit, rtol, iters, relres, hist);
 }
 
@@ -1767,10 +1718,6 @@ extern "C" TPILU_API tpilu_status tpilu_bicgstab(tpilu_ctx ctx, tpilu_pattern pa
     DeviceGuard dg(ctx->device);
     hipStream_t s = ctx->stream;
     const bool inv = inverse != 0;
-    if (inv) {
-        st = build_inv_rows(ctx, pat);
-        if (st) return st;
-    }
     // workspace: r rs p v ph sv sh t tmp (n each) | 3 partial blocks | scalars
     const size_t nn = (size_t)n;
     double* wsd = pat->grow(pat->ws_bi, sizeof(double) * (9 * nn + 3 * kDotBlocks + 16));
