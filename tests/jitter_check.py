@@ -6,10 +6,11 @@ every hand-off then happens at times the normal timing never produces, and
 every result must still equal the oracle's bits.
 
 Cases: pattern (levels on the whole device and on one XCD); both
-single-instance factorization kernels in both placements; every solve shape;
+single-instance factorization kernels in both placements, with either
+rounding of the update; every solve shape;
 the incomplete inverses and their products; GMRES; a batch in a graph (short
 rows in LDS, fused forward substitution) and a batch with global-memory
-working rows; the reverse-mode sweeps of a batch.
+working rows, each also with the fused update; the reverse-mode sweeps of a batch.
 """
 from __future__ import annotations
 
@@ -45,6 +46,16 @@ def single(name, A, k, b):
         for mode in modes:
             ctx.set_numeric(mode)
             assert_bits_equal(T.numeric(pat, g(A.val)), vF, f"{name} F numeric {mode} placement {place}")
+        ctx.set_numeric(0)
+        # the fused update (one rounding of f - l u) in both kernels
+        vFf, _ = O.numeric(A.n, A.rowptr, A.col, A.val, rpF, ciF, fused=True)
+        ctx.set_fused(True)
+        try:
+            for mode in modes:
+                ctx.set_numeric(mode)
+                assert_bits_equal(T.numeric(pat, g(A.val)), vFf, f"{name} fused F numeric {mode} placement {place}")
+        finally:
+            ctx.set_fused(False)
         ctx.set_numeric(0)
     ctx.set_placement(0)
     f = T.numeric(pat, g(A.val))
@@ -85,6 +96,15 @@ def batched(name, A, k, rhs):
         _, yr = O.apply(A.n, rpF, ciF, vF, np.ascontiguousarray(rhs[:, i]))
         for what, got, want in (("F", fh, vF), ("y", yh, yr), ("graph F", gf, vF), ("graph y", gy, yr)):
             assert_bits_equal(got[:, i], want, f"{name} {what} instance {i}")
+    ctx = T.context(0)
+    ctx.set_fused(True)
+    try:
+        ffh = T.numeric(pat, av).cpu().numpy()
+    finally:
+        ctx.set_fused(False)
+    for i in range(0, B, 5):
+        vFf, _ = O.numeric(A.n, A.rowptr, A.col, np.ascontiguousarray(A.val[:, i]), rpF, ciF, fused=True)
+        assert_bits_equal(ffh[:, i], vFf, f"{name} fused F instance {i}")
 
 
 def adjoint(name, A, k, B, seed):
