@@ -45,6 +45,39 @@ hipError_t launch_fill_pending(double* p, int64_t n, Ctl* ctl, bool reset_status
     return hipGetLastError();
 }
 
+// The same for a factorization: only the slots other rows wait on, those of
+// U~ (diagonal to row end, every instance), get the marker; the l values
+// pass between rows only inside their own row's wavefront, and every row
+// writes its L~ part when it finishes.  A wavefront per row at a time.
+__global__ void k_fill_pending_upper(double* __restrict__ F, int32_t n, const int64_t* __restrict__ rpF,
+                                     const int32_t* __restrict__ diagF, int32_t batch, Ctl* ctl,
+                                     int reset_status) {
+    if (blockIdx.x == 0 && threadIdx.x < kTicketParts) ctl->part[threadIdx.x * kTicketStride] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->ticket = 0;
+        ctl->leader = 0;
+        if (reset_status) {
+            ctl->abort = 0;
+            ctl->status = 0;
+            ctl->bad_row = ~0ull;
+        }
+    }
+    const double pend = as_f64(kPending);
+    const int32_t waves = (int32_t)(gridDim.x * (blockDim.x / kWave));
+    for (int32_t j = (int32_t)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave); j < n; j += waves) {
+        const int64_t a = (int64_t)diagF[j] * batch, b = rpF[j + 1] * batch;
+        for (int64_t i = a + lane_id(); i < b; i += kWave) F[i] = pend;
+    }
+}
+
+hipError_t launch_fill_pending_upper(double* f_val, int32_t n, const int64_t* rpF, const int32_t* diagF,
+                                     int32_t batch, Ctl* ctl, bool reset_status, hipStream_t s) {
+    const int blocks = std::max(1, std::min((n + 3) / 4, 8192));
+    hipLaunchKernelGGL(k_fill_pending_upper, dim3(blocks), dim3(256), 0, s, f_val, n, rpF, diagF, batch, ctl,
+                       reset_status ? 1 : 0);
+    return hipGetLastError();
+}
+
 // Wait until pivot i of the staged group is final: its diagonal and every
 // value f_ht it contributes.  Each polling round also refreshes the pending
 // values of the next few pivots, so pivots whose rows finish while row j

@@ -146,6 +146,10 @@ struct PatDev {
 // fill `n` doubles with kPending; thread 0 also resets ctl->ticket (and, if
 // reset_status, the sticky status words)
 hipError_t launch_fill_pending(double* p, int64_t n, Ctl* ctl, bool reset_status, hipStream_t s);
+// the same for the U~ slots of a factor (rows diag..end, batch values per
+// slot); the L~ slots are left as they are (the elimination writes them)
+hipError_t launch_fill_pending_upper(double* f_val, int32_t n, const int64_t* rpF, const int32_t* diagF,
+                                     int32_t batch, Ctl* ctl, bool reset_status, hipStream_t s);
 
 constexpr int32_t kXcds = 8;  // XCDs of an MI355X
 

@@ -487,7 +487,8 @@ tpilu_status enqueue_numeric(tpilu_ctx ctx, tpilu_pattern pat, const double* a_v
         // the timed region holds the pending-marker fill of F too: the
         // elimination cannot run without it
         TimedLaunch tl(ctx, TPILU_KERNEL_NUMERIC);
-        HIPCHK(ctx, launch_fill_pending(f_val, pat->nnz_f * batch, ctl, true, ctx->stream));
+        HIPCHK(ctx, launch_fill_pending_upper(f_val, (int32_t)pat->n, pat->rpF, pat->diagF, batch, ctl, true,
+                                              ctx->stream));
         if (x) HIPCHK(ctx, launch_fill_pending(x, pat->n * batch, ctl, false, ctx->stream));
         HIPCHK(ctx, launch_numeric(pdev(ctx, pat, RowKernel::Numeric, true), a_val, batch, f_val, ctl,
                                    ctx->spin_limit, ctx->skip_row, grid, pat->st.max_row, pat->st.max_lrow, flow,
