@@ -570,7 +570,7 @@ def batched_extra(T, I, torch, np, dev, ctx, oracle=True):
            "numeric_roofline": roof(mb["numeric"], statistics.median(num), "numeric (batched)"),
            "forward_roofline": roof(mb["forward"], statistics.median(fw), "forward (batched)"),
            "backward_roofline": roof(mb["backward"], statistics.median(bw), "backward (batched)"),
-           "graph_kernels": "fill F, fill x, factorization with the forward substitution fused in, fill y, "
+           "graph_kernels": "fill the U slots of F, fill x, factorization with the forward substitution fused in, fill y, "
                             "backward substitution",
            "depth_l": info["depth_l"]}
     res["long_rows"] = batched_long_rows(T, I, torch, np, dev, oracle=oracle)
