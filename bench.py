@@ -338,6 +338,23 @@ def main():
         per.append(ms / max(cnt, 1))
     T.check(pat)
     numeric_ms = statistics.median(per)
+    # the same factorization with the update of Eq. 6b as one fused
+    # multiply-add (the optional rounding; compared with the oracle's below)
+    ffused, fused_ms = None, None
+    if not args.step_only:
+        log(f"numeric factorization, fused update, x{args.numeric_reps}")
+        ffused = torch.empty_like(fout)
+        perf = []
+        ctx.set_fused(True)
+        try:
+            for _ in range(args.numeric_reps):
+                T.numeric(pat, av, out=ffused, check=False)
+                ms, cnt = ctx.read_timing(ctx.KERNEL_NUMERIC)
+                perf.append(ms / max(cnt, 1))
+            T.check(pat)
+        finally:
+            ctx.set_fused(False)
+        fused_ms = statistics.median(perf)
     # applies, for their own kernel times
     yout = torch.empty_like(bv)
     xout = torch.empty_like(bv)
@@ -387,6 +404,7 @@ def main():
         "numeric": {"ms": numeric_ms, "min_ms": min(per), "model_bytes": mb["numeric"],
                     "model_gbs": numeric_gbs, "frac": numeric_gbs / HBM_PEAK_GBS,
                     "timed_region": "pending-marker fill of F + elimination kernel",
+                    "fused_update_ms": fused_ms,
                     "updates": pinfo["n_updates"], "depth_l": pinfo["depth_l"], "depth_u": pinfo["depth_u"],
                     "n_over_depth": n / max(pinfo["depth_l"], 1)},
         "phases_ms": {"symbolic": sym_ms, "numeric": numeric_ms, "gmres": gmres_ms,
@@ -419,7 +437,8 @@ def main():
         out["extras"]["paper_scale_ilu1"] = paper_scale_extra(T, I, torch, dev, ctx)
 
     if not args.no_cpu_baseline:
-        cb, match = cpu_baseline(np, A, k, cfg["b"], restart, rtol, maxit, pat, fout, yout, xg, ginfo, bv, T)
+        cb, match = cpu_baseline(np, A, k, cfg["b"], restart, rtol, maxit, pat, fout, yout, xg, ginfo, bv, T,
+                                 ffused)
         out["cpu_baseline"] = cb
         out["bitwise_match"] = match
     # the paper's headline speedups, with their hardware: context for the
@@ -867,11 +886,12 @@ def inverse_extra(T, torch, pat, av, f, bv, restart, rtol, maxit, gmres_ms, ginf
             "gmres_with_substitutions": {"iters": ginfo["iters"], "ms": gmres_ms}}
 
 
-def cpu_baseline(np, A, k, b, restart, rtol, maxit, pat, fout, yout, xg, ginfo, bv, T):
+def cpu_baseline(np, A, k, b, restart, rtol, maxit, pat, fout, yout, xg, ginfo, bv, T, ffused=None):
     """The oracle (sequential, one host core) on the headline workload: every
     phase once, the numeric factorization (the headline) median of 3, and the
     GPU's factor, solve and GMRES iterate compared with the oracle's bit for
-    bit."""
+    bit; with ffused, the GPU's factor in the fused-update mode against the
+    oracle's fused elimination too."""
     import oracle as O
 
     log("cpu baseline: oracle on the n=160000 ILU(2) workload (numeric x3)")
@@ -880,6 +900,9 @@ def cpu_baseline(np, A, k, b, restart, rtol, maxit, pat, fout, yout, xg, ginfo, 
     T.apply(pat, fout, bv, out=yout)
     g = {"pat": pat, "f": fout, "y": yout, "x": xg, "ginfo": ginfo}
     match = bitwise(np, g, ref)
+    if ffused is not None:
+        vFf, _ = O.numeric(A.n, A.rowptr, A.col, A.val, ref["rpF"], ref["ciF"], fused=True)
+        match["factor_fused_update"] = bits_equal(np, ffused.cpu().numpy(), vFf)
     hi = host_info()
     cb = {"value": times["numeric_ms"], "unit": "ms", "cores": 1, "kind": "oracle",
           "sample": "full numeric factorization of the n=160000 ILU(2) workload, median of 3 (pattern "

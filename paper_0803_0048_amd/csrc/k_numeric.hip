@@ -421,16 +421,39 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
                 for (;;) {
                     bool prog = false;
                     if (have) {
-                        while (e < ee) {
+                        // the entry's updates while their inputs are in LDS.  An
+                        // entry mostly takes one or two, so the first is taken
+                        // before the loop: in the default rounding that shape
+                        // measured 5.78 -> 5.26 ms at n=160,000 k=2; with the
+                        // fused update the compiler peels the plain loop itself
+                        // (5.24 ms; 5.32 with the peel written out)
+                        if constexpr (kFused || kHops) {
+                            while (e < ee) {
+                                const uint64_t lb = Lb[Ss[e]];
+                                const uint64_t vb = Sv[e];
+                                if (lb == kPending || vb == kPending) break;
+                                if constexpr (kHops)
+                                    acc = fmax(acc, fmax(as_f64(lb), as_f64(vb) + w_hop));
+                                else
+                                    acc = ikj_update<kFused>(acc, as_f64(lb), as_f64(vb));
+                                ++e;
+                                prog = true;
+                            }
+                        } else if (e < ee) {
                             const uint64_t lb = Lb[Ss[e]];
                             const uint64_t vb = Sv[e];
-                            if (lb == kPending || vb == kPending) break;
-                            if constexpr (kHops)
-                                acc = fmax(acc, fmax(as_f64(lb), as_f64(vb) + w_hop));
-                            else
-                                acc = ikj_update<kFused>(acc, as_f64(lb), as_f64(vb));
-                            ++e;
-                            prog = true;
+                            if (lb != kPending && vb != kPending) {
+                                acc = ikj_update<false>(acc, as_f64(lb), as_f64(vb));
+                                ++e;
+                                prog = true;
+                                while (e < ee) {
+                                    const uint64_t lb2 = Lb[Ss[e]];
+                                    const uint64_t vb2 = Sv[e];
+                                    if (lb2 == kPending || vb2 == kPending) break;
+                                    acc = ikj_update<false>(acc, as_f64(lb2), as_f64(vb2));
+                                    ++e;
+                                }
+                            }
                         }
                         if (e >= ee) {
                             bool fin = true;
