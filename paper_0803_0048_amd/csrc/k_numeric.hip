@@ -320,7 +320,9 @@ __global__ __launch_bounds__(64) void k_numeric_row(PatDev P, const double* __re
 // the U part are published the moment they are final, so rows that pivot on
 // row j need not wait for the rest of it.
 constexpr int kFlowCap = 1024;   // staged updates per chunk of targets (at least the longest L part)
-constexpr int kFlowLook = 4;     // staged values re-polled per lane and round
+// staged values re-polled per lane and round (at n=160,000 k=2: 1 / 2 / 3 / 4 / 6
+// measured 6.12 / 5.44 / 5.19 / 5.25 / 5.44 ms)
+constexpr int kFlowLook = 3;
 
 size_t flow_lds_bytes(int32_t max_row, int32_t cap) {
     return (size_t)max_row * 8 * 3 + (size_t)cap * 8 + (size_t)max_row * 4 + (size_t)cap * 8 +
