@@ -105,7 +105,9 @@ hipError_t launch_isched(int32_t n, const int64_t* rpF, const int32_t* ciF, cons
 // ----------------------------------------------------------------------------------
 // values
 // ----------------------------------------------------------------------------------
-constexpr int kInvChunk = 8;
+// entries whose partner values are loaded together (random banded n=160,000
+// ILU(2), both halves: 2 / 4 / 8 measured 6.2 / 6.3 / 7.1 ms)
+constexpr int kInvChunk = 2;
 
 template <bool kUpper>
 __global__ __launch_bounds__(64) void k_inverse(PatDev P, InvSched S, const double* __restrict__ F, double* G,

@@ -560,7 +560,10 @@ __global__ __launch_bounds__(64) void k_numeric_flow(PatDev P, const double* __r
 constexpr int kBPivCap = 8;
 constexpr int kBPairCap = 32;
 constexpr int kBAChunk = 8;  // A entries loaded per round trip
-constexpr int kBLook = 8;    // pending pair values re-read per polling round
+// pending pair values re-read per polling round (256 x 128^2 ILU(2) factorization:
+// 1 / 2 / 3 / 4 / 8 measured 1.66 / 1.37 / 1.19 / 1.23 / 1.42 ms; 70 x 27-point 20^3
+// ILU(2), global working rows: 21.9 / 22.5 / 23.1 / 23.4 / 23.6 ms)
+constexpr int kBLook = 3;
 constexpr int kBWChunk = 8;  // values loaded per round trip (global working rows, publish, fused forward)
 
 // kGW: the working row lives in global memory (a slice of wrow per
