@@ -251,10 +251,11 @@ __global__ __launch_bounds__(64) void k_apply_inverse_wave(PatDev P, const doubl
 // entries of 64 / kTile rows), then every lane walks its own row there: the
 // in-order sum of a row is one lane's chain, so the wavefront's 64 chains run
 // side by side instead of one at a time.
-// kTile entries per row per staging round: 8 for short rows (a round of 16
-// mostly stages nothing; 7-point 64^3 ILU(1), about 6 entries per half:
-// 0.021 ms with 8, 0.042 with 16, both products), else 16 (27-point 50^3
-// ILU(3), about 82 per half: 0.134 ms with 16, 0.149 with 8, 0.228 with 32).
+// kTile entries per row per staging round (at most 32: one bit per staged
+// slice in `on`): 8 for short rows (a round of 16 mostly stages nothing;
+// 7-point 64^3 ILU(1), about 6 entries per half: 0.021 ms with 8, 0.042 with
+// 16, both products), else 32 (27-point 50^3 ILU(3), about 82 per half: 0.084
+// ms with 32, 0.101 with 16; random banded n=160,000 ILU(2): 0.220 / 0.237 ms).
 // Rows in their natural order, 64 consecutive ones to a wavefront: their
 // entries and the in_j they gather lie close together.  (Sorting the rows by
 // length so that a wavefront's lanes finish together measured slower on every
@@ -350,8 +351,8 @@ hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const doub
             hipLaunchKernelGGL((k_apply_inverse_tile<false, 8>), dim3(grid), dim3(64), 0, s, P, g_val, b, x);
             hipLaunchKernelGGL((k_apply_inverse_tile<true, 8>), dim3(grid), dim3(64), 0, s, P, g_val, x, y);
         } else {
-            hipLaunchKernelGGL((k_apply_inverse_tile<false, 16>), dim3(grid), dim3(64), 0, s, P, g_val, b, x);
-            hipLaunchKernelGGL((k_apply_inverse_tile<true, 16>), dim3(grid), dim3(64), 0, s, P, g_val, x, y);
+            hipLaunchKernelGGL((k_apply_inverse_tile<false, 32>), dim3(grid), dim3(64), 0, s, P, g_val, b, x);
+            hipLaunchKernelGGL((k_apply_inverse_tile<true, 32>), dim3(grid), dim3(64), 0, s, P, g_val, x, y);
         }
     } else {
         const int grid = std::min(P.n, 65536);

@@ -302,7 +302,7 @@ hipError_t launch_inverse(const PatDev& P, const InvSched& S, const double* f_va
                           Ctl* ctl, uint64_t spin_limit, int32_t grid, hipStream_t s);
 // x = L~~^-1 b, y = U~~^-1 x; thread_rows: one thread per row, else a wavefront
 // shapes of the two products of the incomplete inverses
-// (kProdTile stages 16 entries per row and round, kProdTileShort 8)
+// (kProdTile stages 32 entries per row and round, kProdTileShort 8)
 enum { kProdWaveRows = 0, kProdThreadRows = 1, kProdTile = 2, kProdTileShort = 3 };
 hipError_t launch_apply_inverse(const PatDev& P, const double* g_val, const double* b, double* x, double* y,
                                 int shape, hipStream_t s);
