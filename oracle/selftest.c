@@ -138,6 +138,17 @@ static void run_case(int64_t n, double density, int32_t k)
     int64_t bad = 0;
     st = orc_numeric(n, rp, ci, v, P.rowptr, P.col, f, &bad);
     CHECK(st == ORC_OK && bad == -1, "numeric status %d bad %lld", st, (long long)bad);
+    /* the fused update: the same pattern, finite values, within rounding of
+       the default rounding's factor */
+    {
+        double *ff = (double *)malloc((size_t)(nnzf > 0 ? nnzf : 1) * sizeof(double));
+        int64_t badf = 0;
+        st = orc_numeric_fused(n, rp, ci, v, P.rowptr, P.col, ff, &badf);
+        CHECK(st == ORC_OK && badf == -1, "fused numeric status %d bad %lld", st, (long long)badf);
+        for (int64_t e = 0; e < nnzf; ++e)
+            CHECK(isfinite(ff[e]) && fabs(ff[e] - f[e]) <= 1e-9 * (1.0 + fabs(f[e])), "fused entry %lld", (long long)e);
+        free(ff);
+    }
     double *b = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     double *x = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     double *y = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
